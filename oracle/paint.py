@@ -1,0 +1,113 @@
+"""Oracle: painting a catalog onto a periodic mesh (float64, CPU).
+
+TEST INFRASTRUCTURE ONLY -- see the package docstring.
+
+Paper passages followed
+-----------------------
+* Sec. 3.3.1, Eq. (1): the painted field is F(x) = [1 + delta'(x)] V(x) with
+  n'(x) = W(x) n(x); in the default case W = V = 1 and F is 1 + delta.  Here
+  the mesh holds the weighted sum of window values, F_j = sum_p w_p W(u_p - j);
+  the division by sum(w) that turns it into 1 + delta is folded into the power
+  normalisation (``power.py``).
+* Sec. 3.3.2: the CIC, TSC and PCS windows.  The paper fixes them through the
+  sinc^p compensation of Eq. (2) with p = 2, 3, 4; the only window whose
+  Fourier transform is sinc^p is the centred cardinal B-spline of order p
+  (p-fold self-convolution of the unit box), which is what ``bspline`` below
+  evaluates.
+* Sec. 3.3.2 (interlacing): the second mesh is offset by half a cell; it is
+  painted here from u + 1/2 (``shift_cells = 0.5``).
+
+Readings where the paper is silent (each one is pinned by a test):
+* mesh nodes sit at x = j H, H = L / N, so the cell coordinate is u = x N / L;
+* positions outside [0, L) wrap periodically;
+* TSC rounds its centre cell as floor(u + 1/2) (the weights are continuous,
+  so the tie choice does not change the result).
+"""
+
+import numpy as np
+
+WINDOW_ORDER = {"cic": 2, "tsc": 3, "pcs": 4}
+
+
+def wrap_positions(pos, boxsize):
+    """Periodic wrap of positions into [0, L) (reading: positions wrap)."""
+    x = np.asarray(pos, dtype=np.float64)
+    x = x - boxsize * np.floor(x / boxsize)
+    # x / L can round so that a tiny negative x lands exactly on L.
+    x = np.where(x >= boxsize, 0.0, x)
+    return x
+
+
+def cell_coordinates(pos, nmesh, boxsize):
+    """u = x N / L for wrapped positions: mesh node j sits at u = j."""
+    return wrap_positions(pos, boxsize) * nmesh / boxsize
+
+
+def bspline(order, a):
+    """Centred cardinal B-spline M_p(a) of order p = 2, 3, 4 (Sec. 3.3.2).
+
+    M_2 is the CIC tent, M_3 the TSC quadratic, M_4 the PCS cubic.  Each is
+    the p-fold convolution of the unit box on [-1/2, 1/2].
+    """
+    a = np.abs(np.asarray(a, dtype=np.float64))
+    if order == 2:
+        return np.where(a < 1.0, 1.0 - a, 0.0)
+    if order == 3:
+        return np.where(
+            a < 0.5, 0.75 - a * a, np.where(a < 1.5, 0.5 * (1.5 - a) ** 2, 0.0)
+        )
+    if order == 4:
+        return np.where(
+            a < 1.0,
+            (4.0 - 6.0 * a * a + 3.0 * a ** 3) / 6.0,
+            np.where(a < 2.0, (2.0 - a) ** 3 / 6.0, 0.0),
+        )
+    raise ValueError("window order must be 2 (CIC), 3 (TSC) or 4 (PCS)")
+
+
+def window_weights(u, order):
+    """Cells and weights of the order-p window for cell coordinates u.
+
+    Returns ``(cells, weights)``, each of shape ``u.shape + (p,)``: the p
+    (unwrapped) integer cells that the window touches and M_p(u - j) there.
+    Even orders start from floor(u); odd orders centre on floor(u + 1/2).
+    """
+    u = np.asarray(u, dtype=np.float64)
+    if order % 2 == 0:
+        first = np.floor(u) - (order // 2 - 1)
+    else:
+        first = np.floor(u + 0.5) - (order - 1) // 2
+    offsets = np.arange(order, dtype=np.float64)
+    cells = first[..., None] + offsets
+    weights = bspline(order, u[..., None] - cells)
+    return cells.astype(np.int64), weights
+
+
+def paint_mesh(pos, nmesh, boxsize, order, weight=None, shift_cells=0.0):
+    """F_j = sum_p w_p prod_d M_p(u_{p,d} + shift - j_d), periodic (Eq. 1).
+
+    ``pos`` is (N_p, 3) in the box units, ``weight`` is (N_p,) or None for
+    unit weights, ``shift_cells`` is 0 for the plain mesh and 1/2 for the
+    interlaced mesh.  Returns a float64 (N, N, N) array indexed [x, y, z].
+    Each of the p^3 stencil offsets is accumulated with ``np.bincount``, a
+    sequential float64 sum.
+    """
+    pos = np.asarray(pos, dtype=np.float64).reshape(-1, 3)
+    n = nmesh
+    u = cell_coordinates(pos, n, boxsize) + shift_cells
+    w = np.ones(len(pos)) if weight is None else np.asarray(weight, dtype=np.float64)
+    cx, wx = window_weights(u[:, 0], order)
+    cy, wy = window_weights(u[:, 1], order)
+    cz, wz = window_weights(u[:, 2], order)
+    cx %= n
+    cy %= n
+    cz %= n
+    mesh = np.zeros(n ** 3, dtype=np.float64)
+    for a in range(order):
+        for b in range(order):
+            for c in range(order):
+                flat = (cx[:, a] * n + cy[:, b]) * n + cz[:, c]
+                mesh += np.bincount(
+                    flat, weights=w * wx[:, a] * wy[:, b] * wz[:, c], minlength=n ** 3
+                )
+    return mesh.reshape(n, n, n)

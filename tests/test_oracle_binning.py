@@ -1,0 +1,191 @@
+"""Pins for the oracle's FFTPower binning (Sec. 3.4.1).
+
+Expected values come from brute-force enumeration of the full grid of integer
+wave vectors n in [-N/2, N/2)^3 (no Hermitian weights, plain Python / integer
+arithmetic), and from fields whose power is known exactly:
+* a fixed-amplitude field |DFT(F)| = N^3 sqrt(P(|k|) / V) measures
+  P_b = mean of P(|k|) over the modes of bin b exactly;
+* for any isotropic fixed-amplitude field P_2 = 0, since every exact-n^2
+  shell is invariant under axis permutations and sum_shell L_2(mu) = 0;
+* P_4 and P(k, mu) equal brute-force mode averages of P L_4 and P.
+The mode counts of the 64^3 mesh are also stored in tests/golden (written by
+tests/golden/make_golden.py from the oracle) and cross-checked against the
+brute-force enumeration here.
+"""
+
+import math
+import os
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1712_05834_amd import synth
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _full_grid(n):
+    r = np.arange(-n // 2, n // 2)
+    g = np.meshgrid(r, r, r, indexing="ij")
+    return g[0].ravel(), g[1].ravel(), g[2].ravel()
+
+
+def _brute_kbin(n2, nk):
+    """b = isqrt(n^2) for unit edges, DC and b >= nk excluded (math.isqrt)."""
+    b = np.array([math.isqrt(int(v)) for v in n2])
+    return np.where((n2 == 0) | (b >= nk), -1, b)
+
+
+def _brute_mubin(nlos, n2, nmu):
+    """Largest j in 0..Nmu with (j / Nmu)^2 <= nlos^2 / n^2, by exact Fractions."""
+    out = []
+    for a, b in zip(nlos, n2):
+        mu2 = Fraction(int(a) * int(a), int(b))
+        j = 0
+        while j + 1 <= nmu and Fraction((j + 1) ** 2, nmu * nmu) <= mu2:
+            j += 1
+        out.append(min(j, nmu - 1))
+    return np.array(out)
+
+
+def test_mode_counts_64_match_brute_force_and_golden():
+    n, nk = 64, 32
+    gx, gy, gz = _full_grid(n)
+    n2 = gx * gx + gy * gy + gz * gz
+    b = _brute_kbin(n2, nk)
+    brute = np.bincount(b[b >= 0], minlength=nk)
+    kbar = np.bincount(b[b >= 0], weights=np.sqrt(n2[b >= 0]), minlength=nk) / np.maximum(brute, 1)
+    tab = oracle.mode_tables(n, 1000.0)
+    np.testing.assert_array_equal(tab["modes"], brute)
+    kf = 2 * np.pi / 1000.0
+    np.testing.assert_allclose(tab["k"][1:], kf * kbar[1:], rtol=1e-13)
+    assert brute[0] == 0 and np.isnan(tab["k"][0])
+    golden = np.loadtxt(os.path.join(GOLDEN, "modecounts_n64_dk1.txt"), dtype=np.int64)
+    np.testing.assert_array_equal(golden, brute)
+
+
+def test_mu_bin_counts_match_exact_fraction_rule():
+    n, nk, nmu = 16, 8, 5
+    gx, gy, gz = _full_grid(n)
+    n2 = gx * gx + gy * gy + gz * gz
+    b = _brute_kbin(n2, nk)
+    sel = b >= 0
+    j = _brute_mubin(gz[sel], n2[sel], nmu)
+    brute = np.bincount(b[sel] * nmu + j, minlength=nk * nmu).reshape(nk, nmu)
+    mubar = np.bincount(b[sel] * nmu + j, weights=np.abs(gz[sel]) / np.sqrt(n2[sel]),
+                        minlength=nk * nmu).reshape(nk, nmu)
+    tab = oracle.mode_tables(n, 100.0, nmu=nmu)
+    np.testing.assert_array_equal(tab["modes2d"], brute)
+    with np.errstate(invalid="ignore"):
+        np.testing.assert_allclose(tab["mu2d"], mubar / brute, rtol=1e-13, equal_nan=True)
+    # edge ties exist in this enumeration: |mu| exactly on j / Nmu for j > 0
+    mu2 = [Fraction(int(a) ** 2, int(c)) for a, c in zip(gz[sel], n2[sel])]
+    assert any(m == Fraction(k * k, nmu * nmu) for m in mu2 for k in (1, 2, 3, 4))
+    assert any(m == 1 for m in mu2)
+
+
+def test_mu_bin_rule_on_hand_picked_ties():
+    # (n_los, n^2, Nmu) -> bin: mu = 0.8 and 0.6 sit exactly on edges of 5 bins
+    cases = [(4, 25, 5, 4), (3, 25, 5, 3), (5, 25, 5, 4), (0, 25, 5, 0), (1, 2, 2, 1),
+             (2, 9, 3, 2), (1, 9, 3, 1), (1, 10, 3, 0)]
+    for nlos, n2, nmu, want in cases:
+        assert int(oracle.mubin_index(np.array([nlos * nlos]), np.array([n2]), nmu)[0]) == want
+
+
+@pytest.mark.parametrize("los", [0, 1, 2])
+def test_general_edges_and_los_match_brute_force(los):
+    n = 16
+    kmin_f, dk_f, nk, nmu = 0.5, 1.5, 4, 3
+    gx, gy, gz = _full_grid(n)
+    n2 = gx * gx + gy * gy + gz * gz
+    edges = [Fraction(1, 2) + k * Fraction(3, 2) for k in range(nk + 1)]
+    b = []
+    for v in n2:
+        bb = -1
+        for k in range(nk + 1):
+            if edges[k] ** 2 <= int(v):
+                bb = k
+        b.append(-1 if (v == 0 or bb >= nk) else bb)
+    b = np.array(b)
+    sel = b >= 0
+    nl = (gx, gy, gz)[los]
+    j = _brute_mubin(nl[sel], n2[sel], nmu)
+    brute = np.bincount(b[sel], minlength=nk)
+    brute2 = np.bincount(b[sel] * nmu + j, minlength=nk * nmu).reshape(nk, nmu)
+    tab = oracle.mode_tables(n, 10.0, kmin_f, dk_f, nk, nmu, los)
+    np.testing.assert_array_equal(tab["modes"], brute)
+    np.testing.assert_array_equal(tab["modes2d"], brute2)
+
+
+def _brute_expected(n, box, pk, nk, nmu, los=2):
+    gx, gy, gz = _full_grid(n)
+    n2 = gx * gx + gy * gy + gz * gz
+    b = _brute_kbin(n2, nk)
+    sel = b >= 0
+    kf = 2 * np.pi / box
+    p = pk(kf * np.sqrt(n2[sel]))
+    nl = (gx, gy, gz)[los][sel]
+    mu2 = nl * nl / n2[sel]
+    l2 = (3 * mu2 - 1) / 2
+    l4 = (35 * mu2 ** 2 - 30 * mu2 + 3) / 8
+    cnt = np.bincount(b[sel], minlength=nk)
+    out = {
+        "p0": np.bincount(b[sel], weights=p, minlength=nk) / cnt,
+        "p2": 5 * np.bincount(b[sel], weights=p * l2, minlength=nk) / cnt,
+        "p4": 9 * np.bincount(b[sel], weights=p * l4, minlength=nk) / cnt,
+    }
+    j = _brute_mubin(nl, n2[sel], nmu)
+    f = b[sel] * nmu + j
+    c2 = np.bincount(f, minlength=nk * nmu)
+    with np.errstate(invalid="ignore"):
+        out["pkmu"] = (np.bincount(f, weights=p, minlength=nk * nmu) / c2).reshape(nk, nmu)
+    return out
+
+
+@pytest.mark.parametrize("los", [2, 0])
+def test_fixed_amplitude_field_power_is_exact(los):
+    n, box, nk, nmu = 32, 500.0, 16, 4
+    pk = synth.pk_lognormal_c2
+    f = synth.fixed_amplitude_field(n, box, pk, seed=21)
+    assert abs(f.sum() - n ** 3) < 1e-8 * n ** 3
+    c = oracle.r2c(f)
+    res = oracle.fftpower_from_spectra(c, None, n, box, 2, False, wsum=float(n ** 3),
+                                       w2sum=1.0, npart=1, nmu=nmu, poles=(0, 2, 4),
+                                       los=los)
+    want = _brute_expected(n, box, pk, nk, nmu, los)
+    ok = res["modes"] > 0
+    np.testing.assert_allclose(res["power"][ok], want["p0"][ok], rtol=1e-12)
+    np.testing.assert_allclose(res["poles"][0][ok], want["p0"][ok], rtol=1e-12)
+    # P_2 vanishes identically for an isotropic fixed-amplitude field
+    assert np.all(np.abs(res["poles"][2][ok]) <= 1e-12 * want["p0"][ok])
+    np.testing.assert_allclose(res["poles"][4][ok], want["p4"][ok], rtol=0,
+                               atol=1e-12 * want["p0"][ok].max())
+    np.testing.assert_allclose(res["power2d"], want["pkmu"], rtol=1e-12, equal_nan=True)
+
+
+def test_empty_bins_are_nan_and_dc_excluded():
+    n, box = 8, 100.0
+    f = synth.fixed_amplitude_field(n, box, synth.pk_lognormal_c2, seed=1)
+    res = oracle.fftpower_from_spectra(oracle.r2c(f), None, n, box, 2, False,
+                                       float(n ** 3), 1.0, 1)
+    assert res["modes"][0] == 0 and np.isnan(res["power"][0]) and np.isnan(res["k"][0])
+    assert np.all(res["modes"][1:] > 0)
+
+
+def test_top_edge_exclusive_and_nyquist_rule():
+    n = 8
+    tab = oracle.mode_tables(n, 1.0, 0.0, 1.0, n // 2)
+    # modes touching a Nyquist index have n^2 >= (N/2)^2 and are never binned
+    gx, gy, gz = _full_grid(n)
+    n2 = gx * gx + gy * gy + gz * gz
+    inside = (n2 > 0) & (n2 < (n // 2) ** 2)
+    assert tab["modes"].sum() == inside.sum()
+    assert not np.any(inside & ((np.abs(gx) == n // 2) | (np.abs(gy) == n // 2)
+                                | (np.abs(gz) == n // 2)))
+    with pytest.raises(ValueError):
+        oracle.mode_tables(n, 1.0, 0.0, 1.0, n // 2 + 1, interlaced=True)
+    with pytest.raises(ValueError):
+        oracle.fftpower_from_spectra(np.zeros((n, n, n // 2 + 1)), None, n, 1.0, 2, False,
+                                     1.0, 1.0, 1, poles=(1,))
