@@ -1,0 +1,220 @@
+/*
+ * pk.h -- C ABI of libpk, the FFT power-spectrum hot path of nbodykit
+ * (Hand, Feng et al. 2018) for AMD MI355X (gfx950).
+ *
+ * The library paints a particle catalog onto a periodic mesh with the CIC,
+ * TSC or PCS window (optionally interlaced), takes the 3D real-to-complex FFT,
+ * divides out the window and bins |delta(k)|^2 into P(k), P(k, mu) and
+ * Legendre multipoles P_ell(k).  Paper passages:
+ *   painting, Eq. (1) ......................... Sec. 3.3.1 "Painting a Mesh"
+ *   windows, interlacing, compensation Eq. (2)  Sec. 3.3.2 "From Catalog to Mesh"
+ *   r2c between RealField and ComplexField .... Sec. 3.3.1
+ *   FFTPower: P(k), P(k, mu), P_ell(k) ........ Sec. 3.4.1 "Power Spectra"
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Pointers.  Every buffer argument is a DEVICE pointer unless its comment
+ *   says "host".  Device buffers are owned by the caller (typically PyTorch
+ *   allocations); the library never frees them.  The library owns only the
+ *   context, its FFT twiddle tables and the per-binning mode tables, which it
+ *   allocates on first use of a mesh size / binning and frees in
+ *   pk_ctx_destroy.
+ * Streams.  All device work is enqueued on the stream given to
+ *   pk_ctx_create and is asynchronous, except pk_result_to_host, which
+ *   synchronises that stream.
+ * Errors.  Every call returns a pk_status; negative values are failures and
+ *   pk_last_error() holds a message.  Argument errors (PK_EINVAL) are
+ *   detected before any device work, leave outputs untouched and need no GPU.
+ *   PK_EDEVICE carries the HIP error string.  No C++ exception crosses the
+ *   ABI.  A context must not be used from two host threads at once.
+ * Real mesh layout.  N^3 values of the mesh precision, row-major [x][y][z]
+ *   (z fastest); mesh node (i, j, l) sits at position (i, j, l) * L / N.
+ * Spectrum layout ("packed half spectrum", produced in place over the real
+ *   mesh by pk_fft_r2c).  N * N * (N/2) complex values (re, im interleaved),
+ *   row-major [kx][ky][kz'], kz' = 0 .. N/2 - 1.  For kz' >= 1 the element is
+ *   the DFT c(kx, ky, kz') = sum_x F(x) exp(-2 pi i k.x / N) (unnormalised).
+ *   Element kz' = 0 packs the two self-conjugate planes kz = 0 and kz = N/2:
+ *   Z(kx, ky) = c(kx, ky, 0) + i c(kx, ky, N/2), so that
+ *     c(kx, ky, 0)   = [Z(kx, ky) + conj Z(-kx, -ky)] / 2,
+ *     c(kx, ky, N/2) = [Z(kx, ky) - conj Z(-kx, -ky)] / (2 i),
+ *   indices taken mod N.  Array index i maps to the signed wave number
+ *   n = i for i < N/2, else i - N (numpy fftfreq order).
+ */
+#ifndef PK_H
+#define PK_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define PK_ABI_VERSION 1
+
+typedef enum {
+  PK_OK = 0,
+  PK_EINVAL = -1,       /* bad argument; nothing was launched            */
+  PK_ENOMEM = -2,       /* the library could not allocate its own tables */
+  PK_EDEVICE = -3,      /* a HIP call failed                             */
+  PK_EUNSUPPORTED = -4  /* valid request outside the implemented range   */
+} pk_status;
+
+typedef enum { PK_F32 = 0, PK_F64 = 1 } pk_dtype;
+
+/* The value is the order p of the window in Eq. (2): sinc^p. */
+typedef enum { PK_CIC = 2, PK_TSC = 3, PK_PCS = 4 } pk_window;
+
+/* Mesh description (Sec. 3.3.2, Catalog.to_mesh). */
+typedef struct {
+  int32_t nmesh;       /* N, cells per side: a power of two, 8 .. 2048      */
+  int32_t window;      /* pk_window: 2 = CIC, 3 = TSC, 4 = PCS               */
+  int32_t interlaced;  /* 0 or 1: paint a second mesh shifted by half a cell */
+  int32_t compensated; /* 0 or 1: divide by prod_i sinc^p(pi k_i / 2 k_N)    */
+  int32_t dtype;       /* pk_dtype: precision of positions, weights, meshes  */
+  int32_t reserved;    /* must be 0                                          */
+  double boxsize;      /* L > 0, same units as the positions                 */
+} pk_mesh_desc;
+
+/* Binning description (Sec. 3.4.1, FFTPower).  Wave numbers are in units of
+ * the fundamental k_f = 2 pi / L.  k-bin b covers [e_b, e_{b+1}) with
+ * e_b = kmin_f + b * dk_f, decided on the integer n^2 against e_b^2
+ * (float64); the DC mode is never binned and the top edge is exclusive.
+ * |mu| = |n_los| / |n| is split into nmu equal bins; bin j holds
+ * j / nmu <= |mu| < (j + 1) / nmu, decided in exact integers, and |mu| = 1
+ * belongs to the last bin. */
+typedef struct {
+  double kmin_f;      /* >= 0                                                */
+  double dk_f;        /* > 0                                                 */
+  int32_t nk;         /* number of k bins, >= 1                              */
+  int32_t nmu;        /* 0 or 1: no P(k, mu) output; else 2 .. 64            */
+  int32_t npoles;     /* 0 .. 4                                              */
+  int32_t poles[4];   /* even ell in {0, 2, 4, 6}, distinct                  */
+  int32_t los;        /* line-of-sight axis 0, 1 or 2                        */
+} pk_bin_desc;
+
+/* Host-side result of pk_result_to_host.  The caller allocates every array
+ * (host memory) with the sizes given; 2-D arrays are row-major [nk][nmu] and
+ * may be NULL when nmu <= 1.  Empty bins hold NaN and a zero count. */
+typedef struct {
+  double *k;          /* [nk]  mean |k| of the modes in the bin              */
+  double *power;      /* [nk]  P(k) = mean of V |delta(k)|^2                  */
+  int64_t *modes;     /* [nk]  number of modes (full-grid count)             */
+  double *poles;      /* [npoles][nk]  P_ell = (2 ell + 1) mean(P L_ell(mu))  */
+  double *k2d;        /* [nk][nmu] mean |k|                                  */
+  double *mu2d;       /* [nk][nmu] mean |mu|                                 */
+  double *power2d;    /* [nk][nmu] P(k, mu)                                  */
+  int64_t *modes2d;   /* [nk][nmu]                                           */
+  double shotnoise;   /* V sum(w^2) / sum(w)^2, reported, not subtracted     */
+  double wsum;        /* sum of weights                                      */
+  double w2sum;       /* sum of squared weights                              */
+} pk_result;
+
+typedef struct pk_ctx pk_ctx;
+
+/* Device index of a validation-only context: it checks every argument of
+ * every call exactly as a device context does, but any call that would touch
+ * a device returns PK_EDEVICE.  It needs no GPU (front ends, CPU tests). */
+#define PK_DEVICE_NONE (-1)
+
+/* Creates a context on HIP device `device` that enqueues on `hip_stream`
+ * (a hipStream_t; NULL means the legacy default stream), or a
+ * validation-only context for device == PK_DEVICE_NONE.  *ctx receives the
+ * handle (host).  Errors: PK_EINVAL for a NULL ctx or a bad device,
+ * PK_ENOMEM, PK_EDEVICE. */
+pk_status pk_ctx_create(pk_ctx **ctx, int device, void *hip_stream);
+
+/* Frees the context and every device table it owns.  NULL is a no-op. */
+void pk_ctx_destroy(pk_ctx *ctx);
+
+/* Message of the last failed call on this context (static storage inside
+ * the context, valid until the next call).  ctx may be NULL: then the message
+ * of the last failed pk_ctx_create. */
+const char *pk_last_error(const pk_ctx *ctx);
+
+/* Bytes of one real mesh (N^3 values of the mesh precision); the packed
+ * spectrum occupies the same bytes.  0 for an invalid descriptor. */
+size_t pk_mesh_bytes(const pk_mesh_desc *m);
+
+/* Number of float64 slots of the device result buffer used by
+ * pk_bin_power / pk_fftpower:
+ *   [0, nk)                          sum h P over k-bin
+ *   [nk * (1 + i), nk * (2 + i))     sum h P L_ell over k-bin, ell = poles[i]
+ *   next nk * nmu (only if nmu > 1)  sum h P over (k, mu)-bin
+ *   last 2                           sum w, sum w^2
+ * P here is the unnormalised |c|^2 after interlacing and compensation;
+ * pk_result_to_host applies V / (sum w)^2.  0 for an invalid descriptor. */
+size_t pk_result_doubles(const pk_bin_desc *b);
+
+/* Device workspace that pk_fftpower needs for this request (bytes). */
+size_t pk_workspace_bytes(const pk_mesh_desc *m, const pk_bin_desc *b, int64_t npart);
+
+/* Device memory the context currently owns for tables (bytes). */
+size_t pk_ctx_table_bytes(const pk_ctx *ctx);
+
+/* Painting, Eq. (1) with V = 1 (Sec. 3.3.1 / 3.3.2).
+ * mesh[j] = sum_p w_p prod_d M_p(u_{p,d} + shift_cells - j_d), periodic,
+ * u = (x mod L) N / L, M_p the order-p B-spline of the window.
+ *   pos        device, n x 3 positions (x, y, z), dtype of the mesh
+ *   weight     device, n weights, or NULL for unit weights
+ *   n          number of particles, >= 0
+ *   shift_cells  0 for the plain mesh, 0.5 for the interlaced mesh
+ *   mesh       device, pk_mesh_bytes(m); overwritten (zeroed, then painted)
+ *   wsums      device, 2 float64 {sum w, sum w^2} overwritten, or NULL
+ * Accumulation order is not fixed (atomics), so results are reproducible to
+ * rounding only.  Errors: PK_EINVAL (bad descriptor, NULL pos with n > 0,
+ * NULL mesh, non-finite shift), PK_EDEVICE. */
+pk_status pk_paint(pk_ctx *ctx, const pk_mesh_desc *m, const void *pos,
+                   const void *weight, int64_t n, double shift_cells, void *mesh,
+                   double *wsums);
+
+/* Forward 3D real-to-complex FFT in place (Sec. 3.3.1, r2c): exp(-i k.x),
+ * unnormalised; mesh_inout holds the real mesh on entry and the packed half
+ * spectrum (layout above) on exit.  Deterministic.
+ * Errors: PK_EINVAL, PK_EDEVICE. */
+pk_status pk_fft_r2c(pk_ctx *ctx, const pk_mesh_desc *m, void *mesh_inout);
+
+/* Interlacing and window compensation on packed spectra (Sec. 3.3.2, Eq. 2),
+ * in place on cmesh_inout:
+ *   if cmesh_b != NULL: c <- [c + exp(i pi (n_x + n_y + n_z) / N) c_b] / 2
+ *   if m->compensated:  c <- c / prod_d sinc^p(pi n_d / N)
+ * cmesh_b is the spectrum of the mesh painted with shift_cells = 0.5 and is
+ * left unchanged.  The result is a packed spectrum again.
+ * Errors: PK_EINVAL, PK_EDEVICE. */
+pk_status pk_compensate(pk_ctx *ctx, const pk_mesh_desc *m, void *cmesh_inout,
+                        const void *cmesh_b);
+
+/* Binning of a packed spectrum as it is (no interlacing or compensation is
+ * applied here) into the sums described at pk_result_doubles (Sec. 3.4.1).
+ * result_dev: device, pk_result_doubles(b) float64; every sum slot is
+ * overwritten, the two weight slots are left unchanged.
+ * Errors: PK_EINVAL (also for an interlaced m with a top edge above N/2),
+ * PK_EUNSUPPORTED (too many bins for one workgroup's LDS), PK_EDEVICE. */
+pk_status pk_bin_power(pk_ctx *ctx, const pk_mesh_desc *m, const pk_bin_desc *b,
+                       const void *cmesh, double *result_dev);
+
+/* The whole FFTPower hot path for one catalog: paint (both meshes if
+ * interlaced), r2c, interlace, compensate, bin.  workspace: device,
+ * >= pk_workspace_bytes(m, b, n) bytes, caller-owned scratch (content on
+ * entry ignored).  result_dev as in pk_bin_power, all slots overwritten
+ * including sum w and sum w^2.  Nothing is allocated when the context
+ * already holds the tables for this mesh size and binning.
+ * Errors: PK_EINVAL (also a too small workspace), PK_EUNSUPPORTED,
+ * PK_EDEVICE. */
+pk_status pk_fftpower(pk_ctx *ctx, const pk_mesh_desc *m, const pk_bin_desc *b,
+                      const void *pos, const void *weight, int64_t n,
+                      void *workspace, size_t workspace_bytes, double *result_dev);
+
+/* Synchronises the context stream, copies the sums back and finalises them
+ * with the mode tables (counts, mean |k|, mean |mu|):
+ *   P = V sum(h P) / (sum w)^2 / N_b,  P_ell = (2 ell + 1) ... likewise.
+ * out: host struct with caller-allocated arrays (see pk_result).
+ * Errors: PK_EINVAL, PK_EDEVICE. */
+pk_status pk_result_to_host(pk_ctx *ctx, const pk_mesh_desc *m, const pk_bin_desc *b,
+                            const double *result_dev, pk_result *out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PK_H */

@@ -1,0 +1,571 @@
+// The C ABI of libpk (declared in include/pk.h): argument validation, the
+// per-mesh-size and per-binning tables, and the launch sequences of the
+// stages.  No kernel lives here.
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "internal.h"
+
+using namespace pk;
+
+namespace {
+
+thread_local std::string g_create_error;
+
+struct DeviceGuard {
+  int prev = -1;
+  bool changed = false;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) == hipSuccess && prev != dev) {
+      changed = hipSetDevice(dev) == hipSuccess;
+    }
+  }
+  ~DeviceGuard() {
+    if (changed) (void)hipSetDevice(prev);
+  }
+};
+
+pk_status fail(pk_ctx* ctx, pk_status st, const std::string& msg) {
+  if (ctx) ctx->err = msg;
+  return st;
+}
+
+pk_status dev_fail(pk_ctx* ctx, hipError_t e, const char* where) {
+  return fail(ctx, PK_EDEVICE, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+bool is_pow2(int n) { return n > 0 && (n & (n - 1)) == 0; }
+
+size_t elem_bytes(const pk_mesh_desc* m) { return m->dtype == PK_F32 ? 4 : 8; }
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// nullptr when the descriptor is valid, else the reason.
+const char* check_mesh(const pk_mesh_desc* m) {
+  if (!m) return "mesh descriptor is NULL";
+  if (!is_pow2(m->nmesh) || m->nmesh < 8 || m->nmesh > 2048)
+    return "nmesh must be a power of two in [8, 2048]";
+  if (m->window < 2 || m->window > 4) return "window must be 2 (CIC), 3 (TSC) or 4 (PCS)";
+  if (m->interlaced != 0 && m->interlaced != 1) return "interlaced must be 0 or 1";
+  if (m->compensated != 0 && m->compensated != 1) return "compensated must be 0 or 1";
+  if (m->dtype != PK_F32 && m->dtype != PK_F64) return "dtype must be PK_F32 or PK_F64";
+  if (m->reserved != 0) return "reserved must be 0";
+  if (!std::isfinite(m->boxsize) || !(m->boxsize > 0)) return "boxsize must be finite and > 0";
+  return nullptr;
+}
+
+int nsum_of(const pk_bin_desc* b) {
+  return b->nk * (1 + b->npoles) + (b->nmu > 1 ? b->nk * b->nmu : 0);
+}
+
+const char* check_bins(const pk_bin_desc* b, const pk_mesh_desc* m) {
+  if (!b) return "bin descriptor is NULL";
+  if (!std::isfinite(b->kmin_f) || b->kmin_f < 0) return "kmin_f must be finite and >= 0";
+  if (!std::isfinite(b->dk_f) || !(b->dk_f > 0)) return "dk_f must be finite and > 0";
+  if (b->nk < 1 || b->nk > 4096) return "nk must be in [1, 4096]";
+  if (b->nmu < 0 || b->nmu > 64) return "nmu must be in [0, 64]";
+  if (b->npoles < 0 || b->npoles > 4) return "npoles must be in [0, 4]";
+  for (int i = 0; i < b->npoles; ++i) {
+    const int l = b->poles[i];
+    if (l != 0 && l != 2 && l != 4 && l != 6) return "poles must be even ell in {0, 2, 4, 6}";
+    for (int j = 0; j < i; ++j)
+      if (b->poles[j] == l) return "poles must be distinct";
+  }
+  if (b->los < 0 || b->los > 2) return "los must be an axis 0, 1 or 2";
+  const double top = b->kmin_f + b->nk * b->dk_f;
+  if (m) {
+    const double nmax = std::sqrt(3.0) * (m->nmesh / 2) + 1.0;
+    if (top > nmax * 4.0 + 16.0) return "top edge far beyond the largest mode";
+    if (m->interlaced && top > m->nmesh / 2)
+      return "interlaced meshes: the top edge kmin_f + nk * dk_f may not exceed N/2";
+  }
+  return nullptr;
+}
+
+// Slot limits of the LDS bins (float64).
+constexpr int kMaxLdsSlots = 8192;
+
+const char* check_lds(const pk_bin_desc* b) {
+  if (nsum_of(b) > kMaxLdsSlots) return "too many bin slots for the LDS accumulator";
+  if (mode_table_slots(b->nk, b->nmu > 1 ? b->nmu : 0) > kMaxLdsSlots)
+    return "too many (k, mu) bins for the mode-table accumulator";
+  return nullptr;
+}
+
+template <typename T>
+void fill_mesh_tables(int n, unsigned char* buf, size_t off_tw, size_t off_ph, size_t off_si) {
+  T* tw = reinterpret_cast<T*>(buf + off_tw);
+  T* ph = reinterpret_cast<T*>(buf + off_ph);
+  T* si = reinterpret_cast<T*>(buf + off_si);
+  const double pi = 3.14159265358979323846;
+  for (int j = 0; j < n; ++j) {
+    const double a = 2.0 * pi * (double)j / (double)n;
+    tw[2 * j] = (T)std::cos(a);
+    tw[2 * j + 1] = (T)(-std::sin(a));
+  }
+  for (int s = -3 * (n / 2); s <= 3 * (n / 2); ++s) {
+    const double a = pi * (double)s / (double)n;
+    const int i = s + 3 * (n / 2);
+    ph[2 * i] = (T)std::cos(a);
+    ph[2 * i + 1] = (T)std::sin(a);
+  }
+  for (int p = 2; p <= 4; ++p) {
+    for (int i = 0; i < n; ++i) {
+      const int k = i < n / 2 ? i : i - n;
+      const double x = pi * (double)k / (double)n;
+      const double sc = k == 0 ? 1.0 : std::sin(x) / x;
+      si[(size_t)(p - 2) * n + i] = (T)std::pow(sc, -(double)p);
+    }
+  }
+}
+
+pk_status get_mesh_tables(pk_ctx* ctx, int n, int dtype, const MeshTables** out) {
+  const auto key = std::make_pair(n, dtype);
+  auto it = ctx->mesh_tables.find(key);
+  if (it != ctx->mesh_tables.end()) {
+    *out = &it->second;
+    return PK_OK;
+  }
+  const size_t es = dtype == PK_F32 ? 4 : 8;
+  const size_t off_tw = 0;
+  const size_t off_ph = align256(off_tw + (size_t)n * 2 * es);
+  const size_t off_si = align256(off_ph + (size_t)(3 * n + 1) * 2 * es);
+  const size_t bytes = align256(off_si + (size_t)3 * n * es);
+  std::vector<unsigned char> host(bytes, 0);
+  if (dtype == PK_F32)
+    fill_mesh_tables<float>(n, host.data(), off_tw, off_ph, off_si);
+  else
+    fill_mesh_tables<double>(n, host.data(), off_tw, off_ph, off_si);
+  void* dev = nullptr;
+  hipError_t e = hipMalloc(&dev, bytes);
+  if (e != hipSuccess) return fail(ctx, PK_ENOMEM, std::string("hipMalloc(tables): ") + hipGetErrorString(e));
+  e = hipMemcpyAsync(dev, host.data(), bytes, hipMemcpyHostToDevice, ctx->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+  if (e != hipSuccess) {
+    (void)hipFree(dev);
+    return dev_fail(ctx, e, "upload of mesh tables");
+  }
+  MeshTables t;
+  t.dev = dev;
+  t.bytes = bytes;
+  t.tw = static_cast<unsigned char*>(dev) + off_tw;
+  t.phase = static_cast<unsigned char*>(dev) + off_ph;
+  t.sinc_inv = static_cast<unsigned char*>(dev) + off_si;
+  ctx->table_bytes += bytes;
+  auto res = ctx->mesh_tables.emplace(key, t);
+  *out = &res.first->second;
+  return PK_OK;
+}
+
+// Squared bin edges e_b^2 = (kmin + b dk)^2 in float64, without contraction
+// into fused multiply-adds, so that each value is the correctly rounded
+// result of the three operations in this order.
+#pragma clang fp contract(off)
+void edges_squared(double kmin, double dk, int nk, std::vector<double>& e2) {
+  e2.resize(nk + 1);
+  for (int i = 0; i <= nk; ++i) {
+    volatile double prod = (double)i * dk;
+    volatile double e = kmin + prod;
+    e2[i] = e * e;
+  }
+}
+#pragma clang fp contract(on)
+
+BinSpec make_spec(const pk_mesh_desc* m, const pk_bin_desc* b, const double* e2_dev) {
+  BinSpec s;
+  s.nmesh = m->nmesh;
+  s.nk = b->nk;
+  s.nmu = b->nmu > 1 ? b->nmu : 0;
+  s.los = b->los;
+  s.npoles = b->npoles;
+  s.zero_mask = 0;
+  s.npl = 0;
+  for (int i = 0; i < b->npoles; ++i) {
+    if (b->poles[i] == 0) {
+      s.zero_mask |= 1 << i;
+    } else {
+      s.pole_ell[s.npl] = b->poles[i];
+      s.pole_slot[s.npl] = b->nk * (1 + i);
+      ++s.npl;
+    }
+  }
+  s.off2d = b->nmu > 1 ? b->nk * (1 + b->npoles) : -1;
+  s.nsum = nsum_of(b);
+  s.kmin_f = b->kmin_f;
+  s.dk_f = b->dk_f;
+  s.e2 = e2_dev;
+  return s;
+}
+
+pk_status get_bin_tables(pk_ctx* ctx, const pk_mesh_desc* m, const pk_bin_desc* b,
+                         BinTables** out) {
+  const int nmu = b->nmu > 1 ? b->nmu : 0;
+  const pk_ctx::BinKey key{m->nmesh, b->kmin_f, b->dk_f, b->nk, nmu, b->los};
+  auto it = ctx->bin_tables.find(key);
+  if (it != ctx->bin_tables.end()) {
+    *out = it->second.get();
+    return PK_OK;
+  }
+  std::unique_ptr<BinTables> bt(new (std::nothrow) BinTables());
+  if (!bt) return fail(ctx, PK_ENOMEM, "host allocation of bin tables");
+  std::vector<double> e2;
+  edges_squared(b->kmin_f, b->dk_f, b->nk, e2);
+  hipError_t e = hipMalloc(&bt->e2_dev, e2.size() * sizeof(double));
+  if (e != hipSuccess) return fail(ctx, PK_ENOMEM, std::string("hipMalloc(edges): ") + hipGetErrorString(e));
+  e = hipMemcpyAsync(bt->e2_dev, e2.data(), e2.size() * sizeof(double), hipMemcpyHostToDevice,
+                     ctx->stream);
+  const BinSpec spec = make_spec(m, b, bt->e2_dev);
+  const int groups = mode_table_groups(m->nmesh);
+  const int slots = mode_table_slots(b->nk, nmu);
+  double* scratch = nullptr;
+  if (e == hipSuccess) e = hipMalloc(&scratch, ((size_t)groups + 1) * slots * sizeof(double));
+  if (e == hipSuccess)
+    e = launch_mode_tables(m->nmesh, spec, scratch, groups, scratch + (size_t)groups * slots,
+                           ctx->stream);
+  std::vector<double> host(slots);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(host.data(), scratch + (size_t)groups * slots, slots * sizeof(double),
+                       hipMemcpyDeviceToHost, ctx->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+  if (scratch) (void)hipFree(scratch);
+  if (e != hipSuccess) {
+    (void)hipFree(bt->e2_dev);
+    return dev_fail(ctx, e, "mode tables");
+  }
+  const int nk = b->nk;
+  bt->modes.resize(nk);
+  bt->sum_n.resize(nk);
+  for (int k = 0; k < nk; ++k) {
+    uint64_t c;
+    std::memcpy(&c, &host[k], 8);
+    bt->modes[k] = (int64_t)c;
+    bt->sum_n[k] = host[nk + k];
+  }
+  if (nmu > 1) {
+    const int n2 = nk * nmu;
+    bt->modes2d.resize(n2);
+    bt->sum_n2d.resize(n2);
+    bt->sum_mu2d.resize(n2);
+    for (int f = 0; f < n2; ++f) {
+      uint64_t c;
+      std::memcpy(&c, &host[2 * nk + f], 8);
+      bt->modes2d[f] = (int64_t)c;
+      bt->sum_n2d[f] = host[2 * nk + n2 + f];
+      bt->sum_mu2d[f] = host[2 * nk + 2 * n2 + f];
+    }
+  }
+  ctx->table_bytes += e2.size() * sizeof(double);
+  *out = bt.get();
+  ctx->bin_tables.emplace(key, std::move(bt));
+  return PK_OK;
+}
+
+// Context-owned scratch for the stand-alone binning (partial sums); grown on
+// demand and kept until pk_ctx_destroy.
+pk_status get_scratch(pk_ctx* ctx, size_t bytes, double** out) {
+  if (ctx->scratch_bytes < bytes) {
+    if (ctx->scratch) {
+      (void)hipStreamSynchronize(ctx->stream);
+      (void)hipFree(ctx->scratch);
+      ctx->table_bytes -= ctx->scratch_bytes;
+      ctx->scratch = nullptr;
+      ctx->scratch_bytes = 0;
+    }
+    hipError_t e = hipMalloc(&ctx->scratch, bytes);
+    if (e != hipSuccess) {
+      ctx->scratch = nullptr;
+      return fail(ctx, PK_ENOMEM, std::string("hipMalloc(scratch): ") + hipGetErrorString(e));
+    }
+    ctx->scratch_bytes = bytes;
+    ctx->table_bytes += bytes;
+  }
+  *out = ctx->scratch;
+  return PK_OK;
+}
+
+// Workspace layout of pk_fftpower (offsets in bytes, 256-aligned).
+struct Layout {
+  size_t mesh_a = 0, mesh_b = 0, side_a = 0, side_b = 0, partials = 0, total = 0;
+  int gx = 0, gp = 0;
+};
+
+Layout layout_of(const pk_mesh_desc* m, const pk_bin_desc* b) {
+  Layout l;
+  const size_t n = (size_t)m->nmesh;
+  const size_t mesh = align256(n * n * n * elem_bytes(m));
+  const size_t side = align256(n * n * 2 * elem_bytes(m));
+  const int two = m->interlaced ? 1 : 0;
+  l.gx = xpass_bin_groups(m->dtype, m->nmesh);
+  l.gp = plane_bin_groups(m->nmesh);
+  size_t off = 0;
+  l.mesh_a = off;
+  off += mesh;
+  l.mesh_b = off;
+  off += two * mesh;
+  l.side_a = off;
+  off += side;
+  l.side_b = off;
+  off += two * side;
+  l.partials = off;
+  off += align256((size_t)(l.gx + l.gp) * nsum_of(b) * sizeof(double));
+  l.total = off;
+  return l;
+}
+
+}  // namespace
+
+extern "C" {
+
+pk_status pk_ctx_create(pk_ctx** ctx, int device, void* hip_stream) {
+  if (!ctx) {
+    g_create_error = "ctx is NULL";
+    return PK_EINVAL;
+  }
+  *ctx = nullptr;
+  if (device != PK_DEVICE_NONE) {
+    int ndev = 0;
+    hipError_t e = hipGetDeviceCount(&ndev);
+    if (e != hipSuccess) {
+      g_create_error = std::string("hipGetDeviceCount: ") + hipGetErrorString(e);
+      return PK_EDEVICE;
+    }
+    if (device < 0 || device >= ndev) {
+      g_create_error = "device index out of range";
+      return PK_EINVAL;
+    }
+  }
+  pk_ctx* c = new (std::nothrow) pk_ctx();
+  if (!c) {
+    g_create_error = "host allocation of the context";
+    return PK_ENOMEM;
+  }
+  c->device = device;
+  c->stream = static_cast<hipStream_t>(hip_stream);
+  *ctx = c;
+  return PK_OK;
+}
+
+void pk_ctx_destroy(pk_ctx* ctx) {
+  if (!ctx) return;
+  if (ctx->device == PK_DEVICE_NONE) {
+    delete ctx;
+    return;
+  }
+  DeviceGuard g(ctx->device);
+  (void)hipStreamSynchronize(ctx->stream);
+  for (auto& kv : ctx->mesh_tables) (void)hipFree(kv.second.dev);
+  for (auto& kv : ctx->bin_tables) (void)hipFree(kv.second->e2_dev);
+  if (ctx->scratch) (void)hipFree(ctx->scratch);
+  delete ctx;
+}
+
+const char* pk_last_error(const pk_ctx* ctx) {
+  return ctx ? ctx->err.c_str() : g_create_error.c_str();
+}
+
+size_t pk_mesh_bytes(const pk_mesh_desc* m) {
+  if (check_mesh(m)) return 0;
+  const size_t n = (size_t)m->nmesh;
+  return n * n * n * elem_bytes(m);
+}
+
+size_t pk_result_doubles(const pk_bin_desc* b) {
+  if (check_bins(b, nullptr)) return 0;
+  return (size_t)nsum_of(b) + 2;
+}
+
+size_t pk_workspace_bytes(const pk_mesh_desc* m, const pk_bin_desc* b, int64_t npart) {
+  (void)npart;
+  if (check_mesh(m) || check_bins(b, m)) return 0;
+  return layout_of(m, b).total;
+}
+
+size_t pk_ctx_table_bytes(const pk_ctx* ctx) { return ctx ? ctx->table_bytes : 0; }
+
+pk_status pk_paint(pk_ctx* ctx, const pk_mesh_desc* m, const void* pos, const void* weight,
+                   int64_t n, double shift_cells, void* mesh, double* wsums) {
+  if (!ctx) return PK_EINVAL;
+  if (const char* why = check_mesh(m)) return fail(ctx, PK_EINVAL, why);
+  if (n < 0) return fail(ctx, PK_EINVAL, "n must be >= 0");
+  if (n > 0 && !pos) return fail(ctx, PK_EINVAL, "pos is NULL with n > 0");
+  if (!mesh) return fail(ctx, PK_EINVAL, "mesh is NULL");
+  if (!std::isfinite(shift_cells)) return fail(ctx, PK_EINVAL, "shift_cells must be finite");
+  if (ctx->device == PK_DEVICE_NONE) return fail(ctx, PK_EDEVICE, "validation-only context");
+  DeviceGuard g(ctx->device);
+  hipError_t e = launch_fill_zero(mesh, pk_mesh_bytes(m), ctx->stream);
+  if (e == hipSuccess && wsums) e = launch_fill_zero(wsums, 2 * sizeof(double), ctx->stream);
+  if (e == hipSuccess && n > 0)
+    e = launch_paint_atomic(m->dtype, m->window, m->nmesh, m->boxsize, pos, weight, n, shift_cells,
+                            mesh, 0.0, nullptr, wsums, ctx->stream);
+  if (e != hipSuccess) return dev_fail(ctx, e, "pk_paint");
+  return PK_OK;
+}
+
+pk_status pk_fft_r2c(pk_ctx* ctx, const pk_mesh_desc* m, void* mesh_inout) {
+  if (!ctx) return PK_EINVAL;
+  if (const char* why = check_mesh(m)) return fail(ctx, PK_EINVAL, why);
+  if (!mesh_inout) return fail(ctx, PK_EINVAL, "mesh is NULL");
+  if (ctx->device == PK_DEVICE_NONE) return fail(ctx, PK_EDEVICE, "validation-only context");
+  DeviceGuard g(ctx->device);
+  const MeshTables* t = nullptr;
+  if (pk_status st = get_mesh_tables(ctx, m->nmesh, m->dtype, &t)) return st;
+  const size_t bytes = pk_mesh_bytes(m);
+  hipError_t e = launch_fft_z(m->dtype, m->nmesh, mesh_inout, 1, bytes, t->tw, nullptr, ctx->stream);
+  if (e == hipSuccess) e = launch_fft_cols(m->dtype, m->nmesh, mesh_inout, 1, bytes, t->tw, 1, ctx->stream);
+  if (e == hipSuccess) e = launch_fft_cols(m->dtype, m->nmesh, mesh_inout, 1, bytes, t->tw, 0, ctx->stream);
+  if (e != hipSuccess) return dev_fail(ctx, e, "pk_fft_r2c");
+  return PK_OK;
+}
+
+pk_status pk_compensate(pk_ctx* ctx, const pk_mesh_desc* m, void* cmesh_inout,
+                        const void* cmesh_b) {
+  if (!ctx) return PK_EINVAL;
+  if (const char* why = check_mesh(m)) return fail(ctx, PK_EINVAL, why);
+  if (!cmesh_inout) return fail(ctx, PK_EINVAL, "cmesh is NULL");
+  if (cmesh_b == cmesh_inout) return fail(ctx, PK_EINVAL, "cmesh_b aliases cmesh");
+  if (!cmesh_b && !m->compensated) return PK_OK;
+  if (ctx->device == PK_DEVICE_NONE) return fail(ctx, PK_EDEVICE, "validation-only context");
+  DeviceGuard g(ctx->device);
+  const MeshTables* t = nullptr;
+  if (pk_status st = get_mesh_tables(ctx, m->nmesh, m->dtype, &t)) return st;
+  hipError_t e = launch_compensate(m->dtype, m->nmesh, cmesh_inout, cmesh_b, *t, m->window,
+                                   m->compensated, ctx->stream);
+  if (e != hipSuccess) return dev_fail(ctx, e, "pk_compensate");
+  return PK_OK;
+}
+
+pk_status pk_bin_power(pk_ctx* ctx, const pk_mesh_desc* m, const pk_bin_desc* b,
+                       const void* cmesh, double* result_dev) {
+  if (!ctx) return PK_EINVAL;
+  if (const char* why = check_mesh(m)) return fail(ctx, PK_EINVAL, why);
+  if (const char* why = check_bins(b, m)) return fail(ctx, PK_EINVAL, why);
+  if (!cmesh || !result_dev) return fail(ctx, PK_EINVAL, "cmesh or result is NULL");
+  if (const char* why = check_lds(b)) return fail(ctx, PK_EUNSUPPORTED, why);
+  if (ctx->device == PK_DEVICE_NONE) return fail(ctx, PK_EDEVICE, "validation-only context");
+  DeviceGuard g(ctx->device);
+  BinTables* bt = nullptr;
+  if (pk_status st = get_bin_tables(ctx, m, b, &bt)) return st;
+  const MeshTables* t = nullptr;
+  if (pk_status st = get_mesh_tables(ctx, m->nmesh, m->dtype, &t)) return st;
+  const BinSpec spec = make_spec(m, b, bt->e2_dev);
+  const size_t total = (size_t)m->nmesh * m->nmesh * (m->nmesh / 2);
+  size_t gb = (total + 255) / 256;
+  if (gb > 1024) gb = 1024;
+  const int gp = plane_bin_groups(m->nmesh);
+  double* partials = nullptr;
+  if (pk_status st = get_scratch(ctx, (gb + gp) * spec.nsum * sizeof(double), &partials)) return st;
+  hipError_t e = hipSuccess;
+  e = launch_bin_packed(m->dtype, m->nmesh, cmesh, spec, partials, ctx->stream);
+  if (e == hipSuccess)
+    e = launch_plane_bin(m->dtype, m->nmesh, cmesh, nullptr, m->nmesh / 2, *t, m->window, 0, spec,
+                         partials + gb * spec.nsum, ctx->stream);
+  if (e == hipSuccess) e = launch_reduce(partials, (int)(gb + gp), spec, result_dev, ctx->stream);
+  if (e != hipSuccess) return dev_fail(ctx, e, "pk_bin_power");
+  return PK_OK;
+}
+
+pk_status pk_fftpower(pk_ctx* ctx, const pk_mesh_desc* m, const pk_bin_desc* b, const void* pos,
+                      const void* weight, int64_t n, void* workspace, size_t workspace_bytes,
+                      double* result_dev) {
+  if (!ctx) return PK_EINVAL;
+  if (const char* why = check_mesh(m)) return fail(ctx, PK_EINVAL, why);
+  if (const char* why = check_bins(b, m)) return fail(ctx, PK_EINVAL, why);
+  if (n < 0) return fail(ctx, PK_EINVAL, "n must be >= 0");
+  if (n > 0 && !pos) return fail(ctx, PK_EINVAL, "pos is NULL with n > 0");
+  if (!workspace || !result_dev) return fail(ctx, PK_EINVAL, "workspace or result is NULL");
+  const Layout l = layout_of(m, b);
+  if (workspace_bytes < l.total) return fail(ctx, PK_EINVAL, "workspace too small");
+  if (const char* why = check_lds(b)) return fail(ctx, PK_EUNSUPPORTED, why);
+  if (ctx->device == PK_DEVICE_NONE) return fail(ctx, PK_EDEVICE, "validation-only context");
+  DeviceGuard g(ctx->device);
+  BinTables* bt = nullptr;
+  if (pk_status st = get_bin_tables(ctx, m, b, &bt)) return st;
+  const MeshTables* t = nullptr;
+  if (pk_status st = get_mesh_tables(ctx, m->nmesh, m->dtype, &t)) return st;
+  const BinSpec spec = make_spec(m, b, bt->e2_dev);
+  char* ws = static_cast<char*>(workspace);
+  void* mesh_a = ws + l.mesh_a;
+  void* mesh_b = m->interlaced ? ws + l.mesh_b : nullptr;
+  void* side_a = ws + l.side_a;
+  void* side_b = m->interlaced ? ws + l.side_b : nullptr;
+  double* partials = reinterpret_cast<double*>(ws + l.partials);
+  double* wsums = result_dev + spec.nsum;
+  const size_t mbytes = pk_mesh_bytes(m);
+  const int nm = m->interlaced ? 2 : 1;
+  hipStream_t s = ctx->stream;
+  hipError_t e = launch_fill_zero(mesh_a, (l.mesh_b - l.mesh_a) * nm, s);
+  if (e == hipSuccess) e = launch_fill_zero(wsums, 2 * sizeof(double), s);
+  if (e == hipSuccess && n > 0)
+    e = launch_paint_atomic(m->dtype, m->window, m->nmesh, m->boxsize, pos, weight, n, 0.0, mesh_a,
+                            0.5, mesh_b, wsums, s);
+  const size_t stride = l.mesh_b - l.mesh_a;
+  if (e == hipSuccess) e = launch_fft_z(m->dtype, m->nmesh, mesh_a, nm, stride, t->tw, wsums, s);
+  if (e == hipSuccess) e = launch_fft_cols(m->dtype, m->nmesh, mesh_a, nm, stride, t->tw, 1, s);
+  if (e == hipSuccess)
+    e = launch_xpass_bin(m->dtype, m->nmesh, mesh_a, mesh_b, *t, m->window, m->compensated, spec,
+                         partials, side_a, side_b, s);
+  if (e == hipSuccess)
+    e = launch_plane_bin(m->dtype, m->nmesh, side_a, side_b, 1, *t, m->window, m->compensated,
+                         spec, partials + (size_t)l.gx * spec.nsum, s);
+  if (e == hipSuccess) e = launch_reduce(partials, l.gx + l.gp, spec, result_dev, s);
+  (void)mbytes;
+  if (e != hipSuccess) return dev_fail(ctx, e, "pk_fftpower");
+  return PK_OK;
+}
+
+pk_status pk_result_to_host(pk_ctx* ctx, const pk_mesh_desc* m, const pk_bin_desc* b,
+                            const double* result_dev, pk_result* out) {
+  if (!ctx) return PK_EINVAL;
+  if (const char* why = check_mesh(m)) return fail(ctx, PK_EINVAL, why);
+  if (const char* why = check_bins(b, m)) return fail(ctx, PK_EINVAL, why);
+  if (!result_dev || !out || !out->k || !out->power || !out->modes)
+    return fail(ctx, PK_EINVAL, "result, out or one of its 1-D arrays is NULL");
+  if (b->npoles > 0 && !out->poles) return fail(ctx, PK_EINVAL, "out->poles is NULL");
+  if (const char* why = check_lds(b)) return fail(ctx, PK_EUNSUPPORTED, why);
+  if (ctx->device == PK_DEVICE_NONE) return fail(ctx, PK_EDEVICE, "validation-only context");
+  DeviceGuard g(ctx->device);
+  BinTables* bt = nullptr;
+  if (pk_status st = get_bin_tables(ctx, m, b, &bt)) return st;
+  const int nsum = nsum_of(b);
+  std::vector<double> h(nsum + 2);
+  hipError_t e = hipMemcpyAsync(h.data(), result_dev, h.size() * sizeof(double),
+                                hipMemcpyDeviceToHost, ctx->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+  if (e != hipSuccess) return dev_fail(ctx, e, "pk_result_to_host");
+  const double L = m->boxsize;
+  const double volume = L * L * L;
+  const double kf = 2.0 * 3.14159265358979323846 / L;
+  const double wsum = h[nsum], w2sum = h[nsum + 1];
+  const double norm = volume / (wsum * wsum);
+  const double nan = std::nan("");
+  const int nk = b->nk;
+  for (int k = 0; k < nk; ++k) {
+    const int64_t nb = bt->modes[k];
+    out->modes[k] = nb;
+    out->k[k] = nb ? kf * bt->sum_n[k] / (double)nb : nan;
+    out->power[k] = nb ? norm * h[k] / (double)nb : nan;
+    for (int i = 0; i < b->npoles; ++i) {
+      const int ell = b->poles[i];
+      out->poles[(size_t)i * nk + k] =
+          nb ? (2 * ell + 1) * norm * h[(size_t)nk * (1 + i) + k] / (double)nb : nan;
+    }
+  }
+  if (b->nmu > 1) {
+    const int off = nk * (1 + b->npoles);
+    for (int f = 0; f < nk * b->nmu; ++f) {
+      const int64_t nb = bt->modes2d[f];
+      if (out->modes2d) out->modes2d[f] = nb;
+      if (out->k2d) out->k2d[f] = nb ? kf * bt->sum_n2d[f] / (double)nb : nan;
+      if (out->mu2d) out->mu2d[f] = nb ? bt->sum_mu2d[f] / (double)nb : nan;
+      if (out->power2d) out->power2d[f] = nb ? norm * h[off + f] / (double)nb : nan;
+    }
+  }
+  out->wsum = wsum;
+  out->w2sum = w2sum;
+  out->shotnoise = volume * w2sum / (wsum * wsum);
+  return PK_OK;
+}
+
+}  // extern "C"

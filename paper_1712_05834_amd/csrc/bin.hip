@@ -1,0 +1,507 @@
+// FFTPower binning (Sec. 3.4.1) with interlacing and window compensation
+// (Sec. 3.3.2, Eq. 2) fused in.
+//
+// k_xpass_bin  last FFT pass (along x) of both meshes in LDS, then for every
+//              mode of the tile: interlace, compensate, |c|^2, k / mu bin and
+//              Legendre weights, accumulated in float64 LDS bins.  Persistent
+//              grid: each workgroup walks many (ky, column-chunk) tiles and
+//              writes one row of partial sums at the end.
+// k_plane_bin  the two self-conjugate planes kz = 0 and kz = N/2, which the
+//              packed layout keeps in one complex column; unpacked with the
+//              partner mode (-kx, -ky).
+// k_reduce     sums the partial rows in a fixed order (deterministic given
+//              the partials).
+// k_mode_tables  plan-time counts, sum h|n| and sum h|mu| per bin.
+#include "fft_config.h"
+#include "internal.h"
+
+namespace pk {
+
+// Largest b with e_b^2 <= n^2 among the nk bins, -1 for the DC mode and for
+// modes outside [e_0, e_nk).  A float estimate is corrected with exact
+// comparisons of the integer n^2 against the float64 table e2.
+__device__ __forceinline__ int kbin_of(int n2, const BinSpec& b) {
+  if (n2 == 0) return -1;
+  const double x = (double)n2;
+  const double* __restrict__ e2 = b.e2;
+  if (x < e2[0] || x >= e2[b.nk]) return -1;
+  int k = (int)((sqrtf((float)n2) - (float)b.kmin_f) / (float)b.dk_f);
+  k = k < 0 ? 0 : (k > b.nk - 1 ? b.nk - 1 : k);
+  while (k + 1 < b.nk && x >= e2[k + 1]) ++k;
+  while (k > 0 && x < e2[k]) --k;
+  return k;
+}
+
+// Largest j in [0, nmu] with j^2 n^2 <= nmu^2 n_los^2, clipped to nmu - 1.
+// The products are integers below 2^53, exact in float64.
+__device__ __forceinline__ int mubin_of(int nlos2, int n2, int nmu) {
+  const double rhs = (double)nmu * (double)nmu * (double)nlos2;
+  int j = (int)((float)nmu * sqrtf((float)nlos2 / (float)n2));
+  j = j < 0 ? 0 : (j > nmu ? nmu : j);
+  while (j < nmu && (double)(j + 1) * (double)(j + 1) * (double)n2 <= rhs) ++j;
+  while (j > 0 && (double)j * (double)j * (double)n2 > rhs) --j;
+  return j < nmu ? j : nmu - 1;
+}
+
+template <typename T>
+__device__ __forceinline__ T legendre(int ell, T mu2) {
+  if (ell == 2) return (T(3) * mu2 - T(1)) * T(0.5);
+  if (ell == 4) return ((T(35) * mu2 - T(30)) * mu2 + T(3)) * T(0.125);
+  return (((T(231) * mu2 - T(315)) * mu2 + T(105)) * mu2 - T(5)) * T(0.0625);
+}
+
+// Adds one mode of (Hermitian-weighted) power hp to the LDS bins.
+template <typename T>
+__device__ __forceinline__ void accumulate(double* sb, const BinSpec& b, int n2, int nlos2,
+                                           double hp) {
+  const int k = kbin_of(n2, b);
+  if (k < 0) return;
+  atomicAdd(&sb[k], hp);
+  if (b.npl > 0) {
+    const T mu2 = static_cast<T>(nlos2) / static_cast<T>(n2);
+    for (int i = 0; i < b.npl; ++i)
+      atomicAdd(&sb[b.pole_slot[i] + k], hp * (double)legendre<T>(b.pole_ell[i], mu2));
+  }
+  if (b.off2d >= 0) atomicAdd(&sb[b.off2d + k * b.nmu + mubin_of(nlos2, n2, b.nmu)], hp);
+}
+
+__device__ __forceinline__ int signed_index(int i, int n) { return i < n / 2 ? i : i - n; }
+
+__device__ __forceinline__ void zero_bins(double* sb, int n) {
+  for (int i = threadIdx.x; i < n; i += blockDim.x) sb[i] = 0.0;
+}
+
+__device__ __forceinline__ void flush_bins(const double* sb, int n, double* out) {
+  for (int i = threadIdx.x; i < n; i += blockDim.x) out[i] = sb[i];
+}
+
+template <typename T, int N>
+__global__ void __launch_bounds__((ColCfg<T, N>::THREADS))
+    k_xpass_bin(const cpx<T>* __restrict__ mesh_a, const cpx<T>* __restrict__ mesh_b,
+                const cpx<T>* __restrict__ tw, const cpx<T>* __restrict__ phase,
+                const T* __restrict__ sinv, BinSpec b, double* __restrict__ partials,
+                cpx<T>* __restrict__ side_a, cpx<T>* __restrict__ side_b) {
+  using Cf = ColCfg<T, N>;
+  constexpr int E = Cf::E, TPL = Cf::TPL, C = Cf::C, NC = Cf::NC, CHUNKS = Cf::CHUNKS;
+  __shared__ cpx<T> lds[Cf::LDS_ELEMS];
+  extern __shared__ double sb[];
+  zero_bins(sb, b.nsum);
+  __syncthreads();
+  const int c = threadIdx.x % C, t = threadIdx.x / C;
+  const int los = b.los;
+  const bool two = mesh_b != nullptr;
+  LdsCols<T, C> lc{lds, c};
+  for (int tile = blockIdx.x; tile < N * CHUNKS; tile += gridDim.x) {
+    const int ky = tile / CHUNKS;
+    const int col = (tile % CHUNKS) * C + c;
+    const size_t base = (size_t)ky * NC + col;
+    const size_t step = (size_t)N * NC;
+    cpx<T> va[E], vb[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) va[e] = mesh_a[base + (size_t)(t + TPL * e) * step];
+    stockham<T, N, E, 1>(va, t, tw, 1, lc);
+    if (two) {
+#pragma unroll
+      for (int e = 0; e < E; ++e) vb[e] = mesh_b[base + (size_t)(t + TPL * e) * step];
+      stockham<T, N, E, 1>(vb, t, tw, 1, lc);
+    }
+    if (col == 0) {
+      // packed kz = 0 / N/2 column: handed to k_plane_bin
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        const size_t kx = (size_t)(t + TPL * e);
+        side_a[kx * N + ky] = va[e];
+        if (two) side_b[kx * N + ky] = vb[e];
+      }
+      continue;
+    }
+    const int ny = signed_index(ky, N);
+    const int nz = col;
+    const T syz = sinv ? sinv[ky] * sinv[col] : T(1);
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int kx = t + TPL * e;
+      const int nx = signed_index(kx, N);
+      cpx<T> cc = va[e];
+      if (two) {
+        const cpx<T> ph = phase[nx + ny + nz + 3 * (N / 2)];
+        const cpx<T> bb = cmul(ph, vb[e]);
+        cc = {T(0.5) * (cc.x + bb.x), T(0.5) * (cc.y + bb.y)};
+      }
+      T pw = cc.x * cc.x + cc.y * cc.y;
+      if (sinv) {
+        const T s = sinv[kx] * syz;
+        pw *= s * s;
+      }
+      const int n2 = nx * nx + ny * ny + nz * nz;
+      const int nl = los == 0 ? nx : (los == 1 ? ny : nz);
+      accumulate<T>(sb, b, n2, nl * nl, 2.0 * (double)pw);
+    }
+  }
+  __syncthreads();
+  flush_bins(sb, b.nsum, partials + (size_t)blockIdx.x * b.nsum);
+}
+
+// One thread per (kx, ky): modes (kx, ky, 0) and (kx, ky, N/2), weight h = 1.
+template <typename T>
+__global__ void __launch_bounds__(256)
+    k_plane_bin(int N, const cpx<T>* __restrict__ za, const cpx<T>* __restrict__ zb, size_t zs,
+                const cpx<T>* __restrict__ phase, const T* __restrict__ sinv, BinSpec b,
+                double* __restrict__ partials) {
+  extern __shared__ double sb[];
+  zero_bins(sb, b.nsum);
+  __syncthreads();
+  const int mask = N - 1;
+  const int los = b.los;
+  for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < N * N;
+       idx += gridDim.x * blockDim.x) {
+    const int kx = idx / N, ky = idx % N;
+    const int px = (N - kx) & mask, py = (N - ky) & mask;
+    const int nx = signed_index(kx, N), ny = signed_index(ky, N);
+    cpx<T> pa[2], pb[2];
+    {
+      const cpx<T> z = za[((size_t)kx * N + ky) * zs];
+      const cpx<T> zp = cconj(za[((size_t)px * N + py) * zs]);
+      const cpx<T> s = cadd(z, zp), d = csub(z, zp);
+      pa[0] = {T(0.5) * s.x, T(0.5) * s.y};   // (Z + conj Z') / 2
+      pa[1] = {T(0.5) * d.y, -T(0.5) * d.x};  // (Z - conj Z') / (2i)
+    }
+    if (zb) {
+      const cpx<T> z = zb[((size_t)kx * N + ky) * zs];
+      const cpx<T> zp = cconj(zb[((size_t)px * N + py) * zs]);
+      const cpx<T> s = cadd(z, zp), d = csub(z, zp);
+      pb[0] = {T(0.5) * s.x, T(0.5) * s.y};
+      pb[1] = {T(0.5) * d.y, -T(0.5) * d.x};
+    }
+#pragma unroll
+    for (int pl = 0; pl < 2; ++pl) {
+      const int nz = pl == 0 ? 0 : N / 2;
+      cpx<T> cc = pa[pl];
+      if (zb) {
+        const cpx<T> bb = cmul(phase[nx + ny + nz + 3 * (N / 2)], pb[pl]);
+        cc = {T(0.5) * (cc.x + bb.x), T(0.5) * (cc.y + bb.y)};
+      }
+      T pw = cc.x * cc.x + cc.y * cc.y;
+      if (sinv) {
+        const T s = sinv[kx] * sinv[ky] * sinv[nz];
+        pw *= s * s;
+      }
+      const int n2 = nx * nx + ny * ny + nz * nz;
+      const int nl = los == 0 ? nx : (los == 1 ? ny : nz);
+      accumulate<T>(sb, b, n2, nl * nl, (double)pw);
+    }
+  }
+  __syncthreads();
+  flush_bins(sb, b.nsum, partials + (size_t)blockIdx.x * b.nsum);
+}
+
+// Stand-alone binning of a packed spectrum, columns kz' >= 1 (h = 2).
+template <typename T>
+__global__ void __launch_bounds__(256)
+    k_bin_packed(int N, const cpx<T>* __restrict__ cm, BinSpec b, double* __restrict__ partials) {
+  extern __shared__ double sb[];
+  zero_bins(sb, b.nsum);
+  __syncthreads();
+  const int NC = N / 2;
+  const size_t total = (size_t)N * N * NC;
+  const int los = b.los;
+  for (size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+       idx += (size_t)gridDim.x * blockDim.x) {
+    const int col = (int)(idx % NC);
+    if (col == 0) continue;
+    const size_t rest = idx / NC;
+    const int ky = (int)(rest % N), kx = (int)(rest / N);
+    const int nx = signed_index(kx, N), ny = signed_index(ky, N), nz = col;
+    const cpx<T> cc = cm[idx];
+    const T pw = cc.x * cc.x + cc.y * cc.y;
+    const int n2 = nx * nx + ny * ny + nz * nz;
+    const int nl = los == 0 ? nx : (los == 1 ? ny : nz);
+    accumulate<T>(sb, b, n2, nl * nl, 2.0 * (double)pw);
+  }
+  __syncthreads();
+  flush_bins(sb, b.nsum, partials + (size_t)blockIdx.x * b.nsum);
+}
+
+// result[s] = sum_g partials[g][src(s)] in order g = 0, 1, ...; the slots of
+// an ell = 0 pole take the sum of the plain power slots.
+__global__ void k_reduce(const double* __restrict__ partials, int ngroups, BinSpec b,
+                         double* __restrict__ result) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= b.nsum) return;
+  int src = s;
+  if (s >= b.nk && s < b.nk * (1 + b.npoles)) {
+    const int pi = s / b.nk - 1;
+    if ((b.zero_mask >> pi) & 1) src = s % b.nk;
+  }
+  double acc = 0.0;
+  for (int g = 0; g < ngroups; ++g) acc += partials[(size_t)g * b.nsum + src];
+  result[s] = acc;
+}
+
+// Plan time: per-bin counts (integers), sum h|n| and, for (k, mu) bins, counts,
+// sum h|n| and sum h|mu|, over the r2c half grid with its Hermitian weights.
+__global__ void __launch_bounds__(256)
+    k_mode_tables(int N, BinSpec b, double* __restrict__ partials) {
+  extern __shared__ double sb[];
+  const int nslots = mode_table_slots(b.nk, b.nmu);
+  zero_bins(sb, nslots);
+  __syncthreads();
+  const int NH = N / 2 + 1;
+  const size_t total = (size_t)N * N * NH;
+  const int nk = b.nk, nmu = b.nmu, los = b.los;
+  unsigned long long* cnt = reinterpret_cast<unsigned long long*>(sb);
+  for (size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+       idx += (size_t)gridDim.x * blockDim.x) {
+    const int kz = (int)(idx % NH);
+    const size_t rest = idx / NH;
+    const int ky = (int)(rest % N), kx = (int)(rest / N);
+    const int nx = signed_index(kx, N), ny = signed_index(ky, N), nz = kz;
+    const int n2 = nx * nx + ny * ny + nz * nz;
+    const int k = kbin_of(n2, b);
+    if (k < 0) continue;
+    const int h = (kz == 0 || kz == N / 2) ? 1 : 2;
+    const double kn = sqrt((double)n2);
+    atomicAdd(&cnt[k], (unsigned long long)h);
+    atomicAdd(&sb[nk + k], h * kn);
+    if (nmu > 1) {
+      const int nl = los == 0 ? nx : (los == 1 ? ny : nz);
+      const int f = k * nmu + mubin_of(nl * nl, n2, nmu);
+      atomicAdd(&cnt[2 * nk + f], (unsigned long long)h);
+      atomicAdd(&sb[2 * nk + nk * nmu + f], h * kn);
+      atomicAdd(&sb[2 * nk + 2 * nk * nmu + f], h * (double)abs(nl) / kn);
+    }
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < nslots; i += blockDim.x)
+    partials[(size_t)blockIdx.x * nslots + i] = sb[i];
+}
+
+// Sums the mode-table partial rows; integer slots are summed as integers.
+__global__ void k_reduce_tables(const double* __restrict__ partials, int ngroups, int nk, int nmu,
+                                double* __restrict__ out) {
+  const int nslots = mode_table_slots(nk, nmu);
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= nslots) return;
+  const bool integer = s < nk || (nmu > 1 && s >= 2 * nk && s < 2 * nk + nk * nmu);
+  if (integer) {
+    const unsigned long long* p = reinterpret_cast<const unsigned long long*>(partials);
+    unsigned long long acc = 0;
+    for (int g = 0; g < ngroups; ++g) acc += p[(size_t)g * nslots + s];
+    reinterpret_cast<unsigned long long*>(out)[s] = acc;
+  } else {
+    double acc = 0.0;
+    for (int g = 0; g < ngroups; ++g) acc += partials[(size_t)g * nslots + s];
+    out[s] = acc;
+  }
+}
+
+// Stand-alone interlacing + compensation on packed spectra (in place).
+// Columns kz' >= 1 are independent; in column 0 the thread of the smaller
+// of (kx, ky) and its partner (-kx, -ky) unpacks both, processes the four
+// plane modes and repacks them.
+template <typename T>
+__device__ __forceinline__ cpx<T> comp_mode(cpx<T> a, const cpx<T>* b, int nx, int ny, int nz,
+                                            int kx, int ky, int iz, int N,
+                                            const cpx<T>* __restrict__ phase,
+                                            const T* __restrict__ sinv) {
+  if (b) {
+    const cpx<T> bb = cmul(phase[nx + ny + nz + 3 * (N / 2)], *b);
+    a = {T(0.5) * (a.x + bb.x), T(0.5) * (a.y + bb.y)};
+  }
+  if (sinv) a = cscale(a, sinv[kx] * sinv[ky] * sinv[iz]);
+  return a;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256)
+    k_compensate(int N, cpx<T>* __restrict__ cm, const cpx<T>* __restrict__ cb,
+                 const cpx<T>* __restrict__ phase, const T* __restrict__ sinv) {
+  const int NC = N / 2;
+  const size_t total = (size_t)N * N * NC;
+  const int mask = N - 1;
+  for (size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+       idx += (size_t)gridDim.x * blockDim.x) {
+    const int col = (int)(idx % NC);
+    const size_t rest = idx / NC;
+    const int ky = (int)(rest % N), kx = (int)(rest / N);
+    const int nx = signed_index(kx, N), ny = signed_index(ky, N);
+    if (col != 0) {
+      const cpx<T> bv = cb ? cb[idx] : cpx<T>{T(0), T(0)};
+      cm[idx] = comp_mode<T>(cm[idx], cb ? &bv : nullptr, nx, ny, col, kx, ky, col, N, phase, sinv);
+      continue;
+    }
+    const int px = (N - kx) & mask, py = (N - ky) & mask;
+    const size_t me = (size_t)kx * N + ky, pa = (size_t)px * N + py;
+    if (me > pa) continue;
+    const cpx<T> z = cm[me * NC], zp = cm[pa * NC];
+    const int pnx = signed_index(px, N), pny = signed_index(py, N);
+    // unpack: plane 0 value (Z + conj Z') / 2, plane N/2 value (Z - conj Z') / (2i)
+    auto unpack = [](cpx<T> u, cpx<T> w, cpx<T>& p0, cpx<T>& p1) {
+      const cpx<T> s = cadd(u, cconj(w)), d = csub(u, cconj(w));
+      p0 = {T(0.5) * s.x, T(0.5) * s.y};
+      p1 = {T(0.5) * d.y, -T(0.5) * d.x};
+    };
+    cpx<T> a0, a1, q0, q1;
+    unpack(z, zp, a0, a1);
+    unpack(zp, z, q0, q1);
+    cpx<T> b0, b1, r0, r1;
+    if (cb) {
+      const cpx<T> w = cb[me * NC], wp = cb[pa * NC];
+      unpack(w, wp, b0, b1);
+      unpack(wp, w, r0, r1);
+    }
+    a0 = comp_mode<T>(a0, cb ? &b0 : nullptr, nx, ny, 0, kx, ky, 0, N, phase, sinv);
+    a1 = comp_mode<T>(a1, cb ? &b1 : nullptr, nx, ny, N / 2, kx, ky, N / 2, N, phase, sinv);
+    q0 = comp_mode<T>(q0, cb ? &r0 : nullptr, pnx, pny, 0, px, py, 0, N, phase, sinv);
+    q1 = comp_mode<T>(q1, cb ? &r1 : nullptr, pnx, pny, N / 2, px, py, N / 2, N, phase, sinv);
+    // repack Z = p0 + i p1
+    cm[me * NC] = {a0.x - a1.y, a0.y + a1.x};
+    if (pa != me) cm[pa * NC] = {q0.x - q1.y, q0.y + q1.x};
+  }
+}
+
+// ---------------------------------------------------------------- launchers
+
+int xpass_bin_groups(int dtype, int nmesh) {
+  // tiles = N * CHUNKS; a few workgroups per CU, never more than the tiles
+  long tiles;
+  if (dtype == PK_F32) {
+    switch (nmesh) {
+#define PK_T(NN) case NN: tiles = (long)NN * ColCfg<float, NN>::CHUNKS; break;
+      PK_T(8) PK_T(16) PK_T(32) PK_T(64) PK_T(128) PK_T(256) PK_T(512) PK_T(1024) PK_T(2048)
+#undef PK_T
+      default: return 0;
+    }
+  } else {
+    switch (nmesh) {
+#define PK_T(NN) case NN: tiles = (long)NN * ColCfg<double, NN>::CHUNKS; break;
+      PK_T(8) PK_T(16) PK_T(32) PK_T(64) PK_T(128) PK_T(256) PK_T(512) PK_T(1024) PK_T(2048)
+#undef PK_T
+      default: return 0;
+    }
+  }
+  return (int)(tiles < 1024 ? tiles : 1024);
+}
+
+int plane_bin_groups(int nmesh) {
+  const long threads = (long)nmesh * nmesh;
+  const long g = (threads + 255) / 256;
+  return (int)(g < 256 ? g : 256);
+}
+
+int mode_table_groups(int nmesh) {
+  const long total = (long)nmesh * nmesh * (nmesh / 2 + 1);
+  const long g = (total + 255) / 256;
+  return (int)(g < 1024 ? g : 1024);
+}
+
+size_t bin_lds_bytes(const BinSpec& b) { return (size_t)b.nsum * sizeof(double); }
+
+template <typename T, int N>
+static hipError_t xpass_bin_t(const void* mesh_a, const void* mesh_b, const MeshTables& t,
+                              int order, int compensated, const BinSpec& b, double* partials,
+                              void* side_a, void* side_b, hipStream_t s) {
+  using Cf = ColCfg<T, N>;
+  const int groups = xpass_bin_groups(sizeof(T) == 4 ? PK_F32 : PK_F64, N);
+  const T* sinv = compensated ? static_cast<const T*>(t.sinc_inv) + (size_t)(order - 2) * N
+                              : nullptr;
+  hipLaunchKernelGGL((k_xpass_bin<T, N>), dim3(groups), dim3(Cf::THREADS), bin_lds_bytes(b), s,
+                     static_cast<const cpx<T>*>(mesh_a), static_cast<const cpx<T>*>(mesh_b),
+                     static_cast<const cpx<T>*>(t.tw), static_cast<const cpx<T>*>(t.phase), sinv,
+                     b, partials, static_cast<cpx<T>*>(side_a), static_cast<cpx<T>*>(side_b));
+  return hipGetLastError();
+}
+
+hipError_t launch_xpass_bin(int dtype, int nmesh, const void* mesh_a, const void* mesh_b,
+                            const MeshTables& t, int order, int compensated, const BinSpec& b,
+                            double* partials, void* side_a, void* side_b, hipStream_t s) {
+#define PK_XB(T)                                                                              \
+  switch (nmesh) {                                                                            \
+    case 8: return xpass_bin_t<T, 8>(mesh_a, mesh_b, t, order, compensated, b, partials, side_a, side_b, s); \
+    case 16: return xpass_bin_t<T, 16>(mesh_a, mesh_b, t, order, compensated, b, partials, side_a, side_b, s); \
+    case 32: return xpass_bin_t<T, 32>(mesh_a, mesh_b, t, order, compensated, b, partials, side_a, side_b, s); \
+    case 64: return xpass_bin_t<T, 64>(mesh_a, mesh_b, t, order, compensated, b, partials, side_a, side_b, s); \
+    case 128: return xpass_bin_t<T, 128>(mesh_a, mesh_b, t, order, compensated, b, partials, side_a, side_b, s); \
+    case 256: return xpass_bin_t<T, 256>(mesh_a, mesh_b, t, order, compensated, b, partials, side_a, side_b, s); \
+    case 512: return xpass_bin_t<T, 512>(mesh_a, mesh_b, t, order, compensated, b, partials, side_a, side_b, s); \
+    case 1024: return xpass_bin_t<T, 1024>(mesh_a, mesh_b, t, order, compensated, b, partials, side_a, side_b, s); \
+    case 2048: return xpass_bin_t<T, 2048>(mesh_a, mesh_b, t, order, compensated, b, partials, side_a, side_b, s); \
+    default: return hipErrorInvalidValue;                                                    \
+  }
+  if (dtype == PK_F32) {
+    PK_XB(float)
+  } else {
+    PK_XB(double)
+  }
+#undef PK_XB
+}
+
+hipError_t launch_bin_packed(int dtype, int nmesh, const void* cmesh, const BinSpec& b,
+                             double* partials, hipStream_t s) {
+  const size_t total = (size_t)nmesh * nmesh * (nmesh / 2);
+  size_t g = (total + 255) / 256;
+  if (g > 1024) g = 1024;
+  if (dtype == PK_F32)
+    hipLaunchKernelGGL(k_bin_packed<float>, dim3((unsigned)g), dim3(256), bin_lds_bytes(b), s,
+                       nmesh, static_cast<const cpx<float>*>(cmesh), b, partials);
+  else
+    hipLaunchKernelGGL(k_bin_packed<double>, dim3((unsigned)g), dim3(256), bin_lds_bytes(b), s,
+                       nmesh, static_cast<const cpx<double>*>(cmesh), b, partials);
+  return hipGetLastError();
+}
+
+hipError_t launch_plane_bin(int dtype, int nmesh, const void* za, const void* zb, size_t zstride,
+                            const MeshTables& t, int order, int compensated, const BinSpec& b,
+                            double* partials, hipStream_t s) {
+  const int g = plane_bin_groups(nmesh);
+  if (dtype == PK_F32) {
+    const float* sinv = compensated ? static_cast<const float*>(t.sinc_inv) + (size_t)(order - 2) * nmesh : nullptr;
+    hipLaunchKernelGGL(k_plane_bin<float>, dim3(g), dim3(256), bin_lds_bytes(b), s, nmesh,
+                       static_cast<const cpx<float>*>(za), static_cast<const cpx<float>*>(zb),
+                       zstride, static_cast<const cpx<float>*>(t.phase), sinv, b, partials);
+  } else {
+    const double* sinv = compensated ? static_cast<const double*>(t.sinc_inv) + (size_t)(order - 2) * nmesh : nullptr;
+    hipLaunchKernelGGL(k_plane_bin<double>, dim3(g), dim3(256), bin_lds_bytes(b), s, nmesh,
+                       static_cast<const cpx<double>*>(za), static_cast<const cpx<double>*>(zb),
+                       zstride, static_cast<const cpx<double>*>(t.phase), sinv, b, partials);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce(const double* partials, int ngroups, const BinSpec& b, double* result,
+                         hipStream_t s) {
+  const int blocks = (b.nsum + 255) / 256;
+  hipLaunchKernelGGL(k_reduce, dim3(blocks), dim3(256), 0, s, partials, ngroups, b, result);
+  return hipGetLastError();
+}
+
+hipError_t launch_mode_tables(int nmesh, const BinSpec& b, double* partials, int ngroups,
+                              double* out, hipStream_t s) {
+  const int nslots = mode_table_slots(b.nk, b.nmu);
+  hipLaunchKernelGGL(k_mode_tables, dim3(ngroups), dim3(256), (size_t)nslots * sizeof(double), s,
+                     nmesh, b, partials);
+  hipLaunchKernelGGL(k_reduce_tables, dim3((nslots + 255) / 256), dim3(256), 0, s, partials,
+                     ngroups, b.nk, b.nmu, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_compensate(int dtype, int nmesh, void* cmesh, const void* cmesh_b,
+                             const MeshTables& t, int order, int compensated, hipStream_t s) {
+  const size_t total = (size_t)nmesh * nmesh * (nmesh / 2);
+  size_t g = (total + 255) / 256;
+  if (g > 65536) g = 65536;
+  if (dtype == PK_F32) {
+    const float* sinv = compensated ? static_cast<const float*>(t.sinc_inv) + (size_t)(order - 2) * nmesh : nullptr;
+    hipLaunchKernelGGL(k_compensate<float>, dim3((unsigned)g), dim3(256), 0, s, nmesh,
+                       static_cast<cpx<float>*>(cmesh), static_cast<const cpx<float>*>(cmesh_b),
+                       static_cast<const cpx<float>*>(t.phase), sinv);
+  } else {
+    const double* sinv = compensated ? static_cast<const double*>(t.sinc_inv) + (size_t)(order - 2) * nmesh : nullptr;
+    hipLaunchKernelGGL(k_compensate<double>, dim3((unsigned)g), dim3(256), 0, s, nmesh,
+                       static_cast<cpx<double>*>(cmesh), static_cast<const cpx<double>*>(cmesh_b),
+                       static_cast<const cpx<double>*>(t.phase), sinv);
+  }
+  return hipGetLastError();
+}
+
+}  // namespace pk

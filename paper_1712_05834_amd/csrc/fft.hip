@@ -1,0 +1,146 @@
+// The 3-D forward r2c FFT (Sec. 3.3.1) as three passes over the mesh:
+//   z-pass: each real row of N points is read as N/2 complex points, given an
+//           N/2-point FFT and split into the N/2 + 1 outputs of the real DFT;
+//           the two real outputs (kz = 0 and kz = N/2) are packed into one
+//           complex slot, so a row stays N reals long and 4 KB aligned;
+//   y-pass: N-point FFTs along y for C neighbouring packed columns at once;
+//   x-pass: the same along x (here for the stand-alone transform; the
+//           power-spectrum path fuses it with the binning).
+// Every pass reads and writes each point once, coalesced along z.
+#include "fft_config.h"
+#include "internal.h"
+
+namespace pk {
+
+template <typename T, int N>
+__global__ void __launch_bounds__((ZCfg<T, N>::THREADS))
+    k_fft_z(T* __restrict__ mesh0, size_t mesh_stride, const cpx<T>* __restrict__ tw,
+            const double* __restrict__ wsum) {
+  using Z = ZCfg<T, N>;
+  constexpr int M = Z::M, E = Z::E, TPL = Z::TPL, RPB = Z::RPB;
+  __shared__ cpx<T> lds[RPB * Z::LP];
+  const int r = threadIdx.x / TPL, t = threadIdx.x % TPL;
+  const size_t nrows = (size_t)N * N;
+  const size_t row = (size_t)blockIdx.x * RPB + r;
+  const bool active = row < nrows;
+  cpx<T>* rowp = reinterpret_cast<cpx<T>*>(mesh0 + blockIdx.z * mesh_stride + row * N);
+  // Subtracting the mean only changes the DC mode, which is never binned; it
+  // keeps the float32 rounding of the other modes relative to the fluctuations.
+  const T mean = wsum ? static_cast<T>(wsum[0] / ((double)N * N * N)) : T(0);
+  cpx<T> v[E];
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    if (active) {
+      v[e] = rowp[t + TPL * e];
+      v[e].x -= mean;
+      v[e].y -= mean;
+    } else {
+      v[e] = {T(0), T(0)};
+    }
+  }
+  LdsLine<T> line{lds + r * Z::LP};
+  stockham<T, M, E, 1>(v, t, tw, 2, line);
+  __syncthreads();
+#pragma unroll
+  for (int e = 0; e < E; ++e) line.put(t + TPL * e, v[e]);
+  __syncthreads();
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const int k = t + TPL * e;
+    cpx<T> out;
+    if (k == 0) {
+      out = {v[e].x + v[e].y, v[e].x - v[e].y};  // {X_0, X_{N/2}}, both real
+    } else {
+      // X_k = (Z_k + conj Z_{M-k}) / 2 - (i / 2) W_N^k (Z_k - conj Z_{M-k})
+      const cpx<T> zc = cconj(line.get(M - k));
+      const cpx<T> s = cadd(v[e], zc);
+      const cpx<T> w = cmul(tw[k], csub(v[e], zc));
+      out = {T(0.5) * (s.x + w.y), T(0.5) * (s.y - w.x)};
+    }
+    if (active) rowp[k] = out;
+  }
+}
+
+template <typename T, int N>
+__global__ void __launch_bounds__((ColCfg<T, N>::THREADS))
+    k_fft_cols(T* __restrict__ mesh0, size_t mesh_stride, const cpx<T>* __restrict__ tw,
+               int axis) {
+  using Cf = ColCfg<T, N>;
+  constexpr int E = Cf::E, TPL = Cf::TPL, C = Cf::C, NC = Cf::NC;
+  __shared__ cpx<T> lds[Cf::LDS_ELEMS];
+  const int c = threadIdx.x % C, t = threadIdx.x / C;
+  const int outer = blockIdx.x / Cf::CHUNKS, chunk = blockIdx.x % Cf::CHUNKS;
+  cpx<T>* mesh = reinterpret_cast<cpx<T>*>(mesh0 + blockIdx.z * mesh_stride);
+  size_t base, step;
+  if (axis == 1) {
+    base = (size_t)outer * N * NC + (size_t)chunk * C + c;
+    step = NC;
+  } else {
+    base = (size_t)outer * NC + (size_t)chunk * C + c;
+    step = (size_t)N * NC;
+  }
+  cpx<T> v[E];
+#pragma unroll
+  for (int e = 0; e < E; ++e) v[e] = mesh[base + (size_t)(t + TPL * e) * step];
+  LdsCols<T, C> lc{lds, c};
+  stockham<T, N, E, 1>(v, t, tw, 1, lc);
+#pragma unroll
+  for (int e = 0; e < E; ++e) mesh[base + (size_t)(t + TPL * e) * step] = v[e];
+}
+
+template <typename T, int N>
+static hipError_t fft_z_t(void* mesh, int nmeshes, size_t stride_bytes, const void* tw,
+                          const double* wsum, hipStream_t s) {
+  using Z = ZCfg<T, N>;
+  const size_t nrows = (size_t)N * N;
+  const unsigned blocks = (unsigned)((nrows + Z::RPB - 1) / Z::RPB);
+  hipLaunchKernelGGL((k_fft_z<T, N>), dim3(blocks, 1, nmeshes), dim3(Z::THREADS), 0, s,
+                     static_cast<T*>(mesh), stride_bytes / sizeof(T),
+                     static_cast<const cpx<T>*>(tw), wsum);
+  return hipGetLastError();
+}
+
+template <typename T, int N>
+static hipError_t fft_cols_t(void* mesh, int nmeshes, size_t stride_bytes, const void* tw,
+                             int axis, hipStream_t s) {
+  using Cf = ColCfg<T, N>;
+  const unsigned blocks = (unsigned)(N * Cf::CHUNKS);
+  hipLaunchKernelGGL((k_fft_cols<T, N>), dim3(blocks, 1, nmeshes), dim3(Cf::THREADS), 0, s,
+                     static_cast<T*>(mesh), stride_bytes / sizeof(T),
+                     static_cast<const cpx<T>*>(tw), axis);
+  return hipGetLastError();
+}
+
+#define PK_DISPATCH_N(FN, T, ...)            \
+  switch (nmesh) {                           \
+    case 8: return FN<T, 8>(__VA_ARGS__);     \
+    case 16: return FN<T, 16>(__VA_ARGS__);   \
+    case 32: return FN<T, 32>(__VA_ARGS__);   \
+    case 64: return FN<T, 64>(__VA_ARGS__);   \
+    case 128: return FN<T, 128>(__VA_ARGS__); \
+    case 256: return FN<T, 256>(__VA_ARGS__); \
+    case 512: return FN<T, 512>(__VA_ARGS__); \
+    case 1024: return FN<T, 1024>(__VA_ARGS__); \
+    case 2048: return FN<T, 2048>(__VA_ARGS__); \
+    default: return hipErrorInvalidValue;    \
+  }
+
+hipError_t launch_fft_z(int dtype, int nmesh, void* mesh, int nmeshes, size_t stride_bytes,
+                        const void* tw, const double* wsum, hipStream_t s) {
+  if (dtype == PK_F32) {
+    PK_DISPATCH_N(fft_z_t, float, mesh, nmeshes, stride_bytes, tw, wsum, s)
+  } else {
+    PK_DISPATCH_N(fft_z_t, double, mesh, nmeshes, stride_bytes, tw, wsum, s)
+  }
+}
+
+hipError_t launch_fft_cols(int dtype, int nmesh, void* mesh, int nmeshes, size_t stride_bytes,
+                           const void* tw, int axis, hipStream_t s) {
+  if (dtype == PK_F32) {
+    PK_DISPATCH_N(fft_cols_t, float, mesh, nmeshes, stride_bytes, tw, axis, s)
+  } else {
+    PK_DISPATCH_N(fft_cols_t, double, mesh, nmeshes, stride_bytes, tw, axis, s)
+  }
+}
+
+}  // namespace pk

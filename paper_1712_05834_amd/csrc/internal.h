@@ -1,0 +1,108 @@
+// Internal declarations shared by the translation units of libpk.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <map>
+#include <memory>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "../../include/pk.h"
+
+namespace pk {
+
+// Per (mesh size, precision) device tables, one allocation:
+//   tw[N]            W_N^j = exp(-2 pi i j / N)                 (complex T)
+//   phase[3N + 1]    exp(i pi s / N), s = -3N/2 .. 3N/2         (complex T)
+//   sinc_inv[3][N]   sinc(pi n_i / N)^-p, p = 2, 3, 4, index i  (real T)
+// All values are computed on the host in float64 and rounded once.
+struct MeshTables {
+  void* dev = nullptr;
+  size_t bytes = 0;
+  const void* tw = nullptr;
+  const void* phase = nullptr;
+  const void* sinc_inv = nullptr;  // row p - 2
+};
+
+// Per binning: device squared edges plus host copies of the field-independent
+// sums (mode counts, sum of h |n|, sum of h |mu|).
+struct BinTables {
+  double* e2_dev = nullptr;  // nk + 1
+  std::vector<int64_t> modes;
+  std::vector<double> sum_n;  // sum over modes of h |n| (units of k_f)
+  std::vector<int64_t> modes2d;
+  std::vector<double> sum_n2d;
+  std::vector<double> sum_mu2d;
+};
+
+// Everything a binning kernel needs to place one mode.
+struct BinSpec {
+  int nmesh = 0;
+  int nk = 0;
+  int nmu = 0;
+  int los = 2;
+  int npoles = 0;       // all requested poles (slot order of the result)
+  int zero_mask = 0;    // bit i set: poles[i] == 0 (aliases the plain power)
+  int npl = 0;          // poles with ell > 0 that are accumulated
+  int pole_ell[4] = {0, 0, 0, 0};
+  int pole_slot[4] = {0, 0, 0, 0};
+  int off2d = -1;       // first (k, mu) slot, -1 if none
+  int nsum = 0;         // number of sum slots (weight slots excluded)
+  double kmin_f = 0.0;
+  double dk_f = 1.0;
+  const double* e2 = nullptr;  // device, nk + 1
+};
+
+// Mode-table accumulator layout (plan time):
+//   [0, nk) counts (as uint64 bits), [nk, 2nk) sum h|n|,
+//   then, if nmu > 1: counts2d, sum h|n| 2d, sum h|mu| 2d (nk * nmu each).
+__host__ __device__ inline int mode_table_slots(int nk, int nmu) { return 2 * nk + (nmu > 1 ? 3 * nk * nmu : 0); }
+
+// ---- launchers (each defined in the translation unit of its kernels) ----
+hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t s);
+hipError_t launch_paint_atomic(int dtype, int order, int nmesh, double boxsize, const void* pos,
+                               const void* weight, int64_t n, double shift_a, void* mesh_a,
+                               double shift_b, void* mesh_b, double* wsums, hipStream_t s);
+
+hipError_t launch_fft_z(int dtype, int nmesh, void* mesh, int nmeshes, size_t mesh_stride_bytes,
+                        const void* tw, const double* wsum_for_mean, hipStream_t s);
+hipError_t launch_fft_cols(int dtype, int nmesh, void* mesh, int nmeshes,
+                           size_t mesh_stride_bytes, const void* tw, int axis, hipStream_t s);
+
+// Workgroup count of the persistent binning kernels for a mesh size.
+int xpass_bin_groups(int dtype, int nmesh);
+int plane_bin_groups(int nmesh);
+size_t bin_lds_bytes(const BinSpec& b);
+hipError_t launch_xpass_bin(int dtype, int nmesh, const void* mesh_a, const void* mesh_b,
+                            const MeshTables& t, int order, int compensated, const BinSpec& b,
+                            double* partials, void* side_a, void* side_b, hipStream_t s);
+hipError_t launch_bin_packed(int dtype, int nmesh, const void* cmesh, const BinSpec& b,
+                             double* partials, hipStream_t s);
+hipError_t launch_plane_bin(int dtype, int nmesh, const void* za, const void* zb, size_t zstride,
+                            const MeshTables& t, int order, int compensated, const BinSpec& b,
+                            double* partials, hipStream_t s);
+hipError_t launch_reduce(const double* partials, int ngroups, const BinSpec& b, double* result,
+                         hipStream_t s);
+hipError_t launch_mode_tables(int nmesh, const BinSpec& b, double* partials, int ngroups,
+                              double* out, hipStream_t s);
+int mode_table_groups(int nmesh);
+hipError_t launch_compensate(int dtype, int nmesh, void* cmesh, const void* cmesh_b,
+                             const MeshTables& t, int order, int compensated, hipStream_t s);
+
+}  // namespace pk
+
+struct pk_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  std::string err;
+  size_t table_bytes = 0;
+  std::map<std::pair<int, int>, pk::MeshTables> mesh_tables;  // (nmesh, dtype)
+  using BinKey = std::tuple<int, double, double, int, int, int>;  // nmesh, kmin, dk, nk, nmu, los
+  std::map<BinKey, std::unique_ptr<pk::BinTables>> bin_tables;
+  double* scratch = nullptr;  // plan-time scratch for the mode-table kernel
+  size_t scratch_bytes = 0;
+};

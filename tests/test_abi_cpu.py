@@ -1,0 +1,124 @@
+"""C ABI checks that need no GPU: the library loads, exports every symbol
+include/pk.h declares, sizes its buffers, and rejects bad arguments with
+PK_EINVAL before any device work (validation-only context)."""
+
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_1712_05834_amd import _lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "pk.h")
+
+
+def declared_symbols():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(pk_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = _lib.load()
+    decl = declared_symbols()
+    assert len(decl) >= 13
+    for name in decl:
+        assert hasattr(lib, name), name
+    assert set(decl) == set(_lib.EXPORTS)
+
+
+def test_sizes():
+    m = _lib.mesh_desc(64, 1000.0, "cic", False, True, "f8")
+    assert _lib.mesh_bytes(m) == 64 ** 3 * 8
+    m32 = _lib.mesh_desc(512, 1380.0, "tsc", True, True, "f4")
+    assert _lib.mesh_bytes(m32) == 512 ** 3 * 4
+    b = _lib.bin_desc(256, 0.0, 1.0, 5, (0, 2, 4), 2)
+    assert _lib.result_doubles(b) == 256 * 4 + 256 * 5 + 2
+    ws = _lib.workspace_bytes(m32, b, 10_000_000)
+    assert ws >= 2 * 512 ** 3 * 4
+    bad = _lib.mesh_desc(100, 1000.0)
+    assert _lib.mesh_bytes(bad) == 0
+    assert _lib.workspace_bytes(bad, b, 1) == 0
+
+
+@pytest.fixture(scope="module")
+def vctx():
+    lib = _lib.load()
+    h = ctypes.c_void_p()
+    assert lib.pk_ctx_create(ctypes.byref(h), -1, None) == _lib.PK_OK
+    yield lib, h
+    lib.pk_ctx_destroy(h)
+
+
+def _paint(lib, h, m, pos=1, n=10, mesh=1, shift=0.0):
+    return lib.pk_paint(h, ctypes.byref(m), ctypes.c_void_p(pos), None, n, shift,
+                        ctypes.c_void_p(mesh), None)
+
+
+def test_einval_before_device_work(vctx):
+    lib, h = vctx
+    good = _lib.mesh_desc(64, 1000.0, "cic")
+    cases = [
+        _lib.mesh_desc(63, 1000.0), _lib.mesh_desc(4, 1000.0), _lib.mesh_desc(4096, 1000.0),
+        _lib.mesh_desc(64, 0.0), _lib.mesh_desc(64, -1.0), _lib.mesh_desc(64, float("nan")),
+    ]
+    for m in cases:
+        assert _paint(lib, h, m) == _lib.PK_EINVAL
+    m = _lib.mesh_desc(64, 1000.0)
+    m.window = 5
+    assert _paint(lib, h, m) == _lib.PK_EINVAL
+    m = _lib.mesh_desc(64, 1000.0)
+    m.reserved = 1
+    assert _paint(lib, h, m) == _lib.PK_EINVAL
+    assert _paint(lib, h, good, pos=0) == _lib.PK_EINVAL          # NULL pos with n > 0
+    assert _paint(lib, h, good, n=-1) == _lib.PK_EINVAL
+    assert _paint(lib, h, good, mesh=0) == _lib.PK_EINVAL
+    assert _paint(lib, h, good, shift=float("inf")) == _lib.PK_EINVAL
+    assert b"NULL" in lib.pk_last_error(h) or b"finite" in lib.pk_last_error(h)
+    # valid arguments reach the device check of a validation-only context
+    assert _paint(lib, h, good) == _lib.PK_EDEVICE
+
+
+def test_bins_einval(vctx):
+    lib, h = vctx
+    inter = _lib.mesh_desc(64, 1000.0, "tsc", True)
+    plain = _lib.mesh_desc(64, 1000.0, "tsc", False)
+    res = ctypes.c_void_p(1)
+
+    def bp(m, b):
+        return lib.pk_bin_power(h, ctypes.byref(m), ctypes.byref(b), ctypes.c_void_p(1), res)
+
+    assert bp(inter, _lib.bin_desc(33)) == _lib.PK_EINVAL          # above Nyquist, interlaced
+    assert bp(plain, _lib.bin_desc(33)) == _lib.PK_EDEVICE         # allowed without interlacing
+    assert bp(inter, _lib.bin_desc(32)) == _lib.PK_EDEVICE
+    assert bp(inter, _lib.bin_desc(0)) == _lib.PK_EINVAL
+    assert bp(inter, _lib.bin_desc(8, dk_f=0.0)) == _lib.PK_EINVAL
+    assert bp(inter, _lib.bin_desc(8, kmin_f=-1.0)) == _lib.PK_EINVAL
+    assert bp(inter, _lib.bin_desc(8, poles=(1,))) == _lib.PK_EINVAL  # odd ell
+    assert bp(inter, _lib.bin_desc(8, poles=(2, 2))) == _lib.PK_EINVAL
+    assert bp(inter, _lib.bin_desc(8, nmu=65)) == _lib.PK_EINVAL
+    assert bp(inter, _lib.bin_desc(8, los=3)) == _lib.PK_EINVAL
+    assert bp(plain, _lib.bin_desc(4000, dk_f=0.01, nmu=64)) == _lib.PK_EUNSUPPORTED
+
+
+def test_fftpower_workspace_check(vctx):
+    lib, h = vctx
+    m = _lib.mesh_desc(32, 100.0, "cic")
+    b = _lib.bin_desc(16)
+    need = _lib.workspace_bytes(m, b, 100)
+    st = lib.pk_fftpower(h, ctypes.byref(m), ctypes.byref(b), ctypes.c_void_p(1), None, 100,
+                         ctypes.c_void_p(1), need - 1, ctypes.c_void_p(1))
+    assert st == _lib.PK_EINVAL and b"workspace" in lib.pk_last_error(h)
+    st = lib.pk_fftpower(h, ctypes.byref(m), ctypes.byref(b), ctypes.c_void_p(1), None, 100,
+                         ctypes.c_void_p(1), need, ctypes.c_void_p(1))
+    assert st == _lib.PK_EDEVICE
+
+
+def test_null_context_and_create_errors():
+    lib = _lib.load()
+    m = _lib.mesh_desc(32, 100.0)
+    assert lib.pk_fft_r2c(None, ctypes.byref(m), ctypes.c_void_p(1)) == _lib.PK_EINVAL
+    assert lib.pk_ctx_create(None, 0, None) == _lib.PK_EINVAL
+    assert lib.pk_last_error(None)
