@@ -1,0 +1,248 @@
+#!/usr/bin/env python3
+"""Benchmark of the FFTPower hot path on one MI355X.
+
+One step = one pass of the whole path over one resident catalog: paint both
+interlaced meshes, r2c FFT, interlace + compensate + bin, finalise (result
+copied to the host).  Default workload (the one the headline metric is quoted
+on): a Poisson-sampled log-normal mock of ~1e7 particles (P(k) =
+2e4 k / (1 + (k / 0.02)^2)^1.4, L = 1380 Mpc/h), TSC interlaced onto a 512^3
+float32 mesh, P(k, mu) with 5 mu bins and ell = 0, 2, 4 along z.
+
+    python bench.py [--steps K] [--warmup W] [--workload NAME]
+
+Prints one JSON line.  ``value`` is meshes/s with the catalog resident in HBM;
+``roofline`` prices the dominant kernel's algorithmic bytes against 8 TB/s
+using HIP events recorded by the library on its stream; ``cpu_baseline`` times
+the CPU float64 oracle on a bounded sample of the same workload.
+"""
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "Mparticles/s painted + P(k) meshes/s at 512³; p50/p99 request latency"
+HBM_PEAK_GBS = 8000.0
+
+WORKLOADS = {
+    "lognormal-512": dict(n=512, box=1380.0, window="tsc", interlaced=True, dtype="f4",
+                          nmu=5, poles=(0, 2, 4), kind="lognormal", seed=2),
+    "zeldovich-1024": dict(n=1024, box=2000.0, window="cic", interlaced=True, dtype="f4",
+                           nmu=0, poles=(0, 2), kind="zeldovich", ngrid=512, seed=3),
+    "uniform-64-fp64": dict(n=64, box=1000.0, window="cic", interlaced=False, dtype="f8",
+                            nmu=0, poles=(), kind="uniform", npart=10_000, seed=1),
+}
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def make_catalog(w):
+    import numpy as np
+
+    from paper_1712_05834_amd import synth
+
+    nd = np.float32 if w["dtype"] == "f4" else np.float64
+    if w["kind"] == "lognormal":
+        n = w["n"]
+        return synth.lognormal_catalog(n, w["box"], synth.pk_lognormal_c2, 1e7 / n ** 3,
+                                       seed=w["seed"], dtype=nd)
+    if w["kind"] == "zeldovich":
+        return synth.zeldovich_lattice(w["ngrid"], w["box"], synth.pk_zeldovich_c3,
+                                       seed=w["seed"], dtype=nd)
+    return synth.uniform_catalog(w["npart"], w["box"], seed=w["seed"], dtype=nd)
+
+
+def algorithmic_bytes(stage, w, npart):
+    """Compulsory HBM bytes of one launch of a stage: each input read once and
+    each output written once (per-unit figures in the design doc)."""
+    es = 4 if w["dtype"] == "f4" else 8
+    n3 = w["n"] ** 3
+    m = 2 if w["interlaced"] else 1
+    return {
+        "paint": 3 * es * npart + m * es * n3,     # positions in, meshes out
+        "fft_z": m * 2 * es * n3,                  # real rows in, packed rows out
+        "fft_y": m * 2 * es * n3,
+        "xpass_bin": m * es * n3,                  # spectra in, ~10 KB of sums out
+        "plane_bin": m * 2 * es * w["n"] ** 2,
+    }.get(stage, 0)
+
+
+def source_hash():
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_1712_05834_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        with open(os.path.join(csrc, f), "rb") as fh:
+            h.update(f.encode() + fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload, kernel):
+    """HBM bytes per launch from committed rocprofv3 counter runs, or None if
+    there are none or the kernels changed since they were taken."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{workload}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        rec = json.load(fh)
+    if rec.get("source_hash") != source_hash():
+        return None
+    k = rec.get("kernels", {}).get(kernel)
+    return None if k is None else k.get("bytes_per_launch")
+
+
+def cpu_baseline(w, pos, frac):
+    """Oracle (float64, CPU) on a bounded sample: painting of a fraction of the
+    catalog onto both meshes (scaled by 1 / frac), the full r2c of each mesh
+    and the full binning."""
+    import numpy as np
+
+    import oracle
+    from oracle.paint import WINDOW_ORDER
+
+    n, box, order = w["n"], w["box"], WINDOW_ORDER[w["window"]]
+    sub = pos[: max(1, int(len(pos) * frac))].astype(np.float64)
+    t0 = time.perf_counter()
+    ma = oracle.paint_mesh(sub, n, box, order)
+    mb = oracle.paint_mesh(sub, n, box, order, shift_cells=0.5) if w["interlaced"] else None
+    t_paint = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    ca = oracle.r2c(ma)
+    del ma
+    cb = oracle.r2c(mb) if mb is not None else None
+    del mb
+    t_fft = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    oracle.fftpower_from_spectra(ca, cb, n, box, order, True, float(len(sub)), float(len(sub)),
+                                 len(sub), nmu=w["nmu"], poles=w["poles"])
+    t_bin = time.perf_counter() - t0
+    per_mesh = t_paint / frac + t_fft + t_bin
+    return {
+        "value": 1.0 / per_mesh,
+        "unit": "meshes/s",
+        "cores": os.cpu_count(),
+        "kind": "oracle",
+        "sample": (f"float64 oracle on this host: painting of {len(sub)} of {len(pos)} "
+                   f"particles onto {'both meshes' if w['interlaced'] else 'the mesh'} "
+                   f"({t_paint:.1f} s, single thread, scaled x{1 / frac:g}), full r2c "
+                   f"({t_fft:.1f} s, scipy workers={os.cpu_count()}) and full binning "
+                   f"({t_bin:.1f} s, single thread) of one {n}^3 mesh"),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="lognormal-512", choices=sorted(WORKLOADS))
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample", type=float, default=0.25,
+                    help="fraction of the catalog the oracle paints for cpu_baseline")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
+              "(each mesh is processed on a single MI355X; see DESIGN.md for sharding)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_1712_05834_amd import _lib
+
+    w = WORKLOADS[args.workload]
+    t0 = time.perf_counter()
+    pos_host = make_catalog(w)
+    npart = len(pos_host)
+    log(f"workload {args.workload}: {npart} particles generated in "
+        f"{time.perf_counter() - t0:.1f} s")
+
+    dev = torch.device("cuda:0")
+    pos = torch.from_numpy(pos_host).to(dev)
+    ctx = _lib.Context(0)
+    m = _lib.mesh_desc(w["n"], w["box"], w["window"], w["interlaced"], True, w["dtype"])
+    b = _lib.bin_desc(w["n"] // 2, 0.0, 1.0, w["nmu"], w["poles"], 2)
+    ws = torch.empty(_lib.workspace_bytes(m, b, npart), dtype=torch.uint8, device=dev)
+    res = torch.empty(_lib.result_doubles(b), dtype=torch.float64, device=dev)
+
+    def step():
+        ctx.pk_fftpower(m, b, pos, None, npart, ws, res)
+        return ctx.pk_result_to_host(m, b, res)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    log(f"warmup done ({args.warmup} steps); timing {args.steps} steps")
+
+    ctx.pk_ctx_set_timing(True)
+    stage_ms = {}
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for _ in range(args.steps):
+        out = step()
+        for k, v in ctx.pk_ctx_stage_times().items():
+            stage_ms.setdefault(k, []).append(v)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t_start
+    ctx.pk_ctx_set_timing(False)
+
+    ms_per_step = 1e3 * elapsed / args.steps
+    mean_ms = {k: float(np.mean(v)) for k, v in stage_ms.items()}
+    log("stage means (ms): " + ", ".join(f"{k} {v:.3f}" for k, v in mean_ms.items()))
+    paint_ms = mean_ms.get("clear", 0.0) + mean_ms.get("paint", 0.0)
+    dominant = max((k for k in mean_ms if algorithmic_bytes(k, w, npart) > 0),
+                   key=lambda k: mean_ms[k])
+    nbytes = algorithmic_bytes(dominant, w, npart)
+    achieved = nbytes / (mean_ms[dominant] * 1e-3) / 1e9
+    total_bytes = sum(algorithmic_bytes(k, w, npart) for k in mean_ms)
+    assert np.isfinite(out["power"][1:]).all(), "non-finite power"
+
+    line = {
+        "metric": METRIC,
+        "value": 1e3 / ms_per_step,
+        "unit": "meshes/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 (paint, FFT) + f64 (bin sums)" if w["dtype"] == "f4" else "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": args.workload,
+            "nmesh": w["n"], "boxsize": w["box"], "window": w["window"],
+            "interlaced": w["interlaced"], "npart": npart, "nmu": w["nmu"],
+            "poles": list(w["poles"]), "los": "z",
+        },
+        "mparticles_per_s_painted": npart / (paint_ms * 1e-3) / 1e6 if paint_ms > 0 else None,
+        "stage_ms": mean_ms,
+        "end_to_end_hbm_frac": total_bytes / (ms_per_step * 1e-3) / (HBM_PEAK_GBS * 1e9),
+        "roofline": {
+            "bound": "hbm",
+            "kernel": dominant,
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": measured_traffic(args.workload, dominant),
+        },
+        "cpu_baseline": None,
+    }
+    if not args.no_cpu_baseline:
+        log("timing the CPU oracle on a bounded sample")
+        line["cpu_baseline"] = cpu_baseline(w, pos_host, args.cpu_sample)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

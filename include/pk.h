@@ -213,6 +213,18 @@ pk_status pk_fftpower(pk_ctx *ctx, const pk_mesh_desc *m, const pk_bin_desc *b,
 pk_status pk_result_to_host(pk_ctx *ctx, const pk_mesh_desc *m, const pk_bin_desc *b,
                             const double *result_dev, pk_result *out);
 
+/* Stage timing (diagnostics, Sec. 6 of the paper reports per-step wall
+ * clock).  While enabled, pk_fftpower records a HIP event on the context
+ * stream before each of its stages and one after the last; the events cost a
+ * few microseconds per call.  pk_ctx_stage_times synchronises on the last
+ * event and writes the milliseconds of every stage of the last timed call
+ * (host array of pk_stage_count() doubles, 0 for stages that did not run).
+ * Errors: PK_EINVAL (NULL arguments, no timed call yet), PK_EDEVICE. */
+pk_status pk_ctx_set_timing(pk_ctx *ctx, int enable);
+int pk_stage_count(void);
+const char *pk_stage_name(int stage); /* NULL outside [0, pk_stage_count()) */
+pk_status pk_ctx_stage_times(pk_ctx *ctx, double *ms);
+
 #ifdef __cplusplus
 }
 #endif

@@ -24,7 +24,7 @@ against a 2x-resolution reference (Sec. 3.3.2, discussion of Fig. 2) depend on
 a mock that cannot be rebuilt, so they are context, not a pin.
 """
 
-from .paint import wrap_positions, cell_coordinates, window_weights, paint_mesh
+from .paint import wrap_positions, cell_coordinates, window_weights, paint_mesh, paint_cells
 from .power import (
     r2c,
     mode_indices,
@@ -44,6 +44,7 @@ __all__ = [
     "cell_coordinates",
     "window_weights",
     "paint_mesh",
+    "paint_cells",
     "r2c",
     "mode_indices",
     "interlace_combine",

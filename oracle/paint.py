@@ -111,3 +111,26 @@ def paint_mesh(pos, nmesh, boxsize, order, weight=None, shift_cells=0.0):
                     flat, weights=w * wx[:, a] * wy[:, b] * wz[:, c], minlength=n ** 3
                 )
     return mesh.reshape(n, n, n)
+
+
+def paint_cells(pos, cells, nmesh, boxsize, order, weight=None, shift_cells=0.0):
+    """F_j of Eq. (1) at the listed cells only, one cell at a time.
+
+    For each cell j = (i, k, l) this sums w_p prod_d M_p(u_{p,d} + shift - j_d
+    - m_d N) over all particles, with m_d the periodic image nearest to the
+    cell (for N >= p no other image is within the window's reach).  Used to
+    check single cells of meshes too large to paint on the host.
+    """
+    pos = np.asarray(pos, dtype=np.float64).reshape(-1, 3)
+    u = cell_coordinates(pos, nmesh, boxsize) + shift_cells
+    w = np.ones(len(pos)) if weight is None else np.asarray(weight, dtype=np.float64)
+    out = np.empty(len(cells))
+    reach = order / 2.0
+    for c, cell in enumerate(np.asarray(cells, dtype=np.int64).reshape(-1, 3)):
+        total = w.copy()
+        for d in range(3):
+            a = u[:, d] - cell[d]
+            a = a - nmesh * np.round(a / nmesh)  # nearest periodic image
+            total = total * np.where(np.abs(a) < reach, bspline(order, a), 0.0)
+        out[c] = total.sum()
+    return out

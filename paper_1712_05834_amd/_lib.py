@@ -23,6 +23,7 @@ EXPORTS = (
     "pk_ctx_create", "pk_ctx_destroy", "pk_last_error", "pk_mesh_bytes",
     "pk_result_doubles", "pk_workspace_bytes", "pk_ctx_table_bytes", "pk_paint",
     "pk_fft_r2c", "pk_compensate", "pk_bin_power", "pk_fftpower", "pk_result_to_host",
+    "pk_ctx_set_timing", "pk_stage_count", "pk_stage_name", "pk_ctx_stage_times",
 )
 
 
@@ -107,6 +108,10 @@ def load(path=None):
             "pk_bin_power": (i32, [vp, md, bd, vp, vp]),
             "pk_fftpower": (i32, [vp, md, bd, vp, vp, i64, vp, sz, vp]),
             "pk_result_to_host": (i32, [vp, md, bd, vp, ctypes.POINTER(Result)]),
+            "pk_ctx_set_timing": (i32, [vp, ctypes.c_int]),
+            "pk_stage_count": (ctypes.c_int, []),
+            "pk_stage_name": (ctypes.c_char_p, [ctypes.c_int]),
+            "pk_ctx_stage_times": (i32, [vp, ctypes.POINTER(ctypes.c_double)]),
         }
         for name, (res, args) in sig.items():
             f = getattr(lib, name)
@@ -177,6 +182,18 @@ class Context:
     def _check(self, st):
         if st != PK_OK:
             raise PkError(st, self.lib.pk_last_error(self.handle).decode())
+
+    def pk_ctx_set_timing(self, enable):
+        self._check(self.lib.pk_ctx_set_timing(self.handle, int(bool(enable))))
+
+    def stage_names(self):
+        return [self.lib.pk_stage_name(i).decode() for i in range(self.lib.pk_stage_count())]
+
+    def pk_ctx_stage_times(self):
+        n = self.lib.pk_stage_count()
+        arr = (ctypes.c_double * n)()
+        self._check(self.lib.pk_ctx_stage_times(self.handle, arr))
+        return dict(zip(self.stage_names(), list(arr)))
 
     def table_bytes(self):
         return int(self.lib.pk_ctx_table_bytes(self.handle))

@@ -285,6 +285,22 @@ pk_status get_scratch(pk_ctx* ctx, size_t bytes, double** out) {
   return PK_OK;
 }
 
+// Records the start event of a stage of pk_fftpower when timing is enabled.
+void mark_stage(pk_ctx* ctx, int stage) {
+  if (!ctx->timing) return;
+  (void)hipEventRecord(ctx->events[stage], ctx->stream);
+  ctx->stage_ran[stage] = true;
+}
+
+void mark_end(pk_ctx* ctx) {
+  if (!ctx->timing) return;
+  (void)hipEventRecord(ctx->events[kNumStages], ctx->stream);
+  ctx->timed_once = true;
+}
+
+const char* const kStageNames[kNumStages] = {"clear", "paint", "fft_z", "fft_y",
+                                             "xpass_bin", "plane_bin", "reduce"};
+
 // Workspace layout of pk_fftpower (offsets in bytes, 256-aligned).
 struct Layout {
   size_t mesh_a = 0, mesh_b = 0, side_a = 0, side_b = 0, partials = 0, total = 0;
@@ -358,6 +374,8 @@ void pk_ctx_destroy(pk_ctx* ctx) {
   for (auto& kv : ctx->mesh_tables) (void)hipFree(kv.second.dev);
   for (auto& kv : ctx->bin_tables) (void)hipFree(kv.second->e2_dev);
   if (ctx->scratch) (void)hipFree(ctx->scratch);
+  for (auto& ev : ctx->events)
+    if (ev) (void)hipEventDestroy(ev);
   delete ctx;
 }
 
@@ -495,21 +513,30 @@ pk_status pk_fftpower(pk_ctx* ctx, const pk_mesh_desc* m, const pk_bin_desc* b, 
   const size_t mbytes = pk_mesh_bytes(m);
   const int nm = m->interlaced ? 2 : 1;
   hipStream_t s = ctx->stream;
+  for (bool& r : ctx->stage_ran) r = false;
+  mark_stage(ctx, kClear);
   hipError_t e = launch_fill_zero(mesh_a, (l.mesh_b - l.mesh_a) * nm, s);
   if (e == hipSuccess) e = launch_fill_zero(wsums, 2 * sizeof(double), s);
+  mark_stage(ctx, kPaint);
   if (e == hipSuccess && n > 0)
     e = launch_paint_atomic(m->dtype, m->window, m->nmesh, m->boxsize, pos, weight, n, 0.0, mesh_a,
                             0.5, mesh_b, wsums, s);
   const size_t stride = l.mesh_b - l.mesh_a;
+  mark_stage(ctx, kFftZ);
   if (e == hipSuccess) e = launch_fft_z(m->dtype, m->nmesh, mesh_a, nm, stride, t->tw, wsums, s);
+  mark_stage(ctx, kFftY);
   if (e == hipSuccess) e = launch_fft_cols(m->dtype, m->nmesh, mesh_a, nm, stride, t->tw, 1, s);
+  mark_stage(ctx, kXpassBin);
   if (e == hipSuccess)
     e = launch_xpass_bin(m->dtype, m->nmesh, mesh_a, mesh_b, *t, m->window, m->compensated, spec,
                          partials, side_a, side_b, s);
+  mark_stage(ctx, kPlaneBin);
   if (e == hipSuccess)
     e = launch_plane_bin(m->dtype, m->nmesh, side_a, side_b, 1, *t, m->window, m->compensated,
                          spec, partials + (size_t)l.gx * spec.nsum, s);
+  mark_stage(ctx, kReduce);
   if (e == hipSuccess) e = launch_reduce(partials, l.gx + l.gp, spec, result_dev, s);
+  mark_end(ctx);
   (void)mbytes;
   if (e != hipSuccess) return dev_fail(ctx, e, "pk_fftpower");
   return PK_OK;
@@ -565,6 +592,46 @@ pk_status pk_result_to_host(pk_ctx* ctx, const pk_mesh_desc* m, const pk_bin_des
   out->wsum = wsum;
   out->w2sum = w2sum;
   out->shotnoise = volume * w2sum / (wsum * wsum);
+  return PK_OK;
+}
+
+pk_status pk_ctx_set_timing(pk_ctx* ctx, int enable) {
+  if (!ctx) return PK_EINVAL;
+  if (enable && ctx->device == PK_DEVICE_NONE)
+    return fail(ctx, PK_EDEVICE, "validation-only context");
+  if (enable && !ctx->events[0]) {
+    DeviceGuard g(ctx->device);
+    for (auto& ev : ctx->events) {
+      const hipError_t e = hipEventCreate(&ev);
+      if (e != hipSuccess) return dev_fail(ctx, e, "hipEventCreate");
+    }
+  }
+  ctx->timing = enable != 0;
+  return PK_OK;
+}
+
+int pk_stage_count(void) { return kNumStages; }
+
+const char* pk_stage_name(int stage) {
+  return (stage >= 0 && stage < kNumStages) ? kStageNames[stage] : nullptr;
+}
+
+pk_status pk_ctx_stage_times(pk_ctx* ctx, double* ms) {
+  if (!ctx || !ms) return PK_EINVAL;
+  if (!ctx->timed_once) return fail(ctx, PK_EINVAL, "no timed pk_fftpower call yet");
+  DeviceGuard g(ctx->device);
+  hipError_t e = hipEventSynchronize(ctx->events[kNumStages]);
+  if (e != hipSuccess) return dev_fail(ctx, e, "hipEventSynchronize");
+  for (int i = 0; i < kNumStages; ++i) {
+    ms[i] = 0.0;
+    if (!ctx->stage_ran[i]) continue;
+    int j = i + 1;
+    while (j < kNumStages && !ctx->stage_ran[j]) ++j;
+    float t = 0.f;
+    e = hipEventElapsedTime(&t, ctx->events[i], ctx->events[j]);
+    if (e != hipSuccess) return dev_fail(ctx, e, "hipEventElapsedTime");
+    ms[i] = t;
+  }
   return PK_OK;
 }
 

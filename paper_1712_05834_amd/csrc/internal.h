@@ -95,6 +95,11 @@ hipError_t launch_compensate(int dtype, int nmesh, void* cmesh, const void* cmes
 
 }  // namespace pk
 
+namespace pk {
+// Stages of pk_fftpower, in launch order (names returned by pk_stage_name).
+enum Stage { kClear = 0, kPaint, kFftZ, kFftY, kXpassBin, kPlaneBin, kReduce, kNumStages };
+}  // namespace pk
+
 struct pk_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
@@ -105,4 +110,8 @@ struct pk_ctx {
   std::map<BinKey, std::unique_ptr<pk::BinTables>> bin_tables;
   double* scratch = nullptr;  // plan-time scratch for the mode-table kernel
   size_t scratch_bytes = 0;
+  bool timing = false;
+  bool timed_once = false;
+  bool stage_ran[pk::kNumStages] = {};
+  hipEvent_t events[pk::kNumStages + 1] = {};
 };

@@ -101,10 +101,14 @@ def test_fft_r2c_matches_oracle(ctx, dtype, n):
     ctx.pk_fft_r2c(m, mesh)
     got = packing.unpack(packing.as_complex(mesh.cpu().numpy().astype(np.float64)))
     want = oracle.r2c(f.astype(NDT[dtype]).astype(np.float64))
+    # float32 FFT rounding grows like eps sqrt(log N) in the rms and a few
+    # times that in the maximum over N^3 / 2 modes
     rms = math.sqrt(np.mean(np.abs(want) ** 2))
-    tol = 1e-13 if dtype == "f8" else 1e-5
-    err = np.abs(got - want).max() / rms
-    assert err <= tol, f"max err / rms = {err:.3e}"
+    err_rms = math.sqrt(np.mean(np.abs(got - want) ** 2)) / rms
+    err_max = np.abs(got - want).max() / rms
+    tol_rms, tol_max = (1e-14, 1e-13) if dtype == "f8" else (1e-6, 3e-5)
+    print(f"n={n} {dtype}: rms err {err_rms:.2e}, max err {err_max:.2e} (relative to rms)")
+    assert err_rms <= tol_rms and err_max <= tol_max, (err_rms, err_max)
 
 
 def test_fft_r2c_plane_wave(ctx):

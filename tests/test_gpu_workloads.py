@@ -1,0 +1,109 @@
+"""GPU parity at the benchmark workloads' full sizes.
+
+* Log-normal mock, 512^3, TSC interlaced, float32, P(k, mu) with 5 mu bins
+  and ell = 0, 2, 4: the whole FFTPower result against the float64 oracle.
+* Zel'dovich lattice of 512^3 particles on a 1024^3 CIC interlaced float32
+  mesh: too large for the oracle's full run inside a test, so it is checked
+  on samples the oracle computes one by one (painted cells of both meshes),
+  on the exact mode counts and mean |k| of all 512 bins, and on properties
+  that hold at any size (mass conservation, Parseval of the r2c, finite
+  results of the fused path).
+"""
+
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1712_05834_amd import _lib, synth
+from tests.test_gpu_parity import check_power, dev
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = _lib.Context(0)
+    yield c
+    torch.cuda.synchronize()
+    c.close()
+
+
+def _fftpower(ctx, m, b, pos):
+    ws = torch.empty(_lib.workspace_bytes(m, b, len(pos)), dtype=torch.uint8, device="cuda:0")
+    res = torch.empty(_lib.result_doubles(b), dtype=torch.float64, device="cuda:0")
+    ctx.pk_fftpower(m, b, pos, None, len(pos), ws, res)
+    out = ctx.pk_result_to_host(m, b, res)
+    del ws
+    return out
+
+
+@pytest.mark.timeout(600)
+def test_lognormal_512_tsc_interlaced_full(ctx):
+    n, box = 512, 1380.0
+    pos = synth.lognormal_catalog(n, box, synth.pk_lognormal_c2, 1e7 / n ** 3, seed=2)
+    print(f"\nlognormal-512: {len(pos)} particles", flush=True)
+    m = _lib.mesh_desc(n, box, "tsc", True, True, "f4")
+    b = _lib.bin_desc(n // 2, 0.0, 1.0, 5, (0, 2, 4), 2)
+    got = _fftpower(ctx, m, b, dev(pos))
+    want = oracle.fftpower(pos.astype(np.float64), n, box, "tsc", True, True, nmu=5,
+                           poles=(0, 2, 4))
+    ok = want["modes"] > 0
+    rel = np.abs(got["power"][ok] / want["power"][ok] - 1)
+    print(f"max |dP/P| = {rel.max():.2e}", flush=True)
+    check_power(got, want, 1e-5, "lognormal-512")
+
+
+def _plane_cells(rng, n, x0, count):
+    cells = np.empty((count, 3), dtype=np.int64)
+    cells[:, 0] = x0
+    cells[:, 1:] = rng.integers(0, n, (count, 2))
+    return cells
+
+
+@pytest.mark.timeout(900)
+def test_zeldovich_1024_cic_interlaced_sampled(ctx):
+    n, box, ngrid = 1024, 2000.0, 512
+    pos = synth.zeldovich_lattice(ngrid, box, synth.pk_zeldovich_c3, seed=3)
+    print(f"\nzeldovich-1024: {len(pos)} particles", flush=True)
+    pos_d = dev(pos)
+    m = _lib.mesh_desc(n, box, "cic", True, True, "f4")
+    b = _lib.bin_desc(n // 2, 0.0, 1.0, 0, (0, 2), 2)
+    got = _fftpower(ctx, m, b, pos_d)
+    assert np.all(np.isfinite(got["power"][1:])) and np.all(np.isfinite(got["poles"][2][1:]))
+    assert got["shotnoise"] == pytest.approx(box ** 3 / len(pos), rel=1e-12)
+    tab = oracle.mode_tables(n, box, 0.0, 1.0, n // 2, interlaced=True)
+    np.testing.assert_array_equal(got["modes"], tab["modes"])
+    np.testing.assert_allclose(got["k"][1:], tab["k"][1:], rtol=1e-12)
+    print("counts ok", flush=True)
+
+    rng = np.random.default_rng(0)
+    u = oracle.cell_coordinates(pos.astype(np.float64), n, box)
+    mesh = torch.empty((n, n, n), dtype=torch.float32, device="cuda:0")
+    for shift in (0.0, 0.5):
+        ctx.pk_paint(m, pos_d, None, len(pos), shift, mesh, None)
+        total = float(mesh.sum(dtype=torch.float64))
+        assert abs(total / len(pos) - 1) < 1e-6, total
+        for x0 in (0, 517):
+            # only particles within one cell of the plane can reach it (CIC)
+            dx = u[:, 0] + shift - x0
+            dx -= n * np.round(dx / n)
+            near = np.abs(dx) < 1.0
+            cells = _plane_cells(rng, n, x0, 48)
+            want = oracle.paint_cells(pos[near].astype(np.float64), cells, n, box, 2,
+                                      shift_cells=shift)
+            idx = torch.from_numpy(cells).to("cuda:0")
+            gotc = mesh[idx[:, 0], idx[:, 1], idx[:, 2]].double().cpu().numpy()
+            np.testing.assert_allclose(gotc, want, rtol=0, atol=2e-6 * max(1.0, want.max()))
+        print(f"sampled cells ok (shift {shift})", flush=True)
+
+    # Parseval of the r2c on the painted mesh A: sum_modes h |c|^2 = N^3 sum F^2
+    ctx.pk_paint(m, pos_d, None, len(pos), 0.0, mesh, None)
+    f2 = float((mesh.double() ** 2).sum())
+    ctx.pk_fft_r2c(m, mesh)
+    c = mesh.view(n, n, n // 2, 2).double()
+    p = c[..., 0] ** 2 + c[..., 1] ** 2
+    lhs = float(p[:, :, 0].sum()) + 2.0 * float(p[:, :, 1:].sum())
+    assert abs(lhs / (n ** 3 * f2) - 1) < 1e-5, lhs / (n ** 3 * f2)

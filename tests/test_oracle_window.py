@@ -128,3 +128,15 @@ def test_wrap_handles_edges():
     got = oracle.wrap_positions(x, box)
     assert np.all(got >= 0) and np.all(got < box)
     np.testing.assert_allclose(got[:4], [0.0, 0.0, 0.0, 5.0])
+
+
+@pytest.mark.parametrize("order,shift", [(2, 0.0), (3, 0.5), (4, 0.0)])
+def test_paint_cells_matches_brute_force(order, shift):
+    n, box = 6, 10.0
+    rng = np.random.default_rng(40 + order)
+    pos = rng.uniform(-3, 13, (9, 3))
+    w = rng.uniform(0.5, 2.0, 9)
+    want = _brute_paint(pos, w, n, box, order, shift)
+    cells = rng.integers(0, n, (25, 3))
+    got = oracle.paint_cells(pos, cells, n, box, order, weight=w, shift_cells=shift)
+    np.testing.assert_allclose(got, want[cells[:, 0], cells[:, 1], cells[:, 2]], atol=1e-13)
