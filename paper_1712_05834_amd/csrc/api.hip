@@ -196,6 +196,15 @@ BinSpec make_spec(const pk_mesh_desc* m, const pk_bin_desc* b, const double* e2_
   s.kmin_f = b->kmin_f;
   s.dk_f = b->dk_f;
   s.e2 = e2_dev;
+  // Whole-number edges e_b = kmin + b dk: e_b^2 <= n^2 iff e_b <= isqrt(n^2),
+  // so the bin follows from the integer square root alone.
+  const double lim = 1 << 20;
+  if (b->kmin_f == std::floor(b->kmin_f) && b->dk_f == std::floor(b->dk_f) && b->kmin_f < lim &&
+      b->dk_f < lim) {
+    s.int_edges = 1;
+    s.kmin_i = (int)b->kmin_f;
+    s.dk_i = (int)b->dk_f;
+  }
   return s;
 }
 
@@ -298,21 +307,24 @@ void mark_end(pk_ctx* ctx) {
   ctx->timed_once = true;
 }
 
-const char* const kStageNames[kNumStages] = {"clear", "paint", "fft_z", "fft_y",
+const char* const kStageNames[kNumStages] = {"bucket", "paint_z", "fft_y",
                                              "xpass_bin", "plane_bin", "reduce"};
 
 // Workspace layout of pk_fftpower (offsets in bytes, 256-aligned).
 struct Layout {
-  size_t mesh_a = 0, mesh_b = 0, side_a = 0, side_b = 0, partials = 0, total = 0;
+  size_t mesh_a = 0, mesh_b = 0, side_a = 0, side_b = 0, partials = 0, bucket = 0, rec = 0,
+         wrec = 0, total = 0;
   int gx = 0, gp = 0;
 };
 
-Layout layout_of(const pk_mesh_desc* m, const pk_bin_desc* b) {
+Layout layout_of(const pk_mesh_desc* m, const pk_bin_desc* b, int64_t npart) {
   Layout l;
   const size_t n = (size_t)m->nmesh;
-  const size_t mesh = align256(n * n * n * elem_bytes(m));
-  const size_t side = align256(n * n * 2 * elem_bytes(m));
+  const size_t es = elem_bytes(m);
+  const size_t mesh = align256(n * n * n * es);
+  const size_t side = align256(n * n * 2 * es);
   const int two = m->interlaced ? 1 : 0;
+  const size_t np = npart > 0 ? (size_t)npart : 0;
   l.gx = xpass_bin_groups(m->dtype, m->nmesh);
   l.gp = plane_bin_groups(m->nmesh);
   size_t off = 0;
@@ -326,6 +338,12 @@ Layout layout_of(const pk_mesh_desc* m, const pk_bin_desc* b) {
   off += two * side;
   l.partials = off;
   off += align256((size_t)(l.gx + l.gp) * nsum_of(b) * sizeof(double));
+  l.bucket = off;
+  off += align256(bucket_bytes(m->nmesh));
+  l.rec = off;
+  off += align256(np * 4 * es);  // one 4-vector record per particle
+  l.wrec = off;
+  off += align256(np * es);
   l.total = off;
   return l;
 }
@@ -397,7 +415,8 @@ size_t pk_result_doubles(const pk_bin_desc* b) {
 size_t pk_workspace_bytes(const pk_mesh_desc* m, const pk_bin_desc* b, int64_t npart) {
   (void)npart;
   if (check_mesh(m) || check_bins(b, m)) return 0;
-  return layout_of(m, b).total;
+  if (npart < 0) return 0;
+  return layout_of(m, b, npart).total;
 }
 
 size_t pk_ctx_table_bytes(const pk_ctx* ctx) { return ctx ? ctx->table_bytes : 0; }
@@ -493,7 +512,7 @@ pk_status pk_fftpower(pk_ctx* ctx, const pk_mesh_desc* m, const pk_bin_desc* b, 
   if (n < 0) return fail(ctx, PK_EINVAL, "n must be >= 0");
   if (n > 0 && !pos) return fail(ctx, PK_EINVAL, "pos is NULL with n > 0");
   if (!workspace || !result_dev) return fail(ctx, PK_EINVAL, "workspace or result is NULL");
-  const Layout l = layout_of(m, b);
+  const Layout l = layout_of(m, b, n);
   if (workspace_bytes < l.total) return fail(ctx, PK_EINVAL, "workspace too small");
   if (const char* why = check_lds(b)) return fail(ctx, PK_EUNSUPPORTED, why);
   if (ctx->device == PK_DEVICE_NONE) return fail(ctx, PK_EDEVICE, "validation-only context");
@@ -510,20 +529,19 @@ pk_status pk_fftpower(pk_ctx* ctx, const pk_mesh_desc* m, const pk_bin_desc* b, 
   void* side_b = m->interlaced ? ws + l.side_b : nullptr;
   double* partials = reinterpret_cast<double*>(ws + l.partials);
   double* wsums = result_dev + spec.nsum;
-  const size_t mbytes = pk_mesh_bytes(m);
   const int nm = m->interlaced ? 2 : 1;
   hipStream_t s = ctx->stream;
   for (bool& r : ctx->stage_ran) r = false;
-  mark_stage(ctx, kClear);
-  hipError_t e = launch_fill_zero(mesh_a, (l.mesh_b - l.mesh_a) * nm, s);
-  if (e == hipSuccess) e = launch_fill_zero(wsums, 2 * sizeof(double), s);
-  mark_stage(ctx, kPaint);
-  if (e == hipSuccess && n > 0)
-    e = launch_paint_atomic(m->dtype, m->window, m->nmesh, m->boxsize, pos, weight, n, 0.0, mesh_a,
-                            0.5, mesh_b, wsums, s);
   const size_t stride = l.mesh_b - l.mesh_a;
-  mark_stage(ctx, kFftZ);
-  if (e == hipSuccess) e = launch_fft_z(m->dtype, m->nmesh, mesh_a, nm, stride, t->tw, wsums, s);
+  void* rec = ws + l.rec;
+  void* wrec = weight ? ws + l.wrec : nullptr;
+  mark_stage(ctx, kBucket);
+  hipError_t e = launch_bucket(m->dtype, m->nmesh, m->boxsize, pos, weight, n, ws + l.bucket, rec,
+                               wrec, wsums, s);
+  mark_stage(ctx, kPaintZ);
+  if (e == hipSuccess)
+    e = launch_paint_z(m->dtype, m->nmesh, m->window, m->interlaced != 0, rec, wrec,
+                       ws + l.bucket, wsums, t->tw, mesh_a, mesh_b, s);
   mark_stage(ctx, kFftY);
   if (e == hipSuccess) e = launch_fft_cols(m->dtype, m->nmesh, mesh_a, nm, stride, t->tw, 1, s);
   mark_stage(ctx, kXpassBin);
@@ -537,7 +555,6 @@ pk_status pk_fftpower(pk_ctx* ctx, const pk_mesh_desc* m, const pk_bin_desc* b, 
   mark_stage(ctx, kReduce);
   if (e == hipSuccess) e = launch_reduce(partials, l.gx + l.gp, spec, result_dev, s);
   mark_end(ctx);
-  (void)mbytes;
   if (e != hipSuccess) return dev_fail(ctx, e, "pk_fftpower");
   return PK_OK;
 }

@@ -17,11 +17,27 @@
 
 namespace pk {
 
+// Exact integer square root of 0 <= v < 2^24 (v converts to float exactly;
+// the float root is within one unit of the answer and is corrected).
+__device__ __forceinline__ int isqrt_exact(int v) {
+  int s = (int)sqrtf((float)v);
+  if (s * s > v) --s;
+  if ((s + 1) * (s + 1) <= v) ++s;
+  return s;
+}
+
 // Largest b with e_b^2 <= n^2 among the nk bins, -1 for the DC mode and for
-// modes outside [e_0, e_nk).  A float estimate is corrected with exact
-// comparisons of the integer n^2 against the float64 table e2.
+// modes outside [e_0, e_nk).  Whole-number edges use the integer root; other
+// edges correct a float estimate with exact comparisons of the integer n^2
+// against the float64 table e2.
 __device__ __forceinline__ int kbin_of(int n2, const BinSpec& b) {
   if (n2 == 0) return -1;
+  if (b.int_edges) {
+    const int s = isqrt_exact(n2) - b.kmin_i;
+    if (s < 0) return -1;
+    const int k = b.dk_i == 1 ? s : s / b.dk_i;
+    return k < b.nk ? k : -1;
+  }
   const double x = (double)n2;
   const double* __restrict__ e2 = b.e2;
   if (x < e2[0] || x >= e2[b.nk]) return -1;
@@ -32,14 +48,14 @@ __device__ __forceinline__ int kbin_of(int n2, const BinSpec& b) {
   return k;
 }
 
-// Largest j in [0, nmu] with j^2 n^2 <= nmu^2 n_los^2, clipped to nmu - 1.
-// The products are integers below 2^53, exact in float64.
+// Largest j in [0, nmu] with j^2 n^2 <= nmu^2 n_los^2, clipped to nmu - 1;
+// a float estimate corrected with exact 64-bit integer products.
 __device__ __forceinline__ int mubin_of(int nlos2, int n2, int nmu) {
-  const double rhs = (double)nmu * (double)nmu * (double)nlos2;
-  int j = (int)((float)nmu * sqrtf((float)nlos2 / (float)n2));
+  const unsigned long long rhs = (unsigned long long)(nmu * nmu) * (unsigned)nlos2;
+  int j = (int)((float)nmu * sqrtf(__fdividef((float)nlos2, (float)n2)));
   j = j < 0 ? 0 : (j > nmu ? nmu : j);
-  while (j < nmu && (double)(j + 1) * (double)(j + 1) * (double)n2 <= rhs) ++j;
-  while (j > 0 && (double)j * (double)j * (double)n2 > rhs) --j;
+  while (j < nmu && (unsigned long long)((j + 1) * (j + 1)) * (unsigned)n2 <= rhs) ++j;
+  while (j > 0 && (unsigned long long)(j * j) * (unsigned)n2 > rhs) --j;
   return j < nmu ? j : nmu - 1;
 }
 
@@ -50,6 +66,17 @@ __device__ __forceinline__ T legendre(int ell, T mu2) {
   return (((T(231) * mu2 - T(315)) * mu2 + T(105)) * mu2 - T(5)) * T(0.0625);
 }
 
+// mu^2 = n_los^2 / n^2 in the path's precision (float: fast reciprocal,
+// ~1 ulp; double: correctly rounded division).
+template <typename T>
+__device__ __forceinline__ T ratio(int a, int b) {
+  if constexpr (sizeof(T) == 4) {
+    return __fdividef((float)a, (float)b);
+  } else {
+    return (double)a / (double)b;
+  }
+}
+
 // Adds one mode of (Hermitian-weighted) power hp to the LDS bins.
 template <typename T>
 __device__ __forceinline__ void accumulate(double* sb, const BinSpec& b, int n2, int nlos2,
@@ -58,7 +85,7 @@ __device__ __forceinline__ void accumulate(double* sb, const BinSpec& b, int n2,
   if (k < 0) return;
   atomicAdd(&sb[k], hp);
   if (b.npl > 0) {
-    const T mu2 = static_cast<T>(nlos2) / static_cast<T>(n2);
+    const T mu2 = ratio<T>(nlos2, n2);
     for (int i = 0; i < b.npl; ++i)
       atomicAdd(&sb[b.pole_slot[i] + k], hp * (double)legendre<T>(b.pole_ell[i], mu2));
   }
@@ -90,6 +117,17 @@ __global__ void __launch_bounds__((ColCfg<T, N>::THREADS))
   const int c = threadIdx.x % C, t = threadIdx.x / C;
   const int los = b.los;
   const bool two = mesh_b != nullptr;
+  // x-dependent factors of this thread's modes kx = t + TPL e (the same for
+  // every tile): interlacing phase exp(i pi n_x / N) and sinc^-p(pi n_x / N)
+  const cpx<T>* __restrict__ ph1 = phase + 3 * (N / 2);  // ph1[n] = exp(i pi n / N)
+  cpx<T> phx[E];
+  T sx[E];
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const int nx = signed_index(t + TPL * e, N);
+    phx[e] = two ? ph1[nx] : cpx<T>{T(1), T(0)};
+    sx[e] = sinv ? sinv[t + TPL * e] : T(1);
+  }
   LdsCols<T, C> lc{lds, c};
   for (int tile = blockIdx.x; tile < N * CHUNKS; tile += gridDim.x) {
     const int ky = tile / CHUNKS;
@@ -117,23 +155,23 @@ __global__ void __launch_bounds__((ColCfg<T, N>::THREADS))
     }
     const int ny = signed_index(ky, N);
     const int nz = col;
-    const T syz = sinv ? sinv[ky] * sinv[col] : T(1);
+    const int syz = ny * ny + nz * nz;
+    const cpx<T> phyz = two ? cmul(ph1[ny], ph1[nz]) : cpx<T>{T(1), T(0)};
+    const T s_yz = sinv ? sinv[ky] * sinv[col] : T(1);
 #pragma unroll
     for (int e = 0; e < E; ++e) {
-      const int kx = t + TPL * e;
-      const int nx = signed_index(kx, N);
+      const int nx = signed_index(t + TPL * e, N);
       cpx<T> cc = va[e];
       if (two) {
-        const cpx<T> ph = phase[nx + ny + nz + 3 * (N / 2)];
-        const cpx<T> bb = cmul(ph, vb[e]);
+        const cpx<T> bb = cmul(cmul(phx[e], phyz), vb[e]);
         cc = {T(0.5) * (cc.x + bb.x), T(0.5) * (cc.y + bb.y)};
       }
       T pw = cc.x * cc.x + cc.y * cc.y;
       if (sinv) {
-        const T s = sinv[kx] * syz;
+        const T s = sx[e] * s_yz;
         pw *= s * s;
       }
-      const int n2 = nx * nx + ny * ny + nz * nz;
+      const int n2 = nx * nx + syz;
       const int nl = los == 0 ? nx : (los == 1 ? ny : nz);
       accumulate<T>(sb, b, n2, nl * nl, 2.0 * (double)pw);
     }
@@ -222,20 +260,34 @@ __global__ void __launch_bounds__(256)
   flush_bins(sb, b.nsum, partials + (size_t)blockIdx.x * b.nsum);
 }
 
-// result[s] = sum_g partials[g][src(s)] in order g = 0, 1, ...; the slots of
-// an ell = 0 pole take the sum of the plain power slots.
-__global__ void k_reduce(const double* __restrict__ partials, int ngroups, BinSpec b,
-                         double* __restrict__ result) {
-  const int s = blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= b.nsum) return;
-  int src = s;
-  if (s >= b.nk && s < b.nk * (1 + b.npoles)) {
-    const int pi = s / b.nk - 1;
-    if ((b.zero_mask >> pi) & 1) src = s % b.nk;
-  }
+// result[s] = sum_g partials[g][src(s)]; the slots of an ell = 0 pole take
+// the sum of the plain power slots.  64 slots per workgroup, 16 lanes per
+// slot: lane l sums the rows g = l, l + 16, ... in increasing g, then the 16
+// lane sums are added in lane order -- a fixed order, so the result depends
+// only on the partial rows.
+__global__ void __launch_bounds__(1024)
+    k_reduce(const double* __restrict__ partials, int ngroups, BinSpec b,
+             double* __restrict__ result) {
+  __shared__ double part[16][64];
+  const int slot_in = threadIdx.x & 63, lane = threadIdx.x >> 6;
+  const int s = blockIdx.x * 64 + slot_in;
   double acc = 0.0;
-  for (int g = 0; g < ngroups; ++g) acc += partials[(size_t)g * b.nsum + src];
-  result[s] = acc;
+  if (s < b.nsum) {
+    int src = s;
+    if (s >= b.nk && s < b.nk * (1 + b.npoles)) {
+      const int pi = s / b.nk - 1;
+      if ((b.zero_mask >> pi) & 1) src = s % b.nk;
+    }
+    for (int g = lane; g < ngroups; g += 16) acc += partials[(size_t)g * b.nsum + src];
+  }
+  part[lane][slot_in] = acc;
+  __syncthreads();
+  if (lane == 0 && s < b.nsum) {
+    double tot = 0.0;
+#pragma unroll
+    for (int l = 0; l < 16; ++l) tot += part[l][slot_in];
+    result[s] = tot;
+  }
 }
 
 // Plan time: per-bin counts (integers), sum h|n| and, for (k, mu) bins, counts,
@@ -470,8 +522,8 @@ hipError_t launch_plane_bin(int dtype, int nmesh, const void* za, const void* zb
 
 hipError_t launch_reduce(const double* partials, int ngroups, const BinSpec& b, double* result,
                          hipStream_t s) {
-  const int blocks = (b.nsum + 255) / 256;
-  hipLaunchKernelGGL(k_reduce, dim3(blocks), dim3(256), 0, s, partials, ngroups, b, result);
+  const int blocks = (b.nsum + 63) / 64;
+  hipLaunchKernelGGL(k_reduce, dim3(blocks), dim3(1024), 0, s, partials, ngroups, b, result);
   return hipGetLastError();
 }
 

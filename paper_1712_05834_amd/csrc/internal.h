@@ -55,6 +55,9 @@ struct BinSpec {
   double kmin_f = 0.0;
   double dk_f = 1.0;
   const double* e2 = nullptr;  // device, nk + 1
+  int int_edges = 0;    // kmin_f and dk_f are whole numbers: exact integer rule
+  int kmin_i = 0;
+  int dk_i = 1;
 };
 
 // Mode-table accumulator layout (plan time):
@@ -67,6 +70,15 @@ hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t s);
 hipError_t launch_paint_atomic(int dtype, int order, int nmesh, double boxsize, const void* pos,
                                const void* weight, int64_t n, double shift_a, void* mesh_a,
                                double shift_b, void* mesh_b, double* wsums, hipStream_t s);
+
+// Sorted painting fused with the z-pass (paint_sorted.hip).
+size_t bucket_bytes(int nmesh);
+hipError_t launch_bucket(int dtype, int nmesh, double boxsize, const void* pos, const void* weight,
+                         int64_t n, void* bucket_ws, void* rec, void* wrec, double* wsums,
+                         hipStream_t s);
+hipError_t launch_paint_z(int dtype, int nmesh, int order, bool inter, const void* rec,
+                          const void* wrec, const void* bucket_ws, const double* wsums,
+                          const void* tw, void* mesh_a, void* mesh_b, hipStream_t s);
 
 hipError_t launch_fft_z(int dtype, int nmesh, void* mesh, int nmeshes, size_t mesh_stride_bytes,
                         const void* tw, const double* wsum_for_mean, hipStream_t s);
@@ -97,7 +109,7 @@ hipError_t launch_compensate(int dtype, int nmesh, void* cmesh, const void* cmes
 
 namespace pk {
 // Stages of pk_fftpower, in launch order (names returned by pk_stage_name).
-enum Stage { kClear = 0, kPaint, kFftZ, kFftY, kXpassBin, kPlaneBin, kReduce, kNumStages };
+enum Stage { kBucket = 0, kPaintZ, kFftY, kXpassBin, kPlaneBin, kReduce, kNumStages };
 }  // namespace pk
 
 struct pk_ctx {

@@ -1,0 +1,495 @@
+// Painting fused with the first FFT pass (Sec. 3.3.1 Eq. 1, Sec. 3.3.2
+// windows and interlacing; r2c along z).
+//
+// 1. k_bucket_count   per particle: its column (ix, iy) = floor(u_x, u_y); the
+//                     column counts are accumulated with one atomic per run of
+//                     equal columns in a wavefront; sum w and sum w^2 in float64.
+// 2. k_scan_*         exclusive prefix sum of the N^2 column counts.
+// 3. k_bucket_scatter per particle: a 16-byte record {t_x, t_y, t_z, iy<<16|iz}
+//                     (fractional offsets from the cell, split off in float64)
+//                     written to its column's segment.
+// 4. k_paint_z        one workgroup owns a TX x TY block of full z-columns of
+//                     both meshes: it reads the records of the columns whose
+//                     windows reach the block, adds the window weights into LDS
+//                     (ds_add), then runs the r2c FFT of every column in LDS
+//                     and writes the packed rows once.  No mesh clear, no
+//                     atomics to HBM, no separate z-pass.
+#include "fft_config.h"
+#include "internal.h"
+#include "window.h"
+
+namespace pk {
+
+template <typename T>
+struct Rec;
+template <>
+struct Rec<float> {
+  using type = float4;
+};
+template <>
+struct Rec<double> {
+  using type = double4;
+};
+
+__device__ __forceinline__ double wave_sum_d(double v) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// Runs of equal keys among consecutive lanes of a wavefront: the head lane of
+// each run adds the run length to counter[key] with one atomic; every lane
+// gets its slot = old value + its offset in the run.  Lanes with key < 0 take
+// no slot.
+__device__ __forceinline__ int claim_slot(int key, int* __restrict__ counter) {
+  const int lane = threadIdx.x & 63;
+  const int prev = __shfl_up(key, 1, 64);
+  const bool valid = key >= 0;
+  const bool head = valid && (lane == 0 || prev != key);
+  const unsigned long long heads = __ballot(head);
+  const unsigned long long valids = __ballot(valid);
+  // head lane of my run: highest head at or below me
+  const unsigned long long below = heads & ((2ull << lane) - 1ull);
+  const int my_head = below ? 63 - __clzll(below) : lane;
+  // run length for a head: up to the next head or the first invalid lane
+  int len = 0;
+  if (head) {
+    const unsigned long long above = (heads | ~valids) & ~((2ull << lane) - 1ull);
+    const int next = above ? __ffsll(above) - 1 : 64;
+    len = next - lane;
+  }
+  int old = 0;
+  if (head) old = atomicAdd(&counter[key], len);
+  const int base = __shfl(old, my_head, 64);
+  return valid ? base + (lane - my_head) : -1;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256)
+    k_bucket_count(const T* __restrict__ pos, const T* __restrict__ weight, int64_t n, int nmesh,
+                   double boxsize, int* __restrict__ count, double* __restrict__ wsums) {
+  const int mask = nmesh - 1;
+  double ws = 0.0, ws2 = 0.0;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  // whole wavefronts iterate together so that claim_slot sees full waves
+  const int64_t nround = (n + stride - 1) / stride * stride;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nround; i += stride) {
+    int key = -1;
+    if (i < n) {
+      const double ux = cell_coordinate((double)pos[3 * i], nmesh, boxsize);
+      const double uy = cell_coordinate((double)pos[3 * i + 1], nmesh, boxsize);
+      key = (((int)floor(ux)) & mask) * nmesh + (((int)floor(uy)) & mask);
+      const double wp = weight ? (double)weight[i] : 1.0;
+      ws += wp;
+      ws2 += wp * wp;
+    }
+    (void)claim_slot(key, count);
+  }
+  ws = wave_sum_d(ws);
+  ws2 = wave_sum_d(ws2);
+  if ((threadIdx.x & 63) == 0) {
+    atomicAdd(&wsums[0], ws);
+    atomicAdd(&wsums[1], ws2);
+  }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256)
+    k_bucket_scatter(const T* __restrict__ pos, const T* __restrict__ weight, int64_t n,
+                     int nmesh, double boxsize, int* __restrict__ cursor,
+                     typename Rec<T>::type* __restrict__ rec, T* __restrict__ wrec) {
+  const int mask = nmesh - 1;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const int64_t nround = (n + stride - 1) / stride * stride;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nround; i += stride) {
+    int key = -1;
+    double u[3] = {0.0, 0.0, 0.0}, f[3] = {0.0, 0.0, 0.0};
+    if (i < n) {
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        u[d] = cell_coordinate((double)pos[3 * i + d], nmesh, boxsize);
+        f[d] = floor(u[d]);
+      }
+      key = (((int)f[0]) & mask) * nmesh + (((int)f[1]) & mask);
+    }
+    const int slot = claim_slot(key, cursor);
+    if (i < n) {
+      const unsigned iy = ((unsigned)(int)f[1]) & mask, iz = ((unsigned)(int)f[2]) & mask;
+      typename Rec<T>::type r;
+      r.x = static_cast<T>(u[0] - f[0]);
+      r.y = static_cast<T>(u[1] - f[1]);
+      r.z = static_cast<T>(u[2] - f[2]);
+      if constexpr (sizeof(T) == 4) {
+        r.w = __uint_as_float((iy << 16) | iz);
+      } else {
+        r.w = (double)((iy << 16) | iz);
+      }
+      rec[slot] = r;
+      if (wrec) wrec[slot] = weight[i];
+    }
+  }
+}
+
+// ---- exclusive scan of the column counts (3 phases, 4096 entries per block)
+
+__device__ __forceinline__ int block_scan_excl(int v, int* sh, int& total) {
+  // 1024 threads; inclusive wave scan, then scan of the 16 wave totals
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  int x = v;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const int y = __shfl_up(x, off, 64);
+    if (lane >= off) x += y;
+  }
+  if (lane == 63) sh[wave] = x;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int acc = 0;
+    for (int w = 0; w < 16; ++w) {
+      const int t = sh[w];
+      sh[w] = acc;
+      acc += t;
+    }
+    sh[16] = acc;
+  }
+  __syncthreads();
+  total = sh[16];
+  const int r = sh[wave] + x - v;
+  __syncthreads();
+  return r;
+}
+
+__global__ void __launch_bounds__(1024)
+    k_scan_blocks(const int* __restrict__ count, int n, int* __restrict__ block_sums) {
+  __shared__ int sh[17];
+  const int base = blockIdx.x * 4096 + threadIdx.x * 4;
+  int s = 0;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) s += (base + j < n) ? count[base + j] : 0;
+  int total;
+  (void)block_scan_excl(s, sh, total);
+  if (threadIdx.x == 0) block_sums[blockIdx.x] = total;
+}
+
+__global__ void __launch_bounds__(1024) k_scan_sums(int* __restrict__ block_sums, int nb) {
+  __shared__ int sh[17];
+  int carry = 0;
+  for (int start = 0; start < nb; start += 1024) {
+    const int i = start + threadIdx.x;
+    const int v = i < nb ? block_sums[i] : 0;
+    int total;
+    const int ex = block_scan_excl(v, sh, total);
+    if (i < nb) block_sums[i] = carry + ex;
+    carry += total;
+  }
+}
+
+__global__ void __launch_bounds__(1024)
+    k_scan_final(const int* __restrict__ count, int n, const int* __restrict__ block_sums,
+                 int* __restrict__ offsets, int* __restrict__ cursor) {
+  __shared__ int sh[17];
+  const int base = blockIdx.x * 4096 + threadIdx.x * 4;
+  int v[4];
+  int s = 0;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    v[j] = (base + j < n) ? count[base + j] : 0;
+    s += v[j];
+  }
+  int total;
+  int ex = block_scan_excl(s, sh, total) + block_sums[blockIdx.x];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    if (base + j < n) {
+      offsets[base + j] = ex;
+      cursor[base + j] = ex;
+    }
+    ex += v[j];
+  }
+  if (blockIdx.x == gridDim.x - 1 && threadIdx.x == blockDim.x - 1) offsets[n] = ex;
+}
+
+// ---- fused paint + r2c z-pass
+
+// Columns per workgroup (TX x TY) and halo of source columns per mesh size.
+template <typename T, int N, int P, bool INTER>
+struct PaintCfg {
+  static constexpr int M = N / 2;
+  static constexpr int E = M < e_max<T>() ? M : e_max<T>();
+  static constexpr int TPL = M / E;
+  static constexpr int LP = lds_pad_len<M>();           // complex per LDS row
+  static constexpr int NM = INTER ? 2 : 1;
+  static constexpr long ROW_BYTES = (long)LP * 2 * sizeof(T);
+  static constexpr int pick_cols() {
+    int cols = 64;
+    while (cols > 1 && (long)cols * NM * ROW_BYTES > 144 * 1024) cols /= 2;
+    while (cols > 1 && (long)cols * NM * TPL > 1024) cols /= 2;
+    return cols;
+  }
+  static constexpr int COLS = pick_cols();
+  static constexpr int TX0 = COLS >= 16 ? 4 : (COLS >= 4 ? 2 : 1);
+  static constexpr int TX = COLS / TX0 > N ? COLS / N : TX0;
+  static constexpr int TY = COLS / TX;
+  static_assert(TX <= N && TY <= N && TX * TY == COLS, "column block must fit the mesh");
+  static constexpr int ROWS = NM * TX * TY;
+  static constexpr int THREADS = ROWS * TPL;
+  // source columns that can reach an owned column: [X - HLO, X + HHI]
+  static constexpr int HLO = P == 2 ? (INTER ? 2 : 1) : (P == 3 ? 2 : (INTER ? 3 : 2));
+  static constexpr int HHI = P == 2 ? 0 : 1;
+};
+
+// Float address of cell z inside a padded LDS row (complex index z / 2 with
+// one pad slot every 16 complex).
+__device__ __forceinline__ int zaddr(int z) {
+  const int j = z >> 1;
+  return ((j + (j >> 4)) << 1) | (z & 1);
+}
+
+template <typename T, int N, int P, bool INTER>
+__global__ void __launch_bounds__((PaintCfg<T, N, P, INTER>::THREADS))
+    k_paint_z(const typename Rec<T>::type* __restrict__ rec, const T* __restrict__ wrec,
+              const int* __restrict__ offsets, const double* __restrict__ wsums,
+              const cpx<T>* __restrict__ tw, T* __restrict__ mesh_a, T* __restrict__ mesh_b) {
+  using Cf = PaintCfg<T, N, P, INTER>;
+  constexpr int M = Cf::M, E = Cf::E, TPL = Cf::TPL, LP = Cf::LP, TX = Cf::TX, TY = Cf::TY;
+  constexpr int ROWS = Cf::ROWS;
+  constexpr int mask = N - 1;
+  __shared__ cpx<T> lds[ROWS * LP];
+  __shared__ int seg_start[2 * (TX + 4)], seg_cum[2 * (TX + 4) + 1], seg_row[2 * (TX + 4)];
+  __shared__ int nseg_sh;
+  T* ldsf = reinterpret_cast<T*>(lds);
+
+  const int tiles_y = N / TY;
+  const int X0 = (blockIdx.x / tiles_y) * TX, Y0 = (blockIdx.x % tiles_y) * TY;
+
+  for (int i = threadIdx.x; i < ROWS * LP * 2; i += blockDim.x) ldsf[i] = T(0);
+
+  // segments of the sorted records: for each source row bx, the contiguous
+  // column range [by0, by0 + wy) (split where it wraps around N)
+  if (threadIdx.x == 0) {
+    const int wx = (TX + Cf::HLO + Cf::HHI) >= N ? N : TX + Cf::HLO + Cf::HHI;
+    const int bx0 = (TX + Cf::HLO + Cf::HHI) >= N ? 0 : X0 - Cf::HLO;
+    const int wy = (TY + Cf::HLO + Cf::HHI) >= N ? N : TY + Cf::HLO + Cf::HHI;
+    const int by0 = (TY + Cf::HLO + Cf::HHI) >= N ? 0 : Y0 - Cf::HLO;
+    int ns = 0, cum = 0;
+    for (int r = 0; r < wx; ++r) {
+      const int bx = (bx0 + r) & mask;
+      int y = (by0 % N + N) % N;
+      int left = wy;
+      while (left > 0) {
+        const int run = (N - y) < left ? (N - y) : left;
+        const int b0 = bx * N + y;
+        const int s0 = offsets[b0], s1 = offsets[b0 + run];
+        seg_start[ns] = s0;
+        seg_row[ns] = bx;
+        seg_cum[ns] = cum;
+        cum += s1 - s0;
+        ++ns;
+        left -= run;
+        y = 0;
+      }
+    }
+    seg_cum[ns] = cum;
+    nseg_sh = ns;
+  }
+  __syncthreads();
+
+  // scatter-add of the window weights of every source particle into the
+  // owned cells of both meshes
+  const int nseg = nseg_sh;
+  const int total = seg_cum[nseg];
+  for (int q = threadIdx.x; q < total; q += blockDim.x) {
+    int s = 0;
+    while (s + 1 < nseg && seg_cum[s + 1] <= q) ++s;
+    const int idx = seg_start[s] + (q - seg_cum[s]);
+    const auto r = rec[idx];
+    const T wp = wrec ? wrec[idx] : T(1);
+    unsigned packed;
+    if constexpr (sizeof(T) == 4) {
+      packed = __float_as_uint(r.w);
+    } else {
+      packed = (unsigned)r.w;
+    }
+    const int ix = seg_row[s], iy = (int)(packed >> 16), iz = (int)(packed & 0xffff);
+    const T t3[3] = {r.x, r.y, r.z};
+    const int i3[3] = {ix, iy, iz};
+#pragma unroll
+    for (int mesh = 0; mesh < (INTER ? 2 : 1); ++mesh) {
+      int first[3];
+      T w[3][P];
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        // window of u = i + t (+ 1/2 for the interlaced mesh)
+        T tt = t3[d];
+        int base = i3[d];
+        if (mesh == 1) {
+          if (tt >= T(0.5)) {
+            tt -= T(0.5);  // exact
+            base += 1;
+          } else {
+            tt += T(0.5);
+          }
+        }
+        window_frac<T, P>(tt, base, first[d], w[d]);
+      }
+#pragma unroll
+      for (int a = 0; a < P; ++a) {
+        const int lx = (first[0] + a - X0) & mask;
+        if (lx >= TX) continue;
+        const T wa = wp * w[0][a];
+#pragma unroll
+        for (int b2 = 0; b2 < P; ++b2) {
+          const int ly = (first[1] + b2 - Y0) & mask;
+          if (ly >= TY) continue;
+          const T wab = wa * w[1][b2];
+          T* row = ldsf + (size_t)((mesh * TX + lx) * TY + ly) * (LP * 2);
+#pragma unroll
+          for (int c = 0; c < P; ++c) atomicAdd(&row[zaddr((first[2] + c) & mask)], wab * w[2][c]);
+        }
+      }
+    }
+  }
+  __syncthreads();
+
+  // r2c along z of every owned column, mean subtracted (only the DC mode
+  // changes; it keeps float rounding relative to the fluctuations)
+  const T mean = static_cast<T>(wsums[0] / ((double)N * N * N));
+  const int r = threadIdx.x / TPL, t = threadIdx.x % TPL;
+  LdsLine<T> line{lds + r * LP};
+  cpx<T> v[E];
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    v[e] = line.get(t + TPL * e);
+    v[e].x -= mean;
+    v[e].y -= mean;
+  }
+  stockham<T, M, E, 1>(v, t, tw, 2, line);
+  __syncthreads();
+#pragma unroll
+  for (int e = 0; e < E; ++e) line.put(t + TPL * e, v[e]);
+  __syncthreads();
+  const int mesh = r / (TX * TY), lx = (r / TY) % TX, ly = r % TY;
+  T* out = mesh == 0 ? mesh_a : mesh_b;
+  cpx<T>* rowp = reinterpret_cast<cpx<T>*>(out + ((size_t)(X0 + lx) * N + (Y0 + ly)) * N);
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const int k = t + TPL * e;
+    cpx<T> o;
+    if (k == 0) {
+      o = {v[e].x + v[e].y, v[e].x - v[e].y};
+    } else {
+      const cpx<T> zc = cconj(line.get(M - k));
+      const cpx<T> s = cadd(v[e], zc);
+      const cpx<T> w = cmul(tw[k], csub(v[e], zc));
+      o = {T(0.5) * (s.x + w.y), T(0.5) * (s.y - w.x)};
+    }
+    rowp[k] = o;
+  }
+}
+
+// ---------------------------------------------------------------- launchers
+
+size_t bucket_bytes(int nmesh) {
+  const size_t n2 = (size_t)nmesh * nmesh;
+  const size_t nb = (n2 + 4095) / 4096;
+  // count, offsets (+1), cursor, block sums
+  return (3 * n2 + 1 + nb) * sizeof(int);
+}
+
+hipError_t launch_bucket(int dtype, int nmesh, double boxsize, const void* pos, const void* weight,
+                         int64_t n, void* bucket_ws, void* rec, void* wrec, double* wsums,
+                         hipStream_t s) {
+  const int n2 = nmesh * nmesh;
+  int* count = static_cast<int*>(bucket_ws);
+  int* offsets = count + n2;
+  int* cursor = offsets + n2 + 1;
+  int* bsums = cursor + n2;
+  const int nb = (n2 + 4095) / 4096;
+  hipError_t e = launch_fill_zero(count, (size_t)n2 * sizeof(int), s);
+  if (e != hipSuccess) return e;
+  e = launch_fill_zero(wsums, 2 * sizeof(double), s);
+  if (e != hipSuccess) return e;
+  int64_t blocks = (n + 255) / 256;
+  if (blocks > 8192) blocks = 8192;
+  if (blocks < 1) blocks = 1;
+  if (dtype == PK_F32)
+    hipLaunchKernelGGL(k_bucket_count<float>, dim3((unsigned)blocks), dim3(256), 0, s,
+                       static_cast<const float*>(pos), static_cast<const float*>(weight), n,
+                       nmesh, boxsize, count, wsums);
+  else
+    hipLaunchKernelGGL(k_bucket_count<double>, dim3((unsigned)blocks), dim3(256), 0, s,
+                       static_cast<const double*>(pos), static_cast<const double*>(weight), n,
+                       nmesh, boxsize, count, wsums);
+  hipLaunchKernelGGL(k_scan_blocks, dim3(nb), dim3(1024), 0, s, count, n2, bsums);
+  hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(1024), 0, s, bsums, nb);
+  hipLaunchKernelGGL(k_scan_final, dim3(nb), dim3(1024), 0, s, count, n2, bsums, offsets, cursor);
+  if (dtype == PK_F32)
+    hipLaunchKernelGGL(k_bucket_scatter<float>, dim3((unsigned)blocks), dim3(256), 0, s,
+                       static_cast<const float*>(pos), static_cast<const float*>(weight), n,
+                       nmesh, boxsize, cursor, static_cast<float4*>(rec),
+                       weight ? static_cast<float*>(wrec) : nullptr);
+  else
+    hipLaunchKernelGGL(k_bucket_scatter<double>, dim3((unsigned)blocks), dim3(256), 0, s,
+                       static_cast<const double*>(pos), static_cast<const double*>(weight), n,
+                       nmesh, boxsize, cursor, static_cast<double4*>(rec),
+                       weight ? static_cast<double*>(wrec) : nullptr);
+  return hipGetLastError();
+}
+
+template <typename T, int N, int P, bool INTER>
+static hipError_t paint_z_t(const void* rec, const void* wrec, const int* offsets,
+                            const double* wsums, const void* tw, void* mesh_a, void* mesh_b,
+                            hipStream_t s) {
+  using Cf = PaintCfg<T, N, P, INTER>;
+  const unsigned blocks = (unsigned)((N / Cf::TX) * (N / Cf::TY));
+  hipLaunchKernelGGL((k_paint_z<T, N, P, INTER>), dim3(blocks), dim3(Cf::THREADS), 0, s,
+                     static_cast<const typename Rec<T>::type*>(rec),
+                     static_cast<const T*>(wrec), offsets, wsums,
+                     static_cast<const cpx<T>*>(tw), static_cast<T*>(mesh_a),
+                     static_cast<T*>(mesh_b));
+  return hipGetLastError();
+}
+
+template <typename T, int N>
+static hipError_t paint_z_n(int order, bool inter, const void* rec, const void* wrec,
+                            const int* offsets, const double* wsums, const void* tw,
+                            void* mesh_a, void* mesh_b, hipStream_t s) {
+#define PK_PZ(P, I) return paint_z_t<T, N, P, I>(rec, wrec, offsets, wsums, tw, mesh_a, mesh_b, s)
+  if (inter) {
+    if (order == 2) PK_PZ(2, true);
+    if (order == 3) PK_PZ(3, true);
+    PK_PZ(4, true);
+  } else {
+    if (order == 2) PK_PZ(2, false);
+    if (order == 3) PK_PZ(3, false);
+    PK_PZ(4, false);
+  }
+#undef PK_PZ
+}
+
+hipError_t launch_paint_z(int dtype, int nmesh, int order, bool inter, const void* rec,
+                          const void* wrec, const void* bucket_ws, const double* wsums,
+                          const void* tw, void* mesh_a, void* mesh_b, hipStream_t s) {
+  const int* offsets = static_cast<const int*>(bucket_ws) + (size_t)nmesh * nmesh;
+#define PK_PN(T)                                                                           \
+  switch (nmesh) {                                                                         \
+    case 8: return paint_z_n<T, 8>(order, inter, rec, wrec, offsets, wsums, tw, mesh_a, mesh_b, s); \
+    case 16: return paint_z_n<T, 16>(order, inter, rec, wrec, offsets, wsums, tw, mesh_a, mesh_b, s); \
+    case 32: return paint_z_n<T, 32>(order, inter, rec, wrec, offsets, wsums, tw, mesh_a, mesh_b, s); \
+    case 64: return paint_z_n<T, 64>(order, inter, rec, wrec, offsets, wsums, tw, mesh_a, mesh_b, s); \
+    case 128: return paint_z_n<T, 128>(order, inter, rec, wrec, offsets, wsums, tw, mesh_a, mesh_b, s); \
+    case 256: return paint_z_n<T, 256>(order, inter, rec, wrec, offsets, wsums, tw, mesh_a, mesh_b, s); \
+    case 512: return paint_z_n<T, 512>(order, inter, rec, wrec, offsets, wsums, tw, mesh_a, mesh_b, s); \
+    case 1024: return paint_z_n<T, 1024>(order, inter, rec, wrec, offsets, wsums, tw, mesh_a, mesh_b, s); \
+    case 2048: return paint_z_n<T, 2048>(order, inter, rec, wrec, offsets, wsums, tw, mesh_a, mesh_b, s); \
+    default: return hipErrorInvalidValue;                                                  \
+  }
+  if (dtype == PK_F32) {
+    PK_PN(float)
+  } else {
+    PK_PN(double)
+  }
+#undef PK_PN
+}
+
+}  // namespace pk

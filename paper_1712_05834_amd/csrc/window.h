@@ -47,4 +47,32 @@ __device__ __forceinline__ void window_weights(double u, int& first, T* w) {
   }
 }
 
+// The same windows from an integer cell `base` and a fraction t in [0, 1)
+// (u = base + t), all in the mesh precision T.
+template <typename T, int P>
+__device__ __forceinline__ void window_frac(T t, int base, int& first, T* w) {
+  if constexpr (P == 2) {
+    first = base;
+    w[0] = T(1) - t;
+    w[1] = t;
+  } else if constexpr (P == 3) {
+    // centre cell floor(u + 1/2); d = u - centre in [-1/2, 1/2)
+    const bool up = t >= T(0.5);
+    const T d = up ? t - T(1) : t;
+    first = base + (up ? 1 : 0) - 1;
+    const T a = T(0.5) - d, b = T(0.5) + d;
+    w[0] = T(0.5) * a * a;
+    w[1] = T(0.75) - d * d;
+    w[2] = T(0.5) * b * b;
+  } else {
+    const T s = T(1) - t;
+    first = base - 1;
+    const T one6 = T(1) / T(6);
+    w[0] = s * s * s * one6;
+    w[1] = (T(4) - T(6) * t * t + T(3) * t * t * t) * one6;
+    w[2] = (T(4) - T(6) * s * s + T(3) * s * s * s) * one6;
+    w[3] = t * t * t * one6;
+  }
+}
+
 }  // namespace pk
