@@ -179,7 +179,11 @@ pk_status pk_fft_r2c(pk_ctx *ctx, const pk_mesh_desc *m, void *mesh_inout);
  *   if cmesh_b != NULL: c <- [c + exp(i pi (n_x + n_y + n_z) / N) c_b] / 2
  *   if m->compensated:  c <- c / prod_d sinc^p(pi n_d / N)
  * cmesh_b is the spectrum of the mesh painted with shift_cells = 0.5 and is
- * left unchanged.  The result is a packed spectrum again.
+ * left unchanged.  The result is a packed spectrum again.  After interlacing
+ * the kz = N/2 plane is not Hermitian and cannot be packed: it is set to zero,
+ * and plane-0 modes on a Nyquist index (|n_x| or |n_y| = N/2) are left
+ * unspecified.  All these modes have |n| >= N/2 and lie outside every binning
+ * allowed for interlaced meshes.
  * Errors: PK_EINVAL, PK_EDEVICE. */
 pk_status pk_compensate(pk_ctx *ctx, const pk_mesh_desc *m, void *cmesh_inout,
                         const void *cmesh_b);

@@ -406,6 +406,14 @@ __global__ void __launch_bounds__(256)
     a1 = comp_mode<T>(a1, cb ? &b1 : nullptr, nx, ny, N / 2, kx, ky, N / 2, N, phase, sinv);
     q0 = comp_mode<T>(q0, cb ? &r0 : nullptr, pnx, pny, 0, px, py, 0, N, phase, sinv);
     q1 = comp_mode<T>(q1, cb ? &r1 : nullptr, pnx, pny, N / 2, px, py, N / 2, N, phase, sinv);
+    // After interlacing the kz = N/2 plane is no longer Hermitian (its phase
+    // uses n_z = +N/2 for a mode and its mirror), so it cannot share the packed
+    // column; it is set to zero (all its modes have |n| >= N/2, outside every
+    // binning allowed for interlaced meshes).
+    if (cb) {
+      a1 = {T(0), T(0)};
+      q1 = {T(0), T(0)};
+    }
     // repack Z = p0 + i p1
     cm[me * NC] = {a0.x - a1.y, a0.y + a1.x};
     if (pa != me) cm[pa * NC] = {q0.x - q1.y, q0.y + q1.x};

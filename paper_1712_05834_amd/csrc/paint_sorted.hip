@@ -67,7 +67,7 @@ __device__ __forceinline__ int claim_slot(int key, int* __restrict__ counter) {
 template <typename T>
 __global__ void __launch_bounds__(256)
     k_bucket_count(const T* __restrict__ pos, const T* __restrict__ weight, int64_t n, int nmesh,
-                   double boxsize, int* __restrict__ count, double* __restrict__ wsums) {
+                   double boxsize, int* __restrict__ count, double* __restrict__ wpart) {
   const int mask = nmesh - 1;
   double ws = 0.0, ws2 = 0.0;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
@@ -85,11 +85,43 @@ __global__ void __launch_bounds__(256)
     }
     (void)claim_slot(key, count);
   }
+  // per-block partial sums (reduced in a fixed order by k_weight_sums)
+  __shared__ double part[2][4];
   ws = wave_sum_d(ws);
   ws2 = wave_sum_d(ws2);
   if ((threadIdx.x & 63) == 0) {
-    atomicAdd(&wsums[0], ws);
-    atomicAdd(&wsums[1], ws2);
+    part[0][threadIdx.x >> 6] = ws;
+    part[1][threadIdx.x >> 6] = ws2;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    wpart[2 * blockIdx.x] = ((part[0][0] + part[0][1]) + part[0][2]) + part[0][3];
+    wpart[2 * blockIdx.x + 1] = ((part[1][0] + part[1][1]) + part[1][2]) + part[1][3];
+  }
+}
+
+// sum w and sum w^2 from the per-block partials, in block order.
+__global__ void __launch_bounds__(1024)
+    k_weight_sums(const double* __restrict__ wpart, int nblocks, double* __restrict__ wsums) {
+  __shared__ double sh[2][1024];
+  double a = 0.0, b = 0.0;
+  for (int i = threadIdx.x; i < nblocks; i += 1024) {
+    a += wpart[2 * i];
+    b += wpart[2 * i + 1];
+  }
+  sh[0][threadIdx.x] = a;
+  sh[1][threadIdx.x] = b;
+  __syncthreads();
+  for (int half = 512; half >= 1; half >>= 1) {
+    if ((int)threadIdx.x < half) {
+      sh[0][threadIdx.x] += sh[0][threadIdx.x + half];
+      sh[1][threadIdx.x] += sh[1][threadIdx.x + half];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    wsums[0] = sh[0][0];
+    wsums[1] = sh[1][0];
   }
 }
 
@@ -256,6 +288,7 @@ __global__ void __launch_bounds__((PaintCfg<T, N, P, INTER>::THREADS))
   constexpr int mask = N - 1;
   __shared__ cpx<T> lds[ROWS * LP];
   __shared__ int seg_start[2 * (TX + 4)], seg_cum[2 * (TX + 4) + 1], seg_row[2 * (TX + 4)];
+  static_assert(TX + 4 >= (TX + Cf::HLO + Cf::HHI < N ? TX + Cf::HLO + Cf::HHI : N), "segments");
   __shared__ int nseg_sh;
   T* ldsf = reinterpret_cast<T*>(lds);
 
@@ -265,32 +298,36 @@ __global__ void __launch_bounds__((PaintCfg<T, N, P, INTER>::THREADS))
   for (int i = threadIdx.x; i < ROWS * LP * 2; i += blockDim.x) ldsf[i] = T(0);
 
   // segments of the sorted records: for each source row bx, the contiguous
-  // column range [by0, by0 + wy) (split where it wraps around N)
+  // column range [by0, by0 + wy) (split in two where it wraps around N); one
+  // thread per source row reads its offsets, thread 0 forms the prefix sums
+  constexpr int HW = Cf::HLO + Cf::HHI;
+  constexpr int WX = (TX + HW) >= N ? N : TX + HW;
+  constexpr int WY = (TY + HW) >= N ? N : TY + HW;
+  if ((int)threadIdx.x < WX) {
+    const int bx0 = (TX + HW) >= N ? 0 : X0 - Cf::HLO;
+    const int by0 = (TY + HW) >= N ? 0 : ((Y0 - Cf::HLO) & mask);
+    const int bx = (bx0 + (int)threadIdx.x) & mask;
+    const int run0 = (N - by0) < WY ? (N - by0) : WY;
+    const int b0 = bx * N + by0;
+    seg_start[2 * threadIdx.x] = offsets[b0];
+    seg_cum[2 * threadIdx.x] = offsets[b0 + run0] - offsets[b0];
+    seg_row[2 * threadIdx.x] = bx;
+    const int run1 = WY - run0;  // wrapped part, starting at column 0
+    const int b1 = bx * N;
+    seg_start[2 * threadIdx.x + 1] = run1 > 0 ? offsets[b1] : 0;
+    seg_cum[2 * threadIdx.x + 1] = run1 > 0 ? offsets[b1 + run1] - offsets[b1] : 0;
+    seg_row[2 * threadIdx.x + 1] = bx;
+  }
+  __syncthreads();
   if (threadIdx.x == 0) {
-    const int wx = (TX + Cf::HLO + Cf::HHI) >= N ? N : TX + Cf::HLO + Cf::HHI;
-    const int bx0 = (TX + Cf::HLO + Cf::HHI) >= N ? 0 : X0 - Cf::HLO;
-    const int wy = (TY + Cf::HLO + Cf::HHI) >= N ? N : TY + Cf::HLO + Cf::HHI;
-    const int by0 = (TY + Cf::HLO + Cf::HHI) >= N ? 0 : Y0 - Cf::HLO;
-    int ns = 0, cum = 0;
-    for (int r = 0; r < wx; ++r) {
-      const int bx = (bx0 + r) & mask;
-      int y = (by0 % N + N) % N;
-      int left = wy;
-      while (left > 0) {
-        const int run = (N - y) < left ? (N - y) : left;
-        const int b0 = bx * N + y;
-        const int s0 = offsets[b0], s1 = offsets[b0 + run];
-        seg_start[ns] = s0;
-        seg_row[ns] = bx;
-        seg_cum[ns] = cum;
-        cum += s1 - s0;
-        ++ns;
-        left -= run;
-        y = 0;
-      }
+    int cum = 0;
+    for (int i = 0; i < 2 * WX; ++i) {
+      const int len = seg_cum[i];
+      seg_cum[i] = cum;
+      cum += len;
     }
-    seg_cum[ns] = cum;
-    nseg_sh = ns;
+    seg_cum[2 * WX] = cum;
+    nseg_sh = 2 * WX;
   }
   __syncthreads();
 
@@ -389,11 +426,14 @@ __global__ void __launch_bounds__((PaintCfg<T, N, P, INTER>::THREADS))
 
 // ---------------------------------------------------------------- launchers
 
+constexpr int kCountBlocks = 8192;
+
 size_t bucket_bytes(int nmesh) {
   const size_t n2 = (size_t)nmesh * nmesh;
   const size_t nb = (n2 + 4095) / 4096;
-  // count, offsets (+1), cursor, block sums
-  return (3 * n2 + 1 + nb) * sizeof(int);
+  // count, offsets (+1), cursor, scan block sums; then float64 weight partials
+  const size_t ints = (3 * n2 + 1 + nb + 1) & ~(size_t)1;
+  return ints * sizeof(int) + 2 * kCountBlocks * sizeof(double);
 }
 
 hipError_t launch_bucket(int dtype, int nmesh, double boxsize, const void* pos, const void* weight,
@@ -405,21 +445,22 @@ hipError_t launch_bucket(int dtype, int nmesh, double boxsize, const void* pos, 
   int* cursor = offsets + n2 + 1;
   int* bsums = cursor + n2;
   const int nb = (n2 + 4095) / 4096;
+  const size_t ints = (3 * (size_t)n2 + 1 + nb + 1) & ~(size_t)1;
+  double* wpart = reinterpret_cast<double*>(static_cast<int*>(bucket_ws) + ints);
   hipError_t e = launch_fill_zero(count, (size_t)n2 * sizeof(int), s);
   if (e != hipSuccess) return e;
-  e = launch_fill_zero(wsums, 2 * sizeof(double), s);
-  if (e != hipSuccess) return e;
   int64_t blocks = (n + 255) / 256;
-  if (blocks > 8192) blocks = 8192;
+  if (blocks > kCountBlocks) blocks = kCountBlocks;
   if (blocks < 1) blocks = 1;
   if (dtype == PK_F32)
     hipLaunchKernelGGL(k_bucket_count<float>, dim3((unsigned)blocks), dim3(256), 0, s,
                        static_cast<const float*>(pos), static_cast<const float*>(weight), n,
-                       nmesh, boxsize, count, wsums);
+                       nmesh, boxsize, count, wpart);
   else
     hipLaunchKernelGGL(k_bucket_count<double>, dim3((unsigned)blocks), dim3(256), 0, s,
                        static_cast<const double*>(pos), static_cast<const double*>(weight), n,
-                       nmesh, boxsize, count, wsums);
+                       nmesh, boxsize, count, wpart);
+  hipLaunchKernelGGL(k_weight_sums, dim3(1), dim3(1024), 0, s, wpart, (int)blocks, wsums);
   hipLaunchKernelGGL(k_scan_blocks, dim3(nb), dim3(1024), 0, s, count, n2, bsums);
   hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(1024), 0, s, bsums, nb);
   hipLaunchKernelGGL(k_scan_final, dim3(nb), dim3(1024), 0, s, count, n2, bsums, offsets, cursor);

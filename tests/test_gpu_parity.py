@@ -150,11 +150,12 @@ def test_compensate_matches_oracle(ctx, dtype, order):
     ctx.pk_compensate(m, ta, tb)
     got = packing.unpack(packing.as_complex(ta.cpu().numpy().astype(np.float64)))
     want = oracle.compensate(oracle.interlace_combine(ca, cb, n), n, order)
-    # the packed planes cannot hold the (non-Hermitian) interlaced values at a
-    # Nyquist index; those modes are never binned (top edge <= N/2)
+    # the packed column cannot hold the non-Hermitian interlaced values of the
+    # kz = N/2 plane or of plane-0 modes on a Nyquist index; none of them is
+    # ever binned for interlaced meshes (top edge <= N/2)
     nx, ny, nz = oracle.mode_indices(n)
-    skip = ((np.abs(nx)[:, None, None] == n // 2) | (np.abs(ny)[None, :, None] == n // 2)) & \
-        ((nz == 0) | (nz == n // 2))[None, None, :]
+    skip = (((np.abs(nx)[:, None, None] == n // 2) | (np.abs(ny)[None, :, None] == n // 2))
+            & (nz == 0)[None, None, :]) | (nz == n // 2)[None, None, :]
     tol = 1e-12 if dtype == "f8" else 2e-6
     err = np.abs(got - want)[~skip].max() / np.abs(want).max()
     assert err <= tol, err
