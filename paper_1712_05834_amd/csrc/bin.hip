@@ -129,9 +129,21 @@ __global__ void __launch_bounds__((ColCfg<T, N>::THREADS))
     sx[e] = sinv ? sinv[t + TPL * e] : T(1);
   }
   LdsCols<T, C> lc{lds, c};
-  for (int tile = blockIdx.x; tile < N * CHUNKS; tile += gridDim.x) {
+  // binning pass layout: the power of the tile's C x N modes is staged in
+  // LDS as pw[col][kx + kx / S] and re-read so that the 64 lanes of a wave
+  // see one column at kx spaced S = N / 64 apart: distinct |n| bins, hence
+  // few same-address collisions of the LDS atomics
+  constexpr int S = N >= 64 ? N / 64 : 1;
+  constexpr int PROW = N >= 64 ? N + N / S : N;
+  T* pws = reinterpret_cast<T*>(lds);
+  static_assert((long)C * PROW * sizeof(T) <= (long)Cf::LDS_ELEMS * sizeof(cpx<T>), "staging");
+  auto pidx = [](int cc, int kx) { return cc * PROW + (N >= 64 ? kx + kx / S : kx); };
+  const int ntiles = N * CHUNKS;
+  for (int tile_id = blockIdx.x; tile_id < ntiles; tile_id += gridDim.x) {
+    const int tile = xcd_pair_tile(tile_id, ntiles);
     const int ky = tile / CHUNKS;
-    const int col = (tile % CHUNKS) * C + c;
+    const int col0 = (tile % CHUNKS) * C;
+    const int col = col0 + c;
     const size_t base = (size_t)ky * NC + col;
     const size_t step = (size_t)N * NC;
     cpx<T> va[E], vb[E];
@@ -143,24 +155,19 @@ __global__ void __launch_bounds__((ColCfg<T, N>::THREADS))
       for (int e = 0; e < E; ++e) vb[e] = mesh_b[base + (size_t)(t + TPL * e) * step];
       stockham<T, N, E, 1>(vb, t, tw, 1, lc);
     }
-    if (col == 0) {
-      // packed kz = 0 / N/2 column: handed to k_plane_bin
-#pragma unroll
-      for (int e = 0; e < E; ++e) {
-        const size_t kx = (size_t)(t + TPL * e);
-        side_a[kx * N + ky] = va[e];
-        if (two) side_b[kx * N + ky] = vb[e];
-      }
-      continue;
-    }
     const int ny = signed_index(ky, N);
-    const int nz = col;
-    const int syz = ny * ny + nz * nz;
-    const cpx<T> phyz = two ? cmul(ph1[ny], ph1[nz]) : cpx<T>{T(1), T(0)};
+    const cpx<T> phyz = two ? cmul(ph1[ny], ph1[col]) : cpx<T>{T(1), T(0)};
     const T s_yz = sinv ? sinv[ky] * sinv[col] : T(1);
+    __syncthreads();  // every wave is done with the FFT exchanges
 #pragma unroll
     for (int e = 0; e < E; ++e) {
-      const int nx = signed_index(t + TPL * e, N);
+      const int kx = t + TPL * e;
+      if (col == 0) {
+        // packed kz = 0 / N/2 column: handed to k_plane_bin
+        side_a[(size_t)kx * N + ky] = va[e];
+        if (two) side_b[(size_t)kx * N + ky] = vb[e];
+        continue;
+      }
       cpx<T> cc = va[e];
       if (two) {
         const cpx<T> bb = cmul(cmul(phx[e], phyz), vb[e]);
@@ -171,7 +178,29 @@ __global__ void __launch_bounds__((ColCfg<T, N>::THREADS))
         const T s = sx[e] * s_yz;
         pw *= s * s;
       }
-      const int n2 = nx * nx + syz;
+      pws[pidx(c, kx)] = pw;
+    }
+    __syncthreads();
+    // binning: with 64-lane waves, work item m = 64 * slot + lane covers
+    // column slot / S and kx = lane * S + slot % S; small workgroups take
+    // column m / N and kx = m % N
+    constexpr bool WAVEWISE = N >= 64 && Cf::THREADS % 64 == 0;
+    constexpr int STEP = WAVEWISE ? Cf::THREADS : Cf::THREADS;
+    for (int m = threadIdx.x; m < C * N; m += STEP) {
+      int cc_, kx;
+      if constexpr (WAVEWISE) {
+        const int slot = (m >> 6);
+        cc_ = slot / S;
+        kx = (m & 63) * S + slot % S;
+      } else {
+        cc_ = m / N;
+        kx = m % N;
+      }
+      const int nz = col0 + cc_;
+      if (nz == 0) continue;
+      const int nx = signed_index(kx, N);
+      const T pw = pws[pidx(cc_, kx)];
+      const int n2 = nx * nx + ny * ny + nz * nz;
       const int nl = los == 0 ? nx : (los == 1 ? ny : nz);
       accumulate<T>(sb, b, n2, nl * nl, 2.0 * (double)pw);
     }

@@ -69,7 +69,8 @@ __global__ void __launch_bounds__((ColCfg<T, N>::THREADS))
   constexpr int E = Cf::E, TPL = Cf::TPL, C = Cf::C, NC = Cf::NC;
   __shared__ cpx<T> lds[Cf::LDS_ELEMS];
   const int c = threadIdx.x % C, t = threadIdx.x / C;
-  const int outer = blockIdx.x / Cf::CHUNKS, chunk = blockIdx.x % Cf::CHUNKS;
+  const int tile = xcd_pair_tile(blockIdx.x, N * Cf::CHUNKS);
+  const int outer = tile / Cf::CHUNKS, chunk = tile % Cf::CHUNKS;
   cpx<T>* mesh = reinterpret_cast<cpx<T>*>(mesh0 + blockIdx.z * mesh_stride);
   size_t base, step;
   if (axis == 1) {

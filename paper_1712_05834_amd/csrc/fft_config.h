@@ -43,4 +43,15 @@ struct ColCfg {
   static constexpr int LDS_ELEMS = lds_pad_len<L>() * C;
 };
 
+// Tile order for passes whose workgroups read C-column chunks narrower than a
+// 128-byte line: the two chunks sharing a line (tiles 2j and 2j + 1) are
+// given to workgroups g and g + 8, which the dispatcher places on the same
+// XCD (round robin over 8 XCDs) at about the same time, so the second read
+// of each line hits that XCD's L2.  Identity unless `ntiles` is a multiple
+// of 16.
+__device__ __forceinline__ int xcd_pair_tile(int g, int ntiles) {
+  if (ntiles & 15) return g;
+  return (g & ~15) | ((g & 7) << 1) | ((g >> 3) & 1);
+}
+
 }  // namespace pk

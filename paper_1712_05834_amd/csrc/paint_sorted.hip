@@ -333,12 +333,19 @@ __global__ void __launch_bounds__((PaintCfg<T, N, P, INTER>::THREADS))
 
   // scatter-add of the window weights of every source particle into the
   // owned cells of both meshes
+  // Work item q takes particle p = (q mod 64) * R + q / 64, R = ceil(total / 64):
+  // the lanes of a wave handle particles R apart in the sorted order rather
+  // than neighbours, which in clustered or cell-ordered catalogs often share a
+  // cell and would serialise on the same LDS address.
   const int nseg = nseg_sh;
   const int total = seg_cum[nseg];
-  for (int q = threadIdx.x; q < total; q += blockDim.x) {
+  const int R = (total + 63) >> 6;
+  for (int q = threadIdx.x; q < 64 * R; q += blockDim.x) {
+    const int p = (q & 63) * R + (q >> 6);
+    if (p >= total) continue;
     int s = 0;
-    while (s + 1 < nseg && seg_cum[s + 1] <= q) ++s;
-    const int idx = seg_start[s] + (q - seg_cum[s]);
+    while (s + 1 < nseg && seg_cum[s + 1] <= p) ++s;
+    const int idx = seg_start[s] + (p - seg_cum[s]);
     const auto r = rec[idx];
     const T wp = wrec ? wrec[idx] : T(1);
     unsigned packed;
