@@ -10,10 +10,10 @@
 //                     written to its column's segment.
 // 4. k_paint_z        one workgroup owns a TX x TY block of full z-columns of
 //                     both meshes: it reads the records of the columns whose
-//                     windows reach the block, adds the window weights into LDS
-//                     (ds_add), then runs the r2c FFT of every column in LDS
-//                     and writes the packed rows once.  No mesh clear, no
-//                     atomics to HBM, no separate z-pass.
+//                     windows reach the block, adds the window weights into
+//                     float64 LDS rows (ds_add_f64), then runs the r2c FFT of
+//                     every column in LDS and writes the packed rows once.  No
+//                     mesh clear, no atomics to HBM, no separate z-pass.
 #include "fft_config.h"
 #include "internal.h"
 #include "window.h"
@@ -244,14 +244,20 @@ __global__ void __launch_bounds__(1024)
 // ---- fused paint + r2c z-pass
 
 // Columns per workgroup (TX x TY) and halo of source columns per mesh size.
+// The window weights are accumulated in float64 LDS rows (ds_add_f64 runs
+// about 20x faster than ds_add_f32 on gfx950, and is more precise); a row of
+// N doubles is then reused in place as the padded complex line of the r2c.
 template <typename T, int N, int P, bool INTER>
 struct PaintCfg {
   static constexpr int M = N / 2;
   static constexpr int E = M < e_max<T>() ? M : e_max<T>();
   static constexpr int TPL = M / E;
-  static constexpr int LP = lds_pad_len<M>();           // complex per LDS row
+  static constexpr int LP = lds_pad_len<M>();           // complex per FFT line
   static constexpr int NM = INTER ? 2 : 1;
-  static constexpr long ROW_BYTES = (long)LP * 2 * sizeof(T);
+  static constexpr long ACC_BYTES = (long)N * 8;
+  static constexpr long FFT_BYTES = (long)LP * 2 * sizeof(T);
+  static constexpr long ROW_BYTES = ((ACC_BYTES > FFT_BYTES ? ACC_BYTES : FFT_BYTES) + 15) / 16 * 16;
+  static constexpr int ROWD = (int)(ROW_BYTES / 8);     // row stride in doubles
   static constexpr int pick_cols() {
     int cols = 64;
     while (cols > 1 && (long)cols * NM * ROW_BYTES > 144 * 1024) cols /= 2;
@@ -270,32 +276,24 @@ struct PaintCfg {
   static constexpr int HHI = P == 2 ? 0 : 1;
 };
 
-// Float address of cell z inside a padded LDS row (complex index z / 2 with
-// one pad slot every 16 complex).
-__device__ __forceinline__ int zaddr(int z) {
-  const int j = z >> 1;
-  return ((j + (j >> 4)) << 1) | (z & 1);
-}
-
 template <typename T, int N, int P, bool INTER>
 __global__ void __launch_bounds__((PaintCfg<T, N, P, INTER>::THREADS))
     k_paint_z(const typename Rec<T>::type* __restrict__ rec, const T* __restrict__ wrec,
               const int* __restrict__ offsets, const double* __restrict__ wsums,
               const cpx<T>* __restrict__ tw, T* __restrict__ mesh_a, T* __restrict__ mesh_b) {
   using Cf = PaintCfg<T, N, P, INTER>;
-  constexpr int M = Cf::M, E = Cf::E, TPL = Cf::TPL, LP = Cf::LP, TX = Cf::TX, TY = Cf::TY;
-  constexpr int ROWS = Cf::ROWS;
+  constexpr int M = Cf::M, E = Cf::E, TPL = Cf::TPL, TX = Cf::TX, TY = Cf::TY;
+  constexpr int ROWS = Cf::ROWS, ROWD = Cf::ROWD;
   constexpr int mask = N - 1;
-  __shared__ cpx<T> lds[ROWS * LP];
+  __shared__ double acc[ROWS * ROWD];
   __shared__ int seg_start[2 * (TX + 4)], seg_cum[2 * (TX + 4) + 1], seg_row[2 * (TX + 4)];
   static_assert(TX + 4 >= (TX + Cf::HLO + Cf::HHI < N ? TX + Cf::HLO + Cf::HHI : N), "segments");
   __shared__ int nseg_sh;
-  T* ldsf = reinterpret_cast<T*>(lds);
 
   const int tiles_y = N / TY;
   const int X0 = (blockIdx.x / tiles_y) * TX, Y0 = (blockIdx.x % tiles_y) * TY;
 
-  for (int i = threadIdx.x; i < ROWS * LP * 2; i += blockDim.x) ldsf[i] = T(0);
+  for (int i = threadIdx.x; i < ROWS * ROWD; i += blockDim.x) acc[i] = 0.0;
 
   // segments of the sorted records: for each source row bx, the contiguous
   // column range [by0, by0 + wy) (split in two where it wraps around N); one
@@ -331,12 +329,10 @@ __global__ void __launch_bounds__((PaintCfg<T, N, P, INTER>::THREADS))
   }
   __syncthreads();
 
-  // scatter-add of the window weights of every source particle into the
-  // owned cells of both meshes
   // Work item q takes particle p = (q mod 64) * R + q / 64, R = ceil(total / 64):
   // the lanes of a wave handle particles R apart in the sorted order rather
   // than neighbours, which in clustered or cell-ordered catalogs often share a
-  // cell and would serialise on the same LDS address.
+  // cell and would collide on the same LDS address.
   const int nseg = nseg_sh;
   const int total = seg_cum[nseg];
   const int R = (total + 63) >> 6;
@@ -386,27 +382,30 @@ __global__ void __launch_bounds__((PaintCfg<T, N, P, INTER>::THREADS))
           const int ly = (first[1] + b2 - Y0) & mask;
           if (ly >= TY) continue;
           const T wab = wa * w[1][b2];
-          T* row = ldsf + (size_t)((mesh * TX + lx) * TY + ly) * (LP * 2);
+          double* row = acc + ((mesh * TX + lx) * TY + ly) * ROWD;
 #pragma unroll
-          for (int c = 0; c < P; ++c) atomicAdd(&row[zaddr((first[2] + c) & mask)], wab * w[2][c]);
+          for (int c = 0; c < P; ++c)
+            atomicAdd(&row[(first[2] + c) & mask], (double)(wab * w[2][c]));
         }
       }
     }
   }
   __syncthreads();
 
-  // r2c along z of every owned column, mean subtracted (only the DC mode
-  // changes; it keeps float rounding relative to the fluctuations)
-  const T mean = static_cast<T>(wsums[0] / ((double)N * N * N));
+  // r2c along z of every owned column, mean subtracted in float64 before the
+  // rounding to T (only the DC mode changes; it keeps the rounding relative to
+  // the fluctuations).  The row of N doubles becomes the padded complex line.
+  const double mean = wsums[0] / ((double)N * N * N);
   const int r = threadIdx.x / TPL, t = threadIdx.x % TPL;
-  LdsLine<T> line{lds + r * LP};
+  double* arow = acc + r * ROWD;
+  LdsLine<T> line{reinterpret_cast<cpx<T>*>(arow)};
   cpx<T> v[E];
 #pragma unroll
   for (int e = 0; e < E; ++e) {
-    v[e] = line.get(t + TPL * e);
-    v[e].x -= mean;
-    v[e].y -= mean;
+    const int j = t + TPL * e;
+    v[e] = {static_cast<T>(arow[2 * j] - mean), static_cast<T>(arow[2 * j + 1] - mean)};
   }
+  __syncthreads();  // all float64 cells read before the row is reused
   stockham<T, M, E, 1>(v, t, tw, 2, line);
   __syncthreads();
 #pragma unroll
