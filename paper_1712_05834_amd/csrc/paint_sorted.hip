@@ -250,18 +250,18 @@ __global__ void __launch_bounds__(1024)
 template <typename T, int N, int P, bool INTER>
 struct PaintCfg {
   static constexpr int M = N / 2;
-  static constexpr int E = M < e_max<T>() ? M : e_max<T>();
-  static constexpr int TPL = M / E;
   static constexpr int LP = lds_pad_len<M>();           // complex per FFT line
   static constexpr int NM = INTER ? 2 : 1;
   static constexpr long ACC_BYTES = (long)N * 8;
   static constexpr long FFT_BYTES = (long)LP * 2 * sizeof(T);
   static constexpr long ROW_BYTES = ((ACC_BYTES > FFT_BYTES ? ACC_BYTES : FFT_BYTES) + 15) / 16 * 16;
   static constexpr int ROWD = (int)(ROW_BYTES / 8);     // row stride in doubles
+  static constexpr int EMIN = M < 2 ? M : 2;
+  static constexpr int EMAX = M < e_max<T>() ? M : e_max<T>();
   static constexpr int pick_cols() {
     int cols = 64;
     while (cols > 1 && (long)cols * NM * ROW_BYTES > 144 * 1024) cols /= 2;
-    while (cols > 1 && (long)cols * NM * TPL > 1024) cols /= 2;
+    while (cols > 1 && (long)cols * NM * (M / EMAX) > 1024) cols /= 2;
     return cols;
   }
   static constexpr int COLS = pick_cols();
@@ -270,6 +270,15 @@ struct PaintCfg {
   static constexpr int TY = COLS / TX;
   static_assert(TX <= N && TY <= N && TX * TY == COLS, "column block must fit the mesh");
   static constexpr int ROWS = NM * TX * TY;
+  // points per thread of the column FFTs: as few as keep the workgroup at
+  // most 1024 threads, so that the gather phase runs with many waves
+  static constexpr int pick_e() {
+    int e = EMIN;
+    while (e < EMAX && (long)ROWS * (M / e) > 1024) e *= 2;
+    return e;
+  }
+  static constexpr int E = pick_e();
+  static constexpr int TPL = M / E;
   static constexpr int THREADS = ROWS * TPL;
   // source columns that can reach an owned column: [X - HLO, X + HHI]
   static constexpr int HLO = P == 2 ? (INTER ? 2 : 1) : (P == 3 ? 2 : (INTER ? 3 : 2));
@@ -336,59 +345,88 @@ __global__ void __launch_bounds__((PaintCfg<T, N, P, INTER>::THREADS))
   const int nseg = nseg_sh;
   const int total = seg_cum[nseg];
   const int R = (total + 63) >> 6;
-  for (int q = threadIdx.x; q < 64 * R; q += blockDim.x) {
+  // record index of work item q (-1 past the end); the next record is loaded
+  // before the current one is processed, so its latency overlaps the work
+  auto locate = [&](int q, int& seg) -> int {
+    if (q >= 64 * R) return -1;
     const int p = (q & 63) * R + (q >> 6);
-    if (p >= total) continue;
+    if (p >= total) return -1;
     int s = 0;
     while (s + 1 < nseg && seg_cum[s + 1] <= p) ++s;
-    const int idx = seg_start[s] + (p - seg_cum[s]);
-    const auto r = rec[idx];
-    const T wp = wrec ? wrec[idx] : T(1);
-    unsigned packed;
-    if constexpr (sizeof(T) == 4) {
-      packed = __float_as_uint(r.w);
-    } else {
-      packed = (unsigned)r.w;
+    seg = s;
+    return seg_start[s] + (p - seg_cum[s]);
+  };
+  using RecT = typename Rec<T>::type;
+  int seg_cur = 0;
+  int idx_cur = locate(threadIdx.x, seg_cur);
+  RecT r_cur{};
+  T w_cur = T(1);
+  if (idx_cur >= 0) {
+    r_cur = rec[idx_cur];
+    if (wrec) w_cur = wrec[idx_cur];
+  }
+  for (int q = threadIdx.x; q < 64 * R; q += blockDim.x) {
+    int seg_nxt = 0;
+    const int idx_nxt = locate(q + (int)blockDim.x, seg_nxt);
+    RecT r_nxt{};
+    T w_nxt = T(1);
+    if (idx_nxt >= 0) {
+      r_nxt = rec[idx_nxt];
+      if (wrec) w_nxt = wrec[idx_nxt];
     }
-    const int ix = seg_row[s], iy = (int)(packed >> 16), iz = (int)(packed & 0xffff);
-    const T t3[3] = {r.x, r.y, r.z};
-    const int i3[3] = {ix, iy, iz};
+    if (idx_cur >= 0) {
+      const RecT r = r_cur;
+      const T wp = w_cur;
+      unsigned packed;
+      if constexpr (sizeof(T) == 4) {
+        packed = __float_as_uint(r.w);
+      } else {
+        packed = (unsigned)r.w;
+      }
+      const int ix = seg_row[seg_cur], iy = (int)(packed >> 16), iz = (int)(packed & 0xffff);
+      const T t3[3] = {r.x, r.y, r.z};
+      const int i3[3] = {ix, iy, iz};
 #pragma unroll
-    for (int mesh = 0; mesh < (INTER ? 2 : 1); ++mesh) {
-      int first[3];
-      T w[3][P];
+      for (int mesh = 0; mesh < (INTER ? 2 : 1); ++mesh) {
+        int first[3];
+        T w[3][P];
 #pragma unroll
-      for (int d = 0; d < 3; ++d) {
-        // window of u = i + t (+ 1/2 for the interlaced mesh)
-        T tt = t3[d];
-        int base = i3[d];
-        if (mesh == 1) {
-          if (tt >= T(0.5)) {
-            tt -= T(0.5);  // exact
-            base += 1;
-          } else {
-            tt += T(0.5);
+        for (int d = 0; d < 3; ++d) {
+          // window of u = i + t (+ 1/2 for the interlaced mesh)
+          T tt = t3[d];
+          int base = i3[d];
+          if (mesh == 1) {
+            if (tt >= T(0.5)) {
+              tt -= T(0.5);  // exact
+              base += 1;
+            } else {
+              tt += T(0.5);
+            }
+          }
+          window_frac<T, P>(tt, base, first[d], w[d]);
+        }
+#pragma unroll
+        for (int a = 0; a < P; ++a) {
+          const int lx = (first[0] + a - X0) & mask;
+          if (lx >= TX) continue;
+          const T wa = wp * w[0][a];
+#pragma unroll
+          for (int b2 = 0; b2 < P; ++b2) {
+            const int ly = (first[1] + b2 - Y0) & mask;
+            if (ly >= TY) continue;
+            const T wab = wa * w[1][b2];
+            double* row = acc + ((mesh * TX + lx) * TY + ly) * ROWD;
+#pragma unroll
+            for (int c = 0; c < P; ++c)
+              atomicAdd(&row[(first[2] + c) & mask], (double)(wab * w[2][c]));
           }
         }
-        window_frac<T, P>(tt, base, first[d], w[d]);
-      }
-#pragma unroll
-      for (int a = 0; a < P; ++a) {
-        const int lx = (first[0] + a - X0) & mask;
-        if (lx >= TX) continue;
-        const T wa = wp * w[0][a];
-#pragma unroll
-        for (int b2 = 0; b2 < P; ++b2) {
-          const int ly = (first[1] + b2 - Y0) & mask;
-          if (ly >= TY) continue;
-          const T wab = wa * w[1][b2];
-          double* row = acc + ((mesh * TX + lx) * TY + ly) * ROWD;
-#pragma unroll
-          for (int c = 0; c < P; ++c)
-            atomicAdd(&row[(first[2] + c) & mask], (double)(wab * w[2][c]));
-        }
       }
     }
+    idx_cur = idx_nxt;
+    seg_cur = seg_nxt;
+    r_cur = r_nxt;
+    w_cur = w_nxt;
   }
   __syncthreads();
 
