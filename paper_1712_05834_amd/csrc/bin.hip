@@ -12,6 +12,8 @@
 // k_reduce     sums the partial rows in a fixed order (deterministic given
 //              the partials).
 // k_mode_tables  plan-time counts, sum h|n| and sum h|mu| per bin.
+#include <type_traits>
+
 #include "fft_config.h"
 #include "internal.h"
 
@@ -103,31 +105,23 @@ __device__ __forceinline__ void flush_bins(const double* sb, int n, double* out)
 }
 
 template <typename T, int N>
-__global__ void __launch_bounds__((ColCfg<T, N>::THREADS))
+__global__ void __launch_bounds__((XCfg<T, N>::THREADS))
     k_xpass_bin(const cpx<T>* __restrict__ mesh_a, const cpx<T>* __restrict__ mesh_b,
                 const cpx<T>* __restrict__ tw, const cpx<T>* __restrict__ phase,
                 const T* __restrict__ sinv, BinSpec b, double* __restrict__ partials,
                 cpx<T>* __restrict__ side_a, cpx<T>* __restrict__ side_b) {
-  using Cf = ColCfg<T, N>;
+  using Cf = XCfg<T, N>;
   constexpr int E = Cf::E, TPL = Cf::TPL, C = Cf::C, NC = Cf::NC, CHUNKS = Cf::CHUNKS;
   __shared__ cpx<T> lds[Cf::LDS_ELEMS];
+  __shared__ cpx<T> twq[N / 4];
   extern __shared__ double sb[];
   zero_bins(sb, b.nsum);
-  __syncthreads();
+  load_quarter(twq, tw, N);  // ends with a barrier
+  const TwQuarter<T> tw1{twq, 1, ilog2(N / 4)};
   const int c = threadIdx.x % C, t = threadIdx.x / C;
   const int los = b.los;
   const bool two = mesh_b != nullptr;
-  // x-dependent factors of this thread's modes kx = t + TPL e (the same for
-  // every tile): interlacing phase exp(i pi n_x / N) and sinc^-p(pi n_x / N)
   const cpx<T>* __restrict__ ph1 = phase + 3 * (N / 2);  // ph1[n] = exp(i pi n / N)
-  cpx<T> phx[E];
-  T sx[E];
-#pragma unroll
-  for (int e = 0; e < E; ++e) {
-    const int nx = signed_index(t + TPL * e, N);
-    phx[e] = two ? ph1[nx] : cpx<T>{T(1), T(0)};
-    sx[e] = sinv ? sinv[t + TPL * e] : T(1);
-  }
   LdsCols<T, C> lc{lds, c};
   // binning pass layout: the power of the tile's C x N modes is staged in
   // LDS as pw[col][kx + kx / S] and re-read so that the 64 lanes of a wave
@@ -144,20 +138,25 @@ __global__ void __launch_bounds__((ColCfg<T, N>::THREADS))
     const int ky = tile / CHUNKS;
     const int col0 = (tile % CHUNKS) * C;
     const int col = col0 + c;
-    const size_t base = (size_t)ky * NC + col;
-    const size_t step = (size_t)N * NC;
+    // element indices fit 32 bits up to N = 1024 (2^29 complex per mesh)
+    using Ix = typename std::conditional<(N <= 1024), unsigned, size_t>::type;
+    const Ix base = (Ix)ky * NC + col;
+    constexpr Ix step = (Ix)N * NC;
+    // both meshes' loads and the tile's table values are issued before any
+    // transform, so their latencies overlap
     cpx<T> va[E], vb[E];
 #pragma unroll
-    for (int e = 0; e < E; ++e) va[e] = mesh_a[base + (size_t)(t + TPL * e) * step];
-    stockham<T, N, E, 1>(va, t, tw, 1, lc);
+    for (int e = 0; e < E; ++e) va[e] = mesh_a[base + (Ix)(t + TPL * e) * step];
     if (two) {
 #pragma unroll
-      for (int e = 0; e < E; ++e) vb[e] = mesh_b[base + (size_t)(t + TPL * e) * step];
-      stockham<T, N, E, 1>(vb, t, tw, 1, lc);
+      for (int e = 0; e < E; ++e) vb[e] = mesh_b[base + (Ix)(t + TPL * e) * step];
     }
     const int ny = signed_index(ky, N);
-    const cpx<T> phyz = two ? cmul(ph1[ny], ph1[col]) : cpx<T>{T(1), T(0)};
+    const cpx<T> phy = ph1[ny], phz = ph1[col];
     const T s_yz = sinv ? sinv[ky] * sinv[col] : T(1);
+    stockham<T, N, E, 1>(va, t, tw1, lc);
+    if (two) stockham<T, N, E, 1>(vb, t, tw1, lc);
+    const cpx<T> phyz = two ? cmul(phy, phz) : cpx<T>{T(1), T(0)};
     __syncthreads();  // every wave is done with the FFT exchanges
 #pragma unroll
     for (int e = 0; e < E; ++e) {
@@ -170,12 +169,12 @@ __global__ void __launch_bounds__((ColCfg<T, N>::THREADS))
       }
       cpx<T> cc = va[e];
       if (two) {
-        const cpx<T> bb = cmul(cmul(phx[e], phyz), vb[e]);
+        const cpx<T> bb = cmul(cmul(ph1[signed_index(kx, N)], phyz), vb[e]);
         cc = {T(0.5) * (cc.x + bb.x), T(0.5) * (cc.y + bb.y)};
       }
       T pw = cc.x * cc.x + cc.y * cc.y;
       if (sinv) {
-        const T s = sx[e] * s_yz;
+        const T s = sinv[kx] * s_yz;
         pw *= s * s;
       }
       pws[pidx(c, kx)] = pw;
@@ -456,14 +455,14 @@ int xpass_bin_groups(int dtype, int nmesh) {
   long tiles;
   if (dtype == PK_F32) {
     switch (nmesh) {
-#define PK_T(NN) case NN: tiles = (long)NN * ColCfg<float, NN>::CHUNKS; break;
+#define PK_T(NN) case NN: tiles = (long)NN * XCfg<float, NN>::CHUNKS; break;
       PK_T(8) PK_T(16) PK_T(32) PK_T(64) PK_T(128) PK_T(256) PK_T(512) PK_T(1024) PK_T(2048)
 #undef PK_T
       default: return 0;
     }
   } else {
     switch (nmesh) {
-#define PK_T(NN) case NN: tiles = (long)NN * ColCfg<double, NN>::CHUNKS; break;
+#define PK_T(NN) case NN: tiles = (long)NN * XCfg<double, NN>::CHUNKS; break;
       PK_T(8) PK_T(16) PK_T(32) PK_T(64) PK_T(128) PK_T(256) PK_T(512) PK_T(1024) PK_T(2048)
 #undef PK_T
       default: return 0;
@@ -490,7 +489,7 @@ template <typename T, int N>
 static hipError_t xpass_bin_t(const void* mesh_a, const void* mesh_b, const MeshTables& t,
                               int order, int compensated, const BinSpec& b, double* partials,
                               void* side_a, void* side_b, hipStream_t s) {
-  using Cf = ColCfg<T, N>;
+  using Cf = XCfg<T, N>;
   const int groups = xpass_bin_groups(sizeof(T) == 4 ? PK_F32 : PK_F64, N);
   const T* sinv = compensated ? static_cast<const T*>(t.sinc_inv) + (size_t)(order - 2) * N
                               : nullptr;

@@ -19,6 +19,9 @@ __global__ void __launch_bounds__((ZCfg<T, N>::THREADS))
   using Z = ZCfg<T, N>;
   constexpr int M = Z::M, E = Z::E, TPL = Z::TPL, RPB = Z::RPB;
   __shared__ cpx<T> lds[RPB * Z::LP];
+  __shared__ cpx<T> twq[N / 4];
+  load_quarter(twq, tw, N);
+  const TwQuarter<T> tw2{twq, 2, ilog2(N / 4)}, tw1{twq, 1, ilog2(N / 4)};
   const int r = threadIdx.x / TPL, t = threadIdx.x % TPL;
   const size_t nrows = (size_t)N * N;
   const size_t row = (size_t)blockIdx.x * RPB + r;
@@ -39,7 +42,7 @@ __global__ void __launch_bounds__((ZCfg<T, N>::THREADS))
     }
   }
   LdsLine<T> line{lds + r * Z::LP};
-  stockham<T, M, E, 1>(v, t, tw, 2, line);
+  stockham<T, M, E, 1>(v, t, tw2, line);
   __syncthreads();
 #pragma unroll
   for (int e = 0; e < E; ++e) line.put(t + TPL * e, v[e]);
@@ -54,7 +57,7 @@ __global__ void __launch_bounds__((ZCfg<T, N>::THREADS))
       // X_k = (Z_k + conj Z_{M-k}) / 2 - (i / 2) W_N^k (Z_k - conj Z_{M-k})
       const cpx<T> zc = cconj(line.get(M - k));
       const cpx<T> s = cadd(v[e], zc);
-      const cpx<T> w = cmul(tw[k], csub(v[e], zc));
+      const cpx<T> w = cmul(tw1(k), csub(v[e], zc));
       out = {T(0.5) * (s.x + w.y), T(0.5) * (s.y - w.x)};
     }
     if (active) rowp[k] = out;
@@ -68,6 +71,9 @@ __global__ void __launch_bounds__((ColCfg<T, N>::THREADS))
   using Cf = ColCfg<T, N>;
   constexpr int E = Cf::E, TPL = Cf::TPL, C = Cf::C, NC = Cf::NC;
   __shared__ cpx<T> lds[Cf::LDS_ELEMS];
+  __shared__ cpx<T> twq[N / 4];
+  load_quarter(twq, tw, N);
+  const TwQuarter<T> tw1{twq, 1, ilog2(N / 4)};
   const int c = threadIdx.x % C, t = threadIdx.x / C;
   const int tile = xcd_pair_tile(blockIdx.x, N * Cf::CHUNKS);
   const int outer = tile / Cf::CHUNKS, chunk = tile % Cf::CHUNKS;
@@ -84,7 +90,7 @@ __global__ void __launch_bounds__((ColCfg<T, N>::THREADS))
 #pragma unroll
   for (int e = 0; e < E; ++e) v[e] = mesh[base + (size_t)(t + TPL * e) * step];
   LdsCols<T, C> lc{lds, c};
-  stockham<T, N, E, 1>(v, t, tw, 1, lc);
+  stockham<T, N, E, 1>(v, t, tw1, lc);
 #pragma unroll
   for (int e = 0; e < E; ++e) mesh[base + (size_t)(t + TPL * e) * step] = v[e];
 }

@@ -23,16 +23,19 @@ struct ZCfg {
 
 // y- and x-passes: lines of N complex points, C neighbouring packed columns
 // per workgroup (C * 8 bytes contiguous per row for complex float), with the
-// LDS footprint capped at 80 KB so two workgroups fit on a CU.
-template <typename T, int N>
+// LDS footprint capped at 80 KB so two workgroups fit on a CU.  EM caps the
+// points per thread (the fused x-pass + binning keeps two meshes' lines in
+// registers and uses fewer points per thread).
+template <typename T, int N, int EM = e_max<T>()>
 struct ColCfg {
   static constexpr int L = N;
-  static constexpr int E = L < e_max<T>() ? L : e_max<T>();
+  static constexpr int E = L < EM ? L : EM;
   static constexpr int TPL = L / E;
   static constexpr int NC = N / 2;
   static constexpr int pick() {
     int c = 256 / TPL;
     if (c < 8) c = 8;
+    while (c > 1 && c * TPL > 1024) c /= 2;
     while (c > 1 && (long)c * lds_pad_len<L>() * (long)sizeof(cpx<T>) > 80 * 1024) c /= 2;
     if (c > NC) c = NC;
     return c;
@@ -53,5 +56,9 @@ __device__ __forceinline__ int xcd_pair_tile(int g, int ntiles) {
   if (ntiles & 15) return g;
   return (g & ~15) | ((g & 7) << 1) | ((g >> 3) & 1);
 }
+
+// Launch shape of the fused x-pass + binning kernel.
+template <typename T, int N>
+using XCfg = ColCfg<T, N, (sizeof(T) == 4 ? 8 : 4)>;
 
 }  // namespace pk

@@ -137,14 +137,48 @@ struct LdsLine {
   __device__ __forceinline__ cpx<T> get(int j) const { return base[j + (j >> 4)]; }
 };
 
+// Twiddle sources: W_Nt^j for the table length Nt (a power of two >= 4).
+//  TwGlobal   the full table tw[j * s] in global memory;
+//  TwQuarter  the first quarter q[r] = W_Nt^r, r < Nt / 4, kept in LDS; the
+//             other quadrants follow from W^(r + a Nt/4) = (-i)^a W^r.
+template <typename T>
+struct TwGlobal {
+  const cpx<T>* __restrict__ p;
+  int s;
+  __device__ __forceinline__ cpx<T> operator()(int j) const { return p[j * s]; }
+};
+
+template <typename T>
+struct TwQuarter {
+  const cpx<T>* q;
+  int s;          // index stride (2 when an Nt/2-point FFT reads the Nt table)
+  int log2q;      // log2(Nt / 4)
+  __device__ __forceinline__ cpx<T> operator()(int j) const {
+    const int jj = j * s;
+    const int a = (jj >> log2q) & 3;
+    const cpx<T> w = q[jj & ((1 << log2q) - 1)];
+    if (a == 0) return w;
+    if (a == 1) return {w.y, -w.x};
+    if (a == 2) return {-w.x, -w.y};
+    return {-w.y, w.x};
+  }
+};
+
+// Loads the first quarter of the global table W_Nt^j into LDS (all threads
+// call it; it ends with a barrier).
+template <typename T>
+__device__ __forceinline__ void load_quarter(cpx<T>* dst, const cpx<T>* __restrict__ tw, int nt) {
+  for (int i = threadIdx.x; i < nt / 4; i += blockDim.x) dst[i] = tw[i];
+  __syncthreads();
+}
+
 // Forward DFT of one line of L points, in place in registers: on entry
 // v[e] = x[t + TPL e], on exit v[e] = X[t + TPL e], X_k = sum_j x_j W_L^{jk},
-// W_L = exp(-2 pi i / L).  tw[j * tws] must hold W_L^j.  Every thread of the
+// W_L = exp(-2 pi i / L).  tw(j) must return W_L^j.  Every thread of the
 // workgroup must call this with the same template arguments (it contains
 // barriers).
-template <typename T, int L, int E, int P, typename Lds>
-__device__ __forceinline__ void stockham(cpx<T>* v, int t, const cpx<T>* __restrict__ tw,
-                                         int tws, Lds& lds) {
+template <typename T, int L, int E, int P, typename Lds, typename Tw>
+__device__ __forceinline__ void stockham(cpx<T>* v, int t, const Tw& tw, Lds& lds) {
   if constexpr (P < L) {
     constexpr int R = stage_radix<L, E, P>();
     constexpr int TPL = L / E;
@@ -160,7 +194,7 @@ __device__ __forceinline__ void stockham(cpx<T>* v, int t, const cpx<T>* __restr
       for (int m = 0; m < R; ++m) a[m] = v[q + m * Q];
       if constexpr (P > 1) {
 #pragma unroll
-        for (int m = 1; m < R; ++m) a[m] = cmul(a[m], tw[(m * k * (L / (P * R))) * tws]);
+        for (int m = 1; m < R; ++m) a[m] = cmul(a[m], tw(m * k * (L / (P * R))));
       }
       dft<T, R>(a);
       if constexpr (LAST) {
@@ -176,7 +210,7 @@ __device__ __forceinline__ void stockham(cpx<T>* v, int t, const cpx<T>* __restr
       __syncthreads();
 #pragma unroll
       for (int e = 0; e < E; ++e) v[e] = lds.get(t + TPL * e);
-      stockham<T, L, E, P * R>(v, t, tw, tws, lds);
+      stockham<T, L, E, P * R>(v, t, tw, lds);
     }
   }
 }

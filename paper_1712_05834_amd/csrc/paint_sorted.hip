@@ -295,6 +295,7 @@ __global__ void __launch_bounds__((PaintCfg<T, N, P, INTER>::THREADS))
   constexpr int ROWS = Cf::ROWS, ROWD = Cf::ROWD;
   constexpr int mask = N - 1;
   __shared__ double acc[ROWS * ROWD];
+  __shared__ cpx<T> twq[N / 4];
   __shared__ int seg_start[2 * (TX + 4)], seg_cum[2 * (TX + 4) + 1], seg_row[2 * (TX + 4)];
   static_assert(TX + 4 >= (TX + Cf::HLO + Cf::HHI < N ? TX + Cf::HLO + Cf::HHI : N), "segments");
   __shared__ int nseg_sh;
@@ -303,6 +304,7 @@ __global__ void __launch_bounds__((PaintCfg<T, N, P, INTER>::THREADS))
   const int X0 = (blockIdx.x / tiles_y) * TX, Y0 = (blockIdx.x % tiles_y) * TY;
 
   for (int i = threadIdx.x; i < ROWS * ROWD; i += blockDim.x) acc[i] = 0.0;
+  for (int i = threadIdx.x; i < N / 4; i += blockDim.x) twq[i] = tw[i];
 
   // segments of the sorted records: for each source row bx, the contiguous
   // column range [by0, by0 + wy) (split in two where it wraps around N); one
@@ -444,7 +446,8 @@ __global__ void __launch_bounds__((PaintCfg<T, N, P, INTER>::THREADS))
     v[e] = {static_cast<T>(arow[2 * j] - mean), static_cast<T>(arow[2 * j + 1] - mean)};
   }
   __syncthreads();  // all float64 cells read before the row is reused
-  stockham<T, M, E, 1>(v, t, tw, 2, line);
+  const TwQuarter<T> tw2{twq, 2, ilog2(N / 4)}, tw1{twq, 1, ilog2(N / 4)};
+  stockham<T, M, E, 1>(v, t, tw2, line);
   __syncthreads();
 #pragma unroll
   for (int e = 0; e < E; ++e) line.put(t + TPL * e, v[e]);
@@ -461,7 +464,7 @@ __global__ void __launch_bounds__((PaintCfg<T, N, P, INTER>::THREADS))
     } else {
       const cpx<T> zc = cconj(line.get(M - k));
       const cpx<T> s = cadd(v[e], zc);
-      const cpx<T> w = cmul(tw[k], csub(v[e], zc));
+      const cpx<T> w = cmul(tw1(k), csub(v[e], zc));
       o = {T(0.5) * (s.x + w.y), T(0.5) * (s.y - w.x)};
     }
     rowp[k] = o;
