@@ -11,10 +11,9 @@
 // 4. k_paint_z        one workgroup owns a TX x TY block of full z-columns of
 //                     both meshes: it reads the records of the columns whose
 //                     windows reach the block, adds the window weights into
-//                     fixed-point integer LDS rows (ds_add_u32 / _u64), then
-//                     runs the r2c FFT of every column in LDS and writes the
-//                     packed rows once.  No mesh clear, no atomics to HBM, no
-//                     separate z-pass.
+//                     float64 LDS rows (ds_add_f64), then runs the r2c FFT of
+//                     every column in LDS and writes the packed rows once.  No
+//                     mesh clear, no atomics to HBM, no separate z-pass.
 #include "fft_config.h"
 #include "internal.h"
 #include "window.h"
@@ -70,7 +69,7 @@ __global__ void __launch_bounds__(256)
     k_bucket_count(const T* __restrict__ pos, const T* __restrict__ weight, int64_t n, int nmesh,
                    double boxsize, int* __restrict__ count, double* __restrict__ wpart) {
   const int mask = nmesh - 1;
-  double ws = 0.0, ws2 = 0.0, wmax = 0.0;
+  double ws = 0.0, ws2 = 0.0;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   // whole wavefronts iterate together so that claim_slot sees full waves
   const int64_t nround = (n + stride - 1) / stride * stride;
@@ -83,58 +82,46 @@ __global__ void __launch_bounds__(256)
       const double wp = weight ? (double)weight[i] : 1.0;
       ws += wp;
       ws2 += wp * wp;
-      wmax = fmax(wmax, fabs(wp));
     }
     (void)claim_slot(key, count);
   }
-  // per-block partial sums and maximum |w| (reduced in a fixed order by
-  // k_weight_sums)
-  __shared__ double part[3][4];
+  // per-block partial sums (reduced in a fixed order by k_weight_sums)
+  __shared__ double part[2][4];
   ws = wave_sum_d(ws);
   ws2 = wave_sum_d(ws2);
-#pragma unroll
-  for (int off = 32; off >= 1; off >>= 1) wmax = fmax(wmax, __shfl_xor(wmax, off, 64));
   if ((threadIdx.x & 63) == 0) {
     part[0][threadIdx.x >> 6] = ws;
     part[1][threadIdx.x >> 6] = ws2;
-    part[2][threadIdx.x >> 6] = wmax;
   }
   __syncthreads();
   if (threadIdx.x == 0) {
-    wpart[3 * blockIdx.x] = ((part[0][0] + part[0][1]) + part[0][2]) + part[0][3];
-    wpart[3 * blockIdx.x + 1] = ((part[1][0] + part[1][1]) + part[1][2]) + part[1][3];
-    wpart[3 * blockIdx.x + 2] = fmax(fmax(part[2][0], part[2][1]), fmax(part[2][2], part[2][3]));
+    wpart[2 * blockIdx.x] = ((part[0][0] + part[0][1]) + part[0][2]) + part[0][3];
+    wpart[2 * blockIdx.x + 1] = ((part[1][0] + part[1][1]) + part[1][2]) + part[1][3];
   }
 }
 
-// sum w and sum w^2 from the per-block partials, in block order; max |w| into
-// wmax_out (bounds the mass any cell can receive in the fused paint).
+// sum w and sum w^2 from the per-block partials, in block order.
 __global__ void __launch_bounds__(1024)
-    k_weight_sums(const double* __restrict__ wpart, int nblocks, double* __restrict__ wsums,
-                  double* __restrict__ wmax_out) {
-  __shared__ double sh[3][1024];
-  double a = 0.0, b = 0.0, m = 0.0;
+    k_weight_sums(const double* __restrict__ wpart, int nblocks, double* __restrict__ wsums) {
+  __shared__ double sh[2][1024];
+  double a = 0.0, b = 0.0;
   for (int i = threadIdx.x; i < nblocks; i += 1024) {
-    a += wpart[3 * i];
-    b += wpart[3 * i + 1];
-    m = fmax(m, wpart[3 * i + 2]);
+    a += wpart[2 * i];
+    b += wpart[2 * i + 1];
   }
   sh[0][threadIdx.x] = a;
   sh[1][threadIdx.x] = b;
-  sh[2][threadIdx.x] = m;
   __syncthreads();
   for (int half = 512; half >= 1; half >>= 1) {
     if ((int)threadIdx.x < half) {
       sh[0][threadIdx.x] += sh[0][threadIdx.x + half];
       sh[1][threadIdx.x] += sh[1][threadIdx.x + half];
-      sh[2][threadIdx.x] = fmax(sh[2][threadIdx.x], sh[2][threadIdx.x + half]);
     }
     __syncthreads();
   }
   if (threadIdx.x == 0) {
     wsums[0] = sh[0][0];
     wsums[1] = sh[1][0];
-    wmax_out[0] = sh[2][0];
   }
 }
 
@@ -257,37 +244,17 @@ __global__ void __launch_bounds__(1024)
 // ---- fused paint + r2c z-pass
 
 // Columns per workgroup (TX x TY) and halo of source columns per mesh size.
-// The window weights are accumulated in LDS rows as fixed-point integers
-// (int32 for float meshes, int64 for double meshes) with ds_add_u32 / _u64:
-// on gfx950 these run 40x / 25x faster than ds_add_f32, integer sums do not
-// depend on the order of the additions, and a row keeps the footprint of the
-// mesh precision.  The scale of a workgroup, S = (2^(bits-1) - 1 - n) /
-// (n max|w|) for its n source particles, keeps every cell (whose mass is at
-// most n max|w|) clear of overflow.  After the gather a row is reused in place
-// as the padded complex line of the r2c.
-template <typename T>
-struct FixedAcc;
-template <>
-struct FixedAcc<float> {
-  using type = int;
-  static constexpr double kMax = 2147483647.0;
-  __device__ static __forceinline__ int round(float v) { return __float2int_rn(v); }
-  __device__ static __forceinline__ void add(int* p, int v) { atomicAdd(p, v); }
-};
-template <>
-struct FixedAcc<double> {
-  using type = long long;
-  static constexpr double kMax = 9223372036854775807.0 / 2.0;  // headroom for rounding
-  __device__ static __forceinline__ long long round(double v) { return __double2ll_rn(v); }
-  // two's complement: the unsigned add gives the signed sum
-  __device__ static __forceinline__ void add(long long* p, long long v) {
-    atomicAdd(reinterpret_cast<unsigned long long*>(p), static_cast<unsigned long long>(v));
-  }
-};
+// The window weights are accumulated in float64 LDS rows with ds_add_f64: on
+// gfx950 it runs about 20x faster than ds_add_f32, and the accumulation is
+// more precise than the mesh.  (Integer fixed point with ds_add_u32 is faster
+// still, but a 32-bit range cannot hold a dense workgroup's cells at float
+// precision.)  After the gather a row is reused in place as the padded complex
+// line of the r2c.
+constexpr int kPaintLdsBudgetKB = 76;  // two workgroups per CU
 
 template <typename T, int N, int P, bool INTER>
 struct PaintCfg {
-  using Acc = typename FixedAcc<T>::type;
+  using Acc = double;
   static constexpr int M = N / 2;
   static constexpr int LP = lds_pad_len<M>();           // complex per FFT line
   static constexpr int NM = INTER ? 2 : 1;
@@ -300,7 +267,7 @@ struct PaintCfg {
   // LDS budget per workgroup: two workgroups per CU
   static constexpr int pick_cols() {
     int cols = 64;
-    while (cols > 1 && (long)cols * NM * ROW_BYTES > 76 * 1024) cols /= 2;
+    while (cols > 1 && (long)cols * NM * ROW_BYTES > kPaintLdsBudgetKB * 1024) cols /= 2;
     while (cols > 1 && (long)cols * NM * (M / EMAX) > 1024) cols /= 2;
     return cols;
   }
@@ -329,10 +296,10 @@ template <typename T, int N, int P, bool INTER>
 __global__ void __launch_bounds__((PaintCfg<T, N, P, INTER>::THREADS))
     k_paint_z(const typename Rec<T>::type* __restrict__ rec, const T* __restrict__ wrec,
               const int* __restrict__ offsets, const double* __restrict__ wsums,
-              const double* __restrict__ wmax, const cpx<T>* __restrict__ tw,
+              const cpx<T>* __restrict__ tw,
               T* __restrict__ mesh_a, T* __restrict__ mesh_b) {
   using Cf = PaintCfg<T, N, P, INTER>;
-  using Acc = typename Cf::Acc;
+  using Acc = double;
   constexpr int M = Cf::M, E = Cf::E, TPL = Cf::TPL, TX = Cf::TX, TY = Cf::TY;
   constexpr int ROWS = Cf::ROWS, ROWA = Cf::ROWA;
   constexpr int mask = N - 1;
@@ -389,10 +356,6 @@ __global__ void __launch_bounds__((PaintCfg<T, N, P, INTER>::THREADS))
   const int nseg = nseg_sh;
   const int total = seg_cum[nseg];
   const int R = (total + 63) >> 6;
-  // fixed-point scale of this workgroup (see FixedAcc)
-  const double wm = wrec ? wmax[0] : 1.0;
-  const double scale = total > 0 && wm > 0 ? (FixedAcc<T>::kMax - total) / (total * wm) : 1.0;
-  const T scale_t = static_cast<T>(scale);
   // record index of work item q (-1 past the end); the next record is loaded
   // before the current one is processed, so its latency overlaps the work
   auto locate = [&](int q, int& seg) -> int {
@@ -466,7 +429,7 @@ __global__ void __launch_bounds__((PaintCfg<T, N, P, INTER>::THREADS))
             Acc* row = acc + ((mesh * TX + lx) * TY + ly) * ROWA;
 #pragma unroll
             for (int c = 0; c < P; ++c)
-              FixedAcc<T>::add(&row[(first[2] + c) & mask], FixedAcc<T>::round(wab * w[2][c] * scale_t));
+              atomicAdd(&row[(first[2] + c) & mask], (double)(wab * w[2][c]));
           }
         }
       }
@@ -478,12 +441,10 @@ __global__ void __launch_bounds__((PaintCfg<T, N, P, INTER>::THREADS))
   }
   __syncthreads();
 
-  // r2c along z of every owned column; the cells leave fixed point in float64
-  // and the mean is subtracted before the rounding to T (only the DC mode
-  // changes; it keeps the rounding relative to the fluctuations).  The row
-  // becomes the padded complex line.
+  // r2c along z of every owned column, mean subtracted in float64 before the
+  // rounding to T (only the DC mode changes; it keeps the rounding relative to
+  // the fluctuations).  The row becomes the padded complex line.
   const double mean = wsums[0] / ((double)N * N * N);
-  const double inv_scale = 1.0 / scale;
   const int r = threadIdx.x / TPL, t = threadIdx.x % TPL;
   Acc* arow = acc + r * ROWA;
   LdsLine<T> line{reinterpret_cast<cpx<T>*>(arow)};
@@ -491,8 +452,7 @@ __global__ void __launch_bounds__((PaintCfg<T, N, P, INTER>::THREADS))
 #pragma unroll
   for (int e = 0; e < E; ++e) {
     const int j = t + TPL * e;
-    v[e] = {static_cast<T>((double)arow[2 * j] * inv_scale - mean),
-            static_cast<T>((double)arow[2 * j + 1] * inv_scale - mean)};
+    v[e] = {static_cast<T>(arow[2 * j] - mean), static_cast<T>(arow[2 * j + 1] - mean)};
   }
   __syncthreads();  // all cells read before the row is reused
   const TwQuarter<T> tw2{twq, 2, ilog2(N / 4)}, tw1{twq, 1, ilog2(N / 4)};
@@ -527,10 +487,9 @@ constexpr int kCountBlocks = 8192;
 size_t bucket_bytes(int nmesh) {
   const size_t n2 = (size_t)nmesh * nmesh;
   const size_t nb = (n2 + 4095) / 4096;
-  // count, offsets (+1), cursor, scan block sums; then float64 weight
-  // partials (3 per block) and max |w|
+  // count, offsets (+1), cursor, scan block sums; then float64 weight partials
   const size_t ints = (3 * n2 + 1 + nb + 1) & ~(size_t)1;
-  return ints * sizeof(int) + (3 * kCountBlocks + 1) * sizeof(double);
+  return ints * sizeof(int) + 2 * kCountBlocks * sizeof(double);
 }
 
 hipError_t launch_bucket(int dtype, int nmesh, double boxsize, const void* pos, const void* weight,
@@ -557,8 +516,7 @@ hipError_t launch_bucket(int dtype, int nmesh, double boxsize, const void* pos, 
     hipLaunchKernelGGL(k_bucket_count<double>, dim3((unsigned)blocks), dim3(256), 0, s,
                        static_cast<const double*>(pos), static_cast<const double*>(weight), n,
                        nmesh, boxsize, count, wpart);
-  hipLaunchKernelGGL(k_weight_sums, dim3(1), dim3(1024), 0, s, wpart, (int)blocks, wsums,
-                     wpart + 3 * kCountBlocks);
+  hipLaunchKernelGGL(k_weight_sums, dim3(1), dim3(1024), 0, s, wpart, (int)blocks, wsums);
   hipLaunchKernelGGL(k_scan_blocks, dim3(nb), dim3(1024), 0, s, count, n2, bsums);
   hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(1024), 0, s, bsums, nb);
   hipLaunchKernelGGL(k_scan_final, dim3(nb), dim3(1024), 0, s, count, n2, bsums, offsets, cursor);
@@ -577,13 +535,13 @@ hipError_t launch_bucket(int dtype, int nmesh, double boxsize, const void* pos, 
 
 template <typename T, int N, int P, bool INTER>
 static hipError_t paint_z_t(const void* rec, const void* wrec, const int* offsets,
-                            const double* wsums, const double* wmax, const void* tw,
+                            const double* wsums, const void* tw,
                             void* mesh_a, void* mesh_b, hipStream_t s) {
   using Cf = PaintCfg<T, N, P, INTER>;
   const unsigned blocks = (unsigned)((N / Cf::TX) * (N / Cf::TY));
   hipLaunchKernelGGL((k_paint_z<T, N, P, INTER>), dim3(blocks), dim3(Cf::THREADS), 0, s,
                      static_cast<const typename Rec<T>::type*>(rec),
-                     static_cast<const T*>(wrec), offsets, wsums, wmax,
+                     static_cast<const T*>(wrec), offsets, wsums,
                      static_cast<const cpx<T>*>(tw), static_cast<T*>(mesh_a),
                      static_cast<T*>(mesh_b));
   return hipGetLastError();
@@ -591,9 +549,9 @@ static hipError_t paint_z_t(const void* rec, const void* wrec, const int* offset
 
 template <typename T, int N>
 static hipError_t paint_z_n(int order, bool inter, const void* rec, const void* wrec,
-                            const int* offsets, const double* wsums, const double* wmax,
-                            const void* tw, void* mesh_a, void* mesh_b, hipStream_t s) {
-#define PK_PZ(P, I) return paint_z_t<T, N, P, I>(rec, wrec, offsets, wsums, wmax, tw, mesh_a, mesh_b, s)
+                            const int* offsets, const double* wsums, const void* tw,
+                            void* mesh_a, void* mesh_b, hipStream_t s) {
+#define PK_PZ(P, I) return paint_z_t<T, N, P, I>(rec, wrec, offsets, wsums, tw, mesh_a, mesh_b, s)
   if (inter) {
     if (order == 2) PK_PZ(2, true);
     if (order == 3) PK_PZ(3, true);
@@ -610,21 +568,17 @@ hipError_t launch_paint_z(int dtype, int nmesh, int order, bool inter, const voi
                           const void* wrec, const void* bucket_ws, const double* wsums,
                           const void* tw, void* mesh_a, void* mesh_b, hipStream_t s) {
   const int* offsets = static_cast<const int*>(bucket_ws) + (size_t)nmesh * nmesh;
-  const size_t n2 = (size_t)nmesh * nmesh;
-  const size_t ints = (3 * n2 + 1 + (n2 + 4095) / 4096 + 1) & ~(size_t)1;
-  const double* wmax =
-      reinterpret_cast<const double*>(static_cast<const int*>(bucket_ws) + ints) + 3 * kCountBlocks;
 #define PK_PN(T)                                                                           \
   switch (nmesh) {                                                                         \
-    case 8: return paint_z_n<T, 8>(order, inter, rec, wrec, offsets, wsums, wmax, tw, mesh_a, mesh_b, s); \
-    case 16: return paint_z_n<T, 16>(order, inter, rec, wrec, offsets, wsums, wmax, tw, mesh_a, mesh_b, s); \
-    case 32: return paint_z_n<T, 32>(order, inter, rec, wrec, offsets, wsums, wmax, tw, mesh_a, mesh_b, s); \
-    case 64: return paint_z_n<T, 64>(order, inter, rec, wrec, offsets, wsums, wmax, tw, mesh_a, mesh_b, s); \
-    case 128: return paint_z_n<T, 128>(order, inter, rec, wrec, offsets, wsums, wmax, tw, mesh_a, mesh_b, s); \
-    case 256: return paint_z_n<T, 256>(order, inter, rec, wrec, offsets, wsums, wmax, tw, mesh_a, mesh_b, s); \
-    case 512: return paint_z_n<T, 512>(order, inter, rec, wrec, offsets, wsums, wmax, tw, mesh_a, mesh_b, s); \
-    case 1024: return paint_z_n<T, 1024>(order, inter, rec, wrec, offsets, wsums, wmax, tw, mesh_a, mesh_b, s); \
-    case 2048: return paint_z_n<T, 2048>(order, inter, rec, wrec, offsets, wsums, wmax, tw, mesh_a, mesh_b, s); \
+    case 8: return paint_z_n<T, 8>(order, inter, rec, wrec, offsets, wsums, tw, mesh_a, mesh_b, s); \
+    case 16: return paint_z_n<T, 16>(order, inter, rec, wrec, offsets, wsums, tw, mesh_a, mesh_b, s); \
+    case 32: return paint_z_n<T, 32>(order, inter, rec, wrec, offsets, wsums, tw, mesh_a, mesh_b, s); \
+    case 64: return paint_z_n<T, 64>(order, inter, rec, wrec, offsets, wsums, tw, mesh_a, mesh_b, s); \
+    case 128: return paint_z_n<T, 128>(order, inter, rec, wrec, offsets, wsums, tw, mesh_a, mesh_b, s); \
+    case 256: return paint_z_n<T, 256>(order, inter, rec, wrec, offsets, wsums, tw, mesh_a, mesh_b, s); \
+    case 512: return paint_z_n<T, 512>(order, inter, rec, wrec, offsets, wsums, tw, mesh_a, mesh_b, s); \
+    case 1024: return paint_z_n<T, 1024>(order, inter, rec, wrec, offsets, wsums, tw, mesh_a, mesh_b, s); \
+    case 2048: return paint_z_n<T, 2048>(order, inter, rec, wrec, offsets, wsums, tw, mesh_a, mesh_b, s); \
     default: return hipErrorInvalidValue;                                                  \
   }
   if (dtype == PK_F32) {
