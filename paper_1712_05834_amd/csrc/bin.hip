@@ -113,11 +113,11 @@ __global__ void __launch_bounds__((XCfg<T, N>::THREADS))
   using Cf = XCfg<T, N>;
   constexpr int E = Cf::E, TPL = Cf::TPL, C = Cf::C, NC = Cf::NC, CHUNKS = Cf::CHUNKS;
   __shared__ cpx<T> lds[Cf::LDS_ELEMS];
-  __shared__ cpx<T> twq[N / 4];
+  __shared__ cpx<T> tws[stage_table_size<N, E>() + 1];
   extern __shared__ double sb[];
   zero_bins(sb, b.nsum);
-  load_quarter(twq, tw, N);  // ends with a barrier
-  const TwQuarter<T> tw1{twq, 1, ilog2(N / 4)};
+  build_stage_table<T, N, E>(tws, TwGlobal<T>{tw, 1});  // ends with a barrier
+  const TwStage<T, N, E> tw1{tws};
   const int c = threadIdx.x % C, t = threadIdx.x / C;
   const int los = b.los;
   const bool two = mesh_b != nullptr;

@@ -20,8 +20,11 @@ __global__ void __launch_bounds__((ZCfg<T, N>::THREADS))
   constexpr int M = Z::M, E = Z::E, TPL = Z::TPL, RPB = Z::RPB;
   __shared__ cpx<T> lds[RPB * Z::LP];
   __shared__ cpx<T> twq[N / 4];
+  __shared__ cpx<T> tws[stage_table_size<M, E>() + 1];
+  build_stage_table<T, M, E>(tws, TwGlobal<T>{tw, 2});
   load_quarter(twq, tw, N);
-  const TwQuarter<T> tw2{twq, 2, ilog2(N / 4)}, tw1{twq, 1, ilog2(N / 4)};
+  const TwStage<T, M, E> tw2{tws};
+  const TwQuarter<T> tw1{twq, 1, ilog2(N / 4)};
   const int r = threadIdx.x / TPL, t = threadIdx.x % TPL;
   const size_t nrows = (size_t)N * N;
   const size_t row = (size_t)blockIdx.x * RPB + r;
@@ -71,9 +74,9 @@ __global__ void __launch_bounds__((ColCfg<T, N>::THREADS))
   using Cf = ColCfg<T, N>;
   constexpr int E = Cf::E, TPL = Cf::TPL, C = Cf::C, NC = Cf::NC;
   __shared__ cpx<T> lds[Cf::LDS_ELEMS];
-  __shared__ cpx<T> twq[N / 4];
-  load_quarter(twq, tw, N);
-  const TwQuarter<T> tw1{twq, 1, ilog2(N / 4)};
+  __shared__ cpx<T> tws[stage_table_size<N, E>() + 1];
+  build_stage_table<T, N, E>(tws, TwGlobal<T>{tw, 1});
+  const TwStage<T, N, E> tw1{tws};
   const int c = threadIdx.x % C, t = threadIdx.x / C;
   const int tile = xcd_pair_tile(blockIdx.x, N * Cf::CHUNKS);
   const int outer = tile / Cf::CHUNKS, chunk = tile % Cf::CHUNKS;

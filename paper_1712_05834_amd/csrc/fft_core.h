@@ -146,6 +146,11 @@ struct TwGlobal {
   const cpx<T>* __restrict__ p;
   int s;
   __device__ __forceinline__ cpx<T> operator()(int j) const { return p[j * s]; }
+  // twiddle m of butterfly k in the radix-R stage of span P of an L-point FFT
+  template <int L, int P, int R>
+  __device__ __forceinline__ cpx<T> stage(int k, int m) const {
+    return (*this)(m * k * (L / (P * R)));
+  }
 };
 
 template <typename T>
@@ -162,7 +167,69 @@ struct TwQuarter {
     if (a == 2) return {-w.x, -w.y};
     return {-w.y, w.x};
   }
+  template <int L, int P, int R>
+  __device__ __forceinline__ cpx<T> stage(int k, int m) const {
+    return (*this)(m * k * (L / (P * R)));
+  }
 };
+
+// Per-stage twiddle table in LDS: for the stage of span P and radix R the
+// entries W_L^{m k L / (P R)}, k < P, m = 1 .. R-1, stored [k][m-1], built
+// once per workgroup.  A butterfly then reads its R-1 twiddles from
+// consecutive LDS words, with no index arithmetic and no quadrant selects.
+template <int L, int E, int P>
+__host__ __device__ constexpr int stage_table_offset() {
+  if constexpr (P <= 1) {
+    return 0;
+  } else {
+    // offset of span P = offset of the previous span + its entries
+    constexpr int R0 = stage_radix<L, E, 1>();
+    int off = 0, p = R0;  // the first stage (span 1) has no twiddles
+    while (p < P) {
+      off += p * (E - 1);
+      p *= E;
+    }
+    return off;
+  }
+}
+
+template <int L, int E>
+__host__ __device__ constexpr int stage_table_size() {
+  constexpr int R0 = stage_radix<L, E, 1>();
+  int off = 0, p = R0;
+  while (p < L) {
+    off += p * (E - 1);
+    p *= E;
+  }
+  return off;
+}
+
+template <typename T, int L, int E>
+struct TwStage {
+  const cpx<T>* t;
+  template <int LL, int P, int R>
+  __device__ __forceinline__ cpx<T> stage(int k, int m) const {
+    static_assert(LL == L && R == E, "table built for this plan");
+    return t[stage_table_offset<L, E, P>() + k * (R - 1) + (m - 1)];
+  }
+};
+
+// Fills a TwStage table (size stage_table_size<L, E>()) from any twiddle
+// source; all threads call it; it ends with a barrier.
+template <typename T, int L, int E, typename Src>
+__device__ __forceinline__ void build_stage_table(cpx<T>* dst, const Src& src) {
+  constexpr int R0 = stage_radix<L, E, 1>();
+  for (int i = threadIdx.x; i < stage_table_size<L, E>(); i += blockDim.x) {
+    int off = 0, p = R0;
+    while (i >= off + p * (E - 1)) {
+      off += p * (E - 1);
+      p *= E;
+    }
+    const int k = (i - off) / (E - 1), m = (i - off) % (E - 1) + 1;
+    dst[i] = src(m * k * (L / (p * E)));
+  }
+  __syncthreads();
+}
 
 // Loads the first quarter of the global table W_Nt^j into LDS (all threads
 // call it; it ends with a barrier).
@@ -194,7 +261,7 @@ __device__ __forceinline__ void stockham(cpx<T>* v, int t, const Tw& tw, Lds& ld
       for (int m = 0; m < R; ++m) a[m] = v[q + m * Q];
       if constexpr (P > 1) {
 #pragma unroll
-        for (int m = 1; m < R; ++m) a[m] = cmul(a[m], tw(m * k * (L / (P * R))));
+        for (int m = 1; m < R; ++m) a[m] = cmul(a[m], tw.template stage<L, P, R>(k, m));
       }
       dft<T, R>(a);
       if constexpr (LAST) {
