@@ -87,8 +87,11 @@ const char* check_bins(const pk_bin_desc* b, const pk_mesh_desc* m) {
 // Slot limits of the LDS bins (float64).
 constexpr int kMaxLdsSlots = 8192;
 
-const char* check_lds(const pk_bin_desc* b) {
+const char* check_lds(const pk_bin_desc* b, const pk_mesh_desc* m) {
   if (nsum_of(b) > kMaxLdsSlots) return "too many bin slots for the LDS accumulator";
+  if (m && xpass_static_lds(m->dtype, m->nmesh) +
+                   (size_t)nsum_of(b) * sizeof(double) > kLdsBytesPerGroup)
+    return "too many bin slots for the LDS accumulator at this mesh size and precision";
   if (mode_table_slots(b->nk, b->nmu > 1 ? b->nmu : 0) > kMaxLdsSlots)
     return "too many (k, mu) bins for the mode-table accumulator";
   return nullptr;
@@ -312,8 +315,8 @@ const char* const kStageNames[kNumStages] = {"bucket", "paint_z", "fft_y",
 
 // Workspace layout of pk_fftpower (offsets in bytes, 256-aligned).
 struct Layout {
-  size_t mesh_a = 0, mesh_b = 0, side_a = 0, side_b = 0, partials = 0, bucket = 0, rec = 0,
-         wrec = 0, total = 0;
+  size_t mesh_a = 0, mesh_b = 0, ytmp = 0, side_a = 0, side_b = 0, partials = 0, bucket = 0,
+         rec = 0, wrec = 0, total = 0;
   int gx = 0, gp = 0;
 };
 
@@ -332,6 +335,8 @@ Layout layout_of(const pk_mesh_desc* m, const pk_bin_desc* b, int64_t npart) {
   off += mesh;
   l.mesh_b = off;
   off += two * mesh;
+  l.ytmp = off;  // y-pass output of mesh A (mesh B's goes to mesh A's buffer)
+  off += mesh;
   l.side_a = off;
   off += side;
   l.side_b = off;
@@ -479,7 +484,7 @@ pk_status pk_bin_power(pk_ctx* ctx, const pk_mesh_desc* m, const pk_bin_desc* b,
   if (const char* why = check_mesh(m)) return fail(ctx, PK_EINVAL, why);
   if (const char* why = check_bins(b, m)) return fail(ctx, PK_EINVAL, why);
   if (!cmesh || !result_dev) return fail(ctx, PK_EINVAL, "cmesh or result is NULL");
-  if (const char* why = check_lds(b)) return fail(ctx, PK_EUNSUPPORTED, why);
+  if (const char* why = check_lds(b, m)) return fail(ctx, PK_EUNSUPPORTED, why);
   if (ctx->device == PK_DEVICE_NONE) return fail(ctx, PK_EDEVICE, "validation-only context");
   DeviceGuard g(ctx->device);
   BinTables* bt = nullptr;
@@ -514,7 +519,7 @@ pk_status pk_fftpower(pk_ctx* ctx, const pk_mesh_desc* m, const pk_bin_desc* b, 
   if (!workspace || !result_dev) return fail(ctx, PK_EINVAL, "workspace or result is NULL");
   const Layout l = layout_of(m, b, n);
   if (workspace_bytes < l.total) return fail(ctx, PK_EINVAL, "workspace too small");
-  if (const char* why = check_lds(b)) return fail(ctx, PK_EUNSUPPORTED, why);
+  if (const char* why = check_lds(b, m)) return fail(ctx, PK_EUNSUPPORTED, why);
   if (ctx->device == PK_DEVICE_NONE) return fail(ctx, PK_EDEVICE, "validation-only context");
   DeviceGuard g(ctx->device);
   BinTables* bt = nullptr;
@@ -529,10 +534,8 @@ pk_status pk_fftpower(pk_ctx* ctx, const pk_mesh_desc* m, const pk_bin_desc* b, 
   void* side_b = m->interlaced ? ws + l.side_b : nullptr;
   double* partials = reinterpret_cast<double*>(ws + l.partials);
   double* wsums = result_dev + spec.nsum;
-  const int nm = m->interlaced ? 2 : 1;
   hipStream_t s = ctx->stream;
   for (bool& r : ctx->stage_ran) r = false;
-  const size_t stride = l.mesh_b - l.mesh_a;
   void* rec = ws + l.rec;
   void* wrec = weight ? ws + l.wrec : nullptr;
   mark_stage(ctx, kBucket);
@@ -542,11 +545,16 @@ pk_status pk_fftpower(pk_ctx* ctx, const pk_mesh_desc* m, const pk_bin_desc* b, 
   if (e == hipSuccess)
     e = launch_paint_z(m->dtype, m->nmesh, m->window, m->interlaced != 0, rec, wrec,
                        ws + l.bucket, wsums, t->tw, mesh_a, mesh_b, s);
+  // y-pass out of place into the x-pass layout: A into the spare buffer,
+  // then B into A's buffer, which A no longer needs
   mark_stage(ctx, kFftY);
-  if (e == hipSuccess) e = launch_fft_cols(m->dtype, m->nmesh, mesh_a, nm, stride, t->tw, 1, s);
+  void* ya = ws + l.ytmp;
+  void* yb = m->interlaced ? mesh_a : nullptr;
+  if (e == hipSuccess) e = launch_fft_y_relayout(m->dtype, m->nmesh, mesh_a, ya, t->tw, s);
+  if (e == hipSuccess && yb) e = launch_fft_y_relayout(m->dtype, m->nmesh, mesh_b, yb, t->tw, s);
   mark_stage(ctx, kXpassBin);
   if (e == hipSuccess)
-    e = launch_xpass_bin(m->dtype, m->nmesh, mesh_a, mesh_b, *t, m->window, m->compensated, spec,
+    e = launch_xpass_bin(m->dtype, m->nmesh, ya, yb, *t, m->window, m->compensated, spec,
                          partials, side_a, side_b, s);
   mark_stage(ctx, kPlaneBin);
   if (e == hipSuccess)
@@ -567,7 +575,7 @@ pk_status pk_result_to_host(pk_ctx* ctx, const pk_mesh_desc* m, const pk_bin_des
   if (!result_dev || !out || !out->k || !out->power || !out->modes)
     return fail(ctx, PK_EINVAL, "result, out or one of its 1-D arrays is NULL");
   if (b->npoles > 0 && !out->poles) return fail(ctx, PK_EINVAL, "out->poles is NULL");
-  if (const char* why = check_lds(b)) return fail(ctx, PK_EUNSUPPORTED, why);
+  if (const char* why = check_lds(b, m)) return fail(ctx, PK_EUNSUPPORTED, why);
   if (ctx->device == PK_DEVICE_NONE) return fail(ctx, PK_EDEVICE, "validation-only context");
   DeviceGuard g(ctx->device);
   BinTables* bt = nullptr;

@@ -1,11 +1,12 @@
 // FFTPower binning (Sec. 3.4.1) with interlacing and window compensation
 // (Sec. 3.3.2, Eq. 2) fused in.
 //
-// k_xpass_bin  last FFT pass (along x) of both meshes in LDS, then for every
-//              mode of the tile: interlace, compensate, |c|^2, k / mu bin and
-//              Legendre weights, accumulated in float64 LDS bins.  Persistent
-//              grid: each workgroup walks many (ky, column-chunk) tiles and
-//              writes one row of partial sums at the end.
+// k_xpass_bin  last FFT pass (along x) of both meshes in LDS, read from the
+//              y-pass output layout (YLayout), then for every mode of the
+//              tile: interlace, compensate, |c|^2, k / mu bin and Legendre
+//              weights, accumulated in float64 LDS bins.  Persistent grid:
+//              each workgroup walks many (ky, column-chunk) tiles and writes
+//              one row of partial sums at the end.
 // k_plane_bin  the two self-conjugate planes kz = 0 and kz = N/2, which the
 //              packed layout keeps in one complex column; unpacked with the
 //              partner mode (-kx, -ky).
@@ -104,8 +105,10 @@ __device__ __forceinline__ void flush_bins(const double* sb, int n, double* out)
   for (int i = threadIdx.x; i < n; i += blockDim.x) out[i] = sb[i];
 }
 
+// At least 4 waves per SIMD (at most 128 VGPRs): two 512-thread workgroups
+// or one 1024-thread workgroup per CU.
 template <typename T, int N>
-__global__ void __launch_bounds__((XCfg<T, N>::THREADS))
+__global__ void __launch_bounds__((XCfg<T, N>::THREADS)) __attribute__((amdgpu_waves_per_eu(4)))
     k_xpass_bin(const cpx<T>* __restrict__ mesh_a, const cpx<T>* __restrict__ mesh_b,
                 const cpx<T>* __restrict__ tw, const cpx<T>* __restrict__ phase,
                 const T* __restrict__ sinv, BinSpec b, double* __restrict__ partials,
@@ -114,14 +117,22 @@ __global__ void __launch_bounds__((XCfg<T, N>::THREADS))
   constexpr int E = Cf::E, TPL = Cf::TPL, C = Cf::C, NC = Cf::NC, CHUNKS = Cf::CHUNKS;
   __shared__ cpx<T> lds[Cf::LDS_ELEMS];
   __shared__ cpx<T> tws[stage_table_size<N, E>() + 1];
+  // per-index factors, read for every mode: the interlacing phase
+  // exp(i pi n / N) of the signed index n of i, and the compensation 1 / sinc^p
+  __shared__ cpx<T> phx[N];
+  __shared__ T sxs[N];
   extern __shared__ double sb[];
   zero_bins(sb, b.nsum);
+  const cpx<T>* __restrict__ ph1 = phase + 3 * (N / 2);  // ph1[n] = exp(i pi n / N)
+  for (int i = threadIdx.x; i < N; i += blockDim.x) {
+    phx[i] = ph1[signed_index(i, N)];
+    sxs[i] = sinv ? sinv[i] : T(1);
+  }
   build_stage_table<T, N, E>(tws, TwGlobal<T>{tw, 1});  // ends with a barrier
   const TwStage<T, N, E> tw1{tws};
   const int c = threadIdx.x % C, t = threadIdx.x / C;
   const int los = b.los;
   const bool two = mesh_b != nullptr;
-  const cpx<T>* __restrict__ ph1 = phase + 3 * (N / 2);  // ph1[n] = exp(i pi n / N)
   LdsCols<T, C> lc{lds, c};
   // binning pass layout: the power of the tile's C x N modes is staged in
   // LDS as pw[col][kx + kx / S] and re-read so that the 64 lanes of a wave
@@ -133,27 +144,47 @@ __global__ void __launch_bounds__((XCfg<T, N>::THREADS))
   static_assert((long)C * PROW * sizeof(T) <= (long)Cf::LDS_ELEMS * sizeof(cpx<T>), "staging");
   auto pidx = [](int cc, int kx) { return cc * PROW + (N >= 64 ? kx + kx / S : kx); };
   const int ntiles = N * CHUNKS;
+  // The meshes arrive in the y-pass output layout (YLayout).  The lines of a
+  // tile are loaded into registers one tile ahead: the loads of the next
+  // tile are issued once the current tile's power is staged in LDS, so their
+  // latency overlaps the binning of the current tile.
+  using YL = YLayout<T, N>;
+  static_assert(YL::CX == C, "y-pass layout built for this tile width");
+  cpx<T> va[E], vb[E];
+  // kx = t + TPL e: with TPL a multiple of BX the offsets of a thread's
+  // points differ by a constant
+  using Ix = typename YL::Ix;
+  constexpr bool REG = TPL % YL::BX == 0;
+  constexpr Ix kstep = REG ? (Ix)(TPL / YL::BX) * ((Ix)N * YL::BX * YL::W) : 0;
+  auto issue_loads = [&](int tile_id) {
+    const int tile = xcd_pair_tile(tile_id, ntiles);
+    const int ky = tile / CHUNKS, cl = (tile % CHUNKS) * C + c;
+    if constexpr (REG) {
+      const Ix base = YL::at(t, ky, cl);
+#pragma unroll
+      for (int e = 0; e < E; ++e) va[e] = mesh_a[base + (Ix)e * kstep];
+      if (two) {
+#pragma unroll
+        for (int e = 0; e < E; ++e) vb[e] = mesh_b[base + (Ix)e * kstep];
+      }
+    } else {
+#pragma unroll
+      for (int e = 0; e < E; ++e) va[e] = mesh_a[YL::at(t + TPL * e, ky, cl)];
+      if (two) {
+#pragma unroll
+        for (int e = 0; e < E; ++e) vb[e] = mesh_b[YL::at(t + TPL * e, ky, cl)];
+      }
+    }
+  };
+  if ((int)blockIdx.x < ntiles) issue_loads(blockIdx.x);
   for (int tile_id = blockIdx.x; tile_id < ntiles; tile_id += gridDim.x) {
     const int tile = xcd_pair_tile(tile_id, ntiles);
     const int ky = tile / CHUNKS;
     const int col0 = (tile % CHUNKS) * C;
     const int col = col0 + c;
-    // element indices fit 32 bits up to N = 1024 (2^29 complex per mesh)
-    using Ix = typename std::conditional<(N <= 1024), unsigned, size_t>::type;
-    const Ix base = (Ix)ky * NC + col;
-    constexpr Ix step = (Ix)N * NC;
-    // both meshes' loads and the tile's table values are issued before any
-    // transform, so their latencies overlap
-    cpx<T> va[E], vb[E];
-#pragma unroll
-    for (int e = 0; e < E; ++e) va[e] = mesh_a[base + (Ix)(t + TPL * e) * step];
-    if (two) {
-#pragma unroll
-      for (int e = 0; e < E; ++e) vb[e] = mesh_b[base + (Ix)(t + TPL * e) * step];
-    }
     const int ny = signed_index(ky, N);
-    const cpx<T> phy = ph1[ny], phz = ph1[col];
-    const T s_yz = sinv ? sinv[ky] * sinv[col] : T(1);
+    const cpx<T> phy = phx[ky], phz = phx[col];
+    const T s_yz = sxs[ky] * sxs[col];
     stockham<T, N, E, 1>(va, t, tw1, lc);
     if (two) stockham<T, N, E, 1>(vb, t, tw1, lc);
     const cpx<T> phyz = two ? cmul(phy, phz) : cpx<T>{T(1), T(0)};
@@ -169,17 +200,18 @@ __global__ void __launch_bounds__((XCfg<T, N>::THREADS))
       }
       cpx<T> cc = va[e];
       if (two) {
-        const cpx<T> bb = cmul(cmul(ph1[signed_index(kx, N)], phyz), vb[e]);
+        const cpx<T> bb = cmul(cmul(phx[kx], phyz), vb[e]);
         cc = {T(0.5) * (cc.x + bb.x), T(0.5) * (cc.y + bb.y)};
       }
       T pw = cc.x * cc.x + cc.y * cc.y;
       if (sinv) {
-        const T s = sinv[kx] * s_yz;
+        const T s = sxs[kx] * s_yz;
         pw *= s * s;
       }
       pws[pidx(c, kx)] = pw;
     }
     __syncthreads();
+    if (tile_id + (int)gridDim.x < ntiles) issue_loads(tile_id + (int)gridDim.x);
     // binning: with 64-lane waves, work item m = 64 * slot + lane covers
     // column slot / S and kx = lane * S + slot % S; small workgroups take
     // column m / N and kx = m % N
@@ -203,8 +235,8 @@ __global__ void __launch_bounds__((XCfg<T, N>::THREADS))
       const int nl = los == 0 ? nx : (los == 1 ? ny : nz);
       accumulate<T>(sb, b, n2, nl * nl, 2.0 * (double)pw);
     }
+    __syncthreads();  // the staged power is read before the next tile's FFT reuses the LDS
   }
-  __syncthreads();
   flush_bins(sb, b.nsum, partials + (size_t)blockIdx.x * b.nsum);
 }
 
@@ -469,6 +501,22 @@ int xpass_bin_groups(int dtype, int nmesh) {
     }
   }
   return (int)(tiles < 1024 ? tiles : 1024);
+}
+
+template <typename T, int N>
+static size_t xpass_static_lds_t() {
+  using Cf = XCfg<T, N>;
+  return ((size_t)Cf::LDS_ELEMS + stage_table_size<N, Cf::E>() + 1 + N) * sizeof(cpx<T>) +
+         (size_t)N * sizeof(T);
+}
+
+size_t xpass_static_lds(int dtype, int nmesh) {
+#define PK_T(NN) case NN: return dtype == PK_F32 ? xpass_static_lds_t<float, NN>() : xpass_static_lds_t<double, NN>();
+  switch (nmesh) {
+    PK_T(8) PK_T(16) PK_T(32) PK_T(64) PK_T(128) PK_T(256) PK_T(512) PK_T(1024) PK_T(2048)
+    default: return 0;
+  }
+#undef PK_T
 }
 
 int plane_bin_groups(int nmesh) {

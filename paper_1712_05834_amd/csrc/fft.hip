@@ -98,6 +98,47 @@ __global__ void __launch_bounds__((ColCfg<T, N>::THREADS))
   for (int e = 0; e < E; ++e) mesh[base + (size_t)(t + TPL * e) * step] = v[e];
 }
 
+// y-pass of the power-spectrum path: the same transform as k_fft_cols along
+// y, read from the plain packed layout of one mesh and written out of place
+// in the layout the fused x-pass reads (YLayout).  Each row of C columns that
+// a workgroup writes is contiguous; the sibling tile (next chunk, same
+// x-plane, same XCD) writes the other half of its 128-byte lines.
+template <typename T, int N>
+__global__ void __launch_bounds__((ColCfg<T, N>::THREADS))
+    k_fft_y_relayout(const T* __restrict__ src0, cpx<T>* __restrict__ dst,
+                     const cpx<T>* __restrict__ tw) {
+  using Cf = ColCfg<T, N>;
+  using YL = YLayout<T, N>;
+  using Ix = typename YL::Ix;
+  constexpr int E = Cf::E, TPL = Cf::TPL, C = Cf::C, NC = Cf::NC;
+  __shared__ cpx<T> lds[Cf::LDS_ELEMS];
+  __shared__ cpx<T> tws[stage_table_size<N, E>() + 1];
+  build_stage_table<T, N, E>(tws, TwGlobal<T>{tw, 1});
+  const TwStage<T, N, E> tw1{tws};
+  const int c = threadIdx.x % C, t = threadIdx.x / C;
+  const int tile = xcd_pair_tile(blockIdx.x, N * Cf::CHUNKS);
+  const int x = tile / Cf::CHUNKS, col = (tile % Cf::CHUNKS) * C + c;
+  const cpx<T>* src = reinterpret_cast<const cpx<T>*>(src0);
+  const Ix base = (Ix)x * ((Ix)N * NC) + (Ix)col;
+  cpx<T> v[E];
+#pragma unroll
+  for (int e = 0; e < E; ++e) v[e] = src[base + (Ix)(t + TPL * e) * NC];
+  LdsCols<T, C> lc{lds, c};
+  stockham<T, N, E, 1>(v, t, tw1, lc);
+#pragma unroll
+  for (int e = 0; e < E; ++e) dst[YL::at(x, t + TPL * e, col)] = v[e];
+}
+
+template <typename T, int N>
+static hipError_t fft_y_relayout_t(const void* src, void* dst, const void* tw, hipStream_t s) {
+  using Cf = ColCfg<T, N>;
+  const unsigned blocks = (unsigned)(N * Cf::CHUNKS);
+  hipLaunchKernelGGL((k_fft_y_relayout<T, N>), dim3(blocks), dim3(Cf::THREADS), 0, s,
+                     static_cast<const T*>(src), static_cast<cpx<T>*>(dst),
+                     static_cast<const cpx<T>*>(tw));
+  return hipGetLastError();
+}
+
 template <typename T, int N>
 static hipError_t fft_z_t(void* mesh, int nmeshes, size_t stride_bytes, const void* tw,
                           const double* wsum, hipStream_t s) {
@@ -150,6 +191,15 @@ hipError_t launch_fft_cols(int dtype, int nmesh, void* mesh, int nmeshes, size_t
     PK_DISPATCH_N(fft_cols_t, float, mesh, nmeshes, stride_bytes, tw, axis, s)
   } else {
     PK_DISPATCH_N(fft_cols_t, double, mesh, nmeshes, stride_bytes, tw, axis, s)
+  }
+}
+
+hipError_t launch_fft_y_relayout(int dtype, int nmesh, const void* src, void* dst, const void* tw,
+                                 hipStream_t s) {
+  if (dtype == PK_F32) {
+    PK_DISPATCH_N(fft_y_relayout_t, float, src, dst, tw, s)
+  } else {
+    PK_DISPATCH_N(fft_y_relayout_t, double, src, dst, tw, s)
   }
 }
 

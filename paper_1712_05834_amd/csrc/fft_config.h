@@ -2,6 +2,8 @@
 // kernels and the fused x-pass + binning kernel.
 #pragma once
 
+#include <type_traits>
+
 #include "fft_core.h"
 
 namespace pk {
@@ -60,5 +62,31 @@ __device__ __forceinline__ int xcd_pair_tile(int g, int ntiles) {
 // Launch shape of the fused x-pass + binning kernel.
 template <typename T, int N>
 using XCfg = ColCfg<T, N, (sizeof(T) == 4 ? 8 : 4)>;
+
+// Layout of the y-transformed spectrum handed from the y-pass to the fused
+// x-pass in the power-spectrum path.  The x-pass reads, for one ky and C
+// neighbouring packed columns, all N values of kx; the y-pass writes, for one
+// x and C columns, all N values of ky.  In the plain packed layout the x-pass
+// reads would be N * N / 2 complex apart (4 MB at N = 1024), a different
+// page for every kx.  Here the columns are grouped W at a time (two x-pass
+// chunks, 128 bytes of complex float) and x in blocks of BX:
+//   (kx, ky, col) at (col / W) N^2 W + (kx / BX) N BX W + ky BX W
+//                    + (kx % BX) W + col % W,
+// so the y-pass of one x writes N values BX W apart (a 1 MB span at
+// N = 1024), and the x-pass of one ky reads BX consecutive W-wide rows per
+// block, blocks N BX W apart.  The two tiles of a column group, which the
+// XCD pairing runs side by side, fill the two halves of the same 128-byte
+// lines.
+template <typename T, int N>
+struct YLayout {
+  static constexpr int CX = XCfg<T, N>::C;
+  static constexpr int W = 2 * CX <= N / 2 ? 2 * CX : N / 2;
+  static constexpr int BX = N < 8 ? N : 8;
+  using Ix = typename std::conditional<((long)N * N * (N / 2) <= (1L << 31)), unsigned, size_t>::type;
+  __host__ __device__ static constexpr Ix at(int kx, int ky, int col) {
+    return (Ix)(col / W) * ((Ix)N * N * W) + (Ix)(kx / BX) * ((Ix)N * BX * W) +
+           (Ix)ky * (BX * W) + (Ix)(kx % BX) * W + (Ix)(col % W);
+  }
+};
 
 }  // namespace pk

@@ -65,6 +65,9 @@ struct BinSpec {
 //   then, if nmu > 1: counts2d, sum h|n| 2d, sum h|mu| 2d (nk * nmu each).
 __host__ __device__ inline int mode_table_slots(int nk, int nmu) { return 2 * nk + (nmu > 1 ? 3 * nk * nmu : 0); }
 
+// LDS available to one workgroup on gfx950.
+constexpr size_t kLdsBytesPerGroup = 160 * 1024;
+
 // ---- launchers (each defined in the translation unit of its kernels) ----
 hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t s);
 hipError_t launch_paint_atomic(int dtype, int order, int nmesh, double boxsize, const void* pos,
@@ -84,11 +87,17 @@ hipError_t launch_fft_z(int dtype, int nmesh, void* mesh, int nmeshes, size_t me
                         const void* tw, const double* wsum_for_mean, hipStream_t s);
 hipError_t launch_fft_cols(int dtype, int nmesh, void* mesh, int nmeshes,
                            size_t mesh_stride_bytes, const void* tw, int axis, hipStream_t s);
+// y-pass of one z-transformed mesh, out of place into the layout read by the
+// fused x-pass (YLayout in fft_config.h).
+hipError_t launch_fft_y_relayout(int dtype, int nmesh, const void* src, void* dst, const void* tw,
+                                 hipStream_t s);
 
 // Workgroup count of the persistent binning kernels for a mesh size.
 int xpass_bin_groups(int dtype, int nmesh);
 int plane_bin_groups(int nmesh);
 size_t bin_lds_bytes(const BinSpec& b);
+// Static LDS bytes of the fused x-pass + binning kernel (0: unsupported size).
+size_t xpass_static_lds(int dtype, int nmesh);
 hipError_t launch_xpass_bin(int dtype, int nmesh, const void* mesh_a, const void* mesh_b,
                             const MeshTables& t, int order, int compensated, const BinSpec& b,
                             double* partials, void* side_a, void* side_b, hipStream_t s);

@@ -292,6 +292,21 @@ struct PaintCfg {
   static constexpr int HHI = P == 2 ? 0 : 1;
 };
 
+// LDS word of cell z in accumulator row r: within each block of 32 cells the
+// cells are rotated by an even amount that depends on the block and the row.
+// Lanes of a wave often add to cells a power of two apart (lattice-like
+// catalogs: z spaced 8, 64 or 256 cells; rows 8 KB apart), which would put
+// all their float64 atomics on one bank pair; the rotation spreads them.  An
+// even rotation keeps the cells 2j, 2j + 1 adjacent, as the read-back into
+// complex pairs needs.  Rows shorter than 32 cells are left as they are.
+template <int N>
+__device__ __forceinline__ int acc_word(int z, int r) {
+  if constexpr (N < 32) return z;
+  const int b = z >> 5;
+  const int rot = ((b + 3 * (b >> 3) + 5 * r) & 15) << 1;
+  return (z & ~31) | ((z + rot) & 31);
+}
+
 template <typename T, int N, int P, bool INTER>
 __global__ void __launch_bounds__((PaintCfg<T, N, P, INTER>::THREADS))
     k_paint_z(const typename Rec<T>::type* __restrict__ rec, const T* __restrict__ wrec,
@@ -305,6 +320,7 @@ __global__ void __launch_bounds__((PaintCfg<T, N, P, INTER>::THREADS))
   constexpr int mask = N - 1;
   __shared__ Acc acc[ROWS * ROWA];
   __shared__ cpx<T> twq[N / 4];
+  __shared__ cpx<T> tws[stage_table_size<M, E>() + 1];
   __shared__ int seg_start[2 * (TX + 4)], seg_cum[2 * (TX + 4) + 1], seg_row[2 * (TX + 4)];
   static_assert(TX + 4 >= (TX + Cf::HLO + Cf::HHI < N ? TX + Cf::HLO + Cf::HHI : N), "segments");
   __shared__ int nseg_sh;
@@ -314,6 +330,7 @@ __global__ void __launch_bounds__((PaintCfg<T, N, P, INTER>::THREADS))
 
   for (int i = threadIdx.x; i < ROWS * ROWA; i += blockDim.x) acc[i] = 0;
   for (int i = threadIdx.x; i < N / 4; i += blockDim.x) twq[i] = tw[i];
+  build_stage_table<T, M, E>(tws, TwGlobal<T>{tw, 2});  // ends with a barrier
 
   // segments of the sorted records: for each source row bx, the contiguous
   // column range [by0, by0 + wy) (split in two where it wraps around N); one
@@ -349,23 +366,22 @@ __global__ void __launch_bounds__((PaintCfg<T, N, P, INTER>::THREADS))
   }
   __syncthreads();
 
-  // Work item q takes particle p = (q mod 64) * R + q / 64, R = ceil(total / 64):
-  // the lanes of a wave handle particles R apart in the sorted order rather
-  // than neighbours, which in clustered or cell-ordered catalogs often share a
-  // cell and would collide on the same LDS address.
+  // Work item q is the q-th gathered record: the 64 lanes of a wave take
+  // consecutive records, which mostly come from one source column, so the
+  // window cells that fall outside the block are outside for the whole wave
+  // and their branches are skipped.
   const int nseg = nseg_sh;
   const int total = seg_cum[nseg];
-  const int R = (total + 63) >> 6;
-  // record index of work item q (-1 past the end); the next record is loaded
-  // before the current one is processed, so its latency overlaps the work
+  // record index of work item q (-1 past the end); `seg` holds a segment at
+  // or before q's (items only move forward) and returns q's segment.  The
+  // next record is loaded before the current one is processed, so its
+  // latency overlaps the work.
   auto locate = [&](int q, int& seg) -> int {
-    if (q >= 64 * R) return -1;
-    const int p = (q & 63) * R + (q >> 6);
-    if (p >= total) return -1;
-    int s = 0;
-    while (s + 1 < nseg && seg_cum[s + 1] <= p) ++s;
+    if (q >= total) return -1;
+    int s = seg;
+    while (s + 1 < nseg && seg_cum[s + 1] <= q) ++s;
     seg = s;
-    return seg_start[s] + (p - seg_cum[s]);
+    return seg_start[s] + (q - seg_cum[s]);
   };
   using RecT = typename Rec<T>::type;
   int seg_cur = 0;
@@ -376,8 +392,8 @@ __global__ void __launch_bounds__((PaintCfg<T, N, P, INTER>::THREADS))
     r_cur = rec[idx_cur];
     if (wrec) w_cur = wrec[idx_cur];
   }
-  for (int q = threadIdx.x; q < 64 * R; q += blockDim.x) {
-    int seg_nxt = 0;
+  for (int q = threadIdx.x; q < total; q += blockDim.x) {
+    int seg_nxt = seg_cur;
     const int idx_nxt = locate(q + (int)blockDim.x, seg_nxt);
     RecT r_nxt{};
     T w_nxt = T(1);
@@ -426,10 +442,11 @@ __global__ void __launch_bounds__((PaintCfg<T, N, P, INTER>::THREADS))
             const int ly = (first[1] + b2 - Y0) & mask;
             if (ly >= TY) continue;
             const T wab = wa * w[1][b2];
-            Acc* row = acc + ((mesh * TX + lx) * TY + ly) * ROWA;
+            const int ri = (mesh * TX + lx) * TY + ly;
+            Acc* row = acc + ri * ROWA;
 #pragma unroll
             for (int c = 0; c < P; ++c)
-              atomicAdd(&row[(first[2] + c) & mask], (double)(wab * w[2][c]));
+              atomicAdd(&row[acc_word<N>((first[2] + c) & mask, ri)], (double)(wab * w[2][c]));
           }
         }
       }
@@ -452,10 +469,12 @@ __global__ void __launch_bounds__((PaintCfg<T, N, P, INTER>::THREADS))
 #pragma unroll
   for (int e = 0; e < E; ++e) {
     const int j = t + TPL * e;
-    v[e] = {static_cast<T>(arow[2 * j] - mean), static_cast<T>(arow[2 * j + 1] - mean)};
+    const int wj = acc_word<N>(2 * j, r);
+    v[e] = {static_cast<T>(arow[wj] - mean), static_cast<T>(arow[wj + 1] - mean)};
   }
   __syncthreads();  // all cells read before the row is reused
-  const TwQuarter<T> tw2{twq, 2, ilog2(N / 4)}, tw1{twq, 1, ilog2(N / 4)};
+  const TwStage<T, M, E> tw2{tws};
+  const TwQuarter<T> tw1{twq, 1, ilog2(N / 4)};
   stockham<T, M, E, 1>(v, t, tw2, line);
   __syncthreads();
 #pragma unroll

@@ -122,3 +122,16 @@ def test_null_context_and_create_errors():
     assert lib.pk_fft_r2c(None, ctypes.byref(m), ctypes.c_void_p(1)) == _lib.PK_EINVAL
     assert lib.pk_ctx_create(None, 0, None) == _lib.PK_EINVAL
     assert lib.pk_last_error(None)
+
+
+def test_bin_slots_must_fit_lds_beside_the_fused_xpass(vctx):
+    """About 8192 float64 bin slots fit the workgroup's LDS beside the float32
+    x-pass at N = 1024, but not beside the float64 one (its line buffers and
+    tables are twice as large)."""
+    lib, h = vctx
+    b = _lib.bin_desc(1638, 0.0, 1.0, 0, (0, 2, 4, 6), 2)  # 1638 * (1 + 4) = 8190 slots
+    res = ctypes.c_void_p(1)
+    for dtype, want in (("f4", _lib.PK_EDEVICE), ("f8", _lib.PK_EUNSUPPORTED)):
+        m = _lib.mesh_desc(1024, 1000.0, "cic", False, True, dtype)
+        st = lib.pk_bin_power(h, ctypes.byref(m), ctypes.byref(b), ctypes.c_void_p(1), res)
+        assert st == want, (dtype, st, lib.pk_last_error(h))
