@@ -243,41 +243,46 @@ __device__ __forceinline__ void load_quarter(cpx<T>* dst, const cpx<T>* __restri
 // v[e] = x[t + TPL e], on exit v[e] = X[t + TPL e], X_k = sum_j x_j W_L^{jk},
 // W_L = exp(-2 pi i / L).  tw(j) must return W_L^j.  Every thread of the
 // workgroup must call this with the same template arguments (it contains
-// barriers).
+// barriers); threads with active = false only take part in the barriers.
 template <typename T, int L, int E, int P, typename Lds, typename Tw>
-__device__ __forceinline__ void stockham(cpx<T>* v, int t, const Tw& tw, Lds& lds) {
+__device__ __forceinline__ void stockham(cpx<T>* v, int t, const Tw& tw, Lds& lds,
+                                         bool active = true) {
   if constexpr (P < L) {
     constexpr int R = stage_radix<L, E, P>();
     constexpr int TPL = L / E;
     constexpr int Q = E / R;
     constexpr bool LAST = (P * R == L);
     if constexpr (!LAST) __syncthreads();  // earlier readers of the LDS are done
+    if (active) {
 #pragma unroll
-    for (int q = 0; q < Q; ++q) {
-      const int i = t + TPL * q;
-      const int k = i & (P - 1);
-      cpx<T> a[R];
+      for (int q = 0; q < Q; ++q) {
+        const int i = t + TPL * q;
+        const int k = i & (P - 1);
+        cpx<T> a[R];
 #pragma unroll
-      for (int m = 0; m < R; ++m) a[m] = v[q + m * Q];
-      if constexpr (P > 1) {
+        for (int m = 0; m < R; ++m) a[m] = v[q + m * Q];
+        if constexpr (P > 1) {
 #pragma unroll
-        for (int m = 1; m < R; ++m) a[m] = cmul(a[m], tw.template stage<L, P, R>(k, m));
-      }
-      dft<T, R>(a);
-      if constexpr (LAST) {
+          for (int m = 1; m < R; ++m) a[m] = cmul(a[m], tw.template stage<L, P, R>(k, m));
+        }
+        dft<T, R>(a);
+        if constexpr (LAST) {
 #pragma unroll
-        for (int m = 0; m < R; ++m) v[q + m * Q] = a[m];
-      } else {
-        const int j = (i - k) * R + k;
+          for (int m = 0; m < R; ++m) v[q + m * Q] = a[m];
+        } else {
+          const int j = (i - k) * R + k;
 #pragma unroll
-        for (int m = 0; m < R; ++m) lds.put(j + m * P, a[m]);
+          for (int m = 0; m < R; ++m) lds.put(j + m * P, a[m]);
+        }
       }
     }
     if constexpr (!LAST) {
       __syncthreads();
+      if (active) {
 #pragma unroll
-      for (int e = 0; e < E; ++e) v[e] = lds.get(t + TPL * e);
-      stockham<T, L, E, P * R>(v, t, tw, lds);
+        for (int e = 0; e < E; ++e) v[e] = lds.get(t + TPL * e);
+      }
+      stockham<T, L, E, P * R>(v, t, tw, lds, active);
     }
   }
 }

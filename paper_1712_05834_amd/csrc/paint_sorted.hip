@@ -287,6 +287,14 @@ struct PaintCfg {
   static constexpr int E = pick_e();
   static constexpr int TPL = M / E;
   static constexpr int THREADS = ROWS * TPL;
+  // points per thread of the z-FFT itself: radix 8 (radix 4 in float64),
+  // run by the first ROWS * M / FE threads while the others wait at its
+  // barriers -- fewer stages and less address arithmetic than the E of the
+  // gather, and the kernel is bound by VALU issue
+  static constexpr int FE0 = M < (sizeof(T) == 4 ? 8 : 4) ? M : (sizeof(T) == 4 ? 8 : 4);
+  static constexpr int FE = FE0 > E ? FE0 : E;
+  static constexpr int FTPL = M / FE;
+  static constexpr int FTHREADS = ROWS * FTPL;
   // source columns that can reach an owned column: [X - HLO, X + HHI]
   static constexpr int HLO = P == 2 ? (INTER ? 2 : 1) : (P == 3 ? 2 : (INTER ? 3 : 2));
   static constexpr int HHI = P == 2 ? 0 : 1;
@@ -315,12 +323,12 @@ __global__ void __launch_bounds__((PaintCfg<T, N, P, INTER>::THREADS))
               T* __restrict__ mesh_a, T* __restrict__ mesh_b) {
   using Cf = PaintCfg<T, N, P, INTER>;
   using Acc = double;
-  constexpr int M = Cf::M, E = Cf::E, TPL = Cf::TPL, TX = Cf::TX, TY = Cf::TY;
+  constexpr int M = Cf::M, TX = Cf::TX, TY = Cf::TY;
   constexpr int ROWS = Cf::ROWS, ROWA = Cf::ROWA;
   constexpr int mask = N - 1;
   __shared__ Acc acc[ROWS * ROWA];
-  __shared__ cpx<T> twq[N / 4];
-  __shared__ cpx<T> tws[stage_table_size<M, E>() + 1];
+  __shared__ cpx<T> twm[M];  // W_N^k, k < M, for the r2c split
+  __shared__ cpx<T> tws[stage_table_size<M, Cf::FE>() + 1];
   __shared__ int seg_start[2 * (TX + 4)], seg_cum[2 * (TX + 4) + 1], seg_row[2 * (TX + 4)];
   static_assert(TX + 4 >= (TX + Cf::HLO + Cf::HHI < N ? TX + Cf::HLO + Cf::HHI : N), "segments");
   __shared__ int nseg_sh;
@@ -329,8 +337,8 @@ __global__ void __launch_bounds__((PaintCfg<T, N, P, INTER>::THREADS))
   const int X0 = (blockIdx.x / tiles_y) * TX, Y0 = (blockIdx.x % tiles_y) * TY;
 
   for (int i = threadIdx.x; i < ROWS * ROWA; i += blockDim.x) acc[i] = 0;
-  for (int i = threadIdx.x; i < N / 4; i += blockDim.x) twq[i] = tw[i];
-  build_stage_table<T, M, E>(tws, TwGlobal<T>{tw, 2});  // ends with a barrier
+  for (int i = threadIdx.x; i < M; i += blockDim.x) twm[i] = tw[i];
+  build_stage_table<T, M, Cf::FE>(tws, TwGlobal<T>{tw, 2});  // ends with a barrier
 
   // segments of the sorted records: for each source row bx, the contiguous
   // column range [by0, by0 + wy) (split in two where it wraps around N); one
@@ -462,37 +470,42 @@ __global__ void __launch_bounds__((PaintCfg<T, N, P, INTER>::THREADS))
   // rounding to T (only the DC mode changes; it keeps the rounding relative to
   // the fluctuations).  The row becomes the padded complex line.
   const double mean = wsums[0] / ((double)N * N * N);
-  const int r = threadIdx.x / TPL, t = threadIdx.x % TPL;
+  constexpr int FE = Cf::FE, FTPL = Cf::FTPL;
+  const bool fa = (int)threadIdx.x < Cf::FTHREADS;
+  const int r = fa ? (int)threadIdx.x / FTPL : 0, t = (int)threadIdx.x % FTPL;
   Acc* arow = acc + r * ROWA;
   LdsLine<T> line{reinterpret_cast<cpx<T>*>(arow)};
-  cpx<T> v[E];
+  cpx<T> v[FE];
+  if (fa) {
 #pragma unroll
-  for (int e = 0; e < E; ++e) {
-    const int j = t + TPL * e;
-    const int wj = acc_word<N>(2 * j, r);
-    v[e] = {static_cast<T>(arow[wj] - mean), static_cast<T>(arow[wj + 1] - mean)};
+    for (int e = 0; e < FE; ++e) {
+      const int wj = acc_word<N>(2 * (t + FTPL * e), r);
+      v[e] = {static_cast<T>(arow[wj] - mean), static_cast<T>(arow[wj + 1] - mean)};
+    }
   }
   __syncthreads();  // all cells read before the row is reused
-  const TwStage<T, M, E> tw2{tws};
-  const TwQuarter<T> tw1{twq, 1, ilog2(N / 4)};
-  stockham<T, M, E, 1>(v, t, tw2, line);
+  const TwStage<T, M, FE> tw2{tws};
+  stockham<T, M, FE, 1>(v, t, tw2, line, fa);
   __syncthreads();
+  if (fa) {
 #pragma unroll
-  for (int e = 0; e < E; ++e) line.put(t + TPL * e, v[e]);
+    for (int e = 0; e < FE; ++e) line.put(t + FTPL * e, v[e]);
+  }
   __syncthreads();
+  if (!fa) return;
   const int mesh = r / (TX * TY), lx = (r / TY) % TX, ly = r % TY;
   T* out = mesh == 0 ? mesh_a : mesh_b;
   cpx<T>* rowp = reinterpret_cast<cpx<T>*>(out + ((size_t)(X0 + lx) * N + (Y0 + ly)) * N);
 #pragma unroll
-  for (int e = 0; e < E; ++e) {
-    const int k = t + TPL * e;
+  for (int e = 0; e < FE; ++e) {
+    const int k = t + FTPL * e;
     cpx<T> o;
     if (k == 0) {
       o = {v[e].x + v[e].y, v[e].x - v[e].y};
     } else {
       const cpx<T> zc = cconj(line.get(M - k));
       const cpx<T> s = cadd(v[e], zc);
-      const cpx<T> w = cmul(tw1(k), csub(v[e], zc));
+      const cpx<T> w = cmul(twm[k], csub(v[e], zc));
       o = {T(0.5) * (s.x + w.y), T(0.5) * (s.y - w.x)};
     }
     rowp[k] = o;
