@@ -209,6 +209,52 @@ pk_status pk_fftpower(pk_ctx *ctx, const pk_mesh_desc *m, const pk_bin_desc *b,
                       const void *pos, const void *weight, int64_t n,
                       void *workspace, size_t workspace_bytes, double *result_dev);
 
+/* ---- Lanes: concurrent requests on one device (batching and serving).
+ * A lane is a HIP stream of its own (default priority) with a completion
+ * event.  Requests on different lanes run concurrently; each needs its own
+ * workspace while it runs.  Small meshes do not fill the 256 CUs, so several
+ * lanes keep the device busy.  The context is not thread-safe: one host
+ * thread submits and polls. */
+#define PK_MAX_LANES 64
+
+/* Creates lanes until the context has nlanes (1 .. PK_MAX_LANES); existing
+ * lanes are kept.  Errors: PK_EINVAL, PK_EDEVICE. */
+pk_status pk_ctx_set_lanes(pk_ctx *ctx, int nlanes);
+int pk_ctx_lanes(const pk_ctx *ctx);
+
+/* pk_fftpower enqueued on a lane, returning once enqueued.  The tables the
+ * request needs are built first on the context stream (plan time, only the
+ * first time a mesh size or binning is seen) and the lane waits for them.
+ * workspace and result_dev must stay untouched until the lane has finished
+ * (pk_lane_query / pk_lane_wait); then pk_result_to_host reads the result.
+ * Errors: as pk_fftpower, PK_EINVAL for a lane that does not exist. */
+pk_status pk_fftpower_async(pk_ctx *ctx, int lane, const pk_mesh_desc *m,
+                            const pk_bin_desc *b, const void *pos, const void *weight,
+                            int64_t n, void *workspace, size_t workspace_bytes,
+                            double *result_dev);
+
+/* 1 when the lane's last submitted request has finished, 0 while it runs,
+ * a negative pk_status on error. */
+int pk_lane_query(pk_ctx *ctx, int lane);
+/* Blocks until the lane's last submitted request has finished. */
+pk_status pk_lane_wait(pk_ctx *ctx, int lane);
+
+/* A batch of independent requests (Sec. 6: many mocks analysed one after
+ * another) spread over the context's lanes: request i has mesh m[i], bins
+ * b[i], positions pos[i], weights weight[i] (weight may be NULL for all unit
+ * weights, or hold NULL entries), n[i] particles and result_dev[i].  Lane l
+ * works in lane_workspace[l] (lane_workspace_bytes each, enough for every
+ * request).  Requests are taken largest first, each to the lane with the
+ * least queued work; the context stream waits for all lanes, so a
+ * synchronisation of the context stream (pk_result_to_host) sees every
+ * result.  All requests are validated before any work is enqueued.
+ * Errors: PK_EINVAL (also no lanes), PK_EUNSUPPORTED, PK_EDEVICE. */
+pk_status pk_fftpower_batch(pk_ctx *ctx, int count, const pk_mesh_desc *m,
+                            const pk_bin_desc *b, const void *const *pos,
+                            const void *const *weight, const int64_t *n,
+                            void *const *lane_workspace, size_t lane_workspace_bytes,
+                            double *const *result_dev);
+
 /* Synchronises the context stream, copies the sums back and finalises them
  * with the mode tables (counts, mean |k|, mean |mu|):
  *   P = V sum(h P) / (sum w)^2 / N_b,  P_ell = (2 ell + 1) ... likewise.

@@ -24,7 +24,10 @@ EXPORTS = (
     "pk_result_doubles", "pk_workspace_bytes", "pk_ctx_table_bytes", "pk_paint",
     "pk_fft_r2c", "pk_compensate", "pk_bin_power", "pk_fftpower", "pk_result_to_host",
     "pk_ctx_set_timing", "pk_stage_count", "pk_stage_name", "pk_ctx_stage_times",
+    "pk_ctx_set_lanes", "pk_ctx_lanes", "pk_fftpower_async", "pk_lane_query", "pk_lane_wait",
+    "pk_fftpower_batch",
 )
+PK_MAX_LANES = 64
 
 
 class PkError(RuntimeError):
@@ -112,6 +115,14 @@ def load(path=None):
             "pk_stage_count": (ctypes.c_int, []),
             "pk_stage_name": (ctypes.c_char_p, [ctypes.c_int]),
             "pk_ctx_stage_times": (i32, [vp, ctypes.POINTER(ctypes.c_double)]),
+            "pk_ctx_set_lanes": (i32, [vp, ctypes.c_int]),
+            "pk_ctx_lanes": (ctypes.c_int, [vp]),
+            "pk_fftpower_async": (i32, [vp, ctypes.c_int, md, bd, vp, vp, i64, vp, sz, vp]),
+            "pk_lane_query": (ctypes.c_int, [vp, ctypes.c_int]),
+            "pk_lane_wait": (i32, [vp, ctypes.c_int]),
+            "pk_fftpower_batch": (i32, [vp, ctypes.c_int, md, bd, ctypes.POINTER(vp),
+                                        ctypes.POINTER(vp), ctypes.POINTER(i64),
+                                        ctypes.POINTER(vp), sz, ctypes.POINTER(vp)]),
         }
         for name, (res, args) in sig.items():
             f = getattr(lib, name)
@@ -218,6 +229,46 @@ class Context:
         self._check(self.lib.pk_fftpower(self.handle, ctypes.byref(m), ctypes.byref(b), _ptr(pos),
                                          _ptr(weight), int(n), _ptr(workspace), nbytes,
                                          _ptr(result)))
+
+    def pk_ctx_set_lanes(self, nlanes):
+        self._check(self.lib.pk_ctx_set_lanes(self.handle, int(nlanes)))
+
+    def pk_ctx_lanes(self):
+        return int(self.lib.pk_ctx_lanes(self.handle))
+
+    def pk_fftpower_async(self, lane, m, b, pos, weight, n, workspace, result):
+        nbytes = workspace.numel() * workspace.element_size()
+        self._check(self.lib.pk_fftpower_async(self.handle, int(lane), ctypes.byref(m),
+                                               ctypes.byref(b), _ptr(pos), _ptr(weight), int(n),
+                                               _ptr(workspace), nbytes, _ptr(result)))
+
+    def pk_lane_query(self, lane):
+        st = int(self.lib.pk_lane_query(self.handle, int(lane)))
+        if st < 0:
+            self._check(st)
+        return st == 1
+
+    def pk_lane_wait(self, lane):
+        self._check(self.lib.pk_lane_wait(self.handle, int(lane)))
+
+    def pk_fftpower_batch(self, ms, bs, pos, weights, ns, lane_workspaces, results):
+        """ms, bs: sequences of MeshDesc / BinDesc; pos, weights (None entries
+        allowed), results: sequences of device tensors; lane_workspaces: one
+        device tensor per lane, all of the same size."""
+        count = len(ms)
+        marr = (MeshDesc * max(count, 1))(*ms)
+        barr = (BinDesc * max(count, 1))(*bs)
+        vp = ctypes.c_void_p
+
+        def ptrs(ts):
+            return (vp * max(len(ts), 1))(*[None if t is None else t.data_ptr() for t in ts])
+
+        nbytes = lane_workspaces[0].numel() * lane_workspaces[0].element_size()
+        assert all(w.numel() * w.element_size() == nbytes for w in lane_workspaces)
+        narr = (ctypes.c_int64 * max(count, 1))(*[int(n) for n in ns])
+        self._check(self.lib.pk_fftpower_batch(
+            self.handle, count, marr, barr, ptrs(pos), ptrs(weights), narr,
+            ptrs(lane_workspaces), nbytes, ptrs(results)))
 
     def pk_result_to_host(self, m, b, result):
         import numpy as np

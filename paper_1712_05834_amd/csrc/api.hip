@@ -1,6 +1,7 @@
 // The C ABI of libpk (declared in include/pk.h): argument validation, the
 // per-mesh-size and per-binning tables, and the launch sequences of the
 // stages.  No kernel lives here.
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <new>
@@ -399,6 +400,12 @@ void pk_ctx_destroy(pk_ctx* ctx) {
   if (ctx->scratch) (void)hipFree(ctx->scratch);
   for (auto& ev : ctx->events)
     if (ev) (void)hipEventDestroy(ev);
+  for (auto& ln : ctx->lanes) {
+    (void)hipStreamSynchronize(ln.stream);
+    (void)hipEventDestroy(ln.done);
+    (void)hipStreamDestroy(ln.stream);
+  }
+  if (ctx->tables_ready) (void)hipEventDestroy(ctx->tables_ready);
   delete ctx;
 }
 
@@ -508,10 +515,14 @@ pk_status pk_bin_power(pk_ctx* ctx, const pk_mesh_desc* m, const pk_bin_desc* b,
   return PK_OK;
 }
 
-pk_status pk_fftpower(pk_ctx* ctx, const pk_mesh_desc* m, const pk_bin_desc* b, const void* pos,
-                      const void* weight, int64_t n, void* workspace, size_t workspace_bytes,
-                      double* result_dev) {
-  if (!ctx) return PK_EINVAL;
+}  // extern "C"
+
+namespace {
+
+// Argument checks shared by the synchronous and the lane entry points.
+pk_status check_fftpower(pk_ctx* ctx, const pk_mesh_desc* m, const pk_bin_desc* b,
+                         const void* pos, int64_t n, const void* workspace,
+                         size_t workspace_bytes, const double* result_dev) {
   if (const char* why = check_mesh(m)) return fail(ctx, PK_EINVAL, why);
   if (const char* why = check_bins(b, m)) return fail(ctx, PK_EINVAL, why);
   if (n < 0) return fail(ctx, PK_EINVAL, "n must be >= 0");
@@ -521,12 +532,19 @@ pk_status pk_fftpower(pk_ctx* ctx, const pk_mesh_desc* m, const pk_bin_desc* b, 
   if (workspace_bytes < l.total) return fail(ctx, PK_EINVAL, "workspace too small");
   if (const char* why = check_lds(b, m)) return fail(ctx, PK_EUNSUPPORTED, why);
   if (ctx->device == PK_DEVICE_NONE) return fail(ctx, PK_EDEVICE, "validation-only context");
-  DeviceGuard g(ctx->device);
-  BinTables* bt = nullptr;
-  if (pk_status st = get_bin_tables(ctx, m, b, &bt)) return st;
-  const MeshTables* t = nullptr;
-  if (pk_status st = get_mesh_tables(ctx, m->nmesh, m->dtype, &t)) return st;
-  const BinSpec spec = make_spec(m, b, bt->e2_dev);
+  return PK_OK;
+}
+
+// Enqueues the whole path on stream s (tables must exist); stage events are
+// recorded only for the context stream.
+hipError_t enqueue_fftpower(pk_ctx* ctx, hipStream_t s, const pk_mesh_desc* m,
+                            const BinSpec& spec, const MeshTables* t, const void* pos,
+                            const void* weight, int64_t n, void* workspace, const Layout& l,
+                            double* result_dev) {
+  const bool timed = s == ctx->stream;
+  auto stage = [&](int st) {
+    if (timed) mark_stage(ctx, st);
+  };
   char* ws = static_cast<char*>(workspace);
   void* mesh_a = ws + l.mesh_a;
   void* mesh_b = m->interlaced ? ws + l.mesh_b : nullptr;
@@ -534,36 +552,195 @@ pk_status pk_fftpower(pk_ctx* ctx, const pk_mesh_desc* m, const pk_bin_desc* b, 
   void* side_b = m->interlaced ? ws + l.side_b : nullptr;
   double* partials = reinterpret_cast<double*>(ws + l.partials);
   double* wsums = result_dev + spec.nsum;
-  hipStream_t s = ctx->stream;
-  for (bool& r : ctx->stage_ran) r = false;
+  if (timed)
+    for (bool& r : ctx->stage_ran) r = false;
   void* rec = ws + l.rec;
   void* wrec = weight ? ws + l.wrec : nullptr;
-  mark_stage(ctx, kBucket);
+  stage(kBucket);
   hipError_t e = launch_bucket(m->dtype, m->nmesh, m->boxsize, pos, weight, n, ws + l.bucket, rec,
                                wrec, wsums, s);
-  mark_stage(ctx, kPaintZ);
+  stage(kPaintZ);
   if (e == hipSuccess)
     e = launch_paint_z(m->dtype, m->nmesh, m->window, m->interlaced != 0, rec, wrec,
                        ws + l.bucket, wsums, t->tw, mesh_a, mesh_b, s);
   // y-pass out of place into the x-pass layout: A into the spare buffer,
   // then B into A's buffer, which A no longer needs
-  mark_stage(ctx, kFftY);
+  stage(kFftY);
   void* ya = ws + l.ytmp;
   void* yb = m->interlaced ? mesh_a : nullptr;
   if (e == hipSuccess) e = launch_fft_y_relayout(m->dtype, m->nmesh, mesh_a, ya, t->tw, s);
   if (e == hipSuccess && yb) e = launch_fft_y_relayout(m->dtype, m->nmesh, mesh_b, yb, t->tw, s);
-  mark_stage(ctx, kXpassBin);
+  stage(kXpassBin);
   if (e == hipSuccess)
     e = launch_xpass_bin(m->dtype, m->nmesh, ya, yb, *t, m->window, m->compensated, spec,
                          partials, side_a, side_b, s);
-  mark_stage(ctx, kPlaneBin);
+  stage(kPlaneBin);
   if (e == hipSuccess)
     e = launch_plane_bin(m->dtype, m->nmesh, side_a, side_b, 1, *t, m->window, m->compensated,
                          spec, partials + (size_t)l.gx * spec.nsum, s);
-  mark_stage(ctx, kReduce);
+  stage(kReduce);
   if (e == hipSuccess) e = launch_reduce(partials, l.gx + l.gp, spec, result_dev, s);
-  mark_end(ctx);
+  if (timed) mark_end(ctx);
+  return e;
+}
+
+// Builds (on the context stream) whatever tables the request needs and
+// returns them with its kernel-side bin description.
+pk_status prepare_tables(pk_ctx* ctx, const pk_mesh_desc* m, const pk_bin_desc* b,
+                         const MeshTables** t, BinSpec* spec) {
+  BinTables* bt = nullptr;
+  if (pk_status st = get_bin_tables(ctx, m, b, &bt)) return st;
+  if (pk_status st = get_mesh_tables(ctx, m->nmesh, m->dtype, t)) return st;
+  *spec = make_spec(m, b, bt->e2_dev);
+  return PK_OK;
+}
+
+// Creates the lane streams and events up to n lanes.
+pk_status ensure_lanes(pk_ctx* ctx, int n) {
+  while ((int)ctx->lanes.size() < n) {
+    pk_ctx::Lane ln;
+    hipError_t e = hipStreamCreateWithFlags(&ln.stream, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&ln.done, hipEventDisableTiming);
+    if (e != hipSuccess) {
+      if (ln.stream) (void)hipStreamDestroy(ln.stream);
+      return dev_fail(ctx, e, "lane creation");
+    }
+    ctx->lanes.push_back(ln);
+  }
+  if (!ctx->tables_ready) {
+    hipError_t e = hipEventCreateWithFlags(&ctx->tables_ready, hipEventDisableTiming);
+    if (e != hipSuccess) return dev_fail(ctx, e, "lane creation");
+  }
+  return PK_OK;
+}
+
+// Enqueues one request on a lane: the tables are prepared on the context
+// stream, the lane waits for them, runs the path and records its event.
+pk_status submit_on_lane(pk_ctx* ctx, int lane, const pk_mesh_desc* m, const pk_bin_desc* b,
+                         const void* pos, const void* weight, int64_t n, void* workspace,
+                         double* result_dev) {
+  const MeshTables* t = nullptr;
+  BinSpec spec;
+  if (pk_status st = prepare_tables(ctx, m, b, &t, &spec)) return st;
+  pk_ctx::Lane& ln = ctx->lanes[lane];
+  hipError_t e = hipEventRecord(ctx->tables_ready, ctx->stream);
+  if (e == hipSuccess) e = hipStreamWaitEvent(ln.stream, ctx->tables_ready, 0);
+  if (e == hipSuccess)
+    e = enqueue_fftpower(ctx, ln.stream, m, spec, t, pos, weight, n, workspace,
+                         layout_of(m, b, n), result_dev);
+  if (e == hipSuccess) e = hipEventRecord(ln.done, ln.stream);
+  if (e != hipSuccess) return dev_fail(ctx, e, "lane submission");
+  return PK_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+pk_status pk_fftpower(pk_ctx* ctx, const pk_mesh_desc* m, const pk_bin_desc* b, const void* pos,
+                      const void* weight, int64_t n, void* workspace, size_t workspace_bytes,
+                      double* result_dev) {
+  if (!ctx) return PK_EINVAL;
+  if (pk_status st = check_fftpower(ctx, m, b, pos, n, workspace, workspace_bytes, result_dev))
+    return st;
+  DeviceGuard g(ctx->device);
+  const MeshTables* t = nullptr;
+  BinSpec spec;
+  if (pk_status st = prepare_tables(ctx, m, b, &t, &spec)) return st;
+  hipError_t e = enqueue_fftpower(ctx, ctx->stream, m, spec, t, pos, weight, n, workspace,
+                                  layout_of(m, b, n), result_dev);
   if (e != hipSuccess) return dev_fail(ctx, e, "pk_fftpower");
+  return PK_OK;
+}
+
+pk_status pk_ctx_set_lanes(pk_ctx* ctx, int nlanes) {
+  if (!ctx) return PK_EINVAL;
+  if (nlanes < 1 || nlanes > PK_MAX_LANES) return fail(ctx, PK_EINVAL, "nlanes out of range");
+  if (ctx->device == PK_DEVICE_NONE) return fail(ctx, PK_EDEVICE, "validation-only context");
+  DeviceGuard g(ctx->device);
+  return ensure_lanes(ctx, nlanes);
+}
+
+int pk_ctx_lanes(const pk_ctx* ctx) { return ctx ? (int)ctx->lanes.size() : 0; }
+
+pk_status pk_fftpower_async(pk_ctx* ctx, int lane, const pk_mesh_desc* m, const pk_bin_desc* b,
+                            const void* pos, const void* weight, int64_t n, void* workspace,
+                            size_t workspace_bytes, double* result_dev) {
+  if (!ctx) return PK_EINVAL;
+  if (lane < 0 || lane >= (int)ctx->lanes.size()) return fail(ctx, PK_EINVAL, "no such lane");
+  if (pk_status st = check_fftpower(ctx, m, b, pos, n, workspace, workspace_bytes, result_dev))
+    return st;
+  DeviceGuard g(ctx->device);
+  return submit_on_lane(ctx, lane, m, b, pos, weight, n, workspace, result_dev);
+}
+
+int pk_lane_query(pk_ctx* ctx, int lane) {
+  if (!ctx) return PK_EINVAL;
+  if (lane < 0 || lane >= (int)ctx->lanes.size()) return fail(ctx, PK_EINVAL, "no such lane");
+  DeviceGuard g(ctx->device);
+  const hipError_t e = hipEventQuery(ctx->lanes[lane].done);
+  if (e == hipSuccess) return 1;
+  if (e == hipErrorNotReady) return 0;
+  return dev_fail(ctx, e, "pk_lane_query");
+}
+
+pk_status pk_lane_wait(pk_ctx* ctx, int lane) {
+  if (!ctx) return PK_EINVAL;
+  if (lane < 0 || lane >= (int)ctx->lanes.size()) return fail(ctx, PK_EINVAL, "no such lane");
+  DeviceGuard g(ctx->device);
+  const hipError_t e = hipEventSynchronize(ctx->lanes[lane].done);
+  if (e != hipSuccess) return dev_fail(ctx, e, "pk_lane_wait");
+  return PK_OK;
+}
+
+pk_status pk_fftpower_batch(pk_ctx* ctx, int count, const pk_mesh_desc* m, const pk_bin_desc* b,
+                            const void* const* pos, const void* const* weight, const int64_t* n,
+                            void* const* lane_workspace, size_t lane_workspace_bytes,
+                            double* const* result_dev) {
+  if (!ctx) return PK_EINVAL;
+  if (count < 0) return fail(ctx, PK_EINVAL, "count must be >= 0");
+  if (count > 0 && (!m || !b || !pos || !n || !result_dev))
+    return fail(ctx, PK_EINVAL, "request arrays are NULL");
+  const int nl = (int)ctx->lanes.size();
+  if (nl < 1) return fail(ctx, PK_EINVAL, "no lanes: call pk_ctx_set_lanes first");
+  if (!lane_workspace) return fail(ctx, PK_EINVAL, "lane_workspace is NULL");
+  for (int i = 0; i < nl; ++i)
+    if (!lane_workspace[i]) return fail(ctx, PK_EINVAL, "a lane workspace is NULL");
+  for (int i = 0; i < count; ++i)
+    if (pk_status st = check_fftpower(ctx, &m[i], &b[i], pos[i], n[i], lane_workspace[0],
+                                      lane_workspace_bytes, result_dev[i]))
+      return st;
+  if (count == 0) return PK_OK;
+  DeviceGuard g(ctx->device);
+  // every table first, so that no lane waits behind a table build later
+  for (int i = 0; i < count; ++i) {
+    const MeshTables* t = nullptr;
+    BinSpec spec;
+    if (pk_status st = prepare_tables(ctx, &m[i], &b[i], &t, &spec)) return st;
+  }
+  // largest requests first, each to the lane with the least queued work
+  // (estimated as the mesh cells plus the particles it has to process)
+  std::vector<int> order(count);
+  std::vector<double> cost(count);
+  for (int i = 0; i < count; ++i) {
+    const double nm = (double)m[i].nmesh;
+    order[i] = i;
+    cost[i] = (m[i].interlaced ? 2.0 : 1.0) * nm * nm * nm + 4.0 * (double)n[i];
+  }
+  std::stable_sort(order.begin(), order.end(), [&](int a, int c) { return cost[a] > cost[c]; });
+  std::vector<double> queued(nl, 0.0);
+  for (int i : order) {
+    const int lane = (int)(std::min_element(queued.begin(), queued.end()) - queued.begin());
+    queued[lane] += cost[i];
+    if (pk_status st = submit_on_lane(ctx, lane, &m[i], &b[i], pos[i], weight ? weight[i] : nullptr,
+                                      n[i], lane_workspace[lane], result_dev[i]))
+      return st;
+  }
+  // the context stream continues after every lane
+  for (int i = 0; i < nl; ++i) {
+    const hipError_t e = hipStreamWaitEvent(ctx->stream, ctx->lanes[i].done, 0);
+    if (e != hipSuccess) return dev_fail(ctx, e, "pk_fftpower_batch");
+  }
   return PK_OK;
 }
 

@@ -21,9 +21,10 @@
 namespace pk {
 
 // Exact integer square root of 0 <= v < 2^24 (v converts to float exactly;
-// the float root is within one unit of the answer and is corrected).
+// the hardware float root, within an ulp, is at most one unit off the
+// answer and is corrected).
 __device__ __forceinline__ int isqrt_exact(int v) {
-  int s = (int)sqrtf((float)v);
+  int s = (int)__builtin_amdgcn_sqrtf((float)v);
   if (s * s > v) --s;
   if ((s + 1) * (s + 1) <= v) ++s;
   return s;

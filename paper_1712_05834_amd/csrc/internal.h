@@ -135,4 +135,11 @@ struct pk_ctx {
   bool timed_once = false;
   bool stage_ran[pk::kNumStages] = {};
   hipEvent_t events[pk::kNumStages + 1] = {};
+  // asynchronous lanes: one stream and a completion event each
+  struct Lane {
+    hipStream_t stream = nullptr;
+    hipEvent_t done = nullptr;
+  };
+  std::vector<Lane> lanes;
+  hipEvent_t tables_ready = nullptr;  // recorded on the context stream before lane work
 };

@@ -23,6 +23,13 @@ realisations of an input P(k) and a Zel'dovich-displaced lattice):
 * ``zeldovich_lattice``: lattice q = i L / G, psi~ = i k delta~ / k^2 (DC and
   Nyquist planes of psi~ zeroed so psi is real), x = q + psi wrapped into
   [0, L).
+* ``lognormal_catalog_device``: the log-normal recipe drawn on the GPU with
+  torch's seeded device generator (a Philox4x32-10 counter-based stream) and
+  float32 FFTs, for workloads of hundreds of mocks whose host generation would
+  take minutes.  Not bit-identical to ``lognormal_catalog``; tests that need
+  the oracle read the catalog back.
+* ``mock_batch_sizes``: the particle counts and mesh sizes of a batch of
+  mocks: N_i = round(10^U(lo, hi)), meshes cycling through a list.
 """
 
 import os
@@ -153,3 +160,56 @@ def zeldovich_lattice(ngrid, boxsize, pk, seed, dtype=np.float32):
 def uniform_weights(npart, seed, low=0.5, high=1.5, dtype=np.float64):
     """Per-particle weights U[low, high) for the weighted-painting tests."""
     return rng_for(seed).uniform(low, high, size=npart).astype(dtype)
+
+
+def lognormal_catalog_device(nmesh, boxsize, pk, nbar_cell, seed, device="cuda",
+                             dtype=None):
+    """The log-normal recipe on the device; returns an (n, 3) torch tensor in
+    cell order (float32 unless dtype is given)."""
+    import torch
+
+    dtype = dtype or torch.float32
+    g = torch.Generator(device=device)
+    g.manual_seed(int(seed))
+    n = int(nmesh)
+    w = torch.randn((n, n, n), generator=g, device=device, dtype=torch.float32)
+    what = torch.fft.rfftn(w)
+    del w
+    # the amplitude depends on the integer n^2 only: tabulate it on the host
+    kf = 2.0 * np.pi / boxsize
+    n2max = 3 * (n // 2) ** 2
+    table = np.sqrt(n ** 3 * pk(kf * np.sqrt(np.arange(n2max + 1, dtype=np.float64)))
+                    / boxsize ** 3)
+    table = torch.from_numpy(table.astype(np.float32)).to(device)
+    full = torch.fft.fftfreq(n, d=1.0 / n, device=device).round().to(torch.int64)
+    half = torch.arange(n // 2 + 1, device=device, dtype=torch.int64)
+    n2 = full[:, None, None] ** 2 + full[None, :, None] ** 2 + half[None, None, :] ** 2
+    what = what * table[n2]
+    del n2, table
+    what[0, 0, 0] = 0
+    delta = torch.fft.irfftn(what, s=(n, n, n))
+    del what
+    sigma2 = float(delta.double().var())
+    lam = nbar_cell * torch.exp(delta - 0.5 * sigma2)
+    del delta
+    counts = torch.poisson(lam.reshape(-1), generator=g).to(torch.int64)
+    del lam
+    cells = torch.repeat_interleave(torch.arange(n ** 3, device=device, dtype=torch.int64), counts)
+    del counts
+    ix = cells // (n * n)
+    iy = (cells // n) % n
+    iz = cells % n
+    del cells
+    off = torch.rand((ix.numel(), 3), generator=g, device=device, dtype=torch.float64)
+    h = boxsize / n
+    pos = torch.stack([(ix + off[:, 0]) * h, (iy + off[:, 1]) * h, (iz + off[:, 2]) * h], dim=1)
+    del ix, iy, iz, off
+    pos = pos.to(dtype)
+    pos[pos >= boxsize] = 0
+    return pos.contiguous()
+
+
+def mock_batch_sizes(count, seed, meshes=(128, 256, 512), lo=5.0, hi=7.0):
+    """(npart_target, nmesh) per mock: N_i = round(10^U(lo, hi)), mesh i mod len."""
+    u = rng_for(seed).uniform(lo, hi, size=count)
+    return [(int(round(10.0 ** x)), int(meshes[i % len(meshes)])) for i, x in enumerate(u)]

@@ -135,3 +135,24 @@ def test_bin_slots_must_fit_lds_beside_the_fused_xpass(vctx):
         m = _lib.mesh_desc(1024, 1000.0, "cic", False, True, dtype)
         st = lib.pk_bin_power(h, ctypes.byref(m), ctypes.byref(b), ctypes.c_void_p(1), res)
         assert st == want, (dtype, st, lib.pk_last_error(h))
+
+
+def test_lane_entry_points_validate(vctx):
+    lib, h = vctx
+    m = _lib.mesh_desc(32, 100.0, "cic")
+    b = _lib.bin_desc(16)
+    one = ctypes.c_void_p(1)
+    # a validation-only context has no device, hence no lanes
+    assert lib.pk_ctx_set_lanes(h, 2) == _lib.PK_EDEVICE
+    assert lib.pk_ctx_set_lanes(h, 0) == _lib.PK_EINVAL
+    assert lib.pk_ctx_set_lanes(h, _lib.PK_MAX_LANES + 1) == _lib.PK_EINVAL
+    assert lib.pk_ctx_lanes(h) == 0
+    assert lib.pk_fftpower_async(h, 0, ctypes.byref(m), ctypes.byref(b), one, None, 10, one,
+                                 1 << 30, one) == _lib.PK_EINVAL
+    assert lib.pk_lane_query(h, 0) == _lib.PK_EINVAL
+    assert lib.pk_lane_wait(h, -1) == _lib.PK_EINVAL
+    assert lib.pk_fftpower_batch(h, -1, None, None, None, None, None, None, 0, None) == _lib.PK_EINVAL
+    assert lib.pk_fftpower_batch(h, 0, None, None, None, None, None, None, 0, None) == _lib.PK_EINVAL
+    assert b"no lanes" in lib.pk_last_error(h)
+    assert lib.pk_ctx_set_lanes(None, 1) == _lib.PK_EINVAL
+    assert lib.pk_ctx_lanes(None) == 0
