@@ -48,6 +48,14 @@ BATCH = dict(count=256, box=1380.0, meshes=(128, 256, 512), seed=1000, lanes=8,
              window="tsc", poles=(0, 2, 4))
 
 
+# Serving: requests arriving as a Poisson process; per request a uniform or
+# log-normal catalog (50/50), N_p log-uniform in [1e5, 5e7], mesh 128^3 ..
+# 1024^3, CIC or TSC, interlacing on or off, float32.  Catalogs are drawn on
+# the device before the run (untimed, log-normal on a min(N, 512)^3 grid).
+SERVE = dict(count=120, qps=(10.0, 40.0, 160.0, 640.0), seed=5, lanes=8, box=1380.0,
+             meshes=(128, 256, 512, 1024), np_range=(1e5, 5e7), reserve_gib=8.0)
+
+
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
@@ -152,7 +160,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="lognormal-512",
-                    choices=sorted(WORKLOADS) + ["batch-mocks"])
+                    choices=sorted(WORKLOADS) + ["batch-mocks", "serve"])
     ap.add_argument("--mocks", type=int, default=BATCH["count"],
                     help="number of mocks of the batch-mocks workload")
     ap.add_argument("--lanes", type=int, default=BATCH["lanes"],
@@ -188,6 +196,9 @@ def main():
 
     if args.workload == "batch-mocks":
         run_batch(args)
+        return
+    if args.workload == "serve":
+        run_serve(args)
         return
     w = WORKLOADS[args.workload]
     t0 = time.perf_counter()
@@ -358,6 +369,88 @@ def run_batch(args):
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                      "traffic": None},
         "fp32_vs_fp64_max_rel_err": {"max": max(errs), "median": float(np.median(errs))},
+        "cpu_baseline": None,
+    }
+    print(json.dumps(line), flush=True)
+
+
+def run_serve(args):
+    """serve: the same request pool served at several Poisson arrival rates.
+    value = requests/s sustained at the highest rate; p50 / p99 latency
+    (result on the host - arrival) per rate."""
+    import numpy as np
+    import torch
+
+    from paper_1712_05834_amd import _lib, synth
+    from paper_1712_05834_amd.serve import LibpkBackend, Request, Server, latency_stats
+    from paper_1712_05834_amd.serve import poisson_arrivals
+
+    dev = torch.device("cuda:0")
+    rng = synth.rng_for(SERVE["seed"])
+    lo, hi = np.log10(SERVE["np_range"][0]), np.log10(SERVE["np_range"][1])
+    pool = []
+    t0 = time.perf_counter()
+    for i in range(SERVE["count"]):
+        kind = "lognormal" if rng.uniform() < 0.5 else "uniform"
+        target = int(round(10 ** rng.uniform(lo, hi)))
+        n = int(SERVE["meshes"][rng.integers(len(SERVE["meshes"]))])
+        window = "tsc" if rng.uniform() < 0.5 else "cic"
+        inter = bool(rng.uniform() < 0.5)
+        if kind == "lognormal":
+            g = min(n, 512)
+            pos = synth.lognormal_catalog_device(g, SERVE["box"], synth.pk_lognormal_c2,
+                                                 target / g ** 3, seed=SERVE["seed"] * 1000 + i,
+                                                 device=dev)
+        else:
+            gen = torch.Generator(device=dev)
+            gen.manual_seed(SERVE["seed"] * 1000 + i)
+            pos = torch.rand((target, 3), generator=gen, device=dev,
+                             dtype=torch.float64) * SERVE["box"]
+            pos = pos.to(torch.float32)
+            pos[pos >= SERVE["box"]] = 0
+        m = _lib.mesh_desc(n, SERVE["box"], window, inter, True, "f4")
+        b = _lib.bin_desc(n // 2, 0.0, 1.0, 0, (0, 2), 2)
+        pool.append((m, b, pos))
+    torch.cuda.synchronize()
+    log(f"serve: {len(pool)} catalogs ({sum(p[2].shape[0] for p in pool)} particles) drawn on "
+        f"the device in {time.perf_counter() - t0:.1f} s")
+    ctx = _lib.Context(0)
+    backend = LibpkBackend(ctx, SERVE["lanes"])
+    free, _ = torch.cuda.mem_get_info()
+    budget = int(free - SERVE["reserve_gib"] * 2 ** 30)
+    log(f"{SERVE['lanes']} lanes, admission budget {budget / 2**30:.0f} GiB")
+    # warm-up: every mesh size and binning once (plan-time tables)
+    warm = [Request(-1 - i, 0.0, m, b, p, p.shape[0]) for i, (m, b, p) in enumerate(pool[:8])]
+    Server(backend, budget).run(warm)
+    levels = []
+    for qps in SERVE["qps"]:
+        arr = poisson_arrivals(len(pool), qps, synth.rng_for(SERVE["seed"] + int(qps)))
+        reqs = [Request(i, a, m, b, p, p.shape[0]) for i, (a, (m, b, p)) in enumerate(zip(arr, pool))]
+        served = Server(backend, budget).run(reqs)
+        st = latency_stats(served)
+        st["qps"] = qps
+        levels.append(st)
+        log(f"qps {qps:g}: p50 {st['p50_ms']:.1f} ms, p99 {st['p99_ms']:.1f} ms, "
+            f"{st['throughput_rps']:.1f} req/s")
+    top = levels[-1]
+    line = {
+        "metric": "p50/p99 request latency and sustained requests/s (FFTPower serving)",
+        "value": top["throughput_rps"],
+        "unit": "requests/s",
+        "n_gpus": 1,
+        "steps": len(pool),
+        "warmup": len(warm),
+        "ms_per_step": 1e3 / top["throughput_rps"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 (paint, FFT) + f64 (bin sums)",
+        "data": "synthetic (device-drawn uniform and log-normal catalogs)",
+        "config": {"workload": "serve", "requests_per_level": len(pool),
+                   "lanes": SERVE["lanes"], "meshes": list(SERVE["meshes"]),
+                   "np_range": list(SERVE["np_range"]), "qps": list(SERVE["qps"])},
+        "latency": levels,
+        "roofline": None,
         "cpu_baseline": None,
     }
     print(json.dumps(line), flush=True)
