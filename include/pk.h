@@ -197,6 +197,35 @@ pk_status pk_compensate(pk_ctx *ctx, const pk_mesh_desc *m, void *cmesh_inout,
 pk_status pk_bin_power(pk_ctx *ctx, const pk_mesh_desc *m, const pk_bin_desc *b,
                        const void *cmesh, double *result_dev);
 
+/* Cross power of two fields on the same mesh (the two-field form of the
+ * FFTPower estimator, Sec. 3.4.1): as pk_bin_power with |c|^2 replaced by
+ * Re(c1 conj(c2)) mode by mode, for packed spectra prepared the same way
+ * (pk_paint, pk_fft_r2c, pk_compensate).  pk_result_to_host normalises by the
+ * first weight slot squared: store sqrt(W1 W2) there (W = sum of the weights
+ * of each catalog) and 0 in the second, the shot noise of two distinct
+ * catalogs.  Errors: as pk_bin_power, PK_EINVAL for a NULL cmesh2. */
+pk_status pk_bin_cross(pk_ctx *ctx, const pk_mesh_desc *m, const pk_bin_desc *b,
+                       const void *cmesh1, const void *cmesh2, double *result_dev);
+
+/* Projected power (ProjectedFFTPower, Sec. 3.4.1): the power of the field
+ * summed along the axes not kept, P = L^d |c|^2 / (sum w)^2 over the d kept
+ * axes.  The d-dimensional transform of the projected field is the 3-D
+ * spectrum on the plane (or line) where the projected wave numbers vanish,
+ * so it is read from a packed spectrum prepared as for pk_bin_power
+ * (pk_paint, pk_fft_r2c, pk_compensate); every mode of the full kept grid
+ * counts once.  keep: bit 1 = x, 2 = y, 4 = z kept, one or two bits.  b: k-bins
+ * in units of k_f over the kept axes, nmu <= 1 and no poles.  result_dev:
+ * device, pk_projected_doubles(b) float64: [3 nk] sums overwritten (|c|^2,
+ * counts, |n|), then {sum w, sum w^2} left for the caller to fill, as for
+ * pk_bin_power.  Errors: PK_EINVAL, PK_EDEVICE. */
+size_t pk_projected_doubles(const pk_bin_desc *b);
+pk_status pk_bin_projected(pk_ctx *ctx, const pk_mesh_desc *m, const pk_bin_desc *b, int keep,
+                           const void *cmesh, double *result_dev);
+/* Finalises a projected power: out->k, power, modes (the other arrays are
+ * not touched), shotnoise = L^d sum w^2 / (sum w)^2, wsum, w2sum. */
+pk_status pk_projected_to_host(pk_ctx *ctx, const pk_mesh_desc *m, const pk_bin_desc *b,
+                               int keep, const double *result_dev, pk_result *out);
+
 /* The whole FFTPower hot path for one catalog: paint (both meshes if
  * interlaced), r2c, interlace, compensate, bin.  workspace: device,
  * >= pk_workspace_bytes(m, b, n) bytes, caller-owned scratch (content on
@@ -254,6 +283,16 @@ pk_status pk_fftpower_batch(pk_ctx *ctx, int count, const pk_mesh_desc *m,
                             const void *const *weight, const int64_t *n,
                             void *const *lane_workspace, size_t lane_workspace_bytes,
                             double *const *result_dev);
+
+/* pk_fftpower with per-particle field values (Sec. 3.3.1: the painted field
+ * is [1 + delta'] V, delta' the weighted overdensity): each particle paints
+ * w V; the normalisation stays sum w, and the second weight slot holds
+ * sum (w V)^2, so that the reported shot noise is V_box sum (w V)^2 /
+ * (sum w)^2.  value: device, n values of the mesh dtype, or NULL (then this
+ * is pk_fftpower).  Errors: as pk_fftpower. */
+pk_status pk_fftpower_v(pk_ctx *ctx, const pk_mesh_desc *m, const pk_bin_desc *b,
+                        const void *pos, const void *weight, const void *value, int64_t n,
+                        void *workspace, size_t workspace_bytes, double *result_dev);
 
 /* Synchronises the context stream, copies the sums back and finalises them
  * with the mode tables (counts, mean |k|, mean |mu|):

@@ -37,6 +37,9 @@ from .power import (
     fftpower_from_spectra,
     fftpower,
     mode_tables,
+    prepared_spectrum,
+    cross_from_spectra,
+    projected_power,
 )
 
 __all__ = [
@@ -56,4 +59,7 @@ __all__ = [
     "fftpower_from_spectra",
     "fftpower",
     "mode_tables",
+    "prepared_spectrum",
+    "cross_from_spectra",
+    "projected_power",
 ]

@@ -30,6 +30,18 @@ Readings where the paper is silent (all pinned by tests):
   full-grid enumeration;
 * P_ell = (2 ell + 1) x mode average of P L_ell(mu); shot noise
   V sum(w^2) / sum(w)^2 is reported and not subtracted; empty bins are NaN.
+* value painting (Sec. 3.3.1: F = [1 + delta'] V with the weighted
+  overdensity delta'): each particle paints w V, the normalisation stays
+  sum(w), and the reported shot noise becomes V sum((w V)^2) / sum(w)^2, the
+  Poisson noise of the painted field;
+* cross power of two fields on one mesh: P_12 = V Re(c_1 conj(c_2)) /
+  (W_1 W_2), binned like P; its shot noise (distinct catalogs) is zero.
+* projected power (ProjectedFFTPower, Sec. 3.4.1): the painted field is
+  summed over the projected axes, the d kept axes are transformed, and
+  P = L^d |c|^2 / (sum w)^2 is binned in |k| over the kept axes (every mode
+  of the full d-dimensional grid once); interlacing and compensation act on
+  the kept axes (the projected ones have n = 0).  Shot noise L^d sum w^2 /
+  (sum w)^2.
 """
 
 import os
@@ -275,17 +287,114 @@ def fftpower_from_spectra(c_a, c_b, nmesh, boxsize, order, compensated, wsum,
 
 def fftpower(pos, nmesh, boxsize, window="cic", interlaced=False,
              compensated=True, weight=None, kmin_f=0.0, dk_f=1.0, nk=None,
-             nmu=0, poles=(), los=2, workers=None):
-    """End-to-end oracle FFTPower on a periodic box (Sec. 3.3 and 3.4.1)."""
+             nmu=0, poles=(), los=2, workers=None, value=None):
+    """End-to-end oracle FFTPower on a periodic box (Sec. 3.3 and 3.4.1).
+    ``value``: per-particle field value V (Sec. 3.3.1), painted as w V."""
+    order = WINDOW_ORDER[window] if isinstance(window, str) else int(window)
+    pos = np.asarray(pos, dtype=np.float64).reshape(-1, 3)
+    w = np.ones(len(pos)) if weight is None else np.asarray(weight, dtype=np.float64)
+    wv = w if value is None else w * np.asarray(value, dtype=np.float64)
+    wsum = float(np.sum(w))
+    w2sum = float(np.sum(wv * wv))
+    c_a = r2c(paint_mesh(pos, nmesh, boxsize, order, wv), workers)
+    c_b = None
+    if interlaced:
+        c_b = r2c(paint_mesh(pos, nmesh, boxsize, order, wv, 0.5), workers)
+    return fftpower_from_spectra(c_a, c_b, nmesh, boxsize, order, compensated,
+                                 wsum, w2sum, len(pos), kmin_f, dk_f, nk, nmu,
+                                 poles, los)
+
+
+def prepared_spectrum(pos, nmesh, boxsize, window="cic", interlaced=False,
+                      compensated=True, weight=None, workers=None):
+    """The spectrum of one catalog after interlacing and compensation
+    (Sec. 3.3.2, Eq. 2) and its sum of weights: the input of a cross power."""
+    order = WINDOW_ORDER[window] if isinstance(window, str) else int(window)
+    pos = np.asarray(pos, dtype=np.float64).reshape(-1, 3)
+    w = np.ones(len(pos)) if weight is None else np.asarray(weight, dtype=np.float64)
+    c = r2c(paint_mesh(pos, nmesh, boxsize, order, w), workers)
+    if interlaced:
+        c = interlace_combine(c, r2c(paint_mesh(pos, nmesh, boxsize, order, w, 0.5), workers),
+                              nmesh)
+    if compensated:
+        c = compensate(c, nmesh, order)
+    return c, float(np.sum(w))
+
+
+def cross_from_spectra(c1, c2, nmesh, boxsize, wsum1, wsum2, kmin_f=0.0, dk_f=1.0, nk=None,
+                       nmu=0, poles=(), los=2, interlaced=False):
+    """Cross power of two prepared spectra: per mode V Re(c1 conj(c2)) /
+    (W1 W2), binned exactly like the auto power (Sec. 3.4.1)."""
+    n = nmesh
+    if nk is None:
+        nk = n // 2
+    _check_bins(n, interlaced, kmin_f, dk_f, nk, nmu, poles, los)
+    volume = float(boxsize) ** 3
+    pmode = volume * (c1.real * c2.real + c1.imag * c2.imag) / (wsum1 * wsum2)
+    acc = _accumulate(n, kmin_f, dk_f, nk, nmu, tuple(poles), los,
+                      lambda x0, x1: pmode[x0:x1], _slab(n))
+    kf = 2.0 * np.pi / boxsize
+    with np.errstate(invalid="ignore", divide="ignore"):
+        nb = acc["modes"]
+        res = {
+            "k": kf * acc["sum_k"] / nb,
+            "power": acc["sum_p"] / nb,
+            "modes": nb,
+            "poles": {ell: (2 * ell + 1) * acc["sum_pl"][ell] / nb for ell in poles},
+            "shotnoise": 0.0,
+            "wsum": float(np.sqrt(wsum1 * wsum2)),
+            "w2sum": 0.0,
+        }
+        if nmu > 1:
+            m2 = acc["modes2d"]
+            res["modes2d"] = m2.reshape(nk, nmu)
+            res["k2d"] = (kf * acc["sum_k2d"] / m2).reshape(nk, nmu)
+            res["mu2d"] = (acc["sum_mu2d"] / m2).reshape(nk, nmu)
+            res["power2d"] = (acc["sum_p2d"] / m2).reshape(nk, nmu)
+    return res
+
+
+def projected_power(pos, nmesh, boxsize, keep, window="cic", interlaced=False,
+                    compensated=True, weight=None, kmin_f=0.0, dk_f=1.0, nk=None):
+    """ProjectedFFTPower of a periodic box: power of the field projected
+    along the axes not in ``keep`` (a tuple of one or two axes)."""
+    keep = tuple(sorted(int(a) for a in keep))
+    if not 1 <= len(keep) <= 2 or any(a not in (0, 1, 2) for a in keep):
+        raise ValueError("keep must hold one or two distinct axes")
+    drop = tuple(a for a in range(3) if a not in keep)
+    d = len(keep)
+    n = nmesh
+    if nk is None:
+        nk = n // 2
     order = WINDOW_ORDER[window] if isinstance(window, str) else int(window)
     pos = np.asarray(pos, dtype=np.float64).reshape(-1, 3)
     w = np.ones(len(pos)) if weight is None else np.asarray(weight, dtype=np.float64)
     wsum = float(np.sum(w))
     w2sum = float(np.sum(w * w))
-    c_a = r2c(paint_mesh(pos, nmesh, boxsize, order, weight), workers)
-    c_b = None
+
+    def spectrum(shift):
+        proj = paint_mesh(pos, n, boxsize, order, w, shift).sum(axis=drop)
+        return np.fft.fftn(proj)  # full d-dimensional grid, exp(-i k.x)
+
+    c = spectrum(0.0)
+    full = np.arange(n, dtype=np.int64)
+    full = np.where(full < n // 2, full, full - n)
+    grids = np.meshgrid(*([full] * d), indexing="ij")
     if interlaced:
-        c_b = r2c(paint_mesh(pos, nmesh, boxsize, order, weight, 0.5), workers)
-    return fftpower_from_spectra(c_a, c_b, nmesh, boxsize, order, compensated,
-                                 wsum, w2sum, len(pos), kmin_f, dk_f, nk, nmu,
-                                 poles, los)
+        s = sum(grids)
+        c = 0.5 * (c + np.exp(1j * np.pi * s / n) * spectrum(0.5))
+    if compensated:
+        for g in grids:
+            c = c / _sinc(np.pi * g / n) ** order
+    n2 = sum(g * g for g in grids).ravel()
+    area = float(boxsize) ** d
+    pmode = (area * (c.real ** 2 + c.imag ** 2) / (wsum * wsum)).ravel()
+    b = kbin_index(n2, kbin_edges_sq(kmin_f, dk_f, nk))
+    sel = b >= 0
+    cnt = np.bincount(b[sel], minlength=nk).astype(np.int64)
+    sk = np.bincount(b[sel], weights=np.sqrt(n2[sel].astype(np.float64)), minlength=nk)
+    sp = np.bincount(b[sel], weights=pmode[sel], minlength=nk)
+    kf = 2.0 * np.pi / boxsize
+    with np.errstate(invalid="ignore", divide="ignore"):
+        return {"k": kf * sk / cnt, "power": sp / cnt, "modes": cnt, "poles": {},
+                "shotnoise": area * w2sum / (wsum * wsum), "wsum": wsum, "w2sum": w2sum}

@@ -25,7 +25,8 @@ EXPORTS = (
     "pk_fft_r2c", "pk_compensate", "pk_bin_power", "pk_fftpower", "pk_result_to_host",
     "pk_ctx_set_timing", "pk_stage_count", "pk_stage_name", "pk_ctx_stage_times",
     "pk_ctx_set_lanes", "pk_ctx_lanes", "pk_fftpower_async", "pk_lane_query", "pk_lane_wait",
-    "pk_fftpower_batch",
+    "pk_fftpower_batch", "pk_bin_cross", "pk_fftpower_v", "pk_projected_doubles",
+    "pk_bin_projected", "pk_projected_to_host",
 )
 PK_MAX_LANES = 64
 
@@ -109,7 +110,13 @@ def load(path=None):
             "pk_fft_r2c": (i32, [vp, md, vp]),
             "pk_compensate": (i32, [vp, md, vp, vp]),
             "pk_bin_power": (i32, [vp, md, bd, vp, vp]),
+            "pk_bin_cross": (i32, [vp, md, bd, vp, vp, vp]),
+            "pk_projected_doubles": (sz, [bd]),
+            "pk_bin_projected": (i32, [vp, md, bd, ctypes.c_int, vp, vp]),
+            "pk_projected_to_host": (i32, [vp, md, bd, ctypes.c_int, vp,
+                                           ctypes.POINTER(Result)]),
             "pk_fftpower": (i32, [vp, md, bd, vp, vp, i64, vp, sz, vp]),
+            "pk_fftpower_v": (i32, [vp, md, bd, vp, vp, vp, i64, vp, sz, vp]),
             "pk_result_to_host": (i32, [vp, md, bd, vp, ctypes.POINTER(Result)]),
             "pk_ctx_set_timing": (i32, [vp, ctypes.c_int]),
             "pk_stage_count": (ctypes.c_int, []),
@@ -151,6 +158,10 @@ def mesh_bytes(m):
 
 def result_doubles(b):
     return int(load().pk_result_doubles(ctypes.byref(b)))
+
+
+def projected_doubles(b):
+    return int(load().pk_projected_doubles(ctypes.byref(b)))
 
 
 def workspace_bytes(m, b, npart):
@@ -224,11 +235,41 @@ class Context:
         self._check(self.lib.pk_bin_power(self.handle, ctypes.byref(m), ctypes.byref(b),
                                           _ptr(cmesh), _ptr(result)))
 
+    def pk_bin_cross(self, m, b, cmesh1, cmesh2, result):
+        self._check(self.lib.pk_bin_cross(self.handle, ctypes.byref(m), ctypes.byref(b),
+                                          _ptr(cmesh1), _ptr(cmesh2), _ptr(result)))
+
+    def pk_bin_projected(self, m, b, keep, cmesh, result):
+        self._check(self.lib.pk_bin_projected(self.handle, ctypes.byref(m), ctypes.byref(b),
+                                              int(keep), _ptr(cmesh), _ptr(result)))
+
+    def pk_projected_to_host(self, m, b, keep, result):
+        import numpy as np
+
+        nk = b.nk
+        out = {"k": np.empty(nk), "power": np.empty(nk), "modes": np.empty(nk, dtype=np.int64)}
+        dbl, i64 = ctypes.c_double, ctypes.c_int64
+        r = Result(out["k"].ctypes.data_as(ctypes.POINTER(dbl)),
+                   out["power"].ctypes.data_as(ctypes.POINTER(dbl)),
+                   out["modes"].ctypes.data_as(ctypes.POINTER(i64)),
+                   None, None, None, None, None, 0.0, 0.0, 0.0)
+        self._check(self.lib.pk_projected_to_host(self.handle, ctypes.byref(m), ctypes.byref(b),
+                                                  int(keep), _ptr(result), ctypes.byref(r)))
+        out["poles"] = {}
+        out["shotnoise"], out["wsum"], out["w2sum"] = r.shotnoise, r.wsum, r.w2sum
+        return out
+
     def pk_fftpower(self, m, b, pos, weight, n, workspace, result):
         nbytes = workspace.numel() * workspace.element_size()
         self._check(self.lib.pk_fftpower(self.handle, ctypes.byref(m), ctypes.byref(b), _ptr(pos),
                                          _ptr(weight), int(n), _ptr(workspace), nbytes,
                                          _ptr(result)))
+
+    def pk_fftpower_v(self, m, b, pos, weight, value, n, workspace, result):
+        nbytes = workspace.numel() * workspace.element_size()
+        self._check(self.lib.pk_fftpower_v(self.handle, ctypes.byref(m), ctypes.byref(b),
+                                           _ptr(pos), _ptr(weight), _ptr(value), int(n),
+                                           _ptr(workspace), nbytes, _ptr(result)))
 
     def pk_ctx_set_lanes(self, nlanes):
         self._check(self.lib.pk_ctx_set_lanes(self.handle, int(nlanes)))

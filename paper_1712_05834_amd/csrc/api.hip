@@ -354,6 +354,36 @@ Layout layout_of(const pk_mesh_desc* m, const pk_bin_desc* b, int64_t npart) {
   return l;
 }
 
+// Binning of one packed spectrum (|c|^2) or of two (Re(c1 conj(c2))).
+pk_status bin_packed(pk_ctx* ctx, const pk_mesh_desc* m, const pk_bin_desc* b, const void* c1,
+                     const void* c2, double* result_dev, const char* who) {
+  if (!ctx) return PK_EINVAL;
+  if (const char* why = check_mesh(m)) return fail(ctx, PK_EINVAL, why);
+  if (const char* why = check_bins(b, m)) return fail(ctx, PK_EINVAL, why);
+  if (!c1 || !result_dev) return fail(ctx, PK_EINVAL, "cmesh or result is NULL");
+  if (const char* why = check_lds(b, m)) return fail(ctx, PK_EUNSUPPORTED, why);
+  if (ctx->device == PK_DEVICE_NONE) return fail(ctx, PK_EDEVICE, "validation-only context");
+  DeviceGuard g(ctx->device);
+  BinTables* bt = nullptr;
+  if (pk_status st = get_bin_tables(ctx, m, b, &bt)) return st;
+  const MeshTables* t = nullptr;
+  if (pk_status st = get_mesh_tables(ctx, m->nmesh, m->dtype, &t)) return st;
+  const BinSpec spec = make_spec(m, b, bt->e2_dev);
+  const size_t total = (size_t)m->nmesh * m->nmesh * (m->nmesh / 2);
+  size_t gb = (total + 255) / 256;
+  if (gb > 1024) gb = 1024;
+  const int gp = plane_bin_groups(m->nmesh);
+  double* partials = nullptr;
+  if (pk_status st = get_scratch(ctx, (gb + gp) * spec.nsum * sizeof(double), &partials)) return st;
+  hipError_t e = launch_bin_packed(m->dtype, m->nmesh, c1, c2, spec, partials, ctx->stream);
+  if (e == hipSuccess)
+    e = launch_plane_bin(m->dtype, m->nmesh, c1, c2, m->nmesh / 2, *t, m->window, 0, spec,
+                         partials + gb * spec.nsum, ctx->stream, c2 ? 1 : 0);
+  if (e == hipSuccess) e = launch_reduce(partials, (int)(gb + gp), spec, result_dev, ctx->stream);
+  if (e != hipSuccess) return dev_fail(ctx, e, who);
+  return PK_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -487,32 +517,89 @@ pk_status pk_compensate(pk_ctx* ctx, const pk_mesh_desc* m, void* cmesh_inout,
 
 pk_status pk_bin_power(pk_ctx* ctx, const pk_mesh_desc* m, const pk_bin_desc* b,
                        const void* cmesh, double* result_dev) {
+  return bin_packed(ctx, m, b, cmesh, nullptr, result_dev, "pk_bin_power");
+}
+
+size_t pk_projected_doubles(const pk_bin_desc* b) {
+  if (!b || b->nk < 1 || b->nk > 4096) return 0;
+  return (size_t)3 * b->nk + 2;
+}
+
+namespace {
+const char* check_projected(const pk_bin_desc* b, int keep) {
+  if (keep <= 0 || keep > 7 || keep == 7) return "keep must name one or two axes (bits 1, 2, 4)";
+  if (b->nmu > 1 || b->npoles != 0) return "the projected power has no mu bins or multipoles";
+  if (3 * b->nk > kMaxLdsSlots) return "too many bins for the LDS accumulator";
+  return nullptr;
+}
+}  // namespace
+
+pk_status pk_bin_projected(pk_ctx* ctx, const pk_mesh_desc* m, const pk_bin_desc* b, int keep,
+                           const void* cmesh, double* result_dev) {
   if (!ctx) return PK_EINVAL;
   if (const char* why = check_mesh(m)) return fail(ctx, PK_EINVAL, why);
   if (const char* why = check_bins(b, m)) return fail(ctx, PK_EINVAL, why);
+  if (const char* why = check_projected(b, keep)) return fail(ctx, PK_EINVAL, why);
   if (!cmesh || !result_dev) return fail(ctx, PK_EINVAL, "cmesh or result is NULL");
-  if (const char* why = check_lds(b, m)) return fail(ctx, PK_EUNSUPPORTED, why);
   if (ctx->device == PK_DEVICE_NONE) return fail(ctx, PK_EDEVICE, "validation-only context");
   DeviceGuard g(ctx->device);
   BinTables* bt = nullptr;
   if (pk_status st = get_bin_tables(ctx, m, b, &bt)) return st;
-  const MeshTables* t = nullptr;
-  if (pk_status st = get_mesh_tables(ctx, m->nmesh, m->dtype, &t)) return st;
-  const BinSpec spec = make_spec(m, b, bt->e2_dev);
-  const size_t total = (size_t)m->nmesh * m->nmesh * (m->nmesh / 2);
-  size_t gb = (total + 255) / 256;
-  if (gb > 1024) gb = 1024;
-  const int gp = plane_bin_groups(m->nmesh);
+  BinSpec spec = make_spec(m, b, bt->e2_dev);
+  spec.nsum = 3 * b->nk;  // the reduce sums these slots plainly
+  spec.npoles = 0;
+  spec.npl = 0;
+  spec.zero_mask = 0;
+  spec.off2d = -1;
+  const int gp = projected_groups(m->nmesh, keep);
   double* partials = nullptr;
-  if (pk_status st = get_scratch(ctx, (gb + gp) * spec.nsum * sizeof(double), &partials)) return st;
-  hipError_t e = hipSuccess;
-  e = launch_bin_packed(m->dtype, m->nmesh, cmesh, spec, partials, ctx->stream);
-  if (e == hipSuccess)
-    e = launch_plane_bin(m->dtype, m->nmesh, cmesh, nullptr, m->nmesh / 2, *t, m->window, 0, spec,
-                         partials + gb * spec.nsum, ctx->stream);
-  if (e == hipSuccess) e = launch_reduce(partials, (int)(gb + gp), spec, result_dev, ctx->stream);
-  if (e != hipSuccess) return dev_fail(ctx, e, "pk_bin_power");
+  if (pk_status st = get_scratch(ctx, (size_t)gp * spec.nsum * sizeof(double), &partials))
+    return st;
+  hipError_t e = launch_bin_projected(m->dtype, m->nmesh, cmesh, keep, spec, partials, ctx->stream);
+  if (e == hipSuccess) e = launch_reduce(partials, gp, spec, result_dev, ctx->stream);
+  if (e != hipSuccess) return dev_fail(ctx, e, "pk_bin_projected");
   return PK_OK;
+}
+
+pk_status pk_projected_to_host(pk_ctx* ctx, const pk_mesh_desc* m, const pk_bin_desc* b,
+                               int keep, const double* result_dev, pk_result* out) {
+  if (!ctx) return PK_EINVAL;
+  if (const char* why = check_mesh(m)) return fail(ctx, PK_EINVAL, why);
+  if (const char* why = check_bins(b, m)) return fail(ctx, PK_EINVAL, why);
+  if (const char* why = check_projected(b, keep)) return fail(ctx, PK_EINVAL, why);
+  if (!result_dev || !out || !out->k || !out->power || !out->modes)
+    return fail(ctx, PK_EINVAL, "result, out or one of its 1-D arrays is NULL");
+  if (ctx->device == PK_DEVICE_NONE) return fail(ctx, PK_EDEVICE, "validation-only context");
+  DeviceGuard g(ctx->device);
+  const int nk = b->nk;
+  std::vector<double> h(3 * (size_t)nk + 2);
+  hipError_t e = hipMemcpyAsync(h.data(), result_dev, h.size() * sizeof(double),
+                                hipMemcpyDeviceToHost, ctx->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+  if (e != hipSuccess) return dev_fail(ctx, e, "pk_projected_to_host");
+  const int d = (keep & 1) + ((keep >> 1) & 1) + ((keep >> 2) & 1);
+  const double L = m->boxsize;
+  const double area = d == 1 ? L : L * L;
+  const double kf = 2.0 * 3.14159265358979323846 / L;
+  const double wsum = h[3 * (size_t)nk], w2sum = h[3 * (size_t)nk + 1];
+  const double norm = area / (wsum * wsum);
+  const double nan = std::nan("");
+  for (int k = 0; k < nk; ++k) {
+    const int64_t nb = (int64_t)std::llround(h[(size_t)nk + k]);
+    out->modes[k] = nb;
+    out->k[k] = nb ? kf * h[2 * (size_t)nk + k] / (double)nb : nan;
+    out->power[k] = nb ? norm * h[k] / (double)nb : nan;
+  }
+  out->shotnoise = area * w2sum / (wsum * wsum);
+  out->wsum = wsum;
+  out->w2sum = w2sum;
+  return PK_OK;
+}
+
+pk_status pk_bin_cross(pk_ctx* ctx, const pk_mesh_desc* m, const pk_bin_desc* b,
+                       const void* cmesh1, const void* cmesh2, double* result_dev) {
+  if (ctx && !cmesh2) return fail(ctx, PK_EINVAL, "cmesh2 is NULL");
+  return bin_packed(ctx, m, b, cmesh1, cmesh2, result_dev, "pk_bin_cross");
 }
 
 }  // extern "C"
@@ -539,8 +626,8 @@ pk_status check_fftpower(pk_ctx* ctx, const pk_mesh_desc* m, const pk_bin_desc* 
 // recorded only for the context stream.
 hipError_t enqueue_fftpower(pk_ctx* ctx, hipStream_t s, const pk_mesh_desc* m,
                             const BinSpec& spec, const MeshTables* t, const void* pos,
-                            const void* weight, int64_t n, void* workspace, const Layout& l,
-                            double* result_dev) {
+                            const void* weight, const void* value, int64_t n, void* workspace,
+                            const Layout& l, double* result_dev) {
   const bool timed = s == ctx->stream;
   auto stage = [&](int st) {
     if (timed) mark_stage(ctx, st);
@@ -555,10 +642,10 @@ hipError_t enqueue_fftpower(pk_ctx* ctx, hipStream_t s, const pk_mesh_desc* m,
   if (timed)
     for (bool& r : ctx->stage_ran) r = false;
   void* rec = ws + l.rec;
-  void* wrec = weight ? ws + l.wrec : nullptr;
+  void* wrec = (weight || value) ? ws + l.wrec : nullptr;
   stage(kBucket);
-  hipError_t e = launch_bucket(m->dtype, m->nmesh, m->boxsize, pos, weight, n, ws + l.bucket, rec,
-                               wrec, wsums, s);
+  hipError_t e = launch_bucket(m->dtype, m->nmesh, m->boxsize, pos, weight, value, n,
+                               ws + l.bucket, rec, wrec, wsums, s);
   stage(kPaintZ);
   if (e == hipSuccess)
     e = launch_paint_z(m->dtype, m->nmesh, m->window, m->interlaced != 0, rec, wrec,
@@ -626,7 +713,7 @@ pk_status submit_on_lane(pk_ctx* ctx, int lane, const pk_mesh_desc* m, const pk_
   hipError_t e = hipEventRecord(ctx->tables_ready, ctx->stream);
   if (e == hipSuccess) e = hipStreamWaitEvent(ln.stream, ctx->tables_ready, 0);
   if (e == hipSuccess)
-    e = enqueue_fftpower(ctx, ln.stream, m, spec, t, pos, weight, n, workspace,
+    e = enqueue_fftpower(ctx, ln.stream, m, spec, t, pos, weight, nullptr, n, workspace,
                          layout_of(m, b, n), result_dev);
   if (e == hipSuccess) e = hipEventRecord(ln.done, ln.stream);
   if (e != hipSuccess) return dev_fail(ctx, e, "lane submission");
@@ -637,9 +724,9 @@ pk_status submit_on_lane(pk_ctx* ctx, int lane, const pk_mesh_desc* m, const pk_
 
 extern "C" {
 
-pk_status pk_fftpower(pk_ctx* ctx, const pk_mesh_desc* m, const pk_bin_desc* b, const void* pos,
-                      const void* weight, int64_t n, void* workspace, size_t workspace_bytes,
-                      double* result_dev) {
+pk_status pk_fftpower_v(pk_ctx* ctx, const pk_mesh_desc* m, const pk_bin_desc* b,
+                        const void* pos, const void* weight, const void* value, int64_t n,
+                        void* workspace, size_t workspace_bytes, double* result_dev) {
   if (!ctx) return PK_EINVAL;
   if (pk_status st = check_fftpower(ctx, m, b, pos, n, workspace, workspace_bytes, result_dev))
     return st;
@@ -647,10 +734,17 @@ pk_status pk_fftpower(pk_ctx* ctx, const pk_mesh_desc* m, const pk_bin_desc* b, 
   const MeshTables* t = nullptr;
   BinSpec spec;
   if (pk_status st = prepare_tables(ctx, m, b, &t, &spec)) return st;
-  hipError_t e = enqueue_fftpower(ctx, ctx->stream, m, spec, t, pos, weight, n, workspace,
+  hipError_t e = enqueue_fftpower(ctx, ctx->stream, m, spec, t, pos, weight, value, n, workspace,
                                   layout_of(m, b, n), result_dev);
   if (e != hipSuccess) return dev_fail(ctx, e, "pk_fftpower");
   return PK_OK;
+}
+
+pk_status pk_fftpower(pk_ctx* ctx, const pk_mesh_desc* m, const pk_bin_desc* b, const void* pos,
+                      const void* weight, int64_t n, void* workspace, size_t workspace_bytes,
+                      double* result_dev) {
+  return pk_fftpower_v(ctx, m, b, pos, weight, nullptr, n, workspace, workspace_bytes,
+                       result_dev);
 }
 
 pk_status pk_ctx_set_lanes(pk_ctx* ctx, int nlanes) {

@@ -242,11 +242,13 @@ __global__ void __launch_bounds__((XCfg<T, N>::THREADS)) __attribute__((amdgpu_w
 }
 
 // One thread per (kx, ky): modes (kx, ky, 0) and (kx, ky, N/2), weight h = 1.
+// With zb: cross = 0 combines the interlaced pair, cross = 1 bins the cross
+// power Re(a conj(b)) of two spectra.
 template <typename T>
 __global__ void __launch_bounds__(256)
     k_plane_bin(int N, const cpx<T>* __restrict__ za, const cpx<T>* __restrict__ zb, size_t zs,
                 const cpx<T>* __restrict__ phase, const T* __restrict__ sinv, BinSpec b,
-                double* __restrict__ partials) {
+                double* __restrict__ partials, int cross) {
   extern __shared__ double sb[];
   zero_bins(sb, b.nsum);
   __syncthreads();
@@ -276,11 +278,16 @@ __global__ void __launch_bounds__(256)
     for (int pl = 0; pl < 2; ++pl) {
       const int nz = pl == 0 ? 0 : N / 2;
       cpx<T> cc = pa[pl];
-      if (zb) {
-        const cpx<T> bb = cmul(phase[nx + ny + nz + 3 * (N / 2)], pb[pl]);
-        cc = {T(0.5) * (cc.x + bb.x), T(0.5) * (cc.y + bb.y)};
+      T pw;
+      if (zb && cross) {
+        pw = cc.x * pb[pl].x + cc.y * pb[pl].y;
+      } else {
+        if (zb) {
+          const cpx<T> bb = cmul(phase[nx + ny + nz + 3 * (N / 2)], pb[pl]);
+          cc = {T(0.5) * (cc.x + bb.x), T(0.5) * (cc.y + bb.y)};
+        }
+        pw = cc.x * cc.x + cc.y * cc.y;
       }
-      T pw = cc.x * cc.x + cc.y * cc.y;
       if (sinv) {
         const T s = sinv[kx] * sinv[ky] * sinv[nz];
         pw *= s * s;
@@ -294,10 +301,12 @@ __global__ void __launch_bounds__(256)
   flush_bins(sb, b.nsum, partials + (size_t)blockIdx.x * b.nsum);
 }
 
-// Stand-alone binning of a packed spectrum, columns kz' >= 1 (h = 2).
+// Stand-alone binning of a packed spectrum, columns kz' >= 1 (h = 2): |c|^2,
+// or Re(c conj(c2)) when a second spectrum is given (cross power).
 template <typename T>
 __global__ void __launch_bounds__(256)
-    k_bin_packed(int N, const cpx<T>* __restrict__ cm, BinSpec b, double* __restrict__ partials) {
+    k_bin_packed(int N, const cpx<T>* __restrict__ cm, const cpx<T>* __restrict__ cm2, BinSpec b,
+                 double* __restrict__ partials) {
   extern __shared__ double sb[];
   zero_bins(sb, b.nsum);
   __syncthreads();
@@ -312,7 +321,8 @@ __global__ void __launch_bounds__(256)
     const int ky = (int)(rest % N), kx = (int)(rest / N);
     const int nx = signed_index(kx, N), ny = signed_index(ky, N), nz = col;
     const cpx<T> cc = cm[idx];
-    const T pw = cc.x * cc.x + cc.y * cc.y;
+    const cpx<T> dd = cm2 ? cm2[idx] : cc;
+    const T pw = cc.x * dd.x + cc.y * dd.y;
     const int n2 = nx * nx + ny * ny + nz * nz;
     const int nl = los == 0 ? nx : (los == 1 ? ny : nz);
     accumulate<T>(sb, b, n2, nl * nl, 2.0 * (double)pw);
@@ -387,6 +397,57 @@ __global__ void __launch_bounds__(256)
   __syncthreads();
   for (int i = threadIdx.x; i < nslots; i += blockDim.x)
     partials[(size_t)blockIdx.x * nslots + i] = sb[i];
+}
+
+// Mode (nx, ny, nz) of a packed half spectrum, signed indices in
+// [-N/2, N/2): columns 1 .. N/2 - 1 directly or through Hermitian symmetry,
+// the planes nz = 0 and nz = -N/2 (= N/2) unpacked from column 0 with the
+// partner (-nx, -ny).
+template <typename T>
+__device__ __forceinline__ cpx<T> packed_mode(const cpx<T>* __restrict__ cm, int N, int nx,
+                                              int ny, int nz) {
+  const int mask = N - 1, NC = N / 2;
+  const size_t me = ((size_t)(nx & mask) * N + (ny & mask)) * NC;
+  const size_t mirror = ((size_t)((-nx) & mask) * N + ((-ny) & mask)) * NC;
+  if (nz > 0) return cm[me + nz];
+  if (nz < 0 && nz > -NC) return cconj(cm[mirror - nz]);
+  const cpx<T> z = cm[me], zp = cconj(cm[mirror]);
+  const cpx<T> s = cadd(z, zp), d = csub(z, zp);
+  if (nz == 0) return {T(0.5) * s.x, T(0.5) * s.y};
+  return {T(0.5) * d.y, -T(0.5) * d.x};
+}
+
+// Projected power (ProjectedFFTPower): the modes whose wave numbers vanish
+// on the projected axes, every mode of the full grid of the kept axes once
+// (keep: bit a set for a kept axis a; one or two bits).  Sums per k-bin:
+// [0, nk) |c|^2, [nk, 2 nk) mode counts, [2 nk, 3 nk) |n|.
+template <typename T>
+__global__ void __launch_bounds__(256)
+    k_bin_projected(int N, const cpx<T>* __restrict__ cm, int keep, BinSpec b,
+                    double* __restrict__ partials) {
+  extern __shared__ double sb[];
+  const int nk = b.nk;
+  zero_bins(sb, 3 * nk);
+  __syncthreads();
+  const int a0 = (keep & 1) ? 0 : ((keep & 2) ? 1 : 2);
+  const int rest = keep & ~(1 << a0);
+  const int a1 = rest ? ((rest & 2) ? 1 : 2) : -1;
+  const int items = a1 >= 0 ? N * N : N;
+  for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < items;
+       idx += gridDim.x * blockDim.x) {
+    int n3[3] = {0, 0, 0};
+    n3[a0] = signed_index(idx % N, N);
+    if (a1 >= 0) n3[a1] = signed_index(idx / N, N);
+    const int n2 = n3[0] * n3[0] + n3[1] * n3[1] + n3[2] * n3[2];
+    const int k = kbin_of(n2, b);
+    if (k < 0) continue;
+    const cpx<T> c = packed_mode(cm, N, n3[0], n3[1], n3[2]);
+    atomicAdd(&sb[k], (double)(c.x * c.x + c.y * c.y));
+    atomicAdd(&sb[nk + k], 1.0);
+    atomicAdd(&sb[2 * nk + k], sqrt((double)n2));
+  }
+  __syncthreads();
+  flush_bins(sb, 3 * nk, partials + (size_t)blockIdx.x * 3 * nk);
 }
 
 // Sums the mode-table partial rows; integer slots are summed as integers.
@@ -573,35 +634,56 @@ hipError_t launch_xpass_bin(int dtype, int nmesh, const void* mesh_a, const void
 #undef PK_XB
 }
 
-hipError_t launch_bin_packed(int dtype, int nmesh, const void* cmesh, const BinSpec& b,
-                             double* partials, hipStream_t s) {
+hipError_t launch_bin_packed(int dtype, int nmesh, const void* cmesh, const void* cmesh2,
+                             const BinSpec& b, double* partials, hipStream_t s) {
   const size_t total = (size_t)nmesh * nmesh * (nmesh / 2);
   size_t g = (total + 255) / 256;
   if (g > 1024) g = 1024;
   if (dtype == PK_F32)
     hipLaunchKernelGGL(k_bin_packed<float>, dim3((unsigned)g), dim3(256), bin_lds_bytes(b), s,
-                       nmesh, static_cast<const cpx<float>*>(cmesh), b, partials);
+                       nmesh, static_cast<const cpx<float>*>(cmesh),
+                       static_cast<const cpx<float>*>(cmesh2), b, partials);
   else
     hipLaunchKernelGGL(k_bin_packed<double>, dim3((unsigned)g), dim3(256), bin_lds_bytes(b), s,
-                       nmesh, static_cast<const cpx<double>*>(cmesh), b, partials);
+                       nmesh, static_cast<const cpx<double>*>(cmesh),
+                       static_cast<const cpx<double>*>(cmesh2), b, partials);
   return hipGetLastError();
 }
 
 hipError_t launch_plane_bin(int dtype, int nmesh, const void* za, const void* zb, size_t zstride,
                             const MeshTables& t, int order, int compensated, const BinSpec& b,
-                            double* partials, hipStream_t s) {
+                            double* partials, hipStream_t s, int cross) {
   const int g = plane_bin_groups(nmesh);
   if (dtype == PK_F32) {
     const float* sinv = compensated ? static_cast<const float*>(t.sinc_inv) + (size_t)(order - 2) * nmesh : nullptr;
     hipLaunchKernelGGL(k_plane_bin<float>, dim3(g), dim3(256), bin_lds_bytes(b), s, nmesh,
                        static_cast<const cpx<float>*>(za), static_cast<const cpx<float>*>(zb),
-                       zstride, static_cast<const cpx<float>*>(t.phase), sinv, b, partials);
+                       zstride, static_cast<const cpx<float>*>(t.phase), sinv, b, partials, cross);
   } else {
     const double* sinv = compensated ? static_cast<const double*>(t.sinc_inv) + (size_t)(order - 2) * nmesh : nullptr;
     hipLaunchKernelGGL(k_plane_bin<double>, dim3(g), dim3(256), bin_lds_bytes(b), s, nmesh,
                        static_cast<const cpx<double>*>(za), static_cast<const cpx<double>*>(zb),
-                       zstride, static_cast<const cpx<double>*>(t.phase), sinv, b, partials);
+                       zstride, static_cast<const cpx<double>*>(t.phase), sinv, b, partials, cross);
   }
+  return hipGetLastError();
+}
+
+int projected_groups(int nmesh, int keep) {
+  const long items = (keep & (keep - 1)) ? (long)nmesh * nmesh : nmesh;
+  const long g = (items + 255) / 256;
+  return (int)(g < 64 ? g : 64);
+}
+
+hipError_t launch_bin_projected(int dtype, int nmesh, const void* cmesh, int keep,
+                                const BinSpec& b, double* partials, hipStream_t s) {
+  const int g = projected_groups(nmesh, keep);
+  const size_t lds = (size_t)3 * b.nk * sizeof(double);
+  if (dtype == PK_F32)
+    hipLaunchKernelGGL(k_bin_projected<float>, dim3(g), dim3(256), lds, s, nmesh,
+                       static_cast<const cpx<float>*>(cmesh), keep, b, partials);
+  else
+    hipLaunchKernelGGL(k_bin_projected<double>, dim3(g), dim3(256), lds, s, nmesh,
+                       static_cast<const cpx<double>*>(cmesh), keep, b, partials);
   return hipGetLastError();
 }
 

@@ -76,9 +76,11 @@ hipError_t launch_paint_atomic(int dtype, int order, int nmesh, double boxsize, 
 
 // Sorted painting fused with the z-pass (paint_sorted.hip).
 size_t bucket_bytes(int nmesh);
+// value: per-particle field values V or NULL; records carry w V, the sums
+// are {sum w, sum (w V)^2}.
 hipError_t launch_bucket(int dtype, int nmesh, double boxsize, const void* pos, const void* weight,
-                         int64_t n, void* bucket_ws, void* rec, void* wrec, double* wsums,
-                         hipStream_t s);
+                         const void* value, int64_t n, void* bucket_ws, void* rec, void* wrec,
+                         double* wsums, hipStream_t s);
 hipError_t launch_paint_z(int dtype, int nmesh, int order, bool inter, const void* rec,
                           const void* wrec, const void* bucket_ws, const double* wsums,
                           const void* tw, void* mesh_a, void* mesh_b, hipStream_t s);
@@ -101,13 +103,19 @@ size_t xpass_static_lds(int dtype, int nmesh);
 hipError_t launch_xpass_bin(int dtype, int nmesh, const void* mesh_a, const void* mesh_b,
                             const MeshTables& t, int order, int compensated, const BinSpec& b,
                             double* partials, void* side_a, void* side_b, hipStream_t s);
-hipError_t launch_bin_packed(int dtype, int nmesh, const void* cmesh, const BinSpec& b,
-                             double* partials, hipStream_t s);
+// cmesh2 != NULL: cross power Re(c conj(c2)) instead of |c|^2.
+hipError_t launch_bin_packed(int dtype, int nmesh, const void* cmesh, const void* cmesh2,
+                             const BinSpec& b, double* partials, hipStream_t s);
+// cross = 0: za (and the interlaced zb) combined; cross = 1: Re(a conj(b)).
 hipError_t launch_plane_bin(int dtype, int nmesh, const void* za, const void* zb, size_t zstride,
                             const MeshTables& t, int order, int compensated, const BinSpec& b,
-                            double* partials, hipStream_t s);
+                            double* partials, hipStream_t s, int cross = 0);
 hipError_t launch_reduce(const double* partials, int ngroups, const BinSpec& b, double* result,
                          hipStream_t s);
+// Projected power: sums [|c|^2, counts, |n|] x nk over the kept axes' grid.
+int projected_groups(int nmesh, int keep);
+hipError_t launch_bin_projected(int dtype, int nmesh, const void* cmesh, int keep,
+                                const BinSpec& b, double* partials, hipStream_t s);
 hipError_t launch_mode_tables(int nmesh, const BinSpec& b, double* partials, int ngroups,
                               double* out, hipStream_t s);
 int mode_table_groups(int nmesh);

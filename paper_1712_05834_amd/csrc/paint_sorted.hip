@@ -66,8 +66,9 @@ __device__ __forceinline__ int claim_slot(int key, int* __restrict__ counter) {
 
 template <typename T>
 __global__ void __launch_bounds__(256)
-    k_bucket_count(const T* __restrict__ pos, const T* __restrict__ weight, int64_t n, int nmesh,
-                   double boxsize, int* __restrict__ count, double* __restrict__ wpart) {
+    k_bucket_count(const T* __restrict__ pos, const T* __restrict__ weight,
+                   const T* __restrict__ value, int64_t n, int nmesh, double boxsize,
+                   int* __restrict__ count, double* __restrict__ wpart) {
   const int mask = nmesh - 1;
   double ws = 0.0, ws2 = 0.0;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
@@ -79,9 +80,11 @@ __global__ void __launch_bounds__(256)
       const double ux = cell_coordinate((double)pos[3 * i], nmesh, boxsize);
       const double uy = cell_coordinate((double)pos[3 * i + 1], nmesh, boxsize);
       key = (((int)floor(ux)) & mask) * nmesh + (((int)floor(uy)) & mask);
+      // normalisation: sum w; shot noise: sum (w V)^2 (V = 1 without values)
       const double wp = weight ? (double)weight[i] : 1.0;
+      const double wv = value ? wp * (double)value[i] : wp;
       ws += wp;
-      ws2 += wp * wp;
+      ws2 += wv * wv;
     }
     (void)claim_slot(key, count);
   }
@@ -127,9 +130,10 @@ __global__ void __launch_bounds__(1024)
 
 template <typename T>
 __global__ void __launch_bounds__(256)
-    k_bucket_scatter(const T* __restrict__ pos, const T* __restrict__ weight, int64_t n,
-                     int nmesh, double boxsize, int* __restrict__ cursor,
-                     typename Rec<T>::type* __restrict__ rec, T* __restrict__ wrec) {
+    k_bucket_scatter(const T* __restrict__ pos, const T* __restrict__ weight,
+                     const T* __restrict__ value, int64_t n, int nmesh, double boxsize,
+                     int* __restrict__ cursor, typename Rec<T>::type* __restrict__ rec,
+                     T* __restrict__ wrec) {
   const int mask = nmesh - 1;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   const int64_t nround = (n + stride - 1) / stride * stride;
@@ -157,7 +161,8 @@ __global__ void __launch_bounds__(256)
         r.w = (double)((iy << 16) | iz);
       }
       rec[slot] = r;
-      if (wrec) wrec[slot] = weight[i];
+      // the painted amount of the particle: w V
+      if (wrec) wrec[slot] = weight ? (value ? weight[i] * value[i] : weight[i]) : value[i];
     }
   }
 }
@@ -525,8 +530,8 @@ size_t bucket_bytes(int nmesh) {
 }
 
 hipError_t launch_bucket(int dtype, int nmesh, double boxsize, const void* pos, const void* weight,
-                         int64_t n, void* bucket_ws, void* rec, void* wrec, double* wsums,
-                         hipStream_t s) {
+                         const void* value, int64_t n, void* bucket_ws, void* rec, void* wrec,
+                         double* wsums, hipStream_t s) {
   const int n2 = nmesh * nmesh;
   int* count = static_cast<int*>(bucket_ws);
   int* offsets = count + n2;
@@ -542,26 +547,28 @@ hipError_t launch_bucket(int dtype, int nmesh, double boxsize, const void* pos, 
   if (blocks < 1) blocks = 1;
   if (dtype == PK_F32)
     hipLaunchKernelGGL(k_bucket_count<float>, dim3((unsigned)blocks), dim3(256), 0, s,
-                       static_cast<const float*>(pos), static_cast<const float*>(weight), n,
-                       nmesh, boxsize, count, wpart);
+                       static_cast<const float*>(pos), static_cast<const float*>(weight),
+                       static_cast<const float*>(value), n, nmesh, boxsize, count, wpart);
   else
     hipLaunchKernelGGL(k_bucket_count<double>, dim3((unsigned)blocks), dim3(256), 0, s,
-                       static_cast<const double*>(pos), static_cast<const double*>(weight), n,
-                       nmesh, boxsize, count, wpart);
+                       static_cast<const double*>(pos), static_cast<const double*>(weight),
+                       static_cast<const double*>(value), n, nmesh, boxsize, count, wpart);
   hipLaunchKernelGGL(k_weight_sums, dim3(1), dim3(1024), 0, s, wpart, (int)blocks, wsums);
   hipLaunchKernelGGL(k_scan_blocks, dim3(nb), dim3(1024), 0, s, count, n2, bsums);
   hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(1024), 0, s, bsums, nb);
   hipLaunchKernelGGL(k_scan_final, dim3(nb), dim3(1024), 0, s, count, n2, bsums, offsets, cursor);
   if (dtype == PK_F32)
     hipLaunchKernelGGL(k_bucket_scatter<float>, dim3((unsigned)blocks), dim3(256), 0, s,
-                       static_cast<const float*>(pos), static_cast<const float*>(weight), n,
-                       nmesh, boxsize, cursor, static_cast<float4*>(rec),
-                       weight ? static_cast<float*>(wrec) : nullptr);
+                       static_cast<const float*>(pos), static_cast<const float*>(weight),
+                       static_cast<const float*>(value), n, nmesh, boxsize, cursor,
+                       static_cast<float4*>(rec),
+                       (weight || value) ? static_cast<float*>(wrec) : nullptr);
   else
     hipLaunchKernelGGL(k_bucket_scatter<double>, dim3((unsigned)blocks), dim3(256), 0, s,
-                       static_cast<const double*>(pos), static_cast<const double*>(weight), n,
-                       nmesh, boxsize, cursor, static_cast<double4*>(rec),
-                       weight ? static_cast<double*>(wrec) : nullptr);
+                       static_cast<const double*>(pos), static_cast<const double*>(weight),
+                       static_cast<const double*>(value), n, nmesh, boxsize, cursor,
+                       static_cast<double4*>(rec),
+                       (weight || value) ? static_cast<double*>(wrec) : nullptr);
   return hipGetLastError();
 }
 
