@@ -52,14 +52,17 @@ __device__ __forceinline__ int kbin_of(int n2, const BinSpec& b) {
   return k;
 }
 
-// Largest j in [0, nmu] with j^2 n^2 <= nmu^2 n_los^2, clipped to nmu - 1;
-// a float estimate corrected with exact 64-bit integer products.
+// Largest j in [0, nmu] with j^2 n^2 <= nmu^2 n_los^2, clipped to nmu - 1.
+// The float estimate nmu |mu| is within a few 1e-7 of its exact value (a
+// few ulp of hardware reciprocal and root, nmu <= 64), so its floor is at
+// most one off; one exact 64-bit integer check each way corrects it.
 __device__ __forceinline__ int mubin_of(int nlos2, int n2, int nmu) {
   const unsigned long long rhs = (unsigned long long)(nmu * nmu) * (unsigned)nlos2;
-  int j = (int)((float)nmu * sqrtf(__fdividef((float)nlos2, (float)n2)));
+  int j = (int)((float)nmu *
+                __builtin_amdgcn_sqrtf((float)nlos2 * __builtin_amdgcn_rcpf((float)n2)));
   j = j < 0 ? 0 : (j > nmu ? nmu : j);
-  while (j < nmu && (unsigned long long)((j + 1) * (j + 1)) * (unsigned)n2 <= rhs) ++j;
-  while (j > 0 && (unsigned long long)(j * j) * (unsigned)n2 > rhs) --j;
+  if (j < nmu && (unsigned long long)((j + 1) * (j + 1)) * (unsigned)n2 <= rhs) ++j;
+  if (j > 0 && (unsigned long long)(j * j) * (unsigned)n2 > rhs) --j;
   return j < nmu ? j : nmu - 1;
 }
 
@@ -81,19 +84,21 @@ __device__ __forceinline__ T ratio(int a, int b) {
   }
 }
 
-// Adds one mode of (Hermitian-weighted) power hp to the LDS bins.
+// Adds one mode of (Hermitian-weighted) power hp to the LDS bins.  The
+// per-mode products hp L_ell are formed in the path's precision; every sum
+// is float64.
 template <typename T>
 __device__ __forceinline__ void accumulate(double* sb, const BinSpec& b, int n2, int nlos2,
-                                           double hp) {
+                                           T hp) {
   const int k = kbin_of(n2, b);
   if (k < 0) return;
-  atomicAdd(&sb[k], hp);
+  atomicAdd(&sb[k], (double)hp);
   if (b.npl > 0) {
     const T mu2 = ratio<T>(nlos2, n2);
     for (int i = 0; i < b.npl; ++i)
-      atomicAdd(&sb[b.pole_slot[i] + k], hp * (double)legendre<T>(b.pole_ell[i], mu2));
+      atomicAdd(&sb[b.pole_slot[i] + k], (double)(hp * legendre<T>(b.pole_ell[i], mu2)));
   }
-  if (b.off2d >= 0) atomicAdd(&sb[b.off2d + k * b.nmu + mubin_of(nlos2, n2, b.nmu)], hp);
+  if (b.off2d >= 0) atomicAdd(&sb[b.off2d + k * b.nmu + mubin_of(nlos2, n2, b.nmu)], (double)hp);
 }
 
 __device__ __forceinline__ int signed_index(int i, int n) { return i < n / 2 ? i : i - n; }
@@ -234,7 +239,7 @@ __global__ void __launch_bounds__((XCfg<T, N>::THREADS)) __attribute__((amdgpu_w
       const T pw = pws[pidx(cc_, kx)];
       const int n2 = nx * nx + ny * ny + nz * nz;
       const int nl = los == 0 ? nx : (los == 1 ? ny : nz);
-      accumulate<T>(sb, b, n2, nl * nl, 2.0 * (double)pw);
+      accumulate<T>(sb, b, n2, nl * nl, T(2) * pw);
     }
     __syncthreads();  // the staged power is read before the next tile's FFT reuses the LDS
   }
@@ -294,7 +299,7 @@ __global__ void __launch_bounds__(256)
       }
       const int n2 = nx * nx + ny * ny + nz * nz;
       const int nl = los == 0 ? nx : (los == 1 ? ny : nz);
-      accumulate<T>(sb, b, n2, nl * nl, (double)pw);
+      accumulate<T>(sb, b, n2, nl * nl, pw);
     }
   }
   __syncthreads();
@@ -325,7 +330,7 @@ __global__ void __launch_bounds__(256)
     const T pw = cc.x * dd.x + cc.y * dd.y;
     const int n2 = nx * nx + ny * ny + nz * nz;
     const int nl = los == 0 ? nx : (los == 1 ? ny : nz);
-    accumulate<T>(sb, b, n2, nl * nl, 2.0 * (double)pw);
+    accumulate<T>(sb, b, n2, nl * nl, T(2) * pw);
   }
   __syncthreads();
   flush_bins(sb, b.nsum, partials + (size_t)blockIdx.x * b.nsum);

@@ -265,7 +265,10 @@ struct PaintCfg {
   static constexpr int NM = INTER ? 2 : 1;
   static constexpr long ACC_BYTES = (long)N * sizeof(Acc);
   static constexpr long FFT_BYTES = (long)LP * 2 * sizeof(T);
-  static constexpr long ROW_BYTES = ((ACC_BYTES > FFT_BYTES ? ACC_BYTES : FFT_BYTES) + 15) / 16 * 16;
+  // row stride: the row rounded to 16 bytes plus 16 bytes, so that
+  // consecutive rows start 4 banks apart
+  static constexpr long ROW_BYTES =
+      ((ACC_BYTES > FFT_BYTES ? ACC_BYTES : FFT_BYTES) + 15) / 16 * 16 + 16;
   static constexpr int ROWA = (int)(ROW_BYTES / sizeof(Acc));  // row stride in Acc units
   static constexpr int EMIN = M < 2 ? M : 2;
   static constexpr int EMAX = M < e_max<T>() ? M : e_max<T>();
@@ -305,18 +308,20 @@ struct PaintCfg {
   static constexpr int HHI = P == 2 ? 0 : 1;
 };
 
-// LDS word of cell z in accumulator row r: within each block of 32 cells the
-// cells are rotated by an even amount that depends on the block and the row.
+// LDS word of cell z within an accumulator row: within each block of 32
+// cells the cells are rotated by an even amount that depends on the block.
 // Lanes of a wave often add to cells a power of two apart (lattice-like
-// catalogs: z spaced 8, 64 or 256 cells; rows 8 KB apart), which would put
-// all their float64 atomics on one bank pair; the rotation spreads them.  An
-// even rotation keeps the cells 2j, 2j + 1 adjacent, as the read-back into
-// complex pairs needs.  Rows shorter than 32 cells are left as they are.
+// catalogs: z spaced 8, 64 or 256 cells), which would put all their float64
+// atomics on one bank pair; the rotation spreads them (the padded row stride
+// does the same across rows).  An even rotation keeps the cells 2j, 2j + 1
+// adjacent, as the read-back into complex pairs needs.  It does not depend
+// on the row, so a particle's z words are computed once for all its rows.
+// Rows shorter than 32 cells are left as they are.
 template <int N>
-__device__ __forceinline__ int acc_word(int z, int r) {
+__device__ __forceinline__ int acc_word(int z) {
   if constexpr (N < 32) return z;
   const int b = z >> 5;
-  const int rot = ((b + 3 * (b >> 3) + 5 * r) & 15) << 1;
+  const int rot = ((b + 3 * (b >> 3)) & 15) << 1;
   return (z & ~31) | ((z + rot) & 31);
 }
 
@@ -445,6 +450,9 @@ __global__ void __launch_bounds__((PaintCfg<T, N, P, INTER>::THREADS))
           }
           window_frac<T, P>(tt, base, first[d], w[d]);
         }
+        int zw[P];
+#pragma unroll
+        for (int c = 0; c < P; ++c) zw[c] = acc_word<N>((first[2] + c) & mask);
 #pragma unroll
         for (int a = 0; a < P; ++a) {
           const int lx = (first[0] + a - X0) & mask;
@@ -455,11 +463,9 @@ __global__ void __launch_bounds__((PaintCfg<T, N, P, INTER>::THREADS))
             const int ly = (first[1] + b2 - Y0) & mask;
             if (ly >= TY) continue;
             const T wab = wa * w[1][b2];
-            const int ri = (mesh * TX + lx) * TY + ly;
-            Acc* row = acc + ri * ROWA;
+            Acc* row = acc + ((mesh * TX + lx) * TY + ly) * ROWA;
 #pragma unroll
-            for (int c = 0; c < P; ++c)
-              atomicAdd(&row[acc_word<N>((first[2] + c) & mask, ri)], (double)(wab * w[2][c]));
+            for (int c = 0; c < P; ++c) atomicAdd(&row[zw[c]], (double)(wab * w[2][c]));
           }
         }
       }
@@ -484,7 +490,7 @@ __global__ void __launch_bounds__((PaintCfg<T, N, P, INTER>::THREADS))
   if (fa) {
 #pragma unroll
     for (int e = 0; e < FE; ++e) {
-      const int wj = acc_word<N>(2 * (t + FTPL * e), r);
+      const int wj = acc_word<N>(2 * (t + FTPL * e));
       v[e] = {static_cast<T>(arow[wj] - mean), static_cast<T>(arow[wj + 1] - mean)};
     }
   }
