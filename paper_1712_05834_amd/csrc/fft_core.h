@@ -231,6 +231,20 @@ __device__ __forceinline__ void build_stage_table(cpx<T>* dst, const Src& src) {
   __syncthreads();
 }
 
+// Index j of the source twiddle W_L^j of entry i of the stage table (as
+// build_stage_table fills it), for i < stage_table_size<L, E>().
+template <int L, int E>
+__host__ __device__ inline int stage_table_source(int i) {
+  constexpr int R0 = stage_radix<L, E, 1>();
+  int off = 0, p = R0;
+  while (i >= off + p * (E - 1)) {
+    off += p * (E - 1);
+    p *= E;
+  }
+  const int k = (i - off) / (E - 1), m = (i - off) % (E - 1) + 1;
+  return m * k * (L / (p * E));
+}
+
 // Loads the first quarter of the global table W_Nt^j into LDS (all threads
 // call it; it ends with a barrier).
 template <typename T>

@@ -346,29 +346,49 @@ __global__ void __launch_bounds__((PaintCfg<T, N, P, INTER>::THREADS))
   const int tiles_y = N / TY;
   const int X0 = (blockIdx.x / tiles_y) * TX, Y0 = (blockIdx.x % tiles_y) * TY;
 
-  for (int i = threadIdx.x; i < ROWS * ROWA; i += blockDim.x) acc[i] = 0;
-  for (int i = threadIdx.x; i < M; i += blockDim.x) twm[i] = tw[i];
-  build_stage_table<T, M, Cf::FE>(tws, TwGlobal<T>{tw, 2});  // ends with a barrier
-
+  // The global loads of the prologue are issued first and consumed late: the
+  // segment offsets after the LDS rows are cleared, the twiddles (only the
+  // z-FFT needs them) after the gather, so their latency is hidden.
   // segments of the sorted records: for each source row bx, the contiguous
   // column range [by0, by0 + wy) (split in two where it wraps around N); one
   // thread per source row reads its offsets, thread 0 forms the prefix sums
   constexpr int HW = Cf::HLO + Cf::HHI;
   constexpr int WX = (TX + HW) >= N ? N : TX + HW;
   constexpr int WY = (TY + HW) >= N ? N : TY + HW;
-  if ((int)threadIdx.x < WX) {
+  const bool seg_thread = (int)threadIdx.x < WX;
+  int o0 = 0, o1 = 0, o2 = 0, o3 = 0, bx = 0;
+  const int run0 = (N - ((TY + HW) >= N ? 0 : ((Y0 - Cf::HLO) & mask))) < WY
+                       ? (N - ((TY + HW) >= N ? 0 : ((Y0 - Cf::HLO) & mask)))
+                       : WY;
+  const int run1 = WY - run0;  // wrapped part, starting at column 0
+  if (seg_thread) {
     const int bx0 = (TX + HW) >= N ? 0 : X0 - Cf::HLO;
     const int by0 = (TY + HW) >= N ? 0 : ((Y0 - Cf::HLO) & mask);
-    const int bx = (bx0 + (int)threadIdx.x) & mask;
-    const int run0 = (N - by0) < WY ? (N - by0) : WY;
+    bx = (bx0 + (int)threadIdx.x) & mask;
     const int b0 = bx * N + by0;
-    seg_start[2 * threadIdx.x] = offsets[b0];
-    seg_cum[2 * threadIdx.x] = offsets[b0 + run0] - offsets[b0];
+    o0 = offsets[b0];
+    o1 = offsets[b0 + run0];
+    if (run1 > 0) {
+      o2 = offsets[bx * N];
+      o3 = offsets[bx * N + run1];
+    }
+  }
+  const double wsum = wsums[0];  // for the mean subtracted before the z-FFT
+  constexpr int STS = stage_table_size<M, Cf::FE>();
+  constexpr bool EARLY_TW = M <= Cf::THREADS && STS <= Cf::THREADS;
+  cpx<T> tw_m{}, tw_s{};
+  if constexpr (EARLY_TW) {
+    if ((int)threadIdx.x < M) tw_m = tw[threadIdx.x];
+    if ((int)threadIdx.x < STS) tw_s = tw[2 * stage_table_source<M, Cf::FE>(threadIdx.x)];
+  }
+
+  for (int i = threadIdx.x; i < ROWS * ROWA; i += blockDim.x) acc[i] = 0;
+  if (seg_thread) {
+    seg_start[2 * threadIdx.x] = o0;
+    seg_cum[2 * threadIdx.x] = o1 - o0;
     seg_row[2 * threadIdx.x] = bx;
-    const int run1 = WY - run0;  // wrapped part, starting at column 0
-    const int b1 = bx * N;
-    seg_start[2 * threadIdx.x + 1] = run1 > 0 ? offsets[b1] : 0;
-    seg_cum[2 * threadIdx.x + 1] = run1 > 0 ? offsets[b1 + run1] - offsets[b1] : 0;
+    seg_start[2 * threadIdx.x + 1] = o2;
+    seg_cum[2 * threadIdx.x + 1] = o3 - o2;
     seg_row[2 * threadIdx.x + 1] = bx;
   }
   __syncthreads();
@@ -477,10 +497,20 @@ __global__ void __launch_bounds__((PaintCfg<T, N, P, INTER>::THREADS))
   }
   __syncthreads();
 
+  // the twiddle tables of the z-FFT (written after the gather's barrier; the
+  // next barrier orders them before their first use)
+  if constexpr (EARLY_TW) {
+    if ((int)threadIdx.x < M) twm[threadIdx.x] = tw_m;
+    if ((int)threadIdx.x < STS) tws[threadIdx.x] = tw_s;
+  } else {
+    for (int i = threadIdx.x; i < M; i += blockDim.x) twm[i] = tw[i];
+    build_stage_table<T, M, Cf::FE>(tws, TwGlobal<T>{tw, 2});  // ends with a barrier
+  }
+
   // r2c along z of every owned column, mean subtracted in float64 before the
   // rounding to T (only the DC mode changes; it keeps the rounding relative to
   // the fluctuations).  The row becomes the padded complex line.
-  const double mean = wsums[0] / ((double)N * N * N);
+  const double mean = wsum / ((double)N * N * N);
   constexpr int FE = Cf::FE, FTPL = Cf::FTPL;
   const bool fa = (int)threadIdx.x < Cf::FTHREADS;
   const int r = fa ? (int)threadIdx.x / FTPL : 0, t = (int)threadIdx.x % FTPL;
