@@ -431,15 +431,16 @@ __global__ void __launch_bounds__((PaintCfg<T, N, P, INTER>::THREADS))
     if (wrec) w_cur = wrec[idx_cur];
   }
   for (int q = threadIdx.x; q < total; q += blockDim.x) {
+    // inside the loop idx_cur is a valid record; past the end the next load
+    // repeats it, so that the load is unconditional and the wait for the
+    // current record does not have to drain it
     int seg_nxt = seg_cur;
     const int idx_nxt = locate(q + (int)blockDim.x, seg_nxt);
-    RecT r_nxt{};
+    const int idx_ld = idx_nxt >= 0 ? idx_nxt : idx_cur;
+    const RecT r_nxt = rec[idx_ld];
     T w_nxt = T(1);
-    if (idx_nxt >= 0) {
-      r_nxt = rec[idx_nxt];
-      if (wrec) w_nxt = wrec[idx_nxt];
-    }
-    if (idx_cur >= 0) {
+    if (wrec) w_nxt = wrec[idx_ld];
+    {
       const RecT r = r_cur;
       const T wp = w_cur;
       unsigned packed;
