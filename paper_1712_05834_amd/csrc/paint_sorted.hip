@@ -40,8 +40,16 @@ __device__ __forceinline__ double wave_sum_d(double v) {
 // Runs of equal keys among consecutive lanes of a wavefront: the head lane of
 // each run adds the run length to counter[key] with one atomic; every lane
 // gets its slot = old value + its offset in the run.  Lanes with key < 0 take
-// no slot.
-__device__ __forceinline__ int claim_slot(int key, int* __restrict__ counter) {
+// no slot.  Split in two halves (issue the atomic / share its result) so that
+// a thread can have the atomics of several particles in flight at once.
+struct RunClaim {
+  int my_head;  // lane of the head of my run
+  int offset;   // my position in the run, -1 if no slot
+  int old;      // the head's atomic result
+};
+
+__device__ __forceinline__ RunClaim claim_issue(int key, int* __restrict__ counter,
+                                                bool need_old) {
   const int lane = threadIdx.x & 63;
   const int prev = __shfl_up(key, 1, 64);
   const bool valid = key >= 0;
@@ -50,19 +58,31 @@ __device__ __forceinline__ int claim_slot(int key, int* __restrict__ counter) {
   const unsigned long long valids = __ballot(valid);
   // head lane of my run: highest head at or below me
   const unsigned long long below = heads & ((2ull << lane) - 1ull);
-  const int my_head = below ? 63 - __clzll(below) : lane;
-  // run length for a head: up to the next head or the first invalid lane
-  int len = 0;
+  RunClaim c;
+  c.my_head = below ? 63 - __clzll(below) : lane;
+  c.offset = valid ? lane - c.my_head : -1;
+  c.old = 0;
   if (head) {
+    // run length for a head: up to the next head or the first invalid lane
     const unsigned long long above = (heads | ~valids) & ~((2ull << lane) - 1ull);
     const int next = above ? __ffsll(above) - 1 : 64;
-    len = next - lane;
+    if (need_old) {
+      c.old = atomicAdd(&counter[key], next - lane);
+    } else {
+      (void)atomicAdd(&counter[key], next - lane);
+    }
   }
-  int old = 0;
-  if (head) old = atomicAdd(&counter[key], len);
-  const int base = __shfl(old, my_head, 64);
-  return valid ? base + (lane - my_head) : -1;
+  return c;
 }
+
+__device__ __forceinline__ int claim_finish(const RunClaim& c) {
+  const int base = __shfl(c.old, c.my_head, 64);
+  return c.offset >= 0 ? base + c.offset : -1;
+}
+
+// Particles per thread per step of the bucketing kernels: their loads and
+// atomics are issued together, so that their latencies overlap.
+constexpr int kBucketUnroll = 4;
 
 template <typename T>
 __global__ void __launch_bounds__(256)
@@ -70,23 +90,32 @@ __global__ void __launch_bounds__(256)
                    const T* __restrict__ value, int64_t n, int nmesh, double boxsize,
                    int* __restrict__ count, double* __restrict__ wpart) {
   const int mask = nmesh - 1;
+  constexpr int U = kBucketUnroll;
   double ws = 0.0, ws2 = 0.0;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  // whole wavefronts iterate together so that claim_slot sees full waves
-  const int64_t nround = (n + stride - 1) / stride * stride;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nround; i += stride) {
-    int key = -1;
-    if (i < n) {
-      const double ux = cell_coordinate((double)pos[3 * i], nmesh, boxsize);
-      const double uy = cell_coordinate((double)pos[3 * i + 1], nmesh, boxsize);
-      key = (((int)floor(ux)) & mask) * nmesh + (((int)floor(uy)) & mask);
-      // normalisation: sum w; shot noise: sum (w V)^2 (V = 1 without values)
-      const double wp = weight ? (double)weight[i] : 1.0;
-      const double wv = value ? wp * (double)value[i] : wp;
-      ws += wp;
-      ws2 += wv * wv;
+  // whole wavefronts iterate together so that the run detection sees full
+  // waves; particle i + u * stride is the u-th of a step
+  const int64_t nround = (n + U * stride - 1) / (U * stride) * (U * stride);
+  for (int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i0 < nround;
+       i0 += U * stride) {
+    int key[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t i = i0 + u * stride;
+      key[u] = -1;
+      if (i < n) {
+        const double ux = cell_coordinate((double)pos[3 * i], nmesh, boxsize);
+        const double uy = cell_coordinate((double)pos[3 * i + 1], nmesh, boxsize);
+        key[u] = (((int)floor(ux)) & mask) * nmesh + (((int)floor(uy)) & mask);
+        // normalisation: sum w; shot noise: sum (w V)^2 (V = 1 without values)
+        const double wp = weight ? (double)weight[i] : 1.0;
+        const double wv = value ? wp * (double)value[i] : wp;
+        ws += wp;
+        ws2 += wv * wv;
+      }
     }
-    (void)claim_slot(key, count);
+#pragma unroll
+    for (int u = 0; u < U; ++u) (void)claim_issue(key[u], count, false);
   }
   // per-block partial sums (reduced in a fixed order by k_weight_sums)
   __shared__ double part[2][4];
@@ -135,34 +164,50 @@ __global__ void __launch_bounds__(256)
                      int* __restrict__ cursor, typename Rec<T>::type* __restrict__ rec,
                      T* __restrict__ wrec) {
   const int mask = nmesh - 1;
+  constexpr int U = kBucketUnroll;
+  using RecT = typename Rec<T>::type;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  const int64_t nround = (n + stride - 1) / stride * stride;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nround; i += stride) {
-    int key = -1;
-    double u[3] = {0.0, 0.0, 0.0}, f[3] = {0.0, 0.0, 0.0};
-    if (i < n) {
+  const int64_t nround = (n + U * stride - 1) / (U * stride) * (U * stride);
+  for (int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i0 < nround;
+       i0 += U * stride) {
+    int key[U];
+    RecT r[U];
 #pragma unroll
-      for (int d = 0; d < 3; ++d) {
-        u[d] = cell_coordinate((double)pos[3 * i + d], nmesh, boxsize);
-        f[d] = floor(u[d]);
+    for (int uu = 0; uu < U; ++uu) {
+      const int64_t i = i0 + uu * stride;
+      key[uu] = -1;
+      r[uu] = RecT{};
+      if (i < n) {
+        double u[3], f[3];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+          u[d] = cell_coordinate((double)pos[3 * i + d], nmesh, boxsize);
+          f[d] = floor(u[d]);
+        }
+        key[uu] = (((int)f[0]) & mask) * nmesh + (((int)f[1]) & mask);
+        const unsigned iy = ((unsigned)(int)f[1]) & mask, iz = ((unsigned)(int)f[2]) & mask;
+        r[uu].x = static_cast<T>(u[0] - f[0]);
+        r[uu].y = static_cast<T>(u[1] - f[1]);
+        r[uu].z = static_cast<T>(u[2] - f[2]);
+        if constexpr (sizeof(T) == 4) {
+          r[uu].w = __uint_as_float((iy << 16) | iz);
+        } else {
+          r[uu].w = (double)((iy << 16) | iz);
+        }
       }
-      key = (((int)f[0]) & mask) * nmesh + (((int)f[1]) & mask);
     }
-    const int slot = claim_slot(key, cursor);
-    if (i < n) {
-      const unsigned iy = ((unsigned)(int)f[1]) & mask, iz = ((unsigned)(int)f[2]) & mask;
-      typename Rec<T>::type r;
-      r.x = static_cast<T>(u[0] - f[0]);
-      r.y = static_cast<T>(u[1] - f[1]);
-      r.z = static_cast<T>(u[2] - f[2]);
-      if constexpr (sizeof(T) == 4) {
-        r.w = __uint_as_float((iy << 16) | iz);
-      } else {
-        r.w = (double)((iy << 16) | iz);
+    RunClaim c[U];
+#pragma unroll
+    for (int uu = 0; uu < U; ++uu) c[uu] = claim_issue(key[uu], cursor, true);
+#pragma unroll
+    for (int uu = 0; uu < U; ++uu) {
+      const int64_t i = i0 + uu * stride;
+      const int slot = claim_finish(c[uu]);
+      if (i < n) {
+        rec[slot] = r[uu];
+        // the painted amount of the particle: w V
+        if (wrec) wrec[slot] = weight ? (value ? weight[i] * value[i] : weight[i]) : value[i];
       }
-      rec[slot] = r;
-      // the painted amount of the particle: w V
-      if (wrec) wrec[slot] = weight ? (value ? weight[i] * value[i] : weight[i]) : value[i];
     }
   }
 }
