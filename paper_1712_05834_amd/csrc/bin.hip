@@ -95,8 +95,12 @@ __device__ __forceinline__ void accumulate(double* sb, const BinSpec& b, int n2,
   atomicAdd(&sb[k], (double)hp);
   if (b.npl > 0) {
     const T mu2 = ratio<T>(nlos2, n2);
-    for (int i = 0; i < b.npl; ++i)
-      atomicAdd(&sb[b.pole_slot[i] + k], (double)(hp * legendre<T>(b.pole_ell[i], mu2)));
+    // at most 4 poles: unrolled, so that the pole tables are read with
+    // constant indices (scalar registers) instead of a runtime loop
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+      if (i < b.npl)
+        atomicAdd(&sb[b.pole_slot[i] + k], (double)(hp * legendre<T>(b.pole_ell[i], mu2)));
   }
   if (b.off2d >= 0) atomicAdd(&sb[b.off2d + k * b.nmu + mubin_of(nlos2, n2, b.nmu)], (double)hp);
 }
