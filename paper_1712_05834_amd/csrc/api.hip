@@ -329,7 +329,7 @@ Layout layout_of(const pk_mesh_desc* m, const pk_bin_desc* b, int64_t npart) {
   const size_t side = align256(n * n * 2 * es);
   const int two = m->interlaced ? 1 : 0;
   const size_t np = npart > 0 ? (size_t)npart : 0;
-  l.gx = xpass_bin_groups(m->dtype, m->nmesh);
+  l.gx = xpass_bin_groups(m->dtype, m->nmesh, nsum_of(b));
   l.gp = plane_bin_groups(m->nmesh);
   size_t off = 0;
   l.mesh_a = off;

@@ -553,25 +553,34 @@ __global__ void __launch_bounds__(256)
 
 // ---------------------------------------------------------------- launchers
 
-int xpass_bin_groups(int dtype, int nmesh) {
-  // tiles = N * CHUNKS; a few workgroups per CU, never more than the tiles
-  long tiles;
-  if (dtype == PK_F32) {
-    switch (nmesh) {
-#define PK_T(NN) case NN: tiles = (long)NN * XCfg<float, NN>::CHUNKS; break;
-      PK_T(8) PK_T(16) PK_T(32) PK_T(64) PK_T(128) PK_T(256) PK_T(512) PK_T(1024) PK_T(2048)
-#undef PK_T
-      default: return 0;
-    }
-  } else {
-    switch (nmesh) {
-#define PK_T(NN) case NN: tiles = (long)NN * XCfg<double, NN>::CHUNKS; break;
-      PK_T(8) PK_T(16) PK_T(32) PK_T(64) PK_T(128) PK_T(256) PK_T(512) PK_T(1024) PK_T(2048)
-#undef PK_T
-      default: return 0;
-    }
+// Workgroups of the persistent x-pass: as many as the device holds at once
+// (a second round would only add a tail and partial rows to reduce), never
+// more than the tiles.  Residency per CU from the LDS of a workgroup (static
+// + nsum float64 bins) and from the waves (at most 128 VGPRs: 4 waves per
+// SIMD, 16 per CU).
+template <typename T, int N>
+static int xpass_groups_t(int nsum) {
+  using Cf = XCfg<T, N>;
+  const long tiles = (long)N * Cf::CHUNKS;
+  const size_t lds = ((size_t)Cf::LDS_ELEMS + stage_table_size<N, Cf::E>() + 1 + N) *
+                         sizeof(cpx<T>) + (size_t)N * sizeof(T) + (size_t)nsum * sizeof(double);
+  long by_lds = (long)(kLdsBytesPerGroup / (lds > 0 ? lds : 1));
+  const long waves = (Cf::THREADS + 63) / 64;
+  long by_waves = 16 / (waves > 0 ? waves : 1);
+  long per_cu = by_lds < by_waves ? by_lds : by_waves;
+  if (per_cu < 1) per_cu = 1;
+  const long groups = per_cu * kComputeUnits;
+  return (int)(tiles < groups ? tiles : groups);
+}
+
+int xpass_bin_groups(int dtype, int nmesh, int nsum) {
+#define PK_T(NN) \
+  case NN: return dtype == PK_F32 ? xpass_groups_t<float, NN>(nsum) : xpass_groups_t<double, NN>(nsum);
+  switch (nmesh) {
+    PK_T(8) PK_T(16) PK_T(32) PK_T(64) PK_T(128) PK_T(256) PK_T(512) PK_T(1024) PK_T(2048)
+    default: return 0;
   }
-  return (int)(tiles < 1024 ? tiles : 1024);
+#undef PK_T
 }
 
 template <typename T, int N>
@@ -609,7 +618,7 @@ static hipError_t xpass_bin_t(const void* mesh_a, const void* mesh_b, const Mesh
                               int order, int compensated, const BinSpec& b, double* partials,
                               void* side_a, void* side_b, hipStream_t s) {
   using Cf = XCfg<T, N>;
-  const int groups = xpass_bin_groups(sizeof(T) == 4 ? PK_F32 : PK_F64, N);
+  const int groups = xpass_bin_groups(sizeof(T) == 4 ? PK_F32 : PK_F64, N, b.nsum);
   const T* sinv = compensated ? static_cast<const T*>(t.sinc_inv) + (size_t)(order - 2) * N
                               : nullptr;
   hipLaunchKernelGGL((k_xpass_bin<T, N>), dim3(groups), dim3(Cf::THREADS), bin_lds_bytes(b), s,

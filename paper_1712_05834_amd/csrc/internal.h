@@ -65,8 +65,9 @@ struct BinSpec {
 //   then, if nmu > 1: counts2d, sum h|n| 2d, sum h|mu| 2d (nk * nmu each).
 __host__ __device__ inline int mode_table_slots(int nk, int nmu) { return 2 * nk + (nmu > 1 ? 3 * nk * nmu : 0); }
 
-// LDS available to one workgroup on gfx950.
+// LDS available to one workgroup on gfx950, and its compute units.
 constexpr size_t kLdsBytesPerGroup = 160 * 1024;
+constexpr long kComputeUnits = 256;
 
 // ---- launchers (each defined in the translation unit of its kernels) ----
 hipError_t launch_fill_zero(void* p, size_t bytes, hipStream_t s);
@@ -95,7 +96,7 @@ hipError_t launch_fft_y_relayout(int dtype, int nmesh, const void* src, void* ds
                                  hipStream_t s);
 
 // Workgroup count of the persistent binning kernels for a mesh size.
-int xpass_bin_groups(int dtype, int nmesh);
+int xpass_bin_groups(int dtype, int nmesh, int nsum);
 int plane_bin_groups(int nmesh);
 size_t bin_lds_bytes(const BinSpec& b);
 // Static LDS bytes of the fused x-pass + binning kernel (0: unsupported size).
