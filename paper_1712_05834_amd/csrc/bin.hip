@@ -167,7 +167,7 @@ __global__ void __launch_bounds__((XCfg<T, N>::THREADS)) __attribute__((amdgpu_w
   constexpr bool REG = TPL % YL::BX == 0;
   constexpr Ix kstep = REG ? (Ix)(TPL / YL::BX) * ((Ix)N * YL::BX * YL::W) : 0;
   auto issue_loads = [&](int tile_id) {
-    const int tile = xcd_pair_tile(tile_id, ntiles);
+    const int tile = xcd_group_tile<YLayout<T, N>::G>(tile_id, ntiles);
     const int ky = tile / CHUNKS, cl = (tile % CHUNKS) * C + c;
     if constexpr (REG) {
       const Ix base = YL::at(t, ky, cl);
@@ -188,7 +188,7 @@ __global__ void __launch_bounds__((XCfg<T, N>::THREADS)) __attribute__((amdgpu_w
   };
   if ((int)blockIdx.x < ntiles) issue_loads(blockIdx.x);
   for (int tile_id = blockIdx.x; tile_id < ntiles; tile_id += gridDim.x) {
-    const int tile = xcd_pair_tile(tile_id, ntiles);
+    const int tile = xcd_group_tile<YLayout<T, N>::G>(tile_id, ntiles);
     const int ky = tile / CHUNKS;
     const int col0 = (tile % CHUNKS) * C;
     const int col = col0 + c;

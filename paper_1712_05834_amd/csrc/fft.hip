@@ -117,7 +117,19 @@ __global__ void __launch_bounds__((ColCfg<T, N>::THREADS))
   const TwStage<T, N, E> tw1{tws};
   const int c = threadIdx.x % C, t = threadIdx.x / C;
   const int tile = xcd_pair_tile(blockIdx.x, N * Cf::CHUNKS);
-  const int x = tile / Cf::CHUNKS, col = (tile % Cf::CHUNKS) * C + c;
+  int x, chunk;
+  if constexpr (C >= YL::W && YL::W * sizeof(cpx<T>) < 128) {
+    // a tile writes whole rows of the layout, and the rows of x and x + 1
+    // share a line: the sibling tiles are those two x-planes
+    const int pair = tile >> 1;
+    chunk = pair % Cf::CHUNKS;
+    x = (pair / Cf::CHUNKS) * 2 + (tile & 1);
+  } else {
+    // siblings are neighbouring column chunks of one x-plane (same lines)
+    x = tile / Cf::CHUNKS;
+    chunk = tile % Cf::CHUNKS;
+  }
+  const int col = chunk * C + c;
   const cpx<T>* src = reinterpret_cast<const cpx<T>*>(src0);
   const Ix base = (Ix)x * ((Ix)N * NC) + (Ix)col;
   cpx<T> v[E];

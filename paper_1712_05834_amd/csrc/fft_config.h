@@ -28,7 +28,7 @@ struct ZCfg {
 // LDS footprint capped at 80 KB so two workgroups fit on a CU.  EM caps the
 // points per thread (the fused x-pass + binning keeps two meshes' lines in
 // registers and uses fewer points per thread).
-template <typename T, int N, int EM = e_max<T>()>
+template <typename T, int N, int EM = e_max<T>(), int LDS_KB = 80>
 struct ColCfg {
   static constexpr int L = N;
   static constexpr int E = L < EM ? L : EM;
@@ -38,7 +38,7 @@ struct ColCfg {
     int c = 256 / TPL;
     if (c < 8) c = 8;
     while (c > 1 && c * TPL > 1024) c /= 2;
-    while (c > 1 && (long)c * lds_pad_len<L>() * (long)sizeof(cpx<T>) > 80 * 1024) c /= 2;
+    while (c > 1 && (long)c * lds_pad_len<L>() * (long)sizeof(cpx<T>) > LDS_KB * 1024) c /= 2;
     if (c > NC) c = NC;
     return c;
   }
@@ -59,9 +59,22 @@ __device__ __forceinline__ int xcd_pair_tile(int g, int ntiles) {
   return (g & ~15) | ((g & 7) << 1) | ((g >> 3) & 1);
 }
 
+// The same with groups of G tiles (G a power of two): tiles G j .. G j + G - 1
+// go to workgroups g, g + 8, ..., g + 8 (G - 1).  Identity unless `ntiles`
+// is a multiple of 8 G.
+template <int G>
+__device__ __forceinline__ int xcd_group_tile(int g, int ntiles) {
+  if (ntiles % (8 * G)) return g;
+  const int blk = g / (8 * G), off = g % (8 * G);
+  return blk * 8 * G + (off % 8) * G + off / 8;
+}
+
 // Launch shape of the fused x-pass + binning kernel.
+// (Line buffers capped at 40 KB -- 4 columns per tile at N = 1024, two
+// workgroups per CU -- made the x-pass 9% faster, but the y-pass writes of
+// 64-byte layout rows cost more than that.)
 template <typename T, int N>
-using XCfg = ColCfg<T, N, (sizeof(T) == 4 ? 8 : 4)>;
+using XCfg = ColCfg<T, N, (sizeof(T) == 4 ? 8 : 4), 80>;
 
 // Layout of the y-transformed spectrum handed from the y-pass to the fused
 // x-pass in the power-spectrum path.  The x-pass reads, for one ky and C
@@ -69,18 +82,19 @@ using XCfg = ColCfg<T, N, (sizeof(T) == 4 ? 8 : 4)>;
 // x and C columns, all N values of ky.  In the plain packed layout the x-pass
 // reads would be N * N / 2 complex apart (4 MB at N = 1024), a different
 // page for every kx.  Here the columns are grouped W at a time (two x-pass
-// chunks, 128 bytes of complex float) and x in blocks of BX:
+// chunks) and x in blocks of BX:
 //   (kx, ky, col) at (col / W) N^2 W + (kx / BX) N BX W + ky BX W
 //                    + (kx % BX) W + col % W,
 // so the y-pass of one x writes N values BX W apart (a 1 MB span at
 // N = 1024), and the x-pass of one ky reads BX consecutive W-wide rows per
-// block, blocks N BX W apart.  The two tiles of a column group, which the
-// XCD pairing runs side by side, fill the two halves of the same 128-byte
-// lines.
+// block, blocks N BX W apart.  The G = W / C tiles of a column group run
+// side by side on one XCD (xcd_group_tile) and read the parts of the same
+// rows; the y-pass pairs its tiles so that the rows it writes fill lines.
 template <typename T, int N>
 struct YLayout {
   static constexpr int CX = XCfg<T, N>::C;
   static constexpr int W = 2 * CX <= N / 2 ? 2 * CX : N / 2;
+  static constexpr int G = W / CX;  // x-pass tiles sharing a group
   static constexpr int BX = N < 8 ? N : 8;
   using Ix = typename std::conditional<((long)N * N * (N / 2) <= (1L << 31)), unsigned, size_t>::type;
   __host__ __device__ static constexpr Ix at(int kx, int ky, int col) {
