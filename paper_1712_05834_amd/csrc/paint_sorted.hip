@@ -1,13 +1,16 @@
 // Painting fused with the first FFT pass (Sec. 3.3.1 Eq. 1, Sec. 3.3.2
 // windows and interlacing; r2c along z).
 //
-// 1. k_bucket_count   per particle: its column (ix, iy) = floor(u_x, u_y); the
-//                     column counts are accumulated with one atomic per run of
-//                     equal columns in a wavefront; sum w and sum w^2 in float64.
+// 1. k_bucket_count   per particle: its column (ix, iy) = floor(u_x, u_y); runs
+//                     of equal columns in a wavefront are added to a block-local
+//                     LDS table, which reaches the global column counts with one
+//                     atomic per column and block; sum w and sum w^2 in float64.
 // 2. k_scan_*         exclusive prefix sum of the N^2 column counts.
 // 3. k_bucket_scatter per particle: a 16-byte record {t_x, t_y, t_z, iy<<16|iz}
 //                     (fractional offsets from the cell, split off in float64)
-//                     written to its column's segment.
+//                     written to its column's segment; the slots of a step are
+//                     reserved with one atomic per column through the same kind
+//                     of LDS table.
 // 4. k_paint_z        one workgroup owns a TX x TY block of full z-columns of
 //                     both meshes: it reads the records of the columns whose
 //                     windows reach the block, adds the window weights into
@@ -37,19 +40,17 @@ __device__ __forceinline__ double wave_sum_d(double v) {
   return v;
 }
 
-// Runs of equal keys among consecutive lanes of a wavefront: the head lane of
-// each run adds the run length to counter[key] with one atomic; every lane
-// gets its slot = old value + its offset in the run.  Lanes with key < 0 take
-// no slot.  Split in two halves (issue the atomic / share its result) so that
-// a thread can have the atomics of several particles in flight at once.
-struct RunClaim {
+// Runs of equal keys among consecutive lanes of a wavefront: the head lane
+// of each run gets the run length; every lane gets its run's head and its
+// offset in the run.  Lanes with key < 0 belong to no run.
+struct WaveRun {
+  bool head;
+  int len;      // run length (head lanes)
   int my_head;  // lane of the head of my run
-  int offset;   // my position in the run, -1 if no slot
-  int old;      // the head's atomic result
+  int offset;   // my position in the run, -1 for key < 0
 };
 
-__device__ __forceinline__ RunClaim claim_issue(int key, int* __restrict__ counter,
-                                                bool need_old) {
+__device__ __forceinline__ WaveRun wave_run(int key) {
   const int lane = threadIdx.x & 63;
   const int prev = __shfl_up(key, 1, 64);
   const bool valid = key >= 0;
@@ -58,50 +59,77 @@ __device__ __forceinline__ RunClaim claim_issue(int key, int* __restrict__ count
   const unsigned long long valids = __ballot(valid);
   // head lane of my run: highest head at or below me
   const unsigned long long below = heads & ((2ull << lane) - 1ull);
-  RunClaim c;
-  c.my_head = below ? 63 - __clzll(below) : lane;
-  c.offset = valid ? lane - c.my_head : -1;
-  c.old = 0;
+  WaveRun r;
+  r.head = head;
+  r.my_head = below ? 63 - __clzll(below) : lane;
+  r.offset = valid ? lane - r.my_head : -1;
+  r.len = 0;
   if (head) {
-    // run length for a head: up to the next head or the first invalid lane
+    // up to the next head or the first invalid lane
     const unsigned long long above = (heads | ~valids) & ~((2ull << lane) - 1ull);
     const int next = above ? __ffsll(above) - 1 : 64;
-    if (need_old) {
-      c.old = atomicAdd(&counter[key], next - lane);
-    } else {
-      (void)atomicAdd(&counter[key], next - lane);
+    r.len = next - lane;
+  }
+  return r;
+}
+
+// Block-local table of column counts in LDS: runs of the same column from
+// the block's particles are added here and reach the global counters with one
+// atomic per column and block.  Global atomics (performed beyond the XCD's L2)
+// were the cost of the bucketing.  Open addressing with a few probes; a key
+// that finds no entry goes straight to the global counter.
+constexpr int kHashSize = 1024;
+constexpr int kHashProbes = 4;
+
+__device__ __forceinline__ int hash_insert(int* keys, int* cnts, int key, int len, int& rank) {
+  const unsigned h = ((unsigned)key * 2654435761u) >> (32 - 10);
+#pragma unroll
+  for (int probe = 0; probe < kHashProbes; ++probe) {
+    const int e = (int)((h + probe) & (kHashSize - 1));
+    int t = keys[e];
+    if (t == -1) {
+      t = atomicCAS(&keys[e], -1, key);
+      if (t == -1) t = key;
+    }
+    if (t == key) {
+      rank = atomicAdd(&cnts[e], len);
+      return e;
     }
   }
-  return c;
+  return -1;
 }
 
-__device__ __forceinline__ int claim_finish(const RunClaim& c) {
-  const int base = __shfl(c.old, c.my_head, 64);
-  return c.offset >= 0 ? base + c.offset : -1;
+__device__ __forceinline__ void hash_clear(int* keys, int* cnts) {
+  for (int e = threadIdx.x; e < kHashSize; e += blockDim.x) {
+    keys[e] = -1;
+    cnts[e] = 0;
+  }
 }
 
-// Particles per thread per step of the bucketing kernels: their loads and
-// atomics are issued together, so that their latencies overlap.
+// Particles per thread per step of the bucketing kernels (256 threads): the
+// loads of a step are issued together.  Each block takes a contiguous chunk
+// of the catalog (a multiple of 256 * kBucketUnroll particles), so that
+// ordered catalogs give it few distinct columns.
 constexpr int kBucketUnroll = 4;
+constexpr int kBucketStep = 256 * kBucketUnroll;
 
 template <typename T>
 __global__ void __launch_bounds__(256)
     k_bucket_count(const T* __restrict__ pos, const T* __restrict__ weight,
-                   const T* __restrict__ value, int64_t n, int nmesh, double boxsize,
-                   int* __restrict__ count, double* __restrict__ wpart) {
+                   const T* __restrict__ value, int64_t n, int64_t chunk, int nmesh,
+                   double boxsize, int* __restrict__ count, double* __restrict__ wpart) {
+  __shared__ int hkeys[kHashSize], hcnts[kHashSize];
+  hash_clear(hkeys, hcnts);
+  __syncthreads();
   const int mask = nmesh - 1;
   constexpr int U = kBucketUnroll;
   double ws = 0.0, ws2 = 0.0;
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  // whole wavefronts iterate together so that the run detection sees full
-  // waves; particle i + u * stride is the u-th of a step
-  const int64_t nround = (n + U * stride - 1) / (U * stride) * (U * stride);
-  for (int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i0 < nround;
-       i0 += U * stride) {
+  const int64_t begin = (int64_t)blockIdx.x * chunk;
+  for (int64_t i0 = begin + threadIdx.x; i0 < begin + chunk; i0 += kBucketStep) {
     int key[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      const int64_t i = i0 + u * stride;
+      const int64_t i = i0 + u * 256;
       key[u] = -1;
       if (i < n) {
         const double ux = cell_coordinate((double)pos[3 * i], nmesh, boxsize);
@@ -115,8 +143,17 @@ __global__ void __launch_bounds__(256)
       }
     }
 #pragma unroll
-    for (int u = 0; u < U; ++u) (void)claim_issue(key[u], count, false);
+    for (int u = 0; u < U; ++u) {
+      const WaveRun r = wave_run(key[u]);
+      if (r.head) {
+        int rank;
+        if (hash_insert(hkeys, hcnts, key[u], r.len, rank) < 0) atomicAdd(&count[key[u]], r.len);
+      }
+    }
   }
+  __syncthreads();
+  for (int e = threadIdx.x; e < kHashSize; e += blockDim.x)
+    if (hkeys[e] >= 0) atomicAdd(&count[hkeys[e]], hcnts[e]);
   // per-block partial sums (reduced in a fixed order by k_weight_sums)
   __shared__ double part[2][4];
   ws = wave_sum_d(ws);
@@ -160,22 +197,26 @@ __global__ void __launch_bounds__(1024)
 template <typename T>
 __global__ void __launch_bounds__(256)
     k_bucket_scatter(const T* __restrict__ pos, const T* __restrict__ weight,
-                     const T* __restrict__ value, int64_t n, int nmesh, double boxsize,
-                     int* __restrict__ cursor, typename Rec<T>::type* __restrict__ rec,
-                     T* __restrict__ wrec) {
+                     const T* __restrict__ value, int64_t n, int64_t chunk, int nmesh,
+                     double boxsize, int* __restrict__ cursor,
+                     typename Rec<T>::type* __restrict__ rec, T* __restrict__ wrec) {
+  // per step: the runs of each column in the step are ranked in the LDS
+  // table, one global atomic per column reserves the step's slots, then every
+  // particle writes its record at base + rank
+  __shared__ int hkeys[kHashSize], hcnts[kHashSize], hbase[kHashSize];
   const int mask = nmesh - 1;
   constexpr int U = kBucketUnroll;
   using RecT = typename Rec<T>::type;
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  const int64_t nround = (n + U * stride - 1) / (U * stride) * (U * stride);
-  for (int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i0 < nround;
-       i0 += U * stride) {
-    int key[U];
+  const int64_t begin = (int64_t)blockIdx.x * chunk;
+  for (int64_t i0 = begin + threadIdx.x; i0 < begin + chunk; i0 += kBucketStep) {
+    hash_clear(hkeys, hcnts);
+    __syncthreads();
+    int ent[U], rk[U];
     RecT r[U];
 #pragma unroll
     for (int uu = 0; uu < U; ++uu) {
-      const int64_t i = i0 + uu * stride;
-      key[uu] = -1;
+      const int64_t i = i0 + uu * 256;
+      int key = -1;
       r[uu] = RecT{};
       if (i < n) {
         double u[3], f[3];
@@ -184,7 +225,7 @@ __global__ void __launch_bounds__(256)
           u[d] = cell_coordinate((double)pos[3 * i + d], nmesh, boxsize);
           f[d] = floor(u[d]);
         }
-        key[uu] = (((int)f[0]) & mask) * nmesh + (((int)f[1]) & mask);
+        key = (((int)f[0]) & mask) * nmesh + (((int)f[1]) & mask);
         const unsigned iy = ((unsigned)(int)f[1]) & mask, iz = ((unsigned)(int)f[2]) & mask;
         r[uu].x = static_cast<T>(u[0] - f[0]);
         r[uu].y = static_cast<T>(u[1] - f[1]);
@@ -195,20 +236,30 @@ __global__ void __launch_bounds__(256)
           r[uu].w = (double)((iy << 16) | iz);
         }
       }
+      const WaveRun run = wave_run(key);
+      int e = -1, rank = 0;
+      if (run.head) {
+        e = hash_insert(hkeys, hcnts, key, run.len, rank);
+        if (e < 0) rank = atomicAdd(&cursor[key], run.len);  // no entry: a direct slot
+      }
+      ent[uu] = __shfl(e, run.my_head, 64);
+      rk[uu] = run.offset >= 0 ? __shfl(rank, run.my_head, 64) + run.offset : -1;
     }
-    RunClaim c[U];
-#pragma unroll
-    for (int uu = 0; uu < U; ++uu) c[uu] = claim_issue(key[uu], cursor, true);
+    __syncthreads();
+    for (int e = threadIdx.x; e < kHashSize; e += blockDim.x)
+      if (hkeys[e] >= 0) hbase[e] = atomicAdd(&cursor[hkeys[e]], hcnts[e]);
+    __syncthreads();
 #pragma unroll
     for (int uu = 0; uu < U; ++uu) {
-      const int64_t i = i0 + uu * stride;
-      const int slot = claim_finish(c[uu]);
+      const int64_t i = i0 + uu * 256;
       if (i < n) {
+        const int slot = (ent[uu] >= 0 ? hbase[ent[uu]] : 0) + rk[uu];
         rec[slot] = r[uu];
         // the painted amount of the particle: w V
         if (wrec) wrec[slot] = weight ? (value ? weight[i] * value[i] : weight[i]) : value[i];
       }
     }
+    __syncthreads();  // the table is read before the next step clears it
   }
 }
 
@@ -624,17 +675,21 @@ hipError_t launch_bucket(int dtype, int nmesh, double boxsize, const void* pos, 
   double* wpart = reinterpret_cast<double*>(static_cast<int*>(bucket_ws) + ints);
   hipError_t e = launch_fill_zero(count, (size_t)n2 * sizeof(int), s);
   if (e != hipSuccess) return e;
-  int64_t blocks = (n + 255) / 256;
-  if (blocks > kCountBlocks) blocks = kCountBlocks;
+  // contiguous chunks of whole steps, at most kCountBlocks blocks
+  int64_t steps = (n + kBucketStep - 1) / kBucketStep;
+  if (steps < 1) steps = 1;
+  int64_t blocks = steps < kCountBlocks ? steps : kCountBlocks;
+  const int64_t chunk = (steps + blocks - 1) / blocks * kBucketStep;
+  blocks = (n + chunk - 1) / chunk;
   if (blocks < 1) blocks = 1;
   if (dtype == PK_F32)
     hipLaunchKernelGGL(k_bucket_count<float>, dim3((unsigned)blocks), dim3(256), 0, s,
                        static_cast<const float*>(pos), static_cast<const float*>(weight),
-                       static_cast<const float*>(value), n, nmesh, boxsize, count, wpart);
+                       static_cast<const float*>(value), n, chunk, nmesh, boxsize, count, wpart);
   else
     hipLaunchKernelGGL(k_bucket_count<double>, dim3((unsigned)blocks), dim3(256), 0, s,
                        static_cast<const double*>(pos), static_cast<const double*>(weight),
-                       static_cast<const double*>(value), n, nmesh, boxsize, count, wpart);
+                       static_cast<const double*>(value), n, chunk, nmesh, boxsize, count, wpart);
   hipLaunchKernelGGL(k_weight_sums, dim3(1), dim3(1024), 0, s, wpart, (int)blocks, wsums);
   hipLaunchKernelGGL(k_scan_blocks, dim3(nb), dim3(1024), 0, s, count, n2, bsums);
   hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(1024), 0, s, bsums, nb);
@@ -642,13 +697,13 @@ hipError_t launch_bucket(int dtype, int nmesh, double boxsize, const void* pos, 
   if (dtype == PK_F32)
     hipLaunchKernelGGL(k_bucket_scatter<float>, dim3((unsigned)blocks), dim3(256), 0, s,
                        static_cast<const float*>(pos), static_cast<const float*>(weight),
-                       static_cast<const float*>(value), n, nmesh, boxsize, cursor,
+                       static_cast<const float*>(value), n, chunk, nmesh, boxsize, cursor,
                        static_cast<float4*>(rec),
                        (weight || value) ? static_cast<float*>(wrec) : nullptr);
   else
     hipLaunchKernelGGL(k_bucket_scatter<double>, dim3((unsigned)blocks), dim3(256), 0, s,
                        static_cast<const double*>(pos), static_cast<const double*>(weight),
-                       static_cast<const double*>(value), n, nmesh, boxsize, cursor,
+                       static_cast<const double*>(value), n, chunk, nmesh, boxsize, cursor,
                        static_cast<double4*>(rec),
                        (weight || value) ? static_cast<double*>(wrec) : nullptr);
   return hipGetLastError();
