@@ -10,6 +10,7 @@
  *   windows, interlacing, compensation Eq. (2)  Sec. 3.3.2 "From Catalog to Mesh"
  *   r2c between RealField and ComplexField .... Sec. 3.3.1
  *   FFTPower: P(k), P(k, mu), P_ell(k) ........ Sec. 3.4.1 "Power Spectra"
+ *   survey multipoles (ConvolvedFFTPower) ..... Sec. 3.4.1, named there
  *
  * Conventions shared by every entry point
  * ---------------------------------------
@@ -293,6 +294,58 @@ pk_status pk_fftpower_batch(pk_ctx *ctx, int count, const pk_mesh_desc *m,
 pk_status pk_fftpower_v(pk_ctx *ctx, const pk_mesh_desc *m, const pk_bin_desc *b,
                         const void *pos, const void *weight, const void *value, int64_t n,
                         void *workspace, size_t workspace_bytes, double *result_dev);
+
+/* ---- Survey multipoles with a varying line of sight (ConvolvedFFTPower,
+ * named in Sec. 3.4.1; the paper cites the FFT estimator of Hand et al. 2017
+ * without writing it out, so the standard form is implemented):
+ *   F(x)     = sum_data w delta_D(x - x_i) - alpha sum_randoms w delta_D(x - x_j),
+ *              alpha = sum_data w / sum_randoms w,
+ *   A_lm(k)  = FFT of F painted with the factor Y_lm(r^), r^ the unit vector
+ *              from the observer to the particle (z^ where they coincide),
+ *              divided by the window when m->compensated (Eq. 2),
+ *   F_ell(k) = 4 pi / (2 ell + 1) sum_m Y_lm(k^) A_lm(k), Y_lm real and
+ *              orthonormal,
+ *   P_ell(k) = (2 ell + 1) / I  <Re F_0(k) conj F_ell(k)>  over the k-bin,
+ * I the survey normalisation (an input of pk_convolved_to_host).  Shot noise
+ * (sum_data w^2 + alpha^2 sum_randoms w^2) / I is reported, not subtracted.
+ * Every multipole ell takes 2 ell + 1 paintings and FFTs (F_0 is always
+ * formed).
+ *
+ * Positions are box coordinates (painted periodically, like pk_fftpower);
+ * the line of sight uses them as given.  m: interlaced must be 0
+ * (PK_EUNSUPPORTED otherwise).  b: 1-D k-bins (nmu 0 or 1), 1 .. 4 poles
+ * among 0, 2, 4, top edge kmin_f + nk dk_f <= N/2 (the kz = N/2 plane is not
+ * formed); los is ignored.
+ *
+ * Result (device, pk_convolved_doubles(b) float64): [npoles][nk] sums of
+ * h Re(F_0 conj F_ell) per k-bin in the order of b->poles, then
+ * {sum_data w, sum_data w^2, sum_randoms w, sum_randoms w^2}.  */
+size_t pk_convolved_doubles(const pk_bin_desc *b);
+/* Device workspace of pk_convolved_power (bytes), 0 for invalid arguments:
+ * the concatenated catalog, its records, one mesh and one spectrum per
+ * field F_ell kept. */
+size_t pk_convolved_workspace_bytes(const pk_mesh_desc *m, const pk_bin_desc *b, int64_t n_data,
+                                    int64_t n_rand);
+/*   observer    host, 3 doubles, box coordinates
+ *   data_pos    device, n_data x 3 positions of the mesh dtype (n_data >= 1)
+ *   data_weight device, n_data weights, or NULL for unit weights
+ *   rand_pos    device, n_rand x 3 positions (n_rand >= 1)
+ *   rand_weight device, n_rand weights, or NULL
+ *   workspace   device, >= pk_convolved_workspace_bytes, caller-owned
+ *   result_dev  device, pk_convolved_doubles(b) float64, overwritten
+ * Enqueued on the context stream.  A zero sum of random weights gives NaN
+ * results.  Errors: PK_EINVAL, PK_EUNSUPPORTED, PK_EDEVICE. */
+pk_status pk_convolved_power(pk_ctx *ctx, const pk_mesh_desc *m, const pk_bin_desc *b,
+                             const double *observer, const void *data_pos,
+                             const void *data_weight, int64_t n_data, const void *rand_pos,
+                             const void *rand_weight, int64_t n_rand, void *workspace,
+                             size_t workspace_bytes, double *result_dev);
+/* Synchronises the context stream and finalises: out->k, out->modes and
+ * out->poles ([npoles][nk], P_ell as above) are written, out->power is not
+ * touched; out->wsum / w2sum are the data sums and out->shotnoise the shot
+ * noise above.  norm: I > 0.  Errors: PK_EINVAL, PK_EDEVICE. */
+pk_status pk_convolved_to_host(pk_ctx *ctx, const pk_mesh_desc *m, const pk_bin_desc *b,
+                               double norm, const double *result_dev, pk_result *out);
 
 /* Synchronises the context stream, copies the sums back and finalises them
  * with the mode tables (counts, mean |k|, mean |mu|):

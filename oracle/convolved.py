@@ -11,8 +11,10 @@ spherical harmonics, a brute-force evaluation of F_ell on a tiny mesh, and the
 limit of a distant observer, where the estimator reduces to the FFTPower
 multipoles along the line of sight.
 
-Definitions (box coordinates x in [0, L), observer o, r = x - o, r^ = r / |r|,
-r^ = z^ where r = 0):
+Definitions (box coordinates x wrapped into [0, L) as for the painting,
+observer o, r = x - o, r^ = r / |r|, r^ = z^ where r = 0; reading: the line
+of sight of a particle is taken at its position in the periodic box, which
+is the position as given for a survey embedded in the box):
 * weighted field F(x) = sum_data w delta_D(x - x_i) - alpha sum_randoms w
   delta_D(x - x_j), alpha = sum_data w / sum_randoms w;
 * A_lm(k) = DFT of the mesh painted with w s Y_lm(r^) (s = 1 for data,
@@ -30,7 +32,7 @@ import math
 
 import numpy as np
 
-from .paint import WINDOW_ORDER, paint_mesh
+from .paint import WINDOW_ORDER, paint_mesh, wrap_positions
 from .power import (_accumulate, _check_bins, _slab, compensate, mode_indices, r2c)
 
 
@@ -95,8 +97,8 @@ def multipole_fields(data, randoms, w_data, w_rand, observer, nmesh, boxsize, wi
     wd = np.ones(len(data)) if w_data is None else np.asarray(w_data, dtype=np.float64)
     wr = np.ones(len(randoms)) if w_rand is None else np.asarray(w_rand, dtype=np.float64)
     alpha = float(wd.sum() / wr.sum())
-    ud = unit_vectors(data, observer)
-    ur = unit_vectors(randoms, observer)
+    ud = unit_vectors(wrap_positions(data, boxsize), observer)
+    ur = unit_vectors(wrap_positions(randoms, boxsize), observer)
     khat = k_unit_vectors(nmesh)
     fields = {}
     for ell in poles:

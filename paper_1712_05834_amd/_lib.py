@@ -26,7 +26,8 @@ EXPORTS = (
     "pk_ctx_set_timing", "pk_stage_count", "pk_stage_name", "pk_ctx_stage_times",
     "pk_ctx_set_lanes", "pk_ctx_lanes", "pk_fftpower_async", "pk_lane_query", "pk_lane_wait",
     "pk_fftpower_batch", "pk_bin_cross", "pk_fftpower_v", "pk_projected_doubles",
-    "pk_bin_projected", "pk_projected_to_host",
+    "pk_bin_projected", "pk_projected_to_host", "pk_convolved_doubles",
+    "pk_convolved_workspace_bytes", "pk_convolved_power", "pk_convolved_to_host",
 )
 PK_MAX_LANES = 64
 
@@ -130,6 +131,11 @@ def load(path=None):
             "pk_fftpower_batch": (i32, [vp, ctypes.c_int, md, bd, ctypes.POINTER(vp),
                                         ctypes.POINTER(vp), ctypes.POINTER(i64),
                                         ctypes.POINTER(vp), sz, ctypes.POINTER(vp)]),
+            "pk_convolved_doubles": (sz, [bd]),
+            "pk_convolved_workspace_bytes": (sz, [md, bd, i64, i64]),
+            "pk_convolved_power": (i32, [vp, md, bd, ctypes.POINTER(dbl), vp, vp, i64, vp, vp,
+                                         i64, vp, sz, vp]),
+            "pk_convolved_to_host": (i32, [vp, md, bd, dbl, vp, ctypes.POINTER(Result)]),
         }
         for name, (res, args) in sig.items():
             f = getattr(lib, name)
@@ -162,6 +168,15 @@ def result_doubles(b):
 
 def projected_doubles(b):
     return int(load().pk_projected_doubles(ctypes.byref(b)))
+
+
+def convolved_doubles(b):
+    return int(load().pk_convolved_doubles(ctypes.byref(b)))
+
+
+def convolved_workspace_bytes(m, b, n_data, n_rand):
+    return int(load().pk_convolved_workspace_bytes(ctypes.byref(m), ctypes.byref(b),
+                                                   int(n_data), int(n_rand)))
 
 
 def workspace_bytes(m, b, npart):
@@ -257,6 +272,36 @@ class Context:
                                                   int(keep), _ptr(result), ctypes.byref(r)))
         out["poles"] = {}
         out["shotnoise"], out["wsum"], out["w2sum"] = r.shotnoise, r.wsum, r.w2sum
+        return out
+
+    def pk_convolved_power(self, m, b, observer, data_pos, data_weight, n_data, rand_pos,
+                           rand_weight, n_rand, workspace, result):
+        nbytes = workspace.numel() * workspace.element_size()
+        obs = (ctypes.c_double * 3)(*[float(v) for v in observer])
+        self._check(self.lib.pk_convolved_power(
+            self.handle, ctypes.byref(m), ctypes.byref(b), obs, _ptr(data_pos),
+            _ptr(data_weight), int(n_data), _ptr(rand_pos), _ptr(rand_weight), int(n_rand),
+            _ptr(workspace), nbytes, _ptr(result)))
+
+    def pk_convolved_to_host(self, m, b, norm, result):
+        """Host dict: k, modes, poles {ell: P_ell}, shotnoise, wsum / w2sum of
+        the data, and alpha read from the weight sums of the result."""
+        import numpy as np
+
+        nk = b.nk
+        out = {"k": np.empty(nk), "modes": np.empty(nk, dtype=np.int64)}
+        poles = np.empty((b.npoles, nk))
+        dbl, i64 = ctypes.c_double, ctypes.c_int64
+        r = Result(out["k"].ctypes.data_as(ctypes.POINTER(dbl)), None,
+                   out["modes"].ctypes.data_as(ctypes.POINTER(i64)),
+                   poles.ctypes.data_as(ctypes.POINTER(dbl)), None, None, None, None,
+                   0.0, 0.0, 0.0)
+        self._check(self.lib.pk_convolved_to_host(self.handle, ctypes.byref(m), ctypes.byref(b),
+                                                  float(norm), _ptr(result), ctypes.byref(r)))
+        out["poles"] = {int(b.poles[i]): poles[i] for i in range(b.npoles)}
+        out["shotnoise"], out["wsum"], out["w2sum"] = r.shotnoise, r.wsum, r.w2sum
+        sums = result[b.npoles * nk:b.npoles * nk + 4].double().cpu().numpy()
+        out["alpha"] = float(sums[0] / sums[2])
         return out
 
     def pk_fftpower(self, m, b, pos, weight, n, workspace, result):

@@ -932,3 +932,245 @@ pk_status pk_ctx_stage_times(pk_ctx* ctx, double* ms) {
 }
 
 }  // extern "C"
+
+// ---- Survey multipoles (ConvolvedFFTPower) ---------------------------------
+
+namespace {
+
+// Survey binning: 1-D k bins, poles among 0, 2, 4, top edge <= N/2.
+const char* check_survey_bins(const pk_bin_desc* b, const pk_mesh_desc* m) {
+  if (const char* why = check_bins(b, m)) return why;
+  if (b->nmu > 1) return "the survey multipoles have no mu bins (nmu must be 0 or 1)";
+  if (b->npoles < 1) return "at least one multipole must be requested";
+  for (int i = 0; i < b->npoles; ++i)
+    if (b->poles[i] > 4) return "survey multipoles: ell must be 0, 2 or 4";
+  if (b->kmin_f + b->nk * b->dk_f > m->nmesh / 2)
+    return "survey multipoles: the top edge kmin_f + nk * dk_f may not exceed N/2";
+  return nullptr;
+}
+
+// The plain k binning the cross sums of the fields use.
+pk_bin_desc survey_plain_bins(const pk_bin_desc* b) {
+  pk_bin_desc p = *b;
+  p.nmu = 0;
+  p.npoles = 0;
+  p.los = 2;
+  return p;
+}
+
+// Fields F_ell kept: F_0 always, then every requested ell > 0.
+int survey_fields(const pk_bin_desc* b, int* ells) {
+  int nf = 0;
+  ells[nf++] = 0;
+  for (int i = 0; i < b->npoles; ++i)
+    if (b->poles[i] != 0) ells[nf++] = b->poles[i];
+  return nf;
+}
+
+struct SurveyLayout {
+  size_t pos = 0, value = 0, sums = 0, zero = 0, bsums = 0, sumpart = 0, bucket = 0, rec = 0,
+         wbase = 0, mesh = 0, fields = 0, bpart = 0, total = 0;
+  size_t field_bytes = 0;
+  int gb = 0, gp = 0;
+};
+
+SurveyLayout survey_layout(const pk_mesh_desc* m, const pk_bin_desc* b, int64_t nd, int64_t nr) {
+  SurveyLayout l;
+  const size_t n = (size_t)m->nmesh;
+  const size_t es = elem_bytes(m);
+  const size_t np = (size_t)(nd > 0 ? nd : 0) + (size_t)(nr > 0 ? nr : 0);
+  int ells[4];
+  const int nf = survey_fields(b, ells);
+  l.field_bytes = align256(n * n * n * es);
+  const size_t total_modes = n * n * (n / 2);
+  size_t gb = (total_modes + 255) / 256;
+  if (gb > 1024) gb = 1024;
+  l.gb = (int)gb;
+  l.gp = plane_bin_groups(m->nmesh);
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = off;
+    off += align256(bytes);
+    return at;
+  };
+  l.pos = take(np * 3 * es);
+  l.value = take(np * es);
+  l.sums = take(4 * sizeof(double));
+  l.zero = take(2 * sizeof(double));
+  l.bsums = take(2 * sizeof(double));
+  l.sumpart = take(survey_sum_partials() * sizeof(double));
+  l.bucket = take(bucket_bytes(m->nmesh));
+  l.rec = take(np * 4 * es);
+  l.wbase = take(np * es);
+  l.mesh = take(l.field_bytes);
+  l.fields = take((size_t)nf * l.field_bytes);
+  l.bpart = take((size_t)(l.gb + l.gp) * b->nk * sizeof(double));
+  l.total = off;
+  return l;
+}
+
+// Normalisation of the real harmonic Y_lm: sqrt((2l+1)/4pi (l-|m|)!/(l+|m|)!),
+// times sqrt(2) for m != 0.
+Harmonic harmonic_of(int ell, int m) {
+  Harmonic h;
+  h.ell = ell;
+  h.am = m < 0 ? -m : m;
+  h.sine = m < 0 ? 1 : 0;
+  double ratio = 1.0;  // (l - |m|)! / (l + |m|)!
+  for (int i = ell - h.am + 1; i <= ell + h.am; ++i) ratio /= (double)i;
+  const double pi = 3.14159265358979323846;
+  h.knorm = std::sqrt((2.0 * ell + 1.0) / (4.0 * pi) * ratio) * (h.am ? std::sqrt(2.0) : 1.0);
+  return h;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t pk_convolved_doubles(const pk_bin_desc* b) {
+  if (!b || b->nk < 1 || b->nk > 4096 || b->npoles < 1 || b->npoles > 4) return 0;
+  return (size_t)b->npoles * b->nk + 4;
+}
+
+size_t pk_convolved_workspace_bytes(const pk_mesh_desc* m, const pk_bin_desc* b, int64_t n_data,
+                                    int64_t n_rand) {
+  if (check_mesh(m) || !b || check_survey_bins(b, m) || n_data < 0 || n_rand < 0) return 0;
+  return survey_layout(m, b, n_data, n_rand).total;
+}
+
+pk_status pk_convolved_power(pk_ctx* ctx, const pk_mesh_desc* m, const pk_bin_desc* b,
+                             const double* observer, const void* data_pos,
+                             const void* data_weight, int64_t n_data, const void* rand_pos,
+                             const void* rand_weight, int64_t n_rand, void* workspace,
+                             size_t workspace_bytes, double* result_dev) {
+  if (!ctx) return PK_EINVAL;
+  if (const char* why = check_mesh(m)) return fail(ctx, PK_EINVAL, why);
+  if (const char* why = check_survey_bins(b, m)) return fail(ctx, PK_EINVAL, why);
+  if (m->interlaced) return fail(ctx, PK_EUNSUPPORTED, "survey multipoles: interlacing is not implemented");
+  if (!observer || !std::isfinite(observer[0]) || !std::isfinite(observer[1]) ||
+      !std::isfinite(observer[2]))
+    return fail(ctx, PK_EINVAL, "observer must be 3 finite host doubles");
+  if (n_data < 1 || n_rand < 1) return fail(ctx, PK_EINVAL, "n_data and n_rand must be >= 1");
+  if (n_data + n_rand > ((int64_t)1 << 40)) return fail(ctx, PK_EINVAL, "catalog too large");
+  if (!data_pos || !rand_pos) return fail(ctx, PK_EINVAL, "data_pos or rand_pos is NULL");
+  if (!workspace || !result_dev) return fail(ctx, PK_EINVAL, "workspace or result is NULL");
+  const SurveyLayout l = survey_layout(m, b, n_data, n_rand);
+  if (workspace_bytes < l.total) return fail(ctx, PK_EINVAL, "workspace too small");
+  const pk_bin_desc pb = survey_plain_bins(b);
+  if (const char* why = check_lds(&pb, m)) return fail(ctx, PK_EUNSUPPORTED, why);
+  if (ctx->device == PK_DEVICE_NONE) return fail(ctx, PK_EDEVICE, "validation-only context");
+  DeviceGuard g(ctx->device);
+  const MeshTables* t = nullptr;
+  BinSpec spec;
+  if (pk_status st = prepare_tables(ctx, m, &pb, &t, &spec)) return st;
+  hipStream_t s = ctx->stream;
+  char* ws = static_cast<char*>(workspace);
+  const size_t es = elem_bytes(m);
+  const int64_t n = n_data + n_rand;
+  void* pos = ws + l.pos;
+  void* value = ws + l.value;
+  double* sums = reinterpret_cast<double*>(ws + l.sums);
+  double* zero = reinterpret_cast<double*>(ws + l.zero);
+  double* bsums = reinterpret_cast<double*>(ws + l.bsums);
+  void* mesh = ws + l.mesh;
+  int ells[4];
+  const int nf = survey_fields(b, ells);
+  auto field = [&](int i) -> void* { return ws + l.fields + (size_t)i * l.field_bytes; };
+  // one catalog, data first, so that one painting covers both
+  hipError_t e = hipMemcpyAsync(pos, data_pos, (size_t)n_data * 3 * es, hipMemcpyDeviceToDevice, s);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(static_cast<char*>(pos) + (size_t)n_data * 3 * es, rand_pos,
+                       (size_t)n_rand * 3 * es, hipMemcpyDeviceToDevice, s);
+  if (e == hipSuccess) e = launch_fill_zero(zero, 2 * sizeof(double), s);
+  if (e == hipSuccess)
+    e = launch_survey_sums(m->dtype, data_weight, n_data, rand_weight, n_rand,
+                           reinterpret_cast<double*>(ws + l.sumpart), sums, s);
+  // the amounts w s (s = 1 for data, -alpha for randoms), bucketed once
+  Harmonic unit;
+  unit.knorm = 1.0;
+  if (e == hipSuccess)
+    e = launch_ylm_value(m->dtype, pos, data_weight, n_data, rand_weight, n_rand, observer, unit,
+                         sums, value, s);
+  void* base = ws + l.wbase;
+  if (e == hipSuccess)
+    e = launch_bucket(m->dtype, m->nmesh, m->boxsize, pos, nullptr, value, n, ws + l.bucket,
+                      ws + l.rec, base, bsums, s);
+  const double pi = 3.14159265358979323846;
+  for (int f = 0; f < nf && e == hipSuccess; ++f) {
+    const int ell = ells[f];
+    for (int mm = -ell; mm <= ell && e == hipSuccess; ++mm) {
+      const Harmonic h = harmonic_of(ell, mm);
+      // the sorted amounts times Y_lm(r^) (value is free after the bucketing)
+      e = launch_ylm_records(m->dtype, m->nmesh, m->boxsize, ws + l.rec, base, ws + l.bucket,
+                             observer, h, value, s);
+      // the painted field has mean ~0: nothing is subtracted before the z-FFT
+      if (e == hipSuccess)
+        e = launch_paint_z(m->dtype, m->nmesh, m->window, false, ws + l.rec, value,
+                           ws + l.bucket, zero, t->tw, mesh, nullptr, s);
+      if (e == hipSuccess)
+        e = launch_fft_cols(m->dtype, m->nmesh, mesh, 1, l.field_bytes, t->tw, 1, s);
+      if (e == hipSuccess)
+        e = launch_fft_cols(m->dtype, m->nmesh, mesh, 1, l.field_bytes, t->tw, 0, s);
+      if (e == hipSuccess)
+        e = launch_ylm_accumulate(m->dtype, m->nmesh, mesh, field(f), h, 4.0 * pi / (2 * ell + 1),
+                                  *t, m->window, m->compensated, mm == -ell ? 1 : 0, s);
+    }
+  }
+  // sums of Re F_0 conj F_ell per k bin, then the weight sums
+  double* part = reinterpret_cast<double*>(ws + l.bpart);
+  for (int i = 0; i < b->npoles && e == hipSuccess; ++i) {
+    int f = 0;
+    while (ells[f] != b->poles[i]) ++f;
+    const void* c2 = f == 0 ? nullptr : field(f);
+    e = launch_bin_packed(m->dtype, m->nmesh, field(0), c2, spec, part, s);
+    if (e == hipSuccess)
+      e = launch_plane_bin(m->dtype, m->nmesh, field(0), c2, m->nmesh / 2, *t, m->window, 0, spec,
+                           part + (size_t)l.gb * spec.nsum, s, c2 ? 1 : 0);
+    if (e == hipSuccess)
+      e = launch_reduce(part, l.gb + l.gp, spec, result_dev + (size_t)i * b->nk, s);
+  }
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(result_dev + (size_t)b->npoles * b->nk, sums, 4 * sizeof(double),
+                       hipMemcpyDeviceToDevice, s);
+  if (e != hipSuccess) return dev_fail(ctx, e, "pk_convolved_power");
+  return PK_OK;
+}
+
+pk_status pk_convolved_to_host(pk_ctx* ctx, const pk_mesh_desc* m, const pk_bin_desc* b,
+                               double norm, const double* result_dev, pk_result* out) {
+  if (!ctx) return PK_EINVAL;
+  if (const char* why = check_mesh(m)) return fail(ctx, PK_EINVAL, why);
+  if (const char* why = check_survey_bins(b, m)) return fail(ctx, PK_EINVAL, why);
+  if (!std::isfinite(norm) || !(norm > 0)) return fail(ctx, PK_EINVAL, "norm must be finite and > 0");
+  if (!result_dev || !out || !out->k || !out->modes || !out->poles)
+    return fail(ctx, PK_EINVAL, "result, out or one of out->k, modes, poles is NULL");
+  if (ctx->device == PK_DEVICE_NONE) return fail(ctx, PK_EDEVICE, "validation-only context");
+  DeviceGuard g(ctx->device);
+  const pk_bin_desc pb = survey_plain_bins(b);
+  BinTables* bt = nullptr;
+  if (pk_status st = get_bin_tables(ctx, m, &pb, &bt)) return st;
+  const int nk = b->nk;
+  std::vector<double> h(pk_convolved_doubles(b));
+  hipError_t e = hipMemcpyAsync(h.data(), result_dev, h.size() * sizeof(double),
+                                hipMemcpyDeviceToHost, ctx->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+  if (e != hipSuccess) return dev_fail(ctx, e, "pk_convolved_to_host");
+  const double kf = 2.0 * 3.14159265358979323846 / m->boxsize;
+  const double nan = std::nan("");
+  for (int k = 0; k < nk; ++k) {
+    const int64_t nb = bt->modes[k];
+    out->modes[k] = nb;
+    out->k[k] = nb ? kf * bt->sum_n[k] / (double)nb : nan;
+    for (int i = 0; i < b->npoles; ++i)
+      out->poles[(size_t)i * nk + k] =
+          nb ? (2 * b->poles[i] + 1) * h[(size_t)i * nk + k] / (norm * (double)nb) : nan;
+  }
+  const double* ws = h.data() + (size_t)b->npoles * nk;
+  const double alpha = ws[0] / ws[2];
+  out->wsum = ws[0];
+  out->w2sum = ws[1];
+  out->shotnoise = (ws[1] + alpha * alpha * ws[3]) / norm;
+  return PK_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,323 @@
+// Survey power multipoles with a line of sight that varies from particle to
+// particle (ConvolvedFFTPower, Sec. 3.4.1).  The paper names the estimator
+// (the FFT multipoles of Hand et al. 2017) without writing it out; the
+// standard form is computed here:
+//
+//   F(x)     = sum_data w delta_D(x - x_i) - alpha sum_randoms w delta_D(x - x_j),
+//              alpha = sum_data w / sum_randoms w,
+//   A_lm(k)  = FFT of F painted with the extra factor Y_lm(r^), r^ the unit
+//              vector from the observer to the particle, divided by the
+//              window (Eq. 2),
+//   F_ell(k) = 4 pi / (2 ell + 1) sum_m Y_lm(k^) A_lm(k),
+//   P_ell(k) = (2 ell + 1) / I <Re F_0(k) conj F_ell(k)>_shell.
+//
+// Y_lm are the real orthonormal spherical harmonics, evaluated through the
+// associated Legendre recurrence in z and the powers of (x + i y), so the
+// same routine serves the positions (r^) and the wave vectors (k^).  The
+// catalog (data and randoms in one) is bucketed by column once, with the
+// amounts w s; every harmonic then rescales the sorted amounts by Y_lm(r^)
+// of the record's position, paints, transforms and accumulates.  This file
+// holds the weight sums, the amounts and the accumulation of F_ell over the
+// packed half spectrum; bucketing, painting, the FFT and the binning are the
+// kernels of the FFTPower path.
+#include "fft_core.h"
+#include "internal.h"
+
+namespace pk {
+
+namespace {
+
+// Q_ell^m(z) = P_ell^m(z) / (1 - z^2)^(m/2) (no Condon-Shortley phase) by
+// the three-term recurrence in ell, started from Q_m^m = (2m - 1)!!.
+__device__ __forceinline__ double legendre_q(int ell, int am, double z) {
+  double q0 = 1.0;
+  for (int i = 1; i <= am; ++i) q0 *= (double)(2 * i - 1);
+  if (ell == am) return q0;
+  double q1 = (double)(2 * am + 1) * z * q0;
+  for (int l = am + 2; l <= ell; ++l) {
+    const double q2 = ((double)(2 * l - 1) * z * q1 - (double)(l + am - 1) * q0) / (double)(l - am);
+    q0 = q1;
+    q1 = q2;
+  }
+  return q1;
+}
+
+// Real spherical harmonic at the unit vector (x, y, z): knorm * Q_ell^|m|(z)
+// times Re (x + i y)^|m| (m >= 0) or Im (x + i y)^|m| (m < 0).  knorm is
+// the normalisation sqrt((2 ell + 1) / 4 pi (ell - |m|)! / (ell + |m|)!),
+// times sqrt(2) for m != 0.
+__device__ __forceinline__ double real_harmonic(int ell, int am, int sine, double knorm, double x,
+                                                double y, double z) {
+  double re = 1.0, im = 0.0;
+  for (int i = 0; i < am; ++i) {
+    const double r2 = re * x - im * y;
+    im = re * y + im * x;
+    re = r2;
+  }
+  return knorm * legendre_q(ell, am, z) * (sine ? im : re);
+}
+
+constexpr int kSumGroups = 512;
+
+// Per-group partial sums {sum_data w, sum_data w^2, sum_randoms w,
+// sum_randoms w^2} in float64; weights NULL mean 1.
+template <typename T>
+__global__ void __launch_bounds__(256)
+    k_survey_sums(const T* __restrict__ wd, int64_t nd, const T* __restrict__ wr, int64_t nr,
+                  double* __restrict__ part) {
+  double s[4] = {0.0, 0.0, 0.0, 0.0};
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nd; i += stride) {
+    const double w = wd ? (double)wd[i] : 1.0;
+    s[0] += w;
+    s[1] += w * w;
+  }
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nr; i += stride) {
+    const double w = wr ? (double)wr[i] : 1.0;
+    s[2] += w;
+    s[3] += w * w;
+  }
+  __shared__ double sh[4][256];
+  for (int j = 0; j < 4; ++j) sh[j][threadIdx.x] = s[j];
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h)
+      for (int j = 0; j < 4; ++j) sh[j][threadIdx.x] += sh[j][threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x < 4) part[blockIdx.x * 4 + threadIdx.x] = sh[threadIdx.x][0];
+}
+
+// Sums the group partials in a fixed order (reproducible).
+__global__ void __launch_bounds__(256)
+    k_survey_sums_final(const double* __restrict__ part, int groups, double* __restrict__ sums) {
+  __shared__ double sh[4][256];
+  double s[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int g = threadIdx.x; g < groups; g += blockDim.x)
+    for (int j = 0; j < 4; ++j) s[j] += part[g * 4 + j];
+  for (int j = 0; j < 4; ++j) sh[j][threadIdx.x] = s[j];
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h)
+      for (int j = 0; j < 4; ++j) sh[j][threadIdx.x] += sh[j][threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x < 4) sums[threadIdx.x] = sh[threadIdx.x][0];
+}
+
+// value_i = w_i s_i Y_lm(r^_i): s = 1 for the nd data particles (first in
+// pos), -alpha for the randoms after them; r = x - observer with the position
+// as given, r^ = z^ where r = 0.  With Y_00 and knorm = 1 (the constant 1)
+// this is the amount w s that the bucketing sorts.
+template <typename T>
+__global__ void __launch_bounds__(256)
+    k_ylm_value(const T* __restrict__ pos, const T* __restrict__ wd, int64_t nd,
+                const T* __restrict__ wr, int64_t nr, double ox, double oy, double oz, int ell,
+                int am, int sine, double knorm, const double* __restrict__ sums,
+                T* __restrict__ value) {
+  const int64_t n = nd + nr;
+  const double neg_alpha = -sums[0] / sums[2];
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    double w;
+    if (i < nd) {
+      w = wd ? (double)wd[i] : 1.0;
+    } else {
+      w = (wr ? (double)wr[i - nd] : 1.0) * neg_alpha;
+    }
+    double rx = (double)pos[3 * i] - ox, ry = (double)pos[3 * i + 1] - oy,
+           rz = (double)pos[3 * i + 2] - oz;
+    const double rn = sqrt(rx * rx + ry * ry + rz * rz);
+    if (rn > 0.0) {
+      const double inv = 1.0 / rn;
+      rx *= inv;
+      ry *= inv;
+      rz *= inv;
+    } else {
+      rx = 0.0;
+      ry = 0.0;
+      rz = 1.0;
+    }
+    value[i] = static_cast<T>(w * real_harmonic(ell, am, sine, knorm, rx, ry, rz));
+  }
+}
+
+// Sorted records of the painting: {t_x, t_y, t_z, iy << 16 | iz} per
+// particle, t the offsets from the cell corner, grouped by column
+// c = ix N + iy (offsets[c] .. offsets[c + 1]).
+__device__ __forceinline__ unsigned record_cell_bits(float w) { return __float_as_uint(w); }
+__device__ __forceinline__ unsigned record_cell_bits(double w) { return (unsigned)w; }
+
+// amount_j = base_j Y_lm(r^_j) for the records of one column per wavefront:
+// base holds w s of every record, r^ points from the observer to the
+// record's position (ix + t_x, iy + t_y, iz + t_z) h in the periodic box.
+template <typename T, typename R>
+__global__ void __launch_bounds__(256)
+    k_ylm_records(const R* __restrict__ rec, const T* __restrict__ base,
+                  const int* __restrict__ offsets, int N, double h, double ox, double oy,
+                  double oz, int ell, int am, int sine, double knorm, T* __restrict__ amount) {
+  const int col = (int)blockIdx.x * 4 + (int)(threadIdx.x >> 6);
+  if (col >= N * N) return;
+  const int ix = col / N;
+  const int lane = threadIdx.x & 63;
+  const int end = offsets[col + 1];
+  for (int j = offsets[col] + lane; j < end; j += 64) {
+    const R r = rec[j];
+    const unsigned bits = record_cell_bits(r.w);
+    const int iy = (int)(bits >> 16), iz = (int)(bits & 0xffffu);
+    double rx = ((double)ix + (double)r.x) * h - ox, ry = ((double)iy + (double)r.y) * h - oy,
+           rz = ((double)iz + (double)r.z) * h - oz;
+    const double rn = sqrt(rx * rx + ry * ry + rz * rz);
+    if (rn > 0.0) {
+      const double inv = 1.0 / rn;
+      rx *= inv;
+      ry *= inv;
+      rz *= inv;
+    } else {
+      rx = 0.0;
+      ry = 0.0;
+      rz = 1.0;
+    }
+    amount[j] = static_cast<T>((double)base[j] * real_harmonic(ell, am, sine, knorm, rx, ry, rz));
+  }
+}
+
+__device__ __forceinline__ int signed_wave(int i, int n) { return i < n / 2 ? i : i - n; }
+
+// F += coef Y_lm(k^) A / W(k) over the packed half spectrum (first: F =).
+// Column kz' >= 1 holds c(kx, ky, kz'); column 0 of A packs the planes
+// kz = 0 and N/2, and its kz = 0 value (Z + conj Z(-k)) / 2 is unpacked
+// here.  F stores the kz = 0 value alone in column 0: F_ell is Hermitian on
+// that plane (A_lm is the transform of a real field and Y_lm(-k^) = Y_lm(k^)
+// for even ell), so this is the packed form of a spectrum whose kz = N/2
+// plane is zero -- those modes have |n| >= N/2 and are never binned.  At the
+// DC mode k^ is taken as z^ (the DC mode is not binned either).
+template <typename T>
+__global__ void __launch_bounds__(256)
+    k_ylm_accumulate(int N, const cpx<T>* __restrict__ a, cpx<T>* __restrict__ f, int ell, int am,
+                     int sine, double knorm, double coef, const T* __restrict__ sinv, int first) {
+  const int NC = N / 2;
+  const size_t total = (size_t)N * N * NC;
+  const int mask = N - 1;
+  for (size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+       idx += (size_t)gridDim.x * blockDim.x) {
+    const int col = (int)(idx % NC);
+    const size_t rest = idx / NC;
+    const int ky = (int)(rest % N), kx = (int)(rest / N);
+    cpx<T> v;
+    if (col != 0) {
+      v = a[idx];
+    } else {
+      const size_t pa = ((size_t)((N - kx) & mask) * N + ((N - ky) & mask)) * NC;
+      const cpx<T> z = a[idx], zp = a[pa];
+      v = {T(0.5) * (z.x + zp.x), T(0.5) * (z.y - zp.y)};
+    }
+    const int nx = signed_wave(kx, N), ny = signed_wave(ky, N);
+    const double n2 = (double)nx * nx + (double)ny * ny + (double)col * col;
+    double ux = 0.0, uy = 0.0, uz = 1.0;
+    if (n2 > 0.0) {
+      const double inv = 1.0 / sqrt(n2);
+      ux = nx * inv;
+      uy = ny * inv;
+      uz = col * inv;
+    }
+    double g = coef * real_harmonic(ell, am, sine, knorm, ux, uy, uz);
+    if (sinv) g *= (double)sinv[kx] * (double)sinv[ky] * (double)sinv[col];
+    const T gt = static_cast<T>(g);
+    cpx<T> o = {gt * v.x, gt * v.y};
+    if (!first) {
+      const cpx<T> old = f[idx];
+      o.x += old.x;
+      o.y += old.y;
+    }
+    f[idx] = o;
+  }
+}
+
+unsigned grid_for(size_t work, size_t cap) {
+  size_t g = (work + 255) / 256;
+  if (g < 1) g = 1;
+  if (g > cap) g = cap;
+  return (unsigned)g;
+}
+
+}  // namespace
+
+size_t survey_sum_partials() { return (size_t)kSumGroups * 4; }
+
+hipError_t launch_survey_sums(int dtype, const void* wd, int64_t nd, const void* wr, int64_t nr,
+                              double* partials, double* sums, hipStream_t s) {
+  const unsigned g = grid_for((size_t)(nd > nr ? nd : nr), kSumGroups);
+  if (dtype == PK_F32)
+    hipLaunchKernelGGL(k_survey_sums<float>, dim3(g), dim3(256), 0, s,
+                       static_cast<const float*>(wd), nd, static_cast<const float*>(wr), nr,
+                       partials);
+  else
+    hipLaunchKernelGGL(k_survey_sums<double>, dim3(g), dim3(256), 0, s,
+                       static_cast<const double*>(wd), nd, static_cast<const double*>(wr), nr,
+                       partials);
+  hipLaunchKernelGGL(k_survey_sums_final, dim3(1), dim3(256), 0, s, partials, (int)g, sums);
+  return hipGetLastError();
+}
+
+hipError_t launch_ylm_value(int dtype, const void* pos, const void* wd, int64_t nd, const void* wr,
+                            int64_t nr, const double* observer, const Harmonic& h,
+                            const double* sums, void* value, hipStream_t s) {
+  const unsigned g = grid_for((size_t)(nd + nr), 8192);
+  if (dtype == PK_F32)
+    hipLaunchKernelGGL(k_ylm_value<float>, dim3(g), dim3(256), 0, s,
+                       static_cast<const float*>(pos), static_cast<const float*>(wd), nd,
+                       static_cast<const float*>(wr), nr, observer[0], observer[1], observer[2],
+                       h.ell, h.am, h.sine, h.knorm, sums, static_cast<float*>(value));
+  else
+    hipLaunchKernelGGL(k_ylm_value<double>, dim3(g), dim3(256), 0, s,
+                       static_cast<const double*>(pos), static_cast<const double*>(wd), nd,
+                       static_cast<const double*>(wr), nr, observer[0], observer[1], observer[2],
+                       h.ell, h.am, h.sine, h.knorm, sums, static_cast<double*>(value));
+  return hipGetLastError();
+}
+
+hipError_t launch_ylm_records(int dtype, int nmesh, double boxsize, const void* rec,
+                              const void* base, const void* bucket_ws, const double* observer,
+                              const Harmonic& hm, void* amount, hipStream_t s) {
+  // the column offsets follow the N^2 column counts at the start of the
+  // bucketing workspace
+  const int* offsets = static_cast<const int*>(bucket_ws) + (size_t)nmesh * nmesh;
+  const unsigned g = (unsigned)(((size_t)nmesh * nmesh + 3) / 4);
+  const double h = boxsize / nmesh;
+  if (dtype == PK_F32)
+    hipLaunchKernelGGL((k_ylm_records<float, float4>), dim3(g), dim3(256), 0, s,
+                       static_cast<const float4*>(rec), static_cast<const float*>(base), offsets,
+                       nmesh, h, observer[0], observer[1], observer[2], hm.ell, hm.am, hm.sine,
+                       hm.knorm, static_cast<float*>(amount));
+  else
+    hipLaunchKernelGGL((k_ylm_records<double, double4>), dim3(g), dim3(256), 0, s,
+                       static_cast<const double4*>(rec), static_cast<const double*>(base), offsets,
+                       nmesh, h, observer[0], observer[1], observer[2], hm.ell, hm.am, hm.sine,
+                       hm.knorm, static_cast<double*>(amount));
+  return hipGetLastError();
+}
+
+hipError_t launch_ylm_accumulate(int dtype, int nmesh, const void* cmesh, void* field,
+                                 const Harmonic& h, double coef, const MeshTables& t, int order,
+                                 int compensated, int first, hipStream_t s) {
+  const size_t total = (size_t)nmesh * nmesh * (nmesh / 2);
+  const unsigned g = grid_for(total, 65536);
+  if (dtype == PK_F32) {
+    const float* sinv =
+        compensated ? static_cast<const float*>(t.sinc_inv) + (size_t)(order - 2) * nmesh : nullptr;
+    hipLaunchKernelGGL(k_ylm_accumulate<float>, dim3(g), dim3(256), 0, s, nmesh,
+                       static_cast<const cpx<float>*>(cmesh), static_cast<cpx<float>*>(field),
+                       h.ell, h.am, h.sine, h.knorm, coef, sinv, first);
+  } else {
+    const double* sinv = compensated
+                             ? static_cast<const double*>(t.sinc_inv) + (size_t)(order - 2) * nmesh
+                             : nullptr;
+    hipLaunchKernelGGL(k_ylm_accumulate<double>, dim3(g), dim3(256), 0, s, nmesh,
+                       static_cast<const cpx<double>*>(cmesh), static_cast<cpx<double>*>(field),
+                       h.ell, h.am, h.sine, h.knorm, coef, sinv, first);
+  }
+  return hipGetLastError();
+}
+
+}  // namespace pk

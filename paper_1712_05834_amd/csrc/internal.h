@@ -123,6 +123,32 @@ int mode_table_groups(int nmesh);
 hipError_t launch_compensate(int dtype, int nmesh, void* cmesh, const void* cmesh_b,
                              const MeshTables& t, int order, int compensated, hipStream_t s);
 
+// Survey multipoles (convolved.hip).  One real spherical harmonic Y_lm:
+// ell, |m|, sine = (m < 0), knorm its normalisation (host float64).
+struct Harmonic {
+  int ell = 0;
+  int am = 0;
+  int sine = 0;
+  double knorm = 0.0;
+};
+// Doubles of the partials buffer of launch_survey_sums.
+size_t survey_sum_partials();
+// sums[4] = {sum_data w, sum_data w^2, sum_randoms w, sum_randoms w^2}.
+hipError_t launch_survey_sums(int dtype, const void* wd, int64_t nd, const void* wr, int64_t nr,
+                              double* partials, double* sums, hipStream_t s);
+// value[i] = w_i s_i Y_lm(r^_i) over the concatenated catalog (data first).
+hipError_t launch_ylm_value(int dtype, const void* pos, const void* wd, int64_t nd, const void* wr,
+                            int64_t nr, const double* observer, const Harmonic& h,
+                            const double* sums, void* value, hipStream_t s);
+// amount[j] = base[j] Y_lm(r^_j) over the sorted records of launch_bucket.
+hipError_t launch_ylm_records(int dtype, int nmesh, double boxsize, const void* rec,
+                              const void* base, const void* bucket_ws, const double* observer,
+                              const Harmonic& hm, void* amount, hipStream_t s);
+// field (+)= coef Y_lm(k^) cmesh / W(k) on packed spectra (see the kernel).
+hipError_t launch_ylm_accumulate(int dtype, int nmesh, const void* cmesh, void* field,
+                                 const Harmonic& h, double coef, const MeshTables& t, int order,
+                                 int compensated, int first, hipStream_t s);
+
 }  // namespace pk
 
 namespace pk {

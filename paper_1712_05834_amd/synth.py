@@ -30,6 +30,9 @@ realisations of an input P(k) and a Zel'dovich-displaced lattice):
   the oracle read the catalog back.
 * ``mock_batch_sizes``: the particle counts and mesh sizes of a batch of
   mocks: N_i = round(10^U(lo, hi)), meshes cycling through a list.
+* ``survey_catalog``: a survey-like geometry for the multipoles with a
+  varying line of sight: the log-normal catalog and rand_factor times as many
+  uniform randoms, both cut to the shell rmin <= |x - observer| < rmax.
 """
 
 import os
@@ -213,3 +216,19 @@ def mock_batch_sizes(count, seed, meshes=(128, 256, 512), lo=5.0, hi=7.0):
     """(npart_target, nmesh) per mock: N_i = round(10^U(lo, hi)), mesh i mod len."""
     u = rng_for(seed).uniform(lo, hi, size=count)
     return [(int(round(10.0 ** x)), int(meshes[i % len(meshes)])) for i, x in enumerate(u)]
+
+
+def survey_catalog(nmesh, boxsize, pk, nbar_cell, seed, observer, rmin, rmax, rand_factor=5.0,
+                   dtype=np.float64):
+    """(data, randoms): log-normal data and uniform randoms (rand_factor times
+    the box's data count) kept where rmin <= |x - observer| < rmax."""
+    obs = np.asarray(observer, dtype=np.float64)
+
+    def cut(pos):
+        r = np.sqrt(np.sum((pos.astype(np.float64) - obs) ** 2, axis=1))
+        return pos[(r >= rmin) & (r < rmax)]
+
+    data = lognormal_catalog(nmesh, boxsize, pk, nbar_cell, seed, dtype=dtype)
+    nrand = int(round(rand_factor * len(data)))
+    rand = uniform_catalog(nrand, boxsize, seed + 104729, dtype=dtype)
+    return np.ascontiguousarray(cut(data)), np.ascontiguousarray(cut(rand))

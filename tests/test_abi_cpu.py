@@ -156,3 +156,36 @@ def test_lane_entry_points_validate(vctx):
     assert b"no lanes" in lib.pk_last_error(h)
     assert lib.pk_ctx_set_lanes(None, 1) == _lib.PK_EINVAL
     assert lib.pk_ctx_lanes(None) == 0
+
+
+def test_survey_multipoles_validate(vctx):
+    lib, h = vctx
+    one = ctypes.c_void_p(1)
+    obs = (ctypes.c_double * 3)(0.0, 0.0, -100.0)
+    m = _lib.mesh_desc(32, 100.0, "tsc")
+    b = _lib.bin_desc(16, poles=(0, 2, 4))
+    need = _lib.convolved_workspace_bytes(m, b, 100, 300)
+    assert need > 3 * _lib.mesh_bytes(m)
+    assert _lib.convolved_doubles(b) == 3 * 16 + 4
+
+    def call(m=m, b=b, obs=obs, nd=100, nr=300, wsb=need, dpos=one, rpos=one):
+        return lib.pk_convolved_power(h, ctypes.byref(m), ctypes.byref(b), obs, dpos, None, nd,
+                                      rpos, None, nr, one, wsb, one)
+
+    assert call() == _lib.PK_EDEVICE  # valid: only the device is missing
+    assert call(wsb=need - 1) == _lib.PK_EINVAL
+    assert call(nd=0) == _lib.PK_EINVAL
+    assert call(nr=0) == _lib.PK_EINVAL
+    assert call(rpos=None) == _lib.PK_EINVAL
+    assert call(obs=(ctypes.c_double * 3)(0.0, float("nan"), 0.0)) == _lib.PK_EINVAL
+    assert call(b=_lib.bin_desc(16, poles=(0, 6))) == _lib.PK_EINVAL
+    assert call(b=_lib.bin_desc(16, nmu=4, poles=(0,))) == _lib.PK_EINVAL
+    assert call(b=_lib.bin_desc(16)) == _lib.PK_EINVAL  # no pole requested
+    assert call(b=_lib.bin_desc(17, poles=(0,))) == _lib.PK_EINVAL  # top edge above N/2
+    inter = _lib.mesh_desc(32, 100.0, "tsc", True)
+    assert call(m=inter) == _lib.PK_EUNSUPPORTED
+    assert _lib.convolved_workspace_bytes(m, _lib.bin_desc(17, poles=(0,)), 1, 1) == 0
+    assert _lib.convolved_workspace_bytes(m, b, -1, 1) == 0
+    res = _lib.Result()
+    assert lib.pk_convolved_to_host(h, ctypes.byref(m), ctypes.byref(b), 0.0, one,
+                                    ctypes.byref(res)) == _lib.PK_EINVAL

@@ -97,3 +97,18 @@ def test_distant_observer_gives_fftpower_multipoles():
         err = np.abs(got["poles"][ell][ok] - want["poles"][ell][ok]) / scale
         assert err.max() < 1e-5, (ell, err.max())
     assert got["shotnoise"] == pytest.approx((len(data) + alpha ** 2 * len(rand)) / norm)
+
+
+def test_periodic_images_give_the_same_multipoles():
+    # the painting and the line of sight both take positions in the periodic
+    # box: shifting particles by whole box lengths changes nothing
+    n, box = 16, 100.0
+    rng = np.random.default_rng(5)
+    data, rand = rng.uniform(0, box, (300, 3)), rng.uniform(0, box, (900, 3))
+    obs = np.array([50.0, 40.0, -80.0])
+    a = cv.convolved_power(data, rand, None, None, obs, n, box, 1.0, "cic", (0, 2, 4))
+    shift = rng.integers(-2, 3, (300, 3)) * box
+    b = cv.convolved_power(data + shift, rand - box, None, None, obs, n, box, 1.0, "cic",
+                           (0, 2, 4))
+    for ell in (0, 2, 4):
+        np.testing.assert_allclose(b["poles"][ell], a["poles"][ell], rtol=1e-9, atol=1e-9)
