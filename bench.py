@@ -48,6 +48,15 @@ BATCH = dict(count=256, box=1380.0, meshes=(128, 256, 512), seed=1000, lanes=8,
              window="tsc", poles=(0, 2, 4))
 
 
+# Survey multipoles with a varying line of sight (ConvolvedFFTPower): a
+# log-normal catalog (0.05 per cell on 512^3, ~6.7M in the box) and 10x as
+# many uniform randoms, both cut to the shell 0.3 L <= |x - o| < 1.2 L around
+# an observer at (L/2, L/2, -L/4); TSC, compensated, float32, ell = 0, 2, 4
+# (1 + 5 + 9 harmonic paintings and FFTs per call).
+SURVEY = dict(n=512, box=2000.0, window="tsc", nbar_cell=0.05, rand_factor=10.0, seed=5,
+              observer=(0.5, 0.5, -0.25), shell=(0.3, 1.2), poles=(0, 2, 4))
+
+
 # Serving: requests arriving as a Poisson process; per request a uniform or
 # log-normal catalog (50/50), N_p log-uniform in [1e5, 5e7], mesh 128^3 ..
 # 1024^3, CIC or TSC, interlacing on or off, float32.  Catalogs are drawn on
@@ -160,7 +169,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="lognormal-512",
-                    choices=sorted(WORKLOADS) + ["batch-mocks", "serve"])
+                    choices=sorted(WORKLOADS) + ["batch-mocks", "serve", "survey-512"])
     ap.add_argument("--mocks", type=int, default=BATCH["count"],
                     help="number of mocks of the batch-mocks workload")
     ap.add_argument("--lanes", type=int, default=BATCH["lanes"],
@@ -199,6 +208,9 @@ def main():
         return
     if args.workload == "serve":
         run_serve(args)
+        return
+    if args.workload == "survey-512":
+        run_survey(args)
         return
     w = WORKLOADS[args.workload]
     t0 = time.perf_counter()
@@ -372,6 +384,62 @@ def run_batch(args):
         "cpu_baseline": None,
     }
     print(json.dumps(line), flush=True)
+
+
+def run_survey(args):
+    """survey-512: one step = pk_convolved_power + the multipoles on the host.
+    value = survey multipole sets per second."""
+    import numpy as np
+    import torch
+
+    from paper_1712_05834_amd import _lib, synth
+
+    w = SURVEY
+    box, n = w["box"], w["n"]
+    obs = np.array(w["observer"]) * box
+    t0 = time.perf_counter()
+    data, rand = synth.survey_catalog(n, box, synth.pk_lognormal_c2, w["nbar_cell"], w["seed"],
+                                      obs, w["shell"][0] * box, w["shell"][1] * box,
+                                      w["rand_factor"], dtype=np.float32)
+    log(f"survey: {len(data)} data, {len(rand)} randoms in {time.perf_counter() - t0:.1f} s")
+    dev = torch.device("cuda:0")
+    d, r = torch.from_numpy(data).to(dev), torch.from_numpy(rand).to(dev)
+    ctx = _lib.Context(0)
+    m = _lib.mesh_desc(n, box, w["window"], False, True, "f4")
+    b = _lib.bin_desc(n // 2, 0.0, 1.0, 0, w["poles"], 2)
+    ws = torch.empty(_lib.convolved_workspace_bytes(m, b, len(data), len(rand)),
+                     dtype=torch.uint8, device=dev)
+    res = torch.empty(_lib.convolved_doubles(b), dtype=torch.float64, device=dev)
+    norm = float(len(data)) ** 2 / box ** 3
+
+    def step():
+        ctx.pk_convolved_power(m, b, obs, d, None, len(data), r, None, len(rand), ws, res)
+        return ctx.pk_convolved_to_host(m, b, norm, res)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    log(f"warmup done ({args.warmup} steps); timing {args.steps} steps")
+    t_start = time.perf_counter()
+    for _ in range(args.steps):
+        out = step()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t_start
+    assert np.isfinite(out["poles"][0][1:]).all(), "non-finite multipoles"
+    ms = 1e3 * elapsed / args.steps
+    harmonics = sum(2 * ell + 1 for ell in set(w["poles"]) | {0})
+    print(json.dumps({
+        "metric": "survey multipole sets (P_0, P_2, P_4 with a varying line of sight) per second",
+        "value": 1e3 / ms, "unit": "sets/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32 (paint, FFT, fields) + f64 (bin sums)",
+        "data": "synthetic",
+        "config": {"workload": "survey-512", "nmesh": n, "boxsize": box,
+                   "window": w["window"], "n_data": len(data), "n_rand": len(rand),
+                   "poles": list(w["poles"]), "harmonics": harmonics},
+        "ms_per_harmonic": ms / harmonics,
+        "mparticles_per_s_painted": harmonics * (len(data) + len(rand)) / (ms * 1e-3) / 1e6,
+    }), flush=True)
 
 
 def run_serve(args):

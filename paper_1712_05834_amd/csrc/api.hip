@@ -1091,22 +1091,23 @@ pk_status pk_convolved_power(pk_ctx* ctx, const pk_mesh_desc* m, const pk_bin_de
   if (e == hipSuccess)
     e = launch_ylm_value(m->dtype, pos, data_weight, n_data, rand_weight, n_rand, observer, unit,
                          sums, value, s);
-  void* base = ws + l.wbase;
   if (e == hipSuccess)
     e = launch_bucket(m->dtype, m->nmesh, m->boxsize, pos, nullptr, value, n, ws + l.bucket,
-                      ws + l.rec, base, bsums, s);
+                      ws + l.rec, ws + l.wbase, bsums, s);
+  void* rec = ws + l.rec;
+  void* base = ws + l.wbase;
   const double pi = 3.14159265358979323846;
   for (int f = 0; f < nf && e == hipSuccess; ++f) {
     const int ell = ells[f];
     for (int mm = -ell; mm <= ell && e == hipSuccess; ++mm) {
       const Harmonic h = harmonic_of(ell, mm);
       // the sorted amounts times Y_lm(r^) (value is free after the bucketing)
-      e = launch_ylm_records(m->dtype, m->nmesh, m->boxsize, ws + l.rec, base, ws + l.bucket,
-                             observer, h, value, s);
+      e = launch_ylm_records(m->dtype, m->nmesh, m->boxsize, rec, base, ws + l.bucket, observer,
+                             h, value, s);
       // the painted field has mean ~0: nothing is subtracted before the z-FFT
       if (e == hipSuccess)
-        e = launch_paint_z(m->dtype, m->nmesh, m->window, false, ws + l.rec, value,
-                           ws + l.bucket, zero, t->tw, mesh, nullptr, s);
+        e = launch_paint_z(m->dtype, m->nmesh, m->window, false, rec, value, ws + l.bucket, zero,
+                           t->tw, mesh, nullptr, s);
       if (e == hipSuccess)
         e = launch_fft_cols(m->dtype, m->nmesh, mesh, 1, l.field_bytes, t->tw, 1, s);
       if (e == hipSuccess)

@@ -222,28 +222,39 @@ __global__ void __launch_bounds__((XCfg<T, N>::THREADS)) __attribute__((amdgpu_w
     }
     __syncthreads();
     if (tile_id + (int)gridDim.x < ntiles) issue_loads(tile_id + (int)gridDim.x);
-    // binning: with 64-lane waves, work item m = 64 * slot + lane covers
-    // column slot / S and kx = lane * S + slot % S; small workgroups take
-    // column m / N and kx = m % N
-    constexpr bool WAVEWISE = N >= 64 && Cf::THREADS % 64 == 0;
-    constexpr int STEP = WAVEWISE ? Cf::THREADS : Cf::THREADS;
-    for (int m = threadIdx.x; m < C * N; m += STEP) {
-      int cc_, kx;
+    // binning: the modes n_x and -n_x of a column share |n|^2 and n_los^2
+    // (for any line of sight), hence every bin, so work item j < N/2 bins
+    // the sum of the powers at kx = j and N - j; item 0 bins n_x = 0 and
+    // n_x = -N/2 separately.  With 64-lane waves, item m = 64 * slot + lane
+    // covers column slot / S2 and j = lane * S2 + slot % S2 (distinct |n|
+    // bins across a wave: few same-address collisions of the LDS atomics);
+    // small workgroups take column m / IC and j = m % IC.
+    constexpr int IC = N / 2;
+    constexpr bool WAVEWISE = IC >= 64 && Cf::THREADS % 64 == 0;
+    constexpr int S2 = IC >= 64 ? IC / 64 : 1;
+    const int ny2 = ny * ny;
+    for (int m = threadIdx.x; m < C * IC; m += Cf::THREADS) {
+      int cc_, j;
       if constexpr (WAVEWISE) {
         const int slot = (m >> 6);
-        cc_ = slot / S;
-        kx = (m & 63) * S + slot % S;
+        cc_ = slot / S2;
+        j = (m & 63) * S2 + slot % S2;
       } else {
-        cc_ = m / N;
-        kx = m % N;
+        cc_ = m / IC;
+        j = m % IC;
       }
       const int nz = col0 + cc_;
       if (nz == 0) continue;
-      const int nx = signed_index(kx, N);
-      const T pw = pws[pidx(cc_, kx)];
-      const int n2 = nx * nx + ny * ny + nz * nz;
-      const int nl = los == 0 ? nx : (los == 1 ? ny : nz);
-      accumulate<T>(sb, b, n2, nl * nl, T(2) * pw);
+      const int nyz2 = ny2 + nz * nz;
+      const int nl2_yz = los == 1 ? ny2 : nz * nz;
+      if (j == 0) {
+        constexpr int H = N / 2;
+        accumulate<T>(sb, b, nyz2, los == 0 ? 0 : nl2_yz, T(2) * pws[pidx(cc_, 0)]);
+        accumulate<T>(sb, b, H * H + nyz2, los == 0 ? H * H : nl2_yz, T(2) * pws[pidx(cc_, H)]);
+      } else {
+        const T pw = pws[pidx(cc_, j)] + pws[pidx(cc_, N - j)];
+        accumulate<T>(sb, b, j * j + nyz2, los == 0 ? j * j : nl2_yz, T(2) * pw);
+      }
     }
     __syncthreads();  // the staged power is read before the next tile's FFT reuses the LDS
   }
