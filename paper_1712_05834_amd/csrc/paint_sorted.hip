@@ -353,12 +353,23 @@ __global__ void __launch_bounds__(1024)
 // line of the r2c.
 constexpr int kPaintLdsBudgetKB = 76;  // two workgroups per CU
 
-template <typename T, int N, int P, bool INTER>
+// Meshes a paint launch produces: kPaintA the plain mesh, kPaintB the mesh
+// shifted by half a cell (interlacing), kPaintAB both in one pass.
+constexpr int kPaintA = 0, kPaintB = 1, kPaintAB = 2;
+// Interlaced CIC meshes are painted by two single-mesh launches: the
+// single-mesh tiles are twice as wide and the plain mesh needs a halo of one
+// column instead of two, so each particle is gathered by fewer workgroups
+// (Zel'dovich 1024^3: 5.19 -> 5.00 ms).  For TSC and PCS the halos of the two
+// meshes differ little and one two-mesh launch is faster (log-normal 512^3
+// TSC: 0.843 against 0.858 ms).
+constexpr bool split_interlaced(int order) { return order == 2; }
+
+template <typename T, int N, int P, int MODE>
 struct PaintCfg {
   using Acc = double;
   static constexpr int M = N / 2;
   static constexpr int LP = lds_pad_len<M>();           // complex per FFT line
-  static constexpr int NM = INTER ? 2 : 1;
+  static constexpr int NM = MODE == kPaintAB ? 2 : 1;
   static constexpr long ACC_BYTES = (long)N * sizeof(Acc);
   static constexpr long FFT_BYTES = (long)LP * 2 * sizeof(T);
   // row stride: the row rounded to 16 bytes plus 16 bytes, so that
@@ -399,9 +410,14 @@ struct PaintCfg {
   static constexpr int FE = FE0 > E ? FE0 : E;
   static constexpr int FTPL = M / FE;
   static constexpr int FTHREADS = ROWS * FTPL;
-  // source columns that can reach an owned column: [X - HLO, X + HHI]
-  static constexpr int HLO = P == 2 ? (INTER ? 2 : 1) : (P == 3 ? 2 : (INTER ? 3 : 2));
-  static constexpr int HHI = P == 2 ? 0 : 1;
+  // source columns that can reach an owned column: [X - HLO, X + HHI].  A
+  // particle in column i touches cells i .. i+1 (CIC), i-1 .. i+2 (TSC, PCS)
+  // of the plain mesh and i .. i+2 (CIC, TSC), i-1 .. i+3 (PCS) of the
+  // shifted one.
+  static constexpr int HLO_A = P == 2 ? 1 : 2, HHI_A = P == 2 ? 0 : 1;
+  static constexpr int HLO_B = P == 4 ? 3 : 2, HHI_B = P == 4 ? 1 : 0;
+  static constexpr int HLO = MODE == kPaintA ? HLO_A : (MODE == kPaintB ? HLO_B : (HLO_A > HLO_B ? HLO_A : HLO_B));
+  static constexpr int HHI = MODE == kPaintA ? HHI_A : (MODE == kPaintB ? HHI_B : (HHI_A > HHI_B ? HHI_A : HHI_B));
 };
 
 // LDS word of cell z within an accumulator row: within each block of 32
@@ -421,13 +437,13 @@ __device__ __forceinline__ int acc_word(int z) {
   return (z & ~31) | ((z + rot) & 31);
 }
 
-template <typename T, int N, int P, bool INTER>
-__global__ void __launch_bounds__((PaintCfg<T, N, P, INTER>::THREADS))
+template <typename T, int N, int P, int MODE>
+__global__ void __launch_bounds__((PaintCfg<T, N, P, MODE>::THREADS))
     k_paint_z(const typename Rec<T>::type* __restrict__ rec, const T* __restrict__ wrec,
               const int* __restrict__ offsets, const double* __restrict__ wsums,
               const cpx<T>* __restrict__ tw,
               T* __restrict__ mesh_a, T* __restrict__ mesh_b) {
-  using Cf = PaintCfg<T, N, P, INTER>;
+  using Cf = PaintCfg<T, N, P, MODE>;
   using Acc = double;
   constexpr int M = Cf::M, TX = Cf::TX, TY = Cf::TY;
   constexpr int ROWS = Cf::ROWS, ROWA = Cf::ROWA;
@@ -549,7 +565,7 @@ __global__ void __launch_bounds__((PaintCfg<T, N, P, INTER>::THREADS))
       const T t3[3] = {r.x, r.y, r.z};
       const int i3[3] = {ix, iy, iz};
 #pragma unroll
-      for (int mesh = 0; mesh < (INTER ? 2 : 1); ++mesh) {
+      for (int mesh = 0; mesh < Cf::NM; ++mesh) {
         int first[3];
         T w[3][P];
 #pragma unroll
@@ -557,7 +573,7 @@ __global__ void __launch_bounds__((PaintCfg<T, N, P, INTER>::THREADS))
           // window of u = i + t (+ 1/2 for the interlaced mesh)
           T tt = t3[d];
           int base = i3[d];
-          if (mesh == 1) {
+          if (MODE == kPaintB || (MODE == kPaintAB && mesh == 1)) {
             if (tt >= T(0.5)) {
               tt -= T(0.5);  // exact
               base += 1;
@@ -709,13 +725,13 @@ hipError_t launch_bucket(int dtype, int nmesh, double boxsize, const void* pos, 
   return hipGetLastError();
 }
 
-template <typename T, int N, int P, bool INTER>
+template <typename T, int N, int P, int MODE>
 static hipError_t paint_z_t(const void* rec, const void* wrec, const int* offsets,
                             const double* wsums, const void* tw,
                             void* mesh_a, void* mesh_b, hipStream_t s) {
-  using Cf = PaintCfg<T, N, P, INTER>;
+  using Cf = PaintCfg<T, N, P, MODE>;
   const unsigned blocks = (unsigned)((N / Cf::TX) * (N / Cf::TY));
-  hipLaunchKernelGGL((k_paint_z<T, N, P, INTER>), dim3(blocks), dim3(Cf::THREADS), 0, s,
+  hipLaunchKernelGGL((k_paint_z<T, N, P, MODE>), dim3(blocks), dim3(Cf::THREADS), 0, s,
                      static_cast<const typename Rec<T>::type*>(rec),
                      static_cast<const T*>(wrec), offsets, wsums,
                      static_cast<const cpx<T>*>(tw), static_cast<T*>(mesh_a),
@@ -727,16 +743,15 @@ template <typename T, int N>
 static hipError_t paint_z_n(int order, bool inter, const void* rec, const void* wrec,
                             const int* offsets, const double* wsums, const void* tw,
                             void* mesh_a, void* mesh_b, hipStream_t s) {
-#define PK_PZ(P, I) return paint_z_t<T, N, P, I>(rec, wrec, offsets, wsums, tw, mesh_a, mesh_b, s)
-  if (inter) {
-    if (order == 2) PK_PZ(2, true);
-    if (order == 3) PK_PZ(3, true);
-    PK_PZ(4, true);
-  } else {
-    if (order == 2) PK_PZ(2, false);
-    if (order == 3) PK_PZ(3, false);
-    PK_PZ(4, false);
-  }
+#define PK_PZ(P, MODE, A) paint_z_t<T, N, P, MODE>(rec, wrec, offsets, wsums, tw, A, mesh_b, s)
+#define PK_PZ_ORDER(MODE, A)                                            \
+  (order == 2 ? PK_PZ(2, MODE, A) : (order == 3 ? PK_PZ(3, MODE, A) : PK_PZ(4, MODE, A)))
+  if (!inter) return PK_PZ_ORDER(kPaintA, mesh_a);
+  if (!split_interlaced(order)) return PK_PZ_ORDER(kPaintAB, mesh_a);
+  hipError_t e = PK_PZ_ORDER(kPaintA, mesh_a);
+  if (e != hipSuccess) return e;
+  return PK_PZ_ORDER(kPaintB, mesh_b);
+#undef PK_PZ_ORDER
 #undef PK_PZ
 }
 
