@@ -175,7 +175,7 @@ def main():
     ap.add_argument("--lanes", type=int, default=BATCH["lanes"],
                     help="concurrent lanes of the batch-mocks workload")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample", type=float, default=0.25,
+    ap.add_argument("--cpu-sample", type=float, default=0.5,
                     help="fraction of the catalog the oracle paints for cpu_baseline")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (3 times) and exit: the "
