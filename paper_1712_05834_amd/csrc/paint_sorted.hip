@@ -453,7 +453,6 @@ __global__ void __launch_bounds__((PaintCfg<T, N, P, MODE>::THREADS))
   __shared__ cpx<T> tws[stage_table_size<M, Cf::FE>() + 1];
   __shared__ int seg_start[2 * (TX + 4)], seg_cum[2 * (TX + 4) + 1], seg_row[2 * (TX + 4)];
   static_assert(TX + 4 >= (TX + Cf::HLO + Cf::HHI < N ? TX + Cf::HLO + Cf::HHI : N), "segments");
-  __shared__ int nseg_sh;
 
   const int tiles_y = N / TY;
   const int X0 = (blockIdx.x / tiles_y) * TX, Y0 = (blockIdx.x % tiles_y) * TY;
@@ -463,7 +462,7 @@ __global__ void __launch_bounds__((PaintCfg<T, N, P, MODE>::THREADS))
   // z-FFT needs them) after the gather, so their latency is hidden.
   // segments of the sorted records: for each source row bx, the contiguous
   // column range [by0, by0 + wy) (split in two where it wraps around N); one
-  // thread per source row reads its offsets, thread 0 forms the prefix sums
+  // thread per source row reads its offsets; their prefix sums follow below
   constexpr int HW = Cf::HLO + Cf::HHI;
   constexpr int WX = (TX + HW) >= N ? N : TX + HW;
   constexpr int WY = (TY + HW) >= N ? N : TY + HW;
@@ -495,24 +494,27 @@ __global__ void __launch_bounds__((PaintCfg<T, N, P, MODE>::THREADS))
   }
 
   for (int i = threadIdx.x; i < ROWS * ROWA; i += blockDim.x) acc[i] = 0;
-  if (seg_thread) {
-    seg_start[2 * threadIdx.x] = o0;
-    seg_cum[2 * threadIdx.x] = o1 - o0;
-    seg_row[2 * threadIdx.x] = bx;
-    seg_start[2 * threadIdx.x + 1] = o2;
-    seg_cum[2 * threadIdx.x + 1] = o3 - o2;
-    seg_row[2 * threadIdx.x + 1] = bx;
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    int cum = 0;
-    for (int i = 0; i < 2 * WX; ++i) {
-      const int len = seg_cum[i];
-      seg_cum[i] = cum;
-      cum += len;
+  // prefix sums of the segment lengths: a scan across the first wavefront
+  // (the segment threads are its first WX lanes; the other lanes add 0)
+  static_assert(WX <= 64, "segment threads within one wavefront");
+  if (threadIdx.x < 64) {
+    const int l0 = o1 - o0, l1 = o3 - o2;
+    int inc = l0 + l1;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+      const int v = __shfl_up(inc, off, 64);
+      if ((int)threadIdx.x >= off) inc += v;
     }
-    seg_cum[2 * WX] = cum;
-    nseg_sh = 2 * WX;
+    const int exc = inc - l0 - l1;
+    if (seg_thread) {
+      seg_start[2 * threadIdx.x] = o0;
+      seg_cum[2 * threadIdx.x] = exc;
+      seg_row[2 * threadIdx.x] = bx;
+      seg_start[2 * threadIdx.x + 1] = o2;
+      seg_cum[2 * threadIdx.x + 1] = exc + l0;
+      seg_row[2 * threadIdx.x + 1] = bx;
+      if ((int)threadIdx.x == WX - 1) seg_cum[2 * WX] = inc;
+    }
   }
   __syncthreads();
 
@@ -520,7 +522,7 @@ __global__ void __launch_bounds__((PaintCfg<T, N, P, MODE>::THREADS))
   // consecutive records, which mostly come from one source column, so the
   // window cells that fall outside the block are outside for the whole wave
   // and their branches are skipped.
-  const int nseg = nseg_sh;
+  constexpr int nseg = 2 * WX;
   const int total = seg_cum[nseg];
   // record index of work item q (-1 past the end); `seg` holds a segment at
   // or before q's (items only move forward) and returns q's segment.  The
@@ -533,9 +535,19 @@ __global__ void __launch_bounds__((PaintCfg<T, N, P, MODE>::THREADS))
     seg = s;
     return seg_start[s] + (q - seg_cum[s]);
   };
+  // the first item's segment: the number of segment starts at or below q,
+  // from independent (broadcast) LDS reads instead of a dependent walk
+  auto locate_first = [&](int q, int& seg) -> int {
+    if (q >= total) return -1;
+    int s = 0;
+#pragma unroll
+    for (int j = 1; j < nseg; ++j) s += seg_cum[j] <= q ? 1 : 0;
+    seg = s;
+    return seg_start[s] + (q - seg_cum[s]);
+  };
   using RecT = typename Rec<T>::type;
   int seg_cur = 0;
-  int idx_cur = locate(threadIdx.x, seg_cur);
+  int idx_cur = locate_first(threadIdx.x, seg_cur);
   RecT r_cur{};
   T w_cur = T(1);
   if (idx_cur >= 0) {
