@@ -113,3 +113,44 @@ def test_survey_multipoles_single_pole_and_observer_inside(ctx):
                                   1.0, 2.0, 7)
     compare(got, want, dtype, (2,))
     assert np.all(np.isfinite(got["poles"][2][got["modes"] > 0]))
+
+
+@pytest.mark.parametrize("dtype", ["f8", "f4"])
+def test_distant_observer_equals_fftpower_multipoles_256(ctx, dtype):
+    # a property that holds at any size: with the observer 10^7 box lengths
+    # away along -z, every r^ is z^ to 1e-7, F_ell -> L_ell(mu) F_0 mode by
+    # mode, and the raw sums of Re F_0 conj F_ell equal the FFTPower sums of
+    # |c|^2 L_ell(mu) along z for the same field (data - alpha randoms painted
+    # as weights), through independent kernels (fused x-pass against
+    # Y_lm paintings and column FFTs)
+    n, box = 256, 1000.0
+    data = synth.lognormal_catalog(n, box, synth.pk_lognormal_c2, 0.05, seed=41,
+                                   dtype=NDT[dtype])
+    rand = synth.uniform_catalog(2 * len(data), box, seed=42, dtype=NDT[dtype])
+    obs = np.array([0.5 * box, 0.5 * box, -1e7 * box])
+    m = _lib.mesh_desc(n, box, "tsc", False, True, dtype)
+    b = _lib.bin_desc(n // 2, 0.0, 1.0, poles=(0, 2, 4))
+    ws = torch.empty(_lib.convolved_workspace_bytes(m, b, len(data), len(rand)),
+                     dtype=torch.uint8, device="cuda:0")
+    res = torch.empty(_lib.convolved_doubles(b), dtype=torch.float64, device="cuda:0")
+    ctx.pk_convolved_power(m, b, obs, dev(data), None, len(data), dev(rand), None, len(rand),
+                           ws, res)
+    alpha = len(data) / len(rand)
+    pos = np.concatenate([data, rand])
+    w = np.concatenate([np.ones(len(data)), np.full(len(rand), -alpha)]).astype(NDT[dtype])
+    wsf = torch.empty(_lib.workspace_bytes(m, b, len(pos)), dtype=torch.uint8, device="cuda:0")
+    resf = torch.empty(_lib.result_doubles(b), dtype=torch.float64, device="cuda:0")
+    ctx.pk_fftpower(m, b, dev(pos), dev(w), len(pos), wsf, resf)
+    torch.cuda.synchronize()
+    nk = b.nk
+    conv = res.cpu().numpy()[:3 * nk].reshape(3, nk)
+    fft = resf.cpu().numpy()[nk:4 * nk].reshape(3, nk)
+    scale = np.abs(fft[0])
+    ok = scale > 0  # bin 0 holds only the DC mode, which is never binned
+    tol = {"f8": 1e-7, "f4": 1e-5}[dtype]
+    for i, ell in enumerate((0, 2, 4)):
+        err = np.abs(conv[i][ok] - fft[i][ok]) / scale[ok]
+        print(f"ell={ell} max rel err {err.max():.3e}")
+        assert err.max() < tol, (ell, err.max())
+    sums = res.cpu().numpy()[3 * nk:]
+    assert sums[0] == pytest.approx(len(data)) and sums[2] == pytest.approx(len(rand))
