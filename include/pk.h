@@ -228,7 +228,9 @@ pk_status pk_projected_to_host(pk_ctx *ctx, const pk_mesh_desc *m, const pk_bin_
                                int keep, const double *result_dev, pk_result *out);
 
 /* The whole FFTPower hot path for one catalog: paint (both meshes if
- * interlaced), r2c, interlace, compensate, bin.  workspace: device,
+ * interlaced), r2c, interlace, compensate, bin.  n <= 2^31 - 1 (the sorted
+ * records are indexed with 32-bit offsets; PK_EUNSUPPORTED beyond; pk_paint
+ * has no such limit).  workspace: device,
  * >= pk_workspace_bytes(m, b, n) bytes, caller-owned scratch (content on
  * entry ignored).  result_dev as in pk_bin_power, all slots overwritten
  * including sum w and sum w^2.  Nothing is allocated when the context
@@ -327,7 +329,8 @@ size_t pk_convolved_doubles(const pk_bin_desc *b);
 size_t pk_convolved_workspace_bytes(const pk_mesh_desc *m, const pk_bin_desc *b, int64_t n_data,
                                     int64_t n_rand);
 /*   observer    host, 3 doubles, box coordinates
- *   data_pos    device, n_data x 3 positions of the mesh dtype (n_data >= 1)
+ *   data_pos    device, n_data x 3 positions of the mesh dtype (n_data >= 1,
+ *               n_data + n_rand <= 2^31 - 1, else PK_EUNSUPPORTED)
  *   data_weight device, n_data weights, or NULL for unit weights
  *   rand_pos    device, n_rand x 3 positions (n_rand >= 1)
  *   rand_weight device, n_rand weights, or NULL

@@ -606,6 +606,9 @@ pk_status pk_bin_cross(pk_ctx* ctx, const pk_mesh_desc* m, const pk_bin_desc* b,
 
 namespace {
 
+// The sorted painting indexes its records with 32-bit offsets.
+constexpr int64_t kMaxSortedParticles = 2147483647;
+
 // Argument checks shared by the synchronous and the lane entry points.
 pk_status check_fftpower(pk_ctx* ctx, const pk_mesh_desc* m, const pk_bin_desc* b,
                          const void* pos, int64_t n, const void* workspace,
@@ -613,6 +616,8 @@ pk_status check_fftpower(pk_ctx* ctx, const pk_mesh_desc* m, const pk_bin_desc* 
   if (const char* why = check_mesh(m)) return fail(ctx, PK_EINVAL, why);
   if (const char* why = check_bins(b, m)) return fail(ctx, PK_EINVAL, why);
   if (n < 0) return fail(ctx, PK_EINVAL, "n must be >= 0");
+  if (n > kMaxSortedParticles)
+    return fail(ctx, PK_EUNSUPPORTED, "more than 2^31 - 1 particles (32-bit record offsets)");
   if (n > 0 && !pos) return fail(ctx, PK_EINVAL, "pos is NULL with n > 0");
   if (!workspace || !result_dev) return fail(ctx, PK_EINVAL, "workspace or result is NULL");
   const Layout l = layout_of(m, b, n);
@@ -1051,7 +1056,8 @@ pk_status pk_convolved_power(pk_ctx* ctx, const pk_mesh_desc* m, const pk_bin_de
       !std::isfinite(observer[2]))
     return fail(ctx, PK_EINVAL, "observer must be 3 finite host doubles");
   if (n_data < 1 || n_rand < 1) return fail(ctx, PK_EINVAL, "n_data and n_rand must be >= 1");
-  if (n_data + n_rand > ((int64_t)1 << 40)) return fail(ctx, PK_EINVAL, "catalog too large");
+  if (n_data > kMaxSortedParticles - n_rand)
+    return fail(ctx, PK_EUNSUPPORTED, "more than 2^31 - 1 particles (32-bit record offsets)");
   if (!data_pos || !rand_pos) return fail(ctx, PK_EINVAL, "data_pos or rand_pos is NULL");
   if (!workspace || !result_dev) return fail(ctx, PK_EINVAL, "workspace or result is NULL");
   const SurveyLayout l = survey_layout(m, b, n_data, n_rand);

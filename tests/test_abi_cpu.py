@@ -189,3 +189,22 @@ def test_survey_multipoles_validate(vctx):
     res = _lib.Result()
     assert lib.pk_convolved_to_host(h, ctypes.byref(m), ctypes.byref(b), 0.0, one,
                                     ctypes.byref(res)) == _lib.PK_EINVAL
+
+
+def test_sorted_paths_reject_more_than_int32_particles(vctx):
+    # the sorted painting indexes records with 32-bit offsets: 2^31 particles
+    # are refused before any device work (no workspace is even looked at)
+    lib, h = vctx
+    one = ctypes.c_void_p(1)
+    m = _lib.mesh_desc(32, 100.0, "cic")
+    b = _lib.bin_desc(16)
+    big = 1 << 31
+    st = lib.pk_fftpower(h, ctypes.byref(m), ctypes.byref(b), one, None, big, one, 1 << 62, one)
+    assert st == _lib.PK_EUNSUPPORTED and b"2^31" in lib.pk_last_error(h)
+    assert lib.pk_fftpower(h, ctypes.byref(m), ctypes.byref(b), one, None, big - 1, one,
+                           1 << 62, one) == _lib.PK_EDEVICE
+    bs = _lib.bin_desc(16, poles=(0,))
+    obs = (ctypes.c_double * 3)(0.0, 0.0, -100.0)
+    st = lib.pk_convolved_power(h, ctypes.byref(m), ctypes.byref(bs), obs, one, None, big // 2,
+                                one, None, big // 2, one, 1 << 62, one)
+    assert st == _lib.PK_EUNSUPPORTED
