@@ -29,7 +29,8 @@ so ``convolved`` follows its standard definition and is pinned against
 identities, not against the paper.
 """
 
-from .paint import wrap_positions, cell_coordinates, window_weights, paint_mesh, paint_cells
+from .paint import (wrap_positions, cell_coordinates, window_weights, paint_mesh, paint_cells,
+                    painted_modes)
 from .power import (
     r2c,
     mode_indices,
@@ -54,6 +55,7 @@ __all__ = [
     "window_weights",
     "paint_mesh",
     "paint_cells",
+    "painted_modes",
     "r2c",
     "mode_indices",
     "interlace_combine",

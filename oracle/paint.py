@@ -134,3 +134,33 @@ def paint_cells(pos, cells, nmesh, boxsize, order, weight=None, shift_cells=0.0)
             total = total * np.where(np.abs(a) < reach, bspline(order, a), 0.0)
         out[c] = total.sum()
     return out
+
+
+def painted_modes(pos, modes, nmesh, boxsize, order, weight=None, shift_cells=0.0):
+    """DFT of the painted mesh, c(n) = sum_j F_j exp(-2 pi i n.j / N), at the
+    listed integer modes only, without forming the mesh.
+
+    F_j is a sum over particles of a product of one window per axis, so each
+    particle contributes prod_d sum_{cells j_d} M_p(u_d - j_d)
+    exp(-2 pi i n_d j_d / N): a few terms per axis and particle.  The
+    exponential is periodic in j_d, so the cells need no wrapping.  Used to
+    check modes of meshes too large to transform on the host.  Returns a
+    complex128 array, one value per row of ``modes``.
+    """
+    pos = np.asarray(pos, dtype=np.float64).reshape(-1, 3)
+    modes = np.asarray(modes, dtype=np.int64).reshape(-1, 3)
+    u = cell_coordinates(pos, nmesh, boxsize) + shift_cells
+    w = np.ones(len(pos)) if weight is None else np.asarray(weight, dtype=np.float64)
+    # per axis, the factor of every particle for every distinct n_d needed
+    factors = []
+    for d in range(3):
+        cells, wts = window_weights(u[:, d], order)
+        table = {}
+        for nd in np.unique(modes[:, d]):
+            phase = np.exp(-2j * np.pi * nd * cells / nmesh)
+            table[int(nd)] = np.sum(wts * phase, axis=1)
+        factors.append(table)
+    out = np.empty(len(modes), dtype=np.complex128)
+    for i, (nx, ny, nz) in enumerate(modes):
+        out[i] = np.sum(w * factors[0][int(nx)] * factors[1][int(ny)] * factors[2][int(nz)])
+    return out
