@@ -8,6 +8,10 @@
   on the exact mode counts and mean |k| of all 512 bins, and on properties
   that hold at any size (mass conservation, Parseval of the r2c, finite
   results of the fused path).
+* The largest mesh, 2048^3 CIC interlaced float32 (96 GiB of workspace): the
+  fused path's lowest k-bins, P_0 and P_2 over 1 <= |n|^2 < 9, against the
+  float64 oracle's modes computed one by one by direct summation over the
+  particles (no mesh), with interlacing and compensation applied per mode.
 """
 
 import math
@@ -107,3 +111,44 @@ def test_zeldovich_1024_cic_interlaced_sampled(ctx):
     p = c[..., 0] ** 2 + c[..., 1] ** 2
     lhs = float(p[:, :, 0].sum()) + 2.0 * float(p[:, :, 1:].sum())
     assert abs(lhs / (n ** 3 * f2) - 1) < 1e-5, lhs / (n ** 3 * f2)
+
+
+@pytest.mark.timeout(900)
+def test_max_mesh_2048_cic_interlaced_low_k_bins(ctx):
+    n, box, ngrid = 2048, 2000.0, 192
+    m = _lib.mesh_desc(n, box, "cic", True, True, "f4")
+    b = _lib.bin_desc(16, 0.0, 1.0, 0, (0, 2), 2)
+    pos = synth.zeldovich_lattice(ngrid, box, synth.pk_zeldovich_c3, seed=7)
+    need = _lib.workspace_bytes(m, b, len(pos))
+    free, _ = torch.cuda.mem_get_info()
+    if free < need + (4 << 30):
+        pytest.skip(f"needs {need / 2**30:.0f} GiB of free device memory")
+    print(f"\n2048^3: {len(pos)} particles, workspace {need / 2**30:.1f} GiB", flush=True)
+    got = _fftpower(ctx, m, b, dev(pos))
+    torch.cuda.empty_cache()
+    # modes of bins 1 and 2: half of the full grid (the other half are the
+    # complex conjugates, of equal power), then every mode counted twice
+    r = np.arange(-2, 3)
+    g = np.stack(np.meshgrid(r, r, r, indexing="ij"), axis=-1).reshape(-1, 3)
+    n2 = (g ** 2).sum(axis=1)
+    half = (g[:, 2] > 0) | ((g[:, 2] == 0) & (g[:, 1] > 0)) | \
+        ((g[:, 2] == 0) & (g[:, 1] == 0) & (g[:, 0] > 0))
+    modes = g[(n2 >= 1) & (n2 < 9) & half]
+    p64 = pos.astype(np.float64)
+    ca = oracle.painted_modes(p64, modes, n, box, 2, None, 0.0)
+    cb = oracle.painted_modes(p64, modes, n, box, 2, None, 0.5)
+    c = 0.5 * (ca + np.exp(1j * np.pi * modes.sum(axis=1) / n) * cb)
+    c /= np.prod(np.sinc(modes / n), axis=1) ** 2
+    pw = box ** 3 * np.abs(c) ** 2 / float(len(pos)) ** 2
+    n2m = (modes ** 2).sum(axis=1)
+    mu2 = modes[:, 2] ** 2 / n2m
+    kb = np.floor(np.sqrt(n2m)).astype(int)
+    for k in (1, 2):
+        sel = kb == k
+        assert got["modes"][k] == 2 * sel.sum()
+        p0 = pw[sel].mean()
+        p2 = 5.0 * (pw[sel] * 0.5 * (3 * mu2[sel] - 1)).mean()
+        print(f"bin {k}: P0 {got['power'][k]:.6e} oracle {p0:.6e}; "
+              f"P2 {got['poles'][2][k]:.6e} oracle {p2:.6e}", flush=True)
+        assert abs(got["power"][k] / p0 - 1) < 1e-5
+        assert abs(got["poles"][2][k] - p2) < 1e-5 * abs(p0)
