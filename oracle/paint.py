@@ -151,14 +151,22 @@ def painted_modes(pos, modes, nmesh, boxsize, order, weight=None, shift_cells=0.
     modes = np.asarray(modes, dtype=np.int64).reshape(-1, 3)
     u = cell_coordinates(pos, nmesh, boxsize) + shift_cells
     w = np.ones(len(pos)) if weight is None else np.asarray(weight, dtype=np.float64)
-    # per axis, the factor of every particle for every distinct n_d needed
+    # per axis, the factor of every particle for every distinct n_d needed;
+    # exp(-2 pi i n_d j / N) is the |n_d|-th power of the n_d = 1 phase
+    # (conjugated for n_d < 0)
     factors = []
     for d in range(3):
         cells, wts = window_weights(u[:, d], order)
+        base = np.exp(-2j * np.pi * cells / nmesh)
         table = {}
         for nd in np.unique(modes[:, d]):
-            phase = np.exp(-2j * np.pi * nd * cells / nmesh)
-            table[int(nd)] = np.sum(wts * phase, axis=1)
+            nd = int(nd)
+            phase = np.ones_like(base)
+            for _ in range(abs(nd)):
+                phase = phase * base
+            if nd < 0:
+                phase = np.conj(phase)
+            table[nd] = np.sum(wts * phase, axis=1)
         factors.append(table)
     out = np.empty(len(modes), dtype=np.complex128)
     for i, (nx, ny, nz) in enumerate(modes):
