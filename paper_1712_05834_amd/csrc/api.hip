@@ -974,7 +974,7 @@ int survey_fields(const pk_bin_desc* b, int* ells) {
 
 struct SurveyLayout {
   size_t pos = 0, value = 0, sums = 0, zero = 0, bsums = 0, sumpart = 0, bucket = 0, rec = 0,
-         wbase = 0, mesh = 0, fields = 0, bpart = 0, total = 0;
+         wbase = 0, mesh = 0, side = 0, fields = 0, bpart = 0, total = 0;
   size_t field_bytes = 0;
   int gb = 0, gp = 0;
 };
@@ -1008,6 +1008,7 @@ SurveyLayout survey_layout(const pk_mesh_desc* m, const pk_bin_desc* b, int64_t 
   l.rec = take(np * 4 * es);
   l.wbase = take(np * es);
   l.mesh = take(l.field_bytes);
+  l.side = take(n * n * 2 * es);
   l.fields = take((size_t)nf * l.field_bytes);
   l.bpart = take((size_t)(l.gb + l.gp) * b->nk * sizeof(double));
   l.total = off;
@@ -1117,10 +1118,9 @@ pk_status pk_convolved_power(pk_ctx* ctx, const pk_mesh_desc* m, const pk_bin_de
       if (e == hipSuccess)
         e = launch_fft_cols(m->dtype, m->nmesh, mesh, 1, l.field_bytes, t->tw, 1, s);
       if (e == hipSuccess)
-        e = launch_fft_cols(m->dtype, m->nmesh, mesh, 1, l.field_bytes, t->tw, 0, s);
-      if (e == hipSuccess)
-        e = launch_ylm_accumulate(m->dtype, m->nmesh, mesh, field(f), h, 4.0 * pi / (2 * ell + 1),
-                                  *t, m->window, m->compensated, mm == -ell ? 1 : 0, s);
+        e = launch_x_accumulate(m->dtype, m->nmesh, mesh, field(f), ws + l.side, h,
+                                4.0 * pi / (2 * ell + 1), *t, m->window, m->compensated,
+                                mm == -ell ? 1 : 0, s);
     }
   }
   // sums of Re F_0 conj F_ell per k bin, then the weight sums

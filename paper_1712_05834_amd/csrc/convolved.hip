@@ -16,11 +16,11 @@
 // same routine serves the positions (r^) and the wave vectors (k^).  The
 // catalog (data and randoms in one) is bucketed by column once, with the
 // amounts w s; every harmonic then rescales the sorted amounts by Y_lm(r^)
-// of the record's position, paints, transforms and accumulates.  This file
-// holds the weight sums, the amounts and the accumulation of F_ell over the
-// packed half spectrum; bucketing, painting, the FFT and the binning are the
-// kernels of the FFTPower path.
-#include "fft_core.h"
+// of the record's position, paints (with the z-pass), runs the y-pass and
+// an x-pass that adds its lines into F_ell.  This file holds the weight sums,
+// the amounts and the fused x-pass + accumulation; bucketing, painting, the
+// y-pass and the binning are the kernels of the FFTPower path.
+#include "fft_config.h"
 #include "internal.h"
 
 namespace pk {
@@ -184,53 +184,101 @@ __global__ void __launch_bounds__(256)
 
 __device__ __forceinline__ int signed_wave(int i, int n) { return i < n / 2 ? i : i - n; }
 
-// F += coef Y_lm(k^) A / W(k) over the packed half spectrum (first: F =).
-// Column kz' >= 1 holds c(kx, ky, kz'); column 0 of A packs the planes
-// kz = 0 and N/2, and its kz = 0 value (Z + conj Z(-k)) / 2 is unpacked
-// here.  F stores the kz = 0 value alone in column 0: F_ell is Hermitian on
-// that plane (A_lm is the transform of a real field and Y_lm(-k^) = Y_lm(k^)
-// for even ell), so this is the packed form of a spectrum whose kz = N/2
-// plane is zero -- those modes have |n| >= N/2 and are never binned.  At the
-// DC mode k^ is taken as z^ (the DC mode is not binned either).
+// Mode factor of the accumulation: coef Y_lm(k^) / W(k) (W the window's
+// sinc^p, or 1 without compensation) at the signed mode (nx, ny, nz); at the
+// DC mode k^ is taken as z^ (the DC mode is never binned).
 template <typename T>
-__global__ void __launch_bounds__(256)
-    k_ylm_accumulate(int N, const cpx<T>* __restrict__ a, cpx<T>* __restrict__ f, int ell, int am,
-                     int sine, double knorm, double coef, const T* __restrict__ sinv, int first) {
-  const int NC = N / 2;
-  const size_t total = (size_t)N * N * NC;
-  const int mask = N - 1;
-  for (size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
-       idx += (size_t)gridDim.x * blockDim.x) {
-    const int col = (int)(idx % NC);
-    const size_t rest = idx / NC;
-    const int ky = (int)(rest % N), kx = (int)(rest / N);
-    cpx<T> v;
-    if (col != 0) {
-      v = a[idx];
-    } else {
-      const size_t pa = ((size_t)((N - kx) & mask) * N + ((N - ky) & mask)) * NC;
-      const cpx<T> z = a[idx], zp = a[pa];
-      v = {T(0.5) * (z.x + zp.x), T(0.5) * (z.y - zp.y)};
+__device__ __forceinline__ double mode_factor(int nx, int ny, int nz, int kx, int ky, int ell,
+                                              int am, int sine, double knorm, double coef,
+                                              const T* __restrict__ sinv) {
+  const double n2 = (double)nx * nx + (double)ny * ny + (double)nz * nz;
+  double ux = 0.0, uy = 0.0, uz = 1.0;
+  if (n2 > 0.0) {
+    const double inv = 1.0 / sqrt(n2);
+    ux = nx * inv;
+    uy = ny * inv;
+    uz = nz * inv;
+  }
+  double g = coef * real_harmonic(ell, am, sine, knorm, ux, uy, uz);
+  if (sinv) g *= (double)sinv[kx] * (double)sinv[ky] * (double)sinv[nz];
+  return g;
+}
+
+// Last FFT pass (along x) of one harmonic's spectrum A_lm, fused with the
+// accumulation F_ell (+)= coef Y_lm(k^) A_lm / W(k): the transformed lines are
+// added into F instead of being written back.  Column kz' >= 1 holds
+// c(kx, ky, kz'); column 0 packs the planes kz = 0 and N/2 and needs the
+// partner mode (-kx, -ky), which another workgroup transforms, so its lines
+// go to `side` ([kx][ky]) for k_plane_accumulate.
+template <typename T, int N>
+__global__ void __launch_bounds__((ColCfg<T, N>::THREADS))
+    k_fft_x_accumulate(const cpx<T>* __restrict__ mesh, cpx<T>* __restrict__ f,
+                       cpx<T>* __restrict__ side, const cpx<T>* __restrict__ tw, int ell, int am,
+                       int sine, double knorm, double coef, const T* __restrict__ sinv,
+                       int first) {
+  using Cf = ColCfg<T, N>;
+  constexpr int E = Cf::E, TPL = Cf::TPL, C = Cf::C, NC = Cf::NC;
+  __shared__ cpx<T> lds[Cf::LDS_ELEMS];
+  __shared__ cpx<T> tws[stage_table_size<N, E>() + 1];
+  build_stage_table<T, N, E>(tws, TwGlobal<T>{tw, 1});
+  const TwStage<T, N, E> tw1{tws};
+  const int c = threadIdx.x % C, t = threadIdx.x / C;
+  const int tile = xcd_pair_tile(blockIdx.x, N * Cf::CHUNKS);
+  const int ky = tile / Cf::CHUNKS, col = (tile % Cf::CHUNKS) * C + c;
+  const size_t base = (size_t)ky * NC + col, step = (size_t)N * NC;
+  cpx<T> v[E];
+#pragma unroll
+  for (int e = 0; e < E; ++e) v[e] = mesh[base + (size_t)(t + TPL * e) * step];
+  LdsCols<T, C> lc{lds, c};
+  stockham<T, N, E, 1>(v, t, tw1, lc);
+  const int ny = signed_wave(ky, N);
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const int kx = t + TPL * e;
+    if (col == 0) {
+      side[(size_t)kx * N + ky] = v[e];
+      continue;
     }
-    const int nx = signed_wave(kx, N), ny = signed_wave(ky, N);
-    const double n2 = (double)nx * nx + (double)ny * ny + (double)col * col;
-    double ux = 0.0, uy = 0.0, uz = 1.0;
-    if (n2 > 0.0) {
-      const double inv = 1.0 / sqrt(n2);
-      ux = nx * inv;
-      uy = ny * inv;
-      uz = col * inv;
-    }
-    double g = coef * real_harmonic(ell, am, sine, knorm, ux, uy, uz);
-    if (sinv) g *= (double)sinv[kx] * (double)sinv[ky] * (double)sinv[col];
-    const T gt = static_cast<T>(g);
-    cpx<T> o = {gt * v.x, gt * v.y};
+    const T g = static_cast<T>(
+        mode_factor<T>(signed_wave(kx, N), ny, col, kx, ky, ell, am, sine, knorm, coef, sinv));
+    const size_t idx = base + (size_t)kx * step;
+    cpx<T> o = {g * v[e].x, g * v[e].y};
     if (!first) {
       const cpx<T> old = f[idx];
       o.x += old.x;
       o.y += old.y;
     }
     f[idx] = o;
+  }
+}
+
+// The packed column of the harmonic (`side`, after the x-pass): its kz = 0
+// value (Z + conj Z(-k)) / 2 is accumulated into column 0 of F.  F stores the
+// kz = 0 value alone there: F_ell is Hermitian on that plane (A_lm is the
+// transform of a real field and Y_lm(-k^) = Y_lm(k^) for even ell), so this
+// is the packed form of a spectrum whose kz = N/2 plane is zero -- those
+// modes have |n| >= N/2 and are never binned.
+template <typename T>
+__global__ void __launch_bounds__(256)
+    k_plane_accumulate(int N, const cpx<T>* __restrict__ side, cpx<T>* __restrict__ f, int ell,
+                       int am, int sine, double knorm, double coef, const T* __restrict__ sinv,
+                       int first) {
+  const int NC = N / 2, mask = N - 1;
+  for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < N * N;
+       idx += gridDim.x * blockDim.x) {
+    const int kx = idx / N, ky = idx % N;
+    const cpx<T> z = side[idx], zp = side[((N - kx) & mask) * N + ((N - ky) & mask)];
+    const cpx<T> v = {T(0.5) * (z.x + zp.x), T(0.5) * (z.y - zp.y)};
+    const T g = static_cast<T>(mode_factor<T>(signed_wave(kx, N), signed_wave(ky, N), 0, kx, ky,
+                                              ell, am, sine, knorm, coef, sinv));
+    const size_t at = (size_t)idx * NC;
+    cpx<T> o = {g * v.x, g * v.y};
+    if (!first) {
+      const cpx<T> old = f[at];
+      o.x += old.x;
+      o.y += old.y;
+    }
+    f[at] = o;
   }
 }
 
@@ -298,26 +346,47 @@ hipError_t launch_ylm_records(int dtype, int nmesh, double boxsize, const void* 
   return hipGetLastError();
 }
 
-hipError_t launch_ylm_accumulate(int dtype, int nmesh, const void* cmesh, void* field,
-                                 const Harmonic& h, double coef, const MeshTables& t, int order,
-                                 int compensated, int first, hipStream_t s) {
-  const size_t total = (size_t)nmesh * nmesh * (nmesh / 2);
-  const unsigned g = grid_for(total, 65536);
+template <typename T, int N>
+static hipError_t x_accumulate_t(const void* cmesh, void* field, void* side, const void* tw,
+                                 const Harmonic& h, double coef, const T* sinv, int first,
+                                 hipStream_t s) {
+  using Cf = ColCfg<T, N>;
+  hipLaunchKernelGGL((k_fft_x_accumulate<T, N>), dim3((unsigned)(N * Cf::CHUNKS)),
+                     dim3(Cf::THREADS), 0, s, static_cast<const cpx<T>*>(cmesh),
+                     static_cast<cpx<T>*>(field), static_cast<cpx<T>*>(side),
+                     static_cast<const cpx<T>*>(tw), h.ell, h.am, h.sine, h.knorm, coef, sinv,
+                     first);
+  hipLaunchKernelGGL(k_plane_accumulate<T>, dim3(grid_for((size_t)N * N, 4096)), dim3(256), 0,
+                     s, N, static_cast<const cpx<T>*>(side), static_cast<cpx<T>*>(field), h.ell,
+                     h.am, h.sine, h.knorm, coef, sinv, first);
+  return hipGetLastError();
+}
+
+template <typename T>
+static hipError_t x_accumulate_n(int nmesh, const void* cmesh, void* field, void* side,
+                                 const void* tw, const Harmonic& h, double coef, const T* sinv,
+                                 int first, hipStream_t s) {
+  switch (nmesh) {
+#define PK_XA(NN) \
+  case NN: return x_accumulate_t<T, NN>(cmesh, field, side, tw, h, coef, sinv, first, s);
+    PK_XA(8) PK_XA(16) PK_XA(32) PK_XA(64) PK_XA(128) PK_XA(256) PK_XA(512) PK_XA(1024)
+    PK_XA(2048)
+#undef PK_XA
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_x_accumulate(int dtype, int nmesh, const void* cmesh, void* field, void* side,
+                               const Harmonic& h, double coef, const MeshTables& t, int order,
+                               int compensated, int first, hipStream_t s) {
   if (dtype == PK_F32) {
     const float* sinv =
         compensated ? static_cast<const float*>(t.sinc_inv) + (size_t)(order - 2) * nmesh : nullptr;
-    hipLaunchKernelGGL(k_ylm_accumulate<float>, dim3(g), dim3(256), 0, s, nmesh,
-                       static_cast<const cpx<float>*>(cmesh), static_cast<cpx<float>*>(field),
-                       h.ell, h.am, h.sine, h.knorm, coef, sinv, first);
-  } else {
-    const double* sinv = compensated
-                             ? static_cast<const double*>(t.sinc_inv) + (size_t)(order - 2) * nmesh
-                             : nullptr;
-    hipLaunchKernelGGL(k_ylm_accumulate<double>, dim3(g), dim3(256), 0, s, nmesh,
-                       static_cast<const cpx<double>*>(cmesh), static_cast<cpx<double>*>(field),
-                       h.ell, h.am, h.sine, h.knorm, coef, sinv, first);
+    return x_accumulate_n<float>(nmesh, cmesh, field, side, t.tw, h, coef, sinv, first, s);
   }
-  return hipGetLastError();
+  const double* sinv =
+      compensated ? static_cast<const double*>(t.sinc_inv) + (size_t)(order - 2) * nmesh : nullptr;
+  return x_accumulate_n<double>(nmesh, cmesh, field, side, t.tw, h, coef, sinv, first, s);
 }
 
 }  // namespace pk

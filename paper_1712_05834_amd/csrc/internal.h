@@ -144,10 +144,11 @@ hipError_t launch_ylm_value(int dtype, const void* pos, const void* wd, int64_t 
 hipError_t launch_ylm_records(int dtype, int nmesh, double boxsize, const void* rec,
                               const void* base, const void* bucket_ws, const double* observer,
                               const Harmonic& hm, void* amount, hipStream_t s);
-// field (+)= coef Y_lm(k^) cmesh / W(k) on packed spectra (see the kernel).
-hipError_t launch_ylm_accumulate(int dtype, int nmesh, const void* cmesh, void* field,
-                                 const Harmonic& h, double coef, const MeshTables& t, int order,
-                                 int compensated, int first, hipStream_t s);
+// x-pass of a y-transformed packed spectrum fused with field (+)= coef
+// Y_lm(k^) A / W(k); side: N^2 complex scratch for the packed column.
+hipError_t launch_x_accumulate(int dtype, int nmesh, const void* cmesh, void* field, void* side,
+                               const Harmonic& h, double coef, const MeshTables& t, int order,
+                               int compensated, int first, hipStream_t s);
 
 }  // namespace pk
 

@@ -4,8 +4,9 @@
   and ell = 0, 2, 4: the whole FFTPower result against the float64 oracle.
 * Zel'dovich lattice of 512^3 particles on a 1024^3 CIC interlaced float32
   mesh: too large for the oracle's full run inside a test, so it is checked
-  on samples the oracle computes one by one (painted cells of both meshes),
-  on the exact mode counts and mean |k| of all 512 bins, and on properties
+  on samples the oracle computes one by one (painted cells of both meshes,
+  and the modes of the lowest k-bin summed directly over the particles), on
+  the exact mode counts and mean |k| of all 512 bins, and on properties
   that hold at any size (mass conservation, Parseval of the r2c, finite
   results of the fused path).
 * The largest mesh, 2048^3 CIC interlaced float32 (96 GiB of workspace): the
@@ -14,7 +15,9 @@
   particles (no mesh), with interlacing and compensation applied per mode.
 """
 
+import concurrent.futures
 import math
+import os
 
 import numpy as np
 import pytest
@@ -82,6 +85,7 @@ def test_zeldovich_1024_cic_interlaced_sampled(ctx):
     np.testing.assert_array_equal(got["modes"], tab["modes"])
     np.testing.assert_allclose(got["k"][1:], tab["k"][1:], rtol=1e-12)
     print("counts ok", flush=True)
+    _check_low_k(got, pos, n, box, 2, kbins=(1,))
 
     rng = np.random.default_rng(0)
     u = oracle.cell_coordinates(pos.astype(np.float64), n, box)
@@ -126,24 +130,40 @@ def test_max_mesh_2048_cic_interlaced_low_k_bins(ctx):
     print(f"\n2048^3: {len(pos)} particles, workspace {need / 2**30:.1f} GiB", flush=True)
     got = _fftpower(ctx, m, b, dev(pos))
     torch.cuda.empty_cache()
-    # modes of bins 1 and 2: half of the full grid (the other half are the
-    # complex conjugates, of equal power), then every mode counted twice
-    r = np.arange(-2, 3)
+    _check_low_k(got, pos, n, box, 2, kbins=(1, 2))
+
+
+def _check_low_k(got, pos, n, box, order, kbins):
+    """P_0 and P_2 of the lowest whole-number k-bins (unit weights, interlaced,
+    compensated, line of sight z) against the oracle's modes summed directly
+    over the particles, in chunks.  Half of the grid is summed (the other half
+    are the complex conjugates, of equal power) and every mode counted twice."""
+    top = max(kbins) + 1
+    r = np.arange(-top, top + 1)
     g = np.stack(np.meshgrid(r, r, r, indexing="ij"), axis=-1).reshape(-1, 3)
     n2 = (g ** 2).sum(axis=1)
     half = (g[:, 2] > 0) | ((g[:, 2] == 0) & (g[:, 1] > 0)) | \
         ((g[:, 2] == 0) & (g[:, 1] == 0) & (g[:, 0] > 0))
-    modes = g[(n2 >= 1) & (n2 < 9) & half]
-    p64 = pos.astype(np.float64)
-    ca = oracle.painted_modes(p64, modes, n, box, 2, None, 0.0)
-    cb = oracle.painted_modes(p64, modes, n, box, 2, None, 0.5)
+    modes = g[(n2 >= min(kbins) ** 2) & (n2 < top ** 2) & half]
+    # chunks of 4M particles on a thread pool (NumPy releases the GIL), the
+    # partial sums added in chunk order
+    def part(i0, shift):
+        p64 = pos[i0:i0 + (1 << 22)].astype(np.float64)
+        return oracle.painted_modes(p64, modes, n, box, order, None, shift)
+
+    starts = range(0, len(pos), 1 << 22)
+    with concurrent.futures.ThreadPoolExecutor(min(16, os.cpu_count() or 1)) as ex:
+        fa = [ex.submit(part, i0, 0.0) for i0 in starts]
+        fb = [ex.submit(part, i0, 0.5) for i0 in starts]
+        ca = sum(f.result() for f in fa)
+        cb = sum(f.result() for f in fb)
     c = 0.5 * (ca + np.exp(1j * np.pi * modes.sum(axis=1) / n) * cb)
-    c /= np.prod(np.sinc(modes / n), axis=1) ** 2
+    c /= np.prod(np.sinc(modes / n), axis=1) ** order
     pw = box ** 3 * np.abs(c) ** 2 / float(len(pos)) ** 2
     n2m = (modes ** 2).sum(axis=1)
     mu2 = modes[:, 2] ** 2 / n2m
     kb = np.floor(np.sqrt(n2m)).astype(int)
-    for k in (1, 2):
+    for k in kbins:
         sel = kb == k
         assert got["modes"][k] == 2 * sel.sum()
         p0 = pw[sel].mean()
