@@ -104,10 +104,10 @@ __global__ void __launch_bounds__((ColCfg<T, N>::THREADS))
 // a workgroup writes is contiguous; the sibling tile (next chunk, same
 // x-plane, same XCD) writes the other half of its 128-byte lines.
 template <typename T, int N>
-__global__ void __launch_bounds__((ColCfg<T, N>::THREADS))
+__global__ void __launch_bounds__((YCfg<T, N>::THREADS))
     k_fft_y_relayout(const T* __restrict__ src0, cpx<T>* __restrict__ dst,
                      const cpx<T>* __restrict__ tw) {
-  using Cf = ColCfg<T, N>;
+  using Cf = YCfg<T, N>;
   using YL = YLayout<T, N>;
   using Ix = typename YL::Ix;
   constexpr int E = Cf::E, TPL = Cf::TPL, C = Cf::C, NC = Cf::NC;
@@ -143,7 +143,7 @@ __global__ void __launch_bounds__((ColCfg<T, N>::THREADS))
 
 template <typename T, int N>
 static hipError_t fft_y_relayout_t(const void* src, void* dst, const void* tw, hipStream_t s) {
-  using Cf = ColCfg<T, N>;
+  using Cf = YCfg<T, N>;
   const unsigned blocks = (unsigned)(N * Cf::CHUNKS);
   hipLaunchKernelGGL((k_fft_y_relayout<T, N>), dim3(blocks), dim3(Cf::THREADS), 0, s,
                      static_cast<const T*>(src), static_cast<cpx<T>*>(dst),

@@ -69,6 +69,13 @@ __device__ __forceinline__ int xcd_group_tile(int g, int ntiles) {
   return blk * 8 * G + (off % 8) * G + off / 8;
 }
 
+// Launch shape of the y-pass of the power-spectrum path (k_fft_y_relayout):
+// 8 points per thread, 1024 threads for N = 1024 (16 points: 512 threads)
+// -- more waves in flight for this HBM-bound pass (1-2% faster; 4 points per
+// thread was 60% slower at 1024^3).
+template <typename T, int N>
+using YCfg = ColCfg<T, N, 8>;
+
 // Launch shape of the fused x-pass + binning kernel.
 // (Line buffers capped at 40 KB -- 4 columns per tile at N = 1024, two
 // workgroups per CU -- made the x-pass 9% faster, but the y-pass writes of
