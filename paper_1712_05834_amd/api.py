@@ -1,4 +1,5 @@
-"""Paper-vocabulary front end: ``to_mesh`` and ``FFTPower`` (Sec. 3.3.2, 3.4.1).
+"""Paper-vocabulary front end: ``to_mesh``, ``FFTPower`` and
+``ConvolvedFFTPower`` (Sec. 3.3.2, 3.4.1).
 
 These wrappers only turn keyword arguments into the C descriptors of
 include/pk.h, allocate device buffers with PyTorch and call the library; the
@@ -117,4 +118,47 @@ def FFTPower(mesh, mode="1d", dk=None, kmin=0.0, kmax=None, Nmu=5, poles=(), los
     ctx.pk_fftpower(mesh.desc, b, mesh.pos, mesh.weight, mesh.pos.shape[0], workspace, result)
     out = ctx.pk_result_to_host(mesh.desc, b, result)
     out["edges"] = (2 * math.pi / mesh.BoxSize) * (b.kmin_f + b.dk_f * __import__("numpy").arange(b.nk + 1))
+    return out
+
+
+def ConvolvedFFTPower(mesh, randoms, poles=(0, 2, 4), observer=(0.0, 0.0, 0.0), norm=None,
+                      dk=None, kmin=0.0, kmax=None, randoms_weight=None, workspace=None):
+    """Survey power multipoles with a varying line of sight (Sec. 3.4.1,
+    ConvolvedFFTPower): ``mesh`` is the data CatalogMesh (window,
+    compensation, precision; interlacing is not offered here), ``randoms`` a
+    CUDA (N_r, 3) tensor of the same dtype and ``randoms_weight`` its optional
+    weights.  ``observer`` is in box coordinates.  ``norm`` is the survey
+    normalisation I of P_ell = (2 ell + 1) / I <Re F_0 F_ell*>; it depends on
+    the survey's mean density, so it must be given.  Returns k, modes,
+    poles {ell: P_ell}, shotnoise (reported, not subtracted), alpha, wsum,
+    w2sum and the k edges."""
+    import numpy as np
+    import torch
+
+    if norm is None:
+        raise ValueError("norm (the survey normalisation I) must be given")
+    if mesh.interlaced:
+        raise ValueError("the survey multipoles are not offered for interlaced meshes")
+    want = mesh.pos.dtype
+    if (randoms.dtype != want or randoms.dim() != 2 or randoms.shape[1] != 3
+            or not randoms.is_cuda):
+        raise ValueError(f"randoms must be a CUDA (N, 3) tensor of {want}")
+    if randoms_weight is not None and (randoms_weight.dtype != want
+                                       or randoms_weight.shape != (randoms.shape[0],)):
+        raise ValueError(f"randoms_weight must be a CUDA (N,) tensor of {want}")
+    b = bins_for(mesh, "1d", dk, kmin, kmax, 0, tuple(poles), (0, 0, 1))
+    randoms = randoms.contiguous()
+    nd, nr = mesh.pos.shape[0], randoms.shape[0]
+    need = _lib.convolved_workspace_bytes(mesh.desc, b, nd, nr)
+    if need == 0:
+        raise ValueError("invalid binning or catalog sizes for the survey multipoles")
+    if workspace is None or workspace.numel() * workspace.element_size() < need:
+        workspace = torch.empty(need, dtype=torch.uint8, device=mesh.pos.device)
+    result = torch.empty(_lib.convolved_doubles(b), dtype=torch.float64, device=mesh.pos.device)
+    ctx = context(mesh.device)
+    ctx.pk_convolved_power(mesh.desc, b, observer, mesh.pos, mesh.weight, nd, randoms,
+                           None if randoms_weight is None else randoms_weight.contiguous(), nr,
+                           workspace, result)
+    out = ctx.pk_convolved_to_host(mesh.desc, b, norm, result)
+    out["edges"] = (2 * math.pi / mesh.BoxSize) * (b.kmin_f + b.dk_f * np.arange(b.nk + 1))
     return out

@@ -154,3 +154,21 @@ def test_distant_observer_equals_fftpower_multipoles_256(ctx, dtype):
         assert err.max() < tol, (ell, err.max())
     sums = res.cpu().numpy()[3 * nk:]
     assert sums[0] == pytest.approx(len(data)) and sums[2] == pytest.approx(len(rand))
+
+
+def test_api_front_end_matches_the_library_call(ctx):
+    from paper_1712_05834_amd import api
+
+    n, box = 32, 400.0
+    obs, data, rand = survey(n, box, 51, "f8")
+    wd = synth.uniform_weights(len(data), seed=52)
+    mesh = api.to_mesh(dev(data), n, box, resampler="pcs", dtype="f8", weight=dev(wd))
+    kf = 2 * math.pi / box
+    r = api.ConvolvedFFTPower(mesh, dev(rand), poles=[0, 2], observer=obs, norm=0.3,
+                              dk=2 * kf, kmin=0.5 * kf)
+    want = oracle.convolved_power(data, rand, wd, None, obs, n, box, 0.3, "pcs", (0, 2), True,
+                                  0.5, 2.0, 7)
+    compare(r, want, "f8", (0, 2))
+    np.testing.assert_allclose(r["edges"], kf * (0.5 + 2.0 * np.arange(8)), rtol=1e-12)
+    with pytest.raises(ValueError):
+        api.ConvolvedFFTPower(mesh, dev(rand), observer=obs)  # no norm
