@@ -175,6 +175,15 @@ pk_status pk_paint(pk_ctx *ctx, const pk_mesh_desc *m, const void *pos,
  * Errors: PK_EINVAL, PK_EDEVICE. */
 pk_status pk_fft_r2c(pk_ctx *ctx, const pk_mesh_desc *m, void *mesh_inout);
 
+/* Backward 3D complex-to-real FFT in place (Sec. 3.3.1, ComplexField to
+ * RealField, c2r): exp(+i k.x), unnormalised, so that
+ * pk_fft_c2r(pk_fft_r2c(F)) = N^3 F.  mesh_inout holds a packed half spectrum
+ * (layout above) on entry and the real mesh on exit.  The spectrum is taken
+ * as that of a real field: the kz = 0 and N/2 planes are read through the
+ * packed column (their Hermitian parts), and m->window, interlaced and
+ * compensated are ignored.  Deterministic.  Errors: PK_EINVAL, PK_EDEVICE. */
+pk_status pk_fft_c2r(pk_ctx *ctx, const pk_mesh_desc *m, void *mesh_inout);
+
 /* Interlacing and window compensation on packed spectra (Sec. 3.3.2, Eq. 2),
  * in place on cmesh_inout:
  *   if cmesh_b != NULL: c <- [c + exp(i pi (n_x + n_y + n_z) / N) c_b] / 2

@@ -33,6 +33,7 @@ from .paint import (wrap_positions, cell_coordinates, window_weights, paint_mesh
                     painted_modes)
 from .power import (
     r2c,
+    c2r,
     mode_indices,
     interlace_combine,
     compensate,
@@ -57,6 +58,7 @@ __all__ = [
     "paint_cells",
     "painted_modes",
     "r2c",
+    "c2r",
     "mode_indices",
     "interlace_combine",
     "compensate",

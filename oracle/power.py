@@ -59,6 +59,17 @@ def r2c(mesh, workers=None):
     return scipy.fft.rfftn(np.asarray(mesh, dtype=np.float64), workers=workers)
 
 
+def c2r(cmesh, nmesh, workers=None):
+    """Backward complex-to-real 3D DFT, exp(+i k.x), unnormalised (float64):
+    the full-grid sum over the Hermitian spectrum whose half is ``cmesh``
+    (N, N, N/2 + 1), so that c2r(r2c(F)) = N^3 F."""
+    if workers is None:
+        workers = os.cpu_count()
+    n = int(nmesh)
+    return scipy.fft.irfftn(np.asarray(cmesh, dtype=np.complex128), s=(n, n, n),
+                            workers=workers) * float(n) ** 3
+
+
 def mode_indices(nmesh):
     """Signed integer wave numbers of the r2c array (numpy fftfreq order).
 

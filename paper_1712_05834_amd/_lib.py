@@ -27,7 +27,7 @@ EXPORTS = (
     "pk_ctx_set_lanes", "pk_ctx_lanes", "pk_fftpower_async", "pk_lane_query", "pk_lane_wait",
     "pk_fftpower_batch", "pk_bin_cross", "pk_fftpower_v", "pk_projected_doubles",
     "pk_bin_projected", "pk_projected_to_host", "pk_convolved_doubles",
-    "pk_convolved_workspace_bytes", "pk_convolved_power", "pk_convolved_to_host",
+    "pk_convolved_workspace_bytes", "pk_convolved_power", "pk_convolved_to_host", "pk_fft_c2r",
 )
 PK_MAX_LANES = 64
 
@@ -109,6 +109,7 @@ def load(path=None):
             "pk_ctx_table_bytes": (sz, [vp]),
             "pk_paint": (i32, [vp, md, vp, vp, i64, dbl, vp, vp]),
             "pk_fft_r2c": (i32, [vp, md, vp]),
+            "pk_fft_c2r": (i32, [vp, md, vp]),
             "pk_compensate": (i32, [vp, md, vp, vp]),
             "pk_bin_power": (i32, [vp, md, bd, vp, vp]),
             "pk_bin_cross": (i32, [vp, md, bd, vp, vp, vp]),
@@ -241,6 +242,9 @@ class Context:
 
     def pk_fft_r2c(self, m, mesh):
         self._check(self.lib.pk_fft_r2c(self.handle, ctypes.byref(m), _ptr(mesh)))
+
+    def pk_fft_c2r(self, m, mesh):
+        self._check(self.lib.pk_fft_c2r(self.handle, ctypes.byref(m), _ptr(mesh)))
 
     def pk_compensate(self, m, cmesh, cmesh_b=None):
         self._check(self.lib.pk_compensate(self.handle, ctypes.byref(m), _ptr(cmesh),

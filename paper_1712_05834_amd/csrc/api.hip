@@ -498,6 +498,23 @@ pk_status pk_fft_r2c(pk_ctx* ctx, const pk_mesh_desc* m, void* mesh_inout) {
   return PK_OK;
 }
 
+pk_status pk_fft_c2r(pk_ctx* ctx, const pk_mesh_desc* m, void* mesh_inout) {
+  if (!ctx) return PK_EINVAL;
+  if (const char* why = check_mesh(m)) return fail(ctx, PK_EINVAL, why);
+  if (!mesh_inout) return fail(ctx, PK_EINVAL, "mesh is NULL");
+  if (ctx->device == PK_DEVICE_NONE) return fail(ctx, PK_EDEVICE, "validation-only context");
+  DeviceGuard g(ctx->device);
+  const MeshTables* t = nullptr;
+  if (pk_status st = get_mesh_tables(ctx, m->nmesh, m->dtype, &t)) return st;
+  const size_t bytes = pk_mesh_bytes(m);
+  hipError_t e = launch_fft_cols(m->dtype, m->nmesh, mesh_inout, 1, bytes, t->tw, 0, ctx->stream, 1);
+  if (e == hipSuccess)
+    e = launch_fft_cols(m->dtype, m->nmesh, mesh_inout, 1, bytes, t->tw, 1, ctx->stream, 1);
+  if (e == hipSuccess) e = launch_ifft_z(m->dtype, m->nmesh, mesh_inout, t->tw, ctx->stream);
+  if (e != hipSuccess) return dev_fail(ctx, e, "pk_fft_c2r");
+  return PK_OK;
+}
+
 pk_status pk_compensate(pk_ctx* ctx, const pk_mesh_desc* m, void* cmesh_inout,
                         const void* cmesh_b) {
   if (!ctx) return PK_EINVAL;

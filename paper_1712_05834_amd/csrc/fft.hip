@@ -67,10 +67,64 @@ __global__ void __launch_bounds__((ZCfg<T, N>::THREADS))
   }
 }
 
+// Inverse z-pass (c2r of each row): the packed half spectrum X_0 .. X_{N/2}
+// of a real row (slot 0 holding X_0 + i X_{N/2}) back to the N real values,
+// unnormalised (x_n = sum_k X_k exp(+2 pi i n k / N) over the full row).  The
+// row is rebuilt as the M-point complex sequence z_j = x_{2j} + i x_{2j+1}:
+// with E_k = X_k + conj X_{M-k} and O_k = (X_k - conj X_{M-k}) W_N^{-k} (twice
+// the transforms of the even and odd samples), Z_k = E_k + i O_k, and the
+// unnormalised inverse M-point transform of Z -- conj(FFT(conj Z)) -- is
+// 2 M z = N z.
+template <typename T, int N>
+__global__ void __launch_bounds__((ZCfg<T, N>::THREADS))
+    k_ifft_z(T* __restrict__ mesh0, const cpx<T>* __restrict__ tw) {
+  using Z = ZCfg<T, N>;
+  constexpr int M = Z::M, E = Z::E, TPL = Z::TPL, RPB = Z::RPB;
+  __shared__ cpx<T> lds[RPB * Z::LP];
+  __shared__ cpx<T> twq[N / 4];
+  __shared__ cpx<T> tws[stage_table_size<M, E>() + 1];
+  build_stage_table<T, M, E>(tws, TwGlobal<T>{tw, 2});
+  load_quarter(twq, tw, N);
+  const TwStage<T, M, E> tw2{tws};
+  const TwQuarter<T> tw1{twq, 1, ilog2(N / 4)};
+  const int r = threadIdx.x / TPL, t = threadIdx.x % TPL;
+  const size_t row = (size_t)blockIdx.x * RPB + r;
+  const bool active = row < (size_t)N * N;
+  cpx<T>* rowp = reinterpret_cast<cpx<T>*>(mesh0 + row * N);
+  LdsLine<T> line{lds + r * Z::LP};
+  cpx<T> v[E];
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    v[e] = active ? rowp[t + TPL * e] : cpx<T>{T(0), T(0)};
+    line.put(t + TPL * e, v[e]);
+  }
+  __syncthreads();
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const int k = t + TPL * e;
+    cpx<T> zk;
+    if (k == 0) {
+      // X_0 and X_{N/2} are real: E_0 = X_0 + X_{N/2}, O_0 = X_0 - X_{N/2}
+      zk = {v[e].x + v[e].y, v[e].x - v[e].y};
+    } else {
+      const cpx<T> xc = cconj(line.get(M - k));
+      const cpx<T> ev = cadd(v[e], xc);
+      const cpx<T> od = cmul(cconj(tw1(k)), csub(v[e], xc));
+      zk = {ev.x - od.y, ev.y + od.x};
+    }
+    v[e] = cconj(zk);
+  }
+  __syncthreads();  // every partner read before the line is reused
+  stockham<T, M, E, 1>(v, t, tw2, line);
+#pragma unroll
+  for (int e = 0; e < E; ++e)
+    if (active) rowp[t + TPL * e] = cconj(v[e]);
+}
+
 template <typename T, int N>
 __global__ void __launch_bounds__((ColCfg<T, N>::THREADS))
     k_fft_cols(T* __restrict__ mesh0, size_t mesh_stride, const cpx<T>* __restrict__ tw,
-               int axis) {
+               int axis, int inverse) {
   using Cf = ColCfg<T, N>;
   constexpr int E = Cf::E, TPL = Cf::TPL, C = Cf::C, NC = Cf::NC;
   __shared__ cpx<T> lds[Cf::LDS_ELEMS];
@@ -91,11 +145,15 @@ __global__ void __launch_bounds__((ColCfg<T, N>::THREADS))
   }
   cpx<T> v[E];
 #pragma unroll
-  for (int e = 0; e < E; ++e) v[e] = mesh[base + (size_t)(t + TPL * e) * step];
+  for (int e = 0; e < E; ++e) {
+    v[e] = mesh[base + (size_t)(t + TPL * e) * step];
+    if (inverse) v[e] = cconj(v[e]);  // inverse transform: conj(FFT(conj x))
+  }
   LdsCols<T, C> lc{lds, c};
   stockham<T, N, E, 1>(v, t, tw1, lc);
 #pragma unroll
-  for (int e = 0; e < E; ++e) mesh[base + (size_t)(t + TPL * e) * step] = v[e];
+  for (int e = 0; e < E; ++e)
+    mesh[base + (size_t)(t + TPL * e) * step] = inverse ? cconj(v[e]) : v[e];
 }
 
 // y-pass of the power-spectrum path: the same transform as k_fft_cols along
@@ -165,12 +223,21 @@ static hipError_t fft_z_t(void* mesh, int nmeshes, size_t stride_bytes, const vo
 
 template <typename T, int N>
 static hipError_t fft_cols_t(void* mesh, int nmeshes, size_t stride_bytes, const void* tw,
-                             int axis, hipStream_t s) {
+                             int axis, int inverse, hipStream_t s) {
   using Cf = ColCfg<T, N>;
   const unsigned blocks = (unsigned)(N * Cf::CHUNKS);
   hipLaunchKernelGGL((k_fft_cols<T, N>), dim3(blocks, 1, nmeshes), dim3(Cf::THREADS), 0, s,
                      static_cast<T*>(mesh), stride_bytes / sizeof(T),
-                     static_cast<const cpx<T>*>(tw), axis);
+                     static_cast<const cpx<T>*>(tw), axis, inverse);
+  return hipGetLastError();
+}
+
+template <typename T, int N>
+static hipError_t ifft_z_t(void* mesh, const void* tw, hipStream_t s) {
+  using Z = ZCfg<T, N>;
+  const unsigned blocks = (unsigned)(((size_t)N * N + Z::RPB - 1) / Z::RPB);
+  hipLaunchKernelGGL((k_ifft_z<T, N>), dim3(blocks), dim3(Z::THREADS), 0, s,
+                     static_cast<T*>(mesh), static_cast<const cpx<T>*>(tw));
   return hipGetLastError();
 }
 
@@ -198,11 +265,19 @@ hipError_t launch_fft_z(int dtype, int nmesh, void* mesh, int nmeshes, size_t st
 }
 
 hipError_t launch_fft_cols(int dtype, int nmesh, void* mesh, int nmeshes, size_t stride_bytes,
-                           const void* tw, int axis, hipStream_t s) {
+                           const void* tw, int axis, hipStream_t s, int inverse) {
   if (dtype == PK_F32) {
-    PK_DISPATCH_N(fft_cols_t, float, mesh, nmeshes, stride_bytes, tw, axis, s)
+    PK_DISPATCH_N(fft_cols_t, float, mesh, nmeshes, stride_bytes, tw, axis, inverse, s)
   } else {
-    PK_DISPATCH_N(fft_cols_t, double, mesh, nmeshes, stride_bytes, tw, axis, s)
+    PK_DISPATCH_N(fft_cols_t, double, mesh, nmeshes, stride_bytes, tw, axis, inverse, s)
+  }
+}
+
+hipError_t launch_ifft_z(int dtype, int nmesh, void* mesh, const void* tw, hipStream_t s) {
+  if (dtype == PK_F32) {
+    PK_DISPATCH_N(ifft_z_t, float, mesh, tw, s)
+  } else {
+    PK_DISPATCH_N(ifft_z_t, double, mesh, tw, s)
   }
 }
 

@@ -88,8 +88,12 @@ hipError_t launch_paint_z(int dtype, int nmesh, int order, bool inter, const voi
 
 hipError_t launch_fft_z(int dtype, int nmesh, void* mesh, int nmeshes, size_t mesh_stride_bytes,
                         const void* tw, const double* wsum_for_mean, hipStream_t s);
+// inverse = 1: the unnormalised backward transform along the axis.
 hipError_t launch_fft_cols(int dtype, int nmesh, void* mesh, int nmeshes,
-                           size_t mesh_stride_bytes, const void* tw, int axis, hipStream_t s);
+                           size_t mesh_stride_bytes, const void* tw, int axis, hipStream_t s,
+                           int inverse = 0);
+// Inverse z-pass: packed half-spectrum rows back to real rows (c2r).
+hipError_t launch_ifft_z(int dtype, int nmesh, void* mesh, const void* tw, hipStream_t s);
 // y-pass of one z-transformed mesh, out of place into the layout read by the
 // fused x-pass (YLayout in fft_config.h).
 hipError_t launch_fft_y_relayout(int dtype, int nmesh, const void* src, void* dst, const void* tw,

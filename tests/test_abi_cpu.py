@@ -208,3 +208,12 @@ def test_sorted_paths_reject_more_than_int32_particles(vctx):
     st = lib.pk_convolved_power(h, ctypes.byref(m), ctypes.byref(bs), obs, one, None, big // 2,
                                 one, None, big // 2, one, 1 << 62, one)
     assert st == _lib.PK_EUNSUPPORTED
+
+
+def test_c2r_validates(vctx):
+    lib, h = vctx
+    m = _lib.mesh_desc(32, 100.0)
+    assert lib.pk_fft_c2r(h, ctypes.byref(m), None) == _lib.PK_EINVAL
+    assert lib.pk_fft_c2r(h, ctypes.byref(m), ctypes.c_void_p(1)) == _lib.PK_EDEVICE
+    bad = _lib.mesh_desc(24, 100.0)
+    assert lib.pk_fft_c2r(h, ctypes.byref(bad), ctypes.c_void_p(1)) == _lib.PK_EINVAL

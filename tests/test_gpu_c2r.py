@@ -1,0 +1,87 @@
+"""GPU parity of the backward transform (pk_fft_c2r, ComplexField -> RealField,
+Sec. 3.3.1) against the oracle: the round trip r2c then c2r gives N^3 F, and
+the backward transform of a spectrum shaped on the host (a random field's
+half spectrum times an isotropic real amplitude, packed into the library's
+layout) equals the oracle's full-grid backward sum.  Tolerances relative to
+the rms of the result: float64 1e-13, float32 1e-6 (rms) and 1e-4 (max), as
+for the forward transform."""
+
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1712_05834_amd import _lib
+from tests import packing
+
+pytestmark = pytest.mark.gpu
+
+NDT = {"f8": np.float64, "f4": np.float32}
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = _lib.Context(0)
+    yield c
+    torch.cuda.synchronize()
+    c.close()
+
+
+def errors(got, want):
+    rms = math.sqrt(np.mean(want ** 2))
+    return (math.sqrt(np.mean((got - want) ** 2)) / rms, np.abs(got - want).max() / rms)
+
+
+TOLS = {"f8": (1e-13, 1e-12), "f4": (1e-6, 1e-4)}
+
+
+@pytest.mark.parametrize("dtype", ["f8", "f4"])
+@pytest.mark.parametrize("n", [8, 16, 64, 128])
+def test_round_trip_is_n_cubed_times_the_field(ctx, dtype, n):
+    f = np.random.default_rng(n + 3).standard_normal((n, n, n)) + 0.2
+    f = f.astype(NDT[dtype])
+    m = _lib.mesh_desc(n, 1.0, "cic", False, True, dtype)
+    mesh = torch.from_numpy(f.copy()).to("cuda:0")
+    ctx.pk_fft_r2c(m, mesh)
+    ctx.pk_fft_c2r(m, mesh)
+    got = mesh.cpu().numpy().astype(np.float64)
+    er, em = errors(got, n ** 3 * f.astype(np.float64))
+    print(f"n={n} {dtype}: rms {er:.2e} max {em:.2e}")
+    assert er <= TOLS[dtype][0] and em <= TOLS[dtype][1], (er, em)
+
+
+@pytest.mark.parametrize("dtype", ["f8", "f4"])
+@pytest.mark.parametrize("n", [16, 32, 256])
+def test_backward_transform_of_a_shaped_spectrum_matches_oracle(ctx, dtype, n):
+    rng = np.random.default_rng(100 + n)
+    c = oracle.r2c(rng.standard_normal((n, n, n)))
+    nx, ny, nz = oracle.mode_indices(n)
+    k = np.sqrt(nx[:, None, None] ** 2 + ny[None, :, None] ** 2 + nz[None, None, :] ** 2)
+    c *= 1.0 / (1.0 + (k / 4.0) ** 2)  # a real isotropic amplitude keeps the spectrum Hermitian
+    want = oracle.c2r(c, n)
+    z = packing.pack(c)
+    m = _lib.mesh_desc(n, 1.0, "tsc", False, True, dtype)
+    mesh = torch.from_numpy(packing.to_real_view(z, NDT[dtype]).reshape(n, n, n)).to("cuda:0")
+    ctx.pk_fft_c2r(m, mesh)
+    got = mesh.cpu().numpy().astype(np.float64)
+    er, em = errors(got, want)
+    print(f"n={n} {dtype}: rms {er:.2e} max {em:.2e}")
+    assert er <= TOLS[dtype][0] and em <= TOLS[dtype][1], (er, em)
+
+
+def test_single_mode_is_a_plane_wave(ctx):
+    n = 32
+    c = np.zeros((n, n, n // 2 + 1), dtype=np.complex128)
+    c[3, (-5) % n, 6] = 1.0 + 0.5j
+    want = oracle.c2r(c, n)
+    x = np.arange(n)
+    g = np.meshgrid(x, x, x, indexing="ij")
+    ph = 2 * np.pi * (3 * g[0] - 5 * g[1] + 6 * g[2]) / n
+    np.testing.assert_allclose(want, 2 * (np.cos(ph) - 0.5 * np.sin(ph)), atol=1e-12)
+    m = _lib.mesh_desc(n, 1.0, "cic", False, True, "f8")
+    mesh = torch.from_numpy(packing.to_real_view(packing.pack(c), np.float64)
+                            .reshape(n, n, n)).to("cuda:0")
+    ctx.pk_fft_c2r(m, mesh)
+    np.testing.assert_allclose(mesh.cpu().numpy(), want, atol=1e-12)

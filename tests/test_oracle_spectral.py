@@ -99,6 +99,25 @@ def test_r2c_plane_wave_single_mode():
     assert np.abs(c).max() < 1e-9
 
 
+def test_c2r_matches_brute_backward_sum_and_inverts_r2c():
+    # the backward sum over the full grid, the half spectrum's other half
+    # taken as the complex conjugate, written out by hand
+    n = 8
+    rng = np.random.default_rng(2)
+    f = rng.standard_normal((n, n, n))
+    c = oracle.r2c(f)
+    full = np.empty((n, n, n), dtype=np.complex128)
+    full[:, :, : n // 2 + 1] = c
+    for kz in range(n // 2 + 1, n):
+        full[:, :, kz] = np.conj(c[(-np.arange(n)) % n][:, (-np.arange(n)) % n, n - kz])
+    idx = np.arange(n)
+    e = np.exp(2j * np.pi * np.outer(idx, idx) / n)  # e[x, k]
+    want = np.einsum("xa,yb,zc,abc->xyz", e, e, e, full)
+    got = oracle.c2r(c, n)
+    np.testing.assert_allclose(got, want.real, rtol=0, atol=1e-10 * np.abs(want).max())
+    np.testing.assert_allclose(got, n ** 3 * f, rtol=0, atol=1e-9)
+
+
 def test_parseval_half_grid_weights():
     n = 16
     f = np.random.default_rng(2).standard_normal((n, n, n))
