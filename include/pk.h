@@ -184,6 +184,19 @@ pk_status pk_fft_r2c(pk_ctx *ctx, const pk_mesh_desc *m, void *mesh_inout);
  * compensated are ignored.  Deterministic.  Errors: PK_EINVAL, PK_EDEVICE. */
 pk_status pk_fft_c2r(pk_ctx *ctx, const pk_mesh_desc *m, void *mesh_inout);
 
+/* Isotropic scaling of a packed spectrum in place, c(k) *= table[|n|^2]
+ * (n the signed integer mode, |n|^2 = n_x^2 + n_y^2 + n_z^2), for device-side
+ * field generation (Sec. 3.2, catalogs from Gaussian fields): white noise,
+ * pk_fft_r2c, pk_shape_spectrum with sqrt(N^3 P(k) / V) / N^3, pk_fft_c2r
+ * gives a Gaussian field of spectrum P.  The spectrum is taken as that of a
+ * real field (the kz = 0 and N/2 planes through the packed column, each pair
+ * of partner modes updated together), so the result stays one.
+ *   table_dev  device, table_len float64, table_len >= pk_shape_table_len(m)
+ * Errors: PK_EINVAL (also a short table), PK_EDEVICE. */
+int64_t pk_shape_table_len(const pk_mesh_desc *m); /* 3 (N/2)^2 + 1, 0 if invalid */
+pk_status pk_shape_spectrum(pk_ctx *ctx, const pk_mesh_desc *m, void *cmesh_inout,
+                            const double *table_dev, int64_t table_len);
+
 /* Interlacing and window compensation on packed spectra (Sec. 3.3.2, Eq. 2),
  * in place on cmesh_inout:
  *   if cmesh_b != NULL: c <- [c + exp(i pi (n_x + n_y + n_z) / N) c_b] / 2

@@ -28,6 +28,7 @@ EXPORTS = (
     "pk_fftpower_batch", "pk_bin_cross", "pk_fftpower_v", "pk_projected_doubles",
     "pk_bin_projected", "pk_projected_to_host", "pk_convolved_doubles",
     "pk_convolved_workspace_bytes", "pk_convolved_power", "pk_convolved_to_host", "pk_fft_c2r",
+    "pk_shape_table_len", "pk_shape_spectrum",
 )
 PK_MAX_LANES = 64
 
@@ -110,6 +111,8 @@ def load(path=None):
             "pk_paint": (i32, [vp, md, vp, vp, i64, dbl, vp, vp]),
             "pk_fft_r2c": (i32, [vp, md, vp]),
             "pk_fft_c2r": (i32, [vp, md, vp]),
+            "pk_shape_table_len": (i64, [md]),
+            "pk_shape_spectrum": (i32, [vp, md, vp, vp, i64]),
             "pk_compensate": (i32, [vp, md, vp, vp]),
             "pk_bin_power": (i32, [vp, md, bd, vp, vp]),
             "pk_bin_cross": (i32, [vp, md, bd, vp, vp, vp]),
@@ -169,6 +172,10 @@ def result_doubles(b):
 
 def projected_doubles(b):
     return int(load().pk_projected_doubles(ctypes.byref(b)))
+
+
+def shape_table_len(m):
+    return int(load().pk_shape_table_len(ctypes.byref(m)))
 
 
 def convolved_doubles(b):
@@ -245,6 +252,10 @@ class Context:
 
     def pk_fft_c2r(self, m, mesh):
         self._check(self.lib.pk_fft_c2r(self.handle, ctypes.byref(m), _ptr(mesh)))
+
+    def pk_shape_spectrum(self, m, cmesh, table):
+        self._check(self.lib.pk_shape_spectrum(self.handle, ctypes.byref(m), _ptr(cmesh),
+                                               _ptr(table), int(table.numel())))
 
     def pk_compensate(self, m, cmesh, cmesh_b=None):
         self._check(self.lib.pk_compensate(self.handle, ctypes.byref(m), _ptr(cmesh),

@@ -515,6 +515,25 @@ pk_status pk_fft_c2r(pk_ctx* ctx, const pk_mesh_desc* m, void* mesh_inout) {
   return PK_OK;
 }
 
+int64_t pk_shape_table_len(const pk_mesh_desc* m) {
+  if (check_mesh(m)) return 0;
+  const int64_t h = m->nmesh / 2;
+  return 3 * h * h + 1;
+}
+
+pk_status pk_shape_spectrum(pk_ctx* ctx, const pk_mesh_desc* m, void* cmesh_inout,
+                            const double* table_dev, int64_t table_len) {
+  if (!ctx) return PK_EINVAL;
+  if (const char* why = check_mesh(m)) return fail(ctx, PK_EINVAL, why);
+  if (!cmesh_inout || !table_dev) return fail(ctx, PK_EINVAL, "cmesh or table is NULL");
+  if (table_len < pk_shape_table_len(m)) return fail(ctx, PK_EINVAL, "table shorter than 3 (N/2)^2 + 1");
+  if (ctx->device == PK_DEVICE_NONE) return fail(ctx, PK_EDEVICE, "validation-only context");
+  DeviceGuard g(ctx->device);
+  hipError_t e = launch_shape_packed(m->dtype, m->nmesh, cmesh_inout, table_dev, ctx->stream);
+  if (e != hipSuccess) return dev_fail(ctx, e, "pk_shape_spectrum");
+  return PK_OK;
+}
+
 pk_status pk_compensate(pk_ctx* ctx, const pk_mesh_desc* m, void* cmesh_inout,
                         const void* cmesh_b) {
   if (!ctx) return PK_EINVAL;

@@ -127,6 +127,11 @@ int mode_table_groups(int nmesh);
 hipError_t launch_compensate(int dtype, int nmesh, void* cmesh, const void* cmesh_b,
                              const MeshTables& t, int order, int compensated, hipStream_t s);
 
+// c(k) *= table[|n|^2] over a packed spectrum (generate.hip); table holds
+// 3 (N/2)^2 + 1 float64 values.
+hipError_t launch_shape_packed(int dtype, int nmesh, void* cmesh, const double* table,
+                               hipStream_t s);
+
 // Survey multipoles (convolved.hip).  One real spherical harmonic Y_lm:
 // ell, |m|, sine = (m < 0), knorm its normalisation (host float64).
 struct Harmonic {

@@ -217,3 +217,15 @@ def test_c2r_validates(vctx):
     assert lib.pk_fft_c2r(h, ctypes.byref(m), ctypes.c_void_p(1)) == _lib.PK_EDEVICE
     bad = _lib.mesh_desc(24, 100.0)
     assert lib.pk_fft_c2r(h, ctypes.byref(bad), ctypes.c_void_p(1)) == _lib.PK_EINVAL
+
+
+def test_shape_spectrum_validates(vctx):
+    lib, h = vctx
+    m = _lib.mesh_desc(32, 100.0)
+    need = _lib.shape_table_len(m)
+    assert need == 3 * 16 ** 2 + 1
+    one = ctypes.c_void_p(1)
+    assert lib.pk_shape_spectrum(h, ctypes.byref(m), one, one, need - 1) == _lib.PK_EINVAL
+    assert lib.pk_shape_spectrum(h, ctypes.byref(m), None, one, need) == _lib.PK_EINVAL
+    assert lib.pk_shape_spectrum(h, ctypes.byref(m), one, one, need) == _lib.PK_EDEVICE
+    assert _lib.shape_table_len(_lib.mesh_desc(24, 1.0)) == 0
