@@ -87,7 +87,9 @@ def make_catalog(w):
 
 def algorithmic_bytes(stage, w, npart):
     """Compulsory HBM bytes of one launch of a stage: each input read once and
-    each output written once (per-unit figures in the design doc).  The bucketing
+    each output written once: painting reads 3e bytes per particle and writes
+    e per cell and mesh, each FFT pass reads and writes e per real point and
+    mesh, the binning reads e per real point and mesh.  The bucketing
     pass only reorders the catalog, so it has none; the fused paint + z-pass
     consumes the catalog and writes the z-transformed meshes."""
     es = 4 if w["dtype"] == "f4" else 8
@@ -194,7 +196,8 @@ def main():
         return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
-              "(each mesh is processed on a single MI355X; see DESIGN.md for sharding)",
+              "(each mesh is processed on a single MI355X; sharding one mesh across GPUs is "
+              "not implemented)",
               file=sys.stderr)
         sys.exit(2)
 
