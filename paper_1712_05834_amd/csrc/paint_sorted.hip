@@ -117,7 +117,8 @@ template <typename T>
 __global__ void __launch_bounds__(256)
     k_bucket_count(const T* __restrict__ pos, const T* __restrict__ weight,
                    const T* __restrict__ value, int64_t n, int64_t chunk, int nmesh,
-                   double boxsize, int* __restrict__ count, double* __restrict__ wpart) {
+                   double boxsize, double inv_box, double cells_per_len,
+                   int* __restrict__ count, double* __restrict__ wpart) {
   __shared__ int hkeys[kHashSize], hcnts[kHashSize];
   hash_clear(hkeys, hcnts);
   __syncthreads();
@@ -132,8 +133,9 @@ __global__ void __launch_bounds__(256)
       const int64_t i = i0 + u * 256;
       key[u] = -1;
       if (i < n) {
-        const double ux = cell_coordinate((double)pos[3 * i], nmesh, boxsize);
-        const double uy = cell_coordinate((double)pos[3 * i + 1], nmesh, boxsize);
+        const double ux = cell_coordinate_rcp((double)pos[3 * i], boxsize, inv_box, cells_per_len);
+        const double uy =
+            cell_coordinate_rcp((double)pos[3 * i + 1], boxsize, inv_box, cells_per_len);
         key[u] = (((int)floor(ux)) & mask) * nmesh + (((int)floor(uy)) & mask);
         // normalisation: sum w; shot noise: sum (w V)^2 (V = 1 without values)
         const double wp = weight ? (double)weight[i] : 1.0;
@@ -198,7 +200,8 @@ template <typename T>
 __global__ void __launch_bounds__(256)
     k_bucket_scatter(const T* __restrict__ pos, const T* __restrict__ weight,
                      const T* __restrict__ value, int64_t n, int64_t chunk, int nmesh,
-                     double boxsize, int* __restrict__ cursor,
+                     double boxsize, double inv_box, double cells_per_len,
+                     int* __restrict__ cursor,
                      typename Rec<T>::type* __restrict__ rec, T* __restrict__ wrec) {
   // per step: the runs of each column in the step are ranked in the LDS
   // table, one global atomic per column reserves the step's slots, then every
@@ -222,7 +225,7 @@ __global__ void __launch_bounds__(256)
         double u[3], f[3];
 #pragma unroll
         for (int d = 0; d < 3; ++d) {
-          u[d] = cell_coordinate((double)pos[3 * i + d], nmesh, boxsize);
+          u[d] = cell_coordinate_rcp((double)pos[3 * i + d], boxsize, inv_box, cells_per_len);
           f[d] = floor(u[d]);
         }
         key = (((int)f[0]) & mask) * nmesh + (((int)f[1]) & mask);
@@ -694,6 +697,7 @@ hipError_t launch_bucket(int dtype, int nmesh, double boxsize, const void* pos, 
                          const void* value, int64_t n, void* bucket_ws, void* rec, void* wrec,
                          double* wsums, hipStream_t s) {
   const int n2 = nmesh * nmesh;
+  const double inv_box = 1.0 / boxsize, cpl = nmesh / boxsize;
   int* count = static_cast<int*>(bucket_ws);
   int* offsets = count + n2;
   int* cursor = offsets + n2 + 1;
@@ -713,11 +717,13 @@ hipError_t launch_bucket(int dtype, int nmesh, double boxsize, const void* pos, 
   if (dtype == PK_F32)
     hipLaunchKernelGGL(k_bucket_count<float>, dim3((unsigned)blocks), dim3(256), 0, s,
                        static_cast<const float*>(pos), static_cast<const float*>(weight),
-                       static_cast<const float*>(value), n, chunk, nmesh, boxsize, count, wpart);
+                       static_cast<const float*>(value), n, chunk, nmesh, boxsize, inv_box, cpl, count,
+                       wpart);
   else
     hipLaunchKernelGGL(k_bucket_count<double>, dim3((unsigned)blocks), dim3(256), 0, s,
                        static_cast<const double*>(pos), static_cast<const double*>(weight),
-                       static_cast<const double*>(value), n, chunk, nmesh, boxsize, count, wpart);
+                       static_cast<const double*>(value), n, chunk, nmesh, boxsize, inv_box, cpl, count,
+                       wpart);
   hipLaunchKernelGGL(k_weight_sums, dim3(1), dim3(1024), 0, s, wpart, (int)blocks, wsums);
   hipLaunchKernelGGL(k_scan_blocks, dim3(nb), dim3(1024), 0, s, count, n2, bsums);
   hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(1024), 0, s, bsums, nb);
@@ -725,13 +731,13 @@ hipError_t launch_bucket(int dtype, int nmesh, double boxsize, const void* pos, 
   if (dtype == PK_F32)
     hipLaunchKernelGGL(k_bucket_scatter<float>, dim3((unsigned)blocks), dim3(256), 0, s,
                        static_cast<const float*>(pos), static_cast<const float*>(weight),
-                       static_cast<const float*>(value), n, chunk, nmesh, boxsize, cursor,
+                       static_cast<const float*>(value), n, chunk, nmesh, boxsize, inv_box, cpl, cursor,
                        static_cast<float4*>(rec),
                        (weight || value) ? static_cast<float*>(wrec) : nullptr);
   else
     hipLaunchKernelGGL(k_bucket_scatter<double>, dim3((unsigned)blocks), dim3(256), 0, s,
                        static_cast<const double*>(pos), static_cast<const double*>(weight),
-                       static_cast<const double*>(value), n, chunk, nmesh, boxsize, cursor,
+                       static_cast<const double*>(value), n, chunk, nmesh, boxsize, inv_box, cpl, cursor,
                        static_cast<double4*>(rec),
                        (weight || value) ? static_cast<double*>(wrec) : nullptr);
   return hipGetLastError();
