@@ -217,6 +217,27 @@ def test_fftpower_matrix(ctx, dtype, window, inter, n):
     check_power(got, want, TOL[dtype], f"{dtype} {window} inter={inter} n={n}")
 
 
+@pytest.mark.parametrize("dtype", ["f8", "f4"])
+@pytest.mark.parametrize("window", ["cic", "tsc"])
+def test_fftpower_wraps_positions_and_piles_up(ctx, dtype, window):
+    # the fused path (bucketing, sorted painting) with positions in [-L, 2L),
+    # values on the box edges (0, +-L, 2L and just below L) and 300 particles
+    # in one spot: periodic wrap and a dense cell against the oracle
+    n, box = 32, 100.0
+    rng = np.random.default_rng(61)
+    pos = rng.uniform(-box, 2 * box, (4000, 3))
+    edges = np.array([0.0, box, -box, 2 * box, box * (1 - 2.0 ** -50), 0.5 * box])
+    special = np.stack(np.meshgrid(edges, edges, edges, indexing="ij"), axis=-1).reshape(-1, 3)
+    pile = np.tile([[37.3, 12.9, 81.05]], (300, 1))
+    pos = np.concatenate([pos, special, pile]).astype(NDT[dtype])
+    w = rng.uniform(0.5, 1.5, len(pos)).astype(NDT[dtype])
+    b = _lib.bin_desc(n // 2, 0.0, 1.0, 3, (0, 2), 2)
+    got = _run_fftpower(ctx, pos, w, n, box, window, True, True, dtype, b)
+    want = oracle.fftpower(pos.astype(np.float64), n, box, window, True, True,
+                           w.astype(np.float64), nmu=3, poles=(0, 2))
+    check_power(got, want, TOL[dtype], f"{dtype} {window} wrap + pile-up")
+
+
 def test_fftpower_uncompensated_los_x(ctx):
     box, n = 200.0, 32
     pos = synth.uniform_catalog(5000, box, seed=77)
