@@ -298,6 +298,37 @@ pk_status get_scratch(pk_ctx* ctx, size_t bytes, double** out) {
   return PK_OK;
 }
 
+// Copies `count` result doubles to the context's host staging (pinned when
+// possible) after the work enqueued before it; *h points at them.
+pk_status read_result(pk_ctx* ctx, const double* result_dev, size_t count, const double** h,
+                      const char* who) {
+  double* dst = nullptr;
+  if (ctx->host_stage_n < count) {
+    if (ctx->host_stage) (void)hipHostFree(ctx->host_stage);
+    ctx->host_stage = nullptr;
+    ctx->host_stage_n = 0;
+    void* p = nullptr;
+    if (hipHostMalloc(&p, count * sizeof(double), hipHostMallocDefault) == hipSuccess) {
+      ctx->host_stage = static_cast<double*>(p);
+      ctx->host_stage_n = count;
+    } else {
+      (void)hipGetLastError();  // refused: read through pageable memory instead
+    }
+  }
+  if (ctx->host_stage_n >= count) {
+    dst = ctx->host_stage;
+  } else {
+    ctx->host_fallback.resize(count);
+    dst = ctx->host_fallback.data();
+  }
+  hipError_t e = hipMemcpyAsync(dst, result_dev, count * sizeof(double), hipMemcpyDeviceToHost,
+                                ctx->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+  if (e != hipSuccess) return dev_fail(ctx, e, who);
+  *h = dst;
+  return PK_OK;
+}
+
 // Records the start event of a stage of pk_fftpower when timing is enabled.
 void mark_stage(pk_ctx* ctx, int stage) {
   if (!ctx->timing) return;
@@ -436,6 +467,7 @@ void pk_ctx_destroy(pk_ctx* ctx) {
     (void)hipStreamDestroy(ln.stream);
   }
   if (ctx->tables_ready) (void)hipEventDestroy(ctx->tables_ready);
+  if (ctx->host_stage) (void)hipHostFree(ctx->host_stage);
   delete ctx;
 }
 
@@ -608,11 +640,9 @@ pk_status pk_projected_to_host(pk_ctx* ctx, const pk_mesh_desc* m, const pk_bin_
   if (ctx->device == PK_DEVICE_NONE) return fail(ctx, PK_EDEVICE, "validation-only context");
   DeviceGuard g(ctx->device);
   const int nk = b->nk;
-  std::vector<double> h(3 * (size_t)nk + 2);
-  hipError_t e = hipMemcpyAsync(h.data(), result_dev, h.size() * sizeof(double),
-                                hipMemcpyDeviceToHost, ctx->stream);
-  if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
-  if (e != hipSuccess) return dev_fail(ctx, e, "pk_projected_to_host");
+  const double* h = nullptr;
+  if (pk_status st = read_result(ctx, result_dev, 3 * (size_t)nk + 2, &h, "pk_projected_to_host"))
+    return st;
   const int d = (keep & 1) + ((keep >> 1) & 1) + ((keep >> 2) & 1);
   const double L = m->boxsize;
   const double area = d == 1 ? L : L * L;
@@ -893,11 +923,9 @@ pk_status pk_result_to_host(pk_ctx* ctx, const pk_mesh_desc* m, const pk_bin_des
   BinTables* bt = nullptr;
   if (pk_status st = get_bin_tables(ctx, m, b, &bt)) return st;
   const int nsum = nsum_of(b);
-  std::vector<double> h(nsum + 2);
-  hipError_t e = hipMemcpyAsync(h.data(), result_dev, h.size() * sizeof(double),
-                                hipMemcpyDeviceToHost, ctx->stream);
-  if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
-  if (e != hipSuccess) return dev_fail(ctx, e, "pk_result_to_host");
+  const double* h = nullptr;
+  if (pk_status st = read_result(ctx, result_dev, (size_t)nsum + 2, &h, "pk_result_to_host"))
+    return st;
   const double L = m->boxsize;
   const double volume = L * L * L;
   const double kf = 2.0 * 3.14159265358979323846 / L;
@@ -1193,11 +1221,10 @@ pk_status pk_convolved_to_host(pk_ctx* ctx, const pk_mesh_desc* m, const pk_bin_
   BinTables* bt = nullptr;
   if (pk_status st = get_bin_tables(ctx, m, &pb, &bt)) return st;
   const int nk = b->nk;
-  std::vector<double> h(pk_convolved_doubles(b));
-  hipError_t e = hipMemcpyAsync(h.data(), result_dev, h.size() * sizeof(double),
-                                hipMemcpyDeviceToHost, ctx->stream);
-  if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
-  if (e != hipSuccess) return dev_fail(ctx, e, "pk_convolved_to_host");
+  const double* h = nullptr;
+  if (pk_status st = read_result(ctx, result_dev, pk_convolved_doubles(b), &h,
+                                 "pk_convolved_to_host"))
+    return st;
   const double kf = 2.0 * 3.14159265358979323846 / m->boxsize;
   const double nan = std::nan("");
   for (int k = 0; k < nk; ++k) {
@@ -1208,7 +1235,7 @@ pk_status pk_convolved_to_host(pk_ctx* ctx, const pk_mesh_desc* m, const pk_bin_
       out->poles[(size_t)i * nk + k] =
           nb ? (2 * b->poles[i] + 1) * h[(size_t)i * nk + k] / (norm * (double)nb) : nan;
   }
-  const double* ws = h.data() + (size_t)b->npoles * nk;
+  const double* ws = h + (size_t)b->npoles * nk;
   const double alpha = ws[0] / ws[2];
   out->wsum = ws[0];
   out->w2sum = ws[1];

@@ -187,4 +187,10 @@ struct pk_ctx {
   };
   std::vector<Lane> lanes;
   hipEvent_t tables_ready = nullptr;  // recorded on the context stream before lane work
+  // pinned host staging of the result sums read back by the *_to_host calls
+  // (a copy into pageable memory goes through a bounce buffer); grown on
+  // demand, the pageable vector only if pinned memory is refused
+  double* host_stage = nullptr;
+  size_t host_stage_n = 0;
+  std::vector<double> host_fallback;
 };
