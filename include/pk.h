@@ -346,8 +346,9 @@ pk_status pk_fftpower_v(pk_ctx *ctx, const pk_mesh_desc *m, const pk_bin_desc *b
  * {sum_data w, sum_data w^2, sum_randoms w, sum_randoms w^2}.  */
 size_t pk_convolved_doubles(const pk_bin_desc *b);
 /* Device workspace of pk_convolved_power (bytes), 0 for invalid arguments:
- * the concatenated catalog, its records, one mesh and one spectrum per
- * field F_ell kept. */
+ * the concatenated catalog, its records, the painted amounts of every
+ * harmonic Y_lm (sum over the fields of 2 ell + 1 values per particle), two
+ * meshes and one spectrum per field F_ell kept. */
 size_t pk_convolved_workspace_bytes(const pk_mesh_desc *m, const pk_bin_desc *b, int64_t n_data,
                                     int64_t n_rand);
 /*   observer    host, 3 doubles, box coordinates

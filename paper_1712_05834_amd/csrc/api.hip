@@ -1038,9 +1038,10 @@ int survey_fields(const pk_bin_desc* b, int* ells) {
 
 struct SurveyLayout {
   size_t pos = 0, value = 0, sums = 0, zero = 0, bsums = 0, sumpart = 0, bucket = 0, rec = 0,
-         wbase = 0, mesh = 0, side = 0, fields = 0, bpart = 0, total = 0;
-  size_t field_bytes = 0;
-  int gb = 0, gp = 0;
+         wbase = 0, amounts = 0, mesh = 0, ymesh = 0, side = 0, fields = 0, planes = 0,
+         bpart = 0, total = 0;
+  size_t field_bytes = 0, plane_bytes = 0, amount_bytes = 0;
+  int gb = 0, gp = 0, nh = 0;
 };
 
 SurveyLayout survey_layout(const pk_mesh_desc* m, const pk_bin_desc* b, int64_t nd, int64_t nr) {
@@ -1050,7 +1051,10 @@ SurveyLayout survey_layout(const pk_mesh_desc* m, const pk_bin_desc* b, int64_t 
   const size_t np = (size_t)(nd > 0 ? nd : 0) + (size_t)(nr > 0 ? nr : 0);
   int ells[4];
   const int nf = survey_fields(b, ells);
+  for (int f = 0; f < nf; ++f) l.nh += 2 * ells[f] + 1;
   l.field_bytes = align256(n * n * n * es);
+  l.plane_bytes = align256(n * n * 2 * es);
+  l.amount_bytes = align256(np * es);
   const size_t total_modes = n * n * (n / 2);
   size_t gb = (total_modes + 255) / 256;
   if (gb > 1024) gb = 1024;
@@ -1071,9 +1075,12 @@ SurveyLayout survey_layout(const pk_mesh_desc* m, const pk_bin_desc* b, int64_t 
   l.bucket = take(bucket_bytes(m->nmesh));
   l.rec = take(np * 4 * es);
   l.wbase = take(np * es);
+  l.amounts = take((size_t)l.nh * l.amount_bytes);
   l.mesh = take(l.field_bytes);
+  l.ymesh = take(l.field_bytes);
   l.side = take(n * n * 2 * es);
   l.fields = take((size_t)nf * l.field_bytes);
+  l.planes = take((size_t)nf * l.plane_bytes);
   l.bpart = take((size_t)(l.gb + l.gp) * b->nk * sizeof(double));
   l.total = off;
   return l;
@@ -1167,36 +1174,46 @@ pk_status pk_convolved_power(pk_ctx* ctx, const pk_mesh_desc* m, const pk_bin_de
                       ws + l.rec, ws + l.wbase, bsums, s);
   void* rec = ws + l.rec;
   void* base = ws + l.wbase;
-  const double pi = 3.14159265358979323846;
-  for (int f = 0; f < nf && e == hipSuccess; ++f) {
-    const int ell = ells[f];
-    for (int mm = -ell; mm <= ell && e == hipSuccess; ++mm) {
-      const Harmonic h = harmonic_of(ell, mm);
-      // the sorted amounts times Y_lm(r^) (value is free after the bucketing)
-      e = launch_ylm_records(m->dtype, m->nmesh, m->boxsize, rec, base, ws + l.bucket, observer,
-                             h, value, s);
-      // the painted field has mean ~0: nothing is subtracted before the z-FFT
-      if (e == hipSuccess)
-        e = launch_paint_z(m->dtype, m->nmesh, m->window, false, rec, value, ws + l.bucket, zero,
-                           t->tw, mesh, nullptr, s);
-      if (e == hipSuccess)
-        e = launch_fft_cols(m->dtype, m->nmesh, mesh, 1, l.field_bytes, t->tw, 1, s);
-      if (e == hipSuccess)
-        e = launch_x_accumulate(m->dtype, m->nmesh, mesh, field(f), ws + l.side, h,
-                                4.0 * pi / (2 * ell + 1), *t, m->window, m->compensated,
-                                mm == -ell ? 1 : 0, s);
+  void* ymesh = ws + l.ymesh;
+  auto plane = [&](int i) -> void* { return ws + l.planes + (size_t)i * l.plane_bytes; };
+  auto amount = [&](int k) -> void* { return ws + l.amounts + (size_t)k * l.amount_bytes; };
+  // the sorted amounts times Y_lm(r^), every harmonic in one pass
+  HarmonicSet hs;
+  int field_of[kMaxHarmonics], first_of[kMaxHarmonics];
+  for (int f = 0; f < nf; ++f)
+    for (int mm = -ells[f]; mm <= ells[f]; ++mm) {
+      field_of[hs.n] = f;
+      first_of[hs.n] = mm == -ells[f] ? 1 : 0;
+      hs.h[hs.n++] = harmonic_of(ells[f], mm);
     }
+  if (e == hipSuccess)
+    e = launch_ylm_records(m->dtype, m->nmesh, m->boxsize, rec, base, ws + l.bucket, observer, hs,
+                           l.amount_bytes / es, ws + l.amounts, s);
+  // each harmonic: paint with the z-pass, the y-pass into the x-pass layout,
+  // the x-pass accumulating into F_ell.  The painted field has mean ~0:
+  // nothing is subtracted before the z-FFT.
+  const double pi = 3.14159265358979323846;
+  for (int k = 0; k < hs.n && e == hipSuccess; ++k) {
+    const int f = field_of[k];
+    e = launch_paint_z(m->dtype, m->nmesh, m->window, false, rec, amount(k), ws + l.bucket, zero,
+                       t->tw, mesh, nullptr, s);
+    if (e == hipSuccess) e = launch_fft_y_relayout(m->dtype, m->nmesh, mesh, ymesh, t->tw, s);
+    if (e == hipSuccess)
+      e = launch_x_accumulate(m->dtype, m->nmesh, ymesh, field(f), plane(f), ws + l.side, hs.h[k],
+                              4.0 * pi / (2 * ells[f] + 1), *t, m->window, m->compensated,
+                              first_of[k], s);
   }
-  // sums of Re F_0 conj F_ell per k bin, then the weight sums
+  // sums of Re F_0 conj F_ell per k bin (the fields in the y-pass output
+  // layout, their kz = 0 planes apart), then the weight sums
   double* part = reinterpret_cast<double*>(ws + l.bpart);
   for (int i = 0; i < b->npoles && e == hipSuccess; ++i) {
     int f = 0;
     while (ells[f] != b->poles[i]) ++f;
     const void* c2 = f == 0 ? nullptr : field(f);
-    e = launch_bin_packed(m->dtype, m->nmesh, field(0), c2, spec, part, s);
+    e = launch_bin_packed(m->dtype, m->nmesh, field(0), c2, spec, part, s, 1);
     if (e == hipSuccess)
-      e = launch_plane_bin(m->dtype, m->nmesh, field(0), c2, m->nmesh / 2, *t, m->window, 0, spec,
-                           part + (size_t)l.gb * spec.nsum, s, c2 ? 1 : 0);
+      e = launch_plane_bin(m->dtype, m->nmesh, plane(0), f == 0 ? nullptr : plane(f), 1, *t,
+                           m->window, 0, spec, part + (size_t)l.gb * spec.nsum, s, c2 ? 1 : 0);
     if (e == hipSuccess)
       e = launch_reduce(part, l.gb + l.gp, spec, result_dev + (size_t)i * b->nk, s);
   }

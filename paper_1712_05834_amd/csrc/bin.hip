@@ -322,23 +322,37 @@ __global__ void __launch_bounds__(256)
 }
 
 // Stand-alone binning of a packed spectrum, columns kz' >= 1 (h = 2): |c|^2,
-// or Re(c conj(c2)) when a second spectrum is given (cross power).
+// or Re(c conj(c2)) when a second spectrum is given (cross power).  lw < 0:
+// the plain packed layout; otherwise the y-pass output layout with groups of
+// 2^lw columns and x blocks of 2^lbx (YLayout), walked in its storage order:
+// the linear index holds, from the lowest bits up, col % W, kx % BX, ky,
+// kx / BX and col / W.
 template <typename T>
 __global__ void __launch_bounds__(256)
     k_bin_packed(int N, const cpx<T>* __restrict__ cm, const cpx<T>* __restrict__ cm2, BinSpec b,
-                 double* __restrict__ partials) {
+                 double* __restrict__ partials, int lw, int lbx) {
   extern __shared__ double sb[];
   zero_bins(sb, b.nsum);
   __syncthreads();
   const int NC = N / 2;
   const size_t total = (size_t)N * N * NC;
   const int los = b.los;
+  const int ln = __ffs(N) - 1;
   for (size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
        idx += (size_t)gridDim.x * blockDim.x) {
-    const int col = (int)(idx % NC);
+    int col, kx, ky;
+    if (lw < 0) {
+      col = (int)(idx % NC);
+      const size_t rest = idx / NC;
+      ky = (int)(rest % N);
+      kx = (int)(rest / N);
+    } else {
+      col = (int)(((idx >> (lw + 2 * ln)) << lw) | (idx & ((1u << lw) - 1)));
+      ky = (int)((idx >> (lw + lbx)) & (size_t)(N - 1));
+      kx = (int)((((idx >> (lw + lbx + ln)) & (size_t)((N >> lbx) - 1)) << lbx) |
+                 ((idx >> lw) & ((1u << lbx) - 1)));
+    }
     if (col == 0) continue;
-    const size_t rest = idx / NC;
-    const int ky = (int)(rest % N), kx = (int)(rest / N);
     const int nx = signed_index(kx, N), ny = signed_index(ky, N), nz = col;
     const cpx<T> cc = cm[idx];
     const cpx<T> dd = cm2 ? cm2[idx] : cc;
@@ -663,19 +677,41 @@ hipError_t launch_xpass_bin(int dtype, int nmesh, const void* mesh_a, const void
 #undef PK_XB
 }
 
+// log2 of the column group width W and of the x block BX of YLayout<T, N>.
+template <typename T>
+static bool ylayout_bits(int nmesh, int* lw, int* lbx) {
+  switch (nmesh) {
+#define PK_YB(NN)                             \
+  case NN:                                    \
+    *lw = ilog2(YLayout<T, NN>::W);           \
+    *lbx = ilog2(YLayout<T, NN>::BX);         \
+    return true;
+    PK_YB(8) PK_YB(16) PK_YB(32) PK_YB(64) PK_YB(128) PK_YB(256) PK_YB(512) PK_YB(1024)
+    PK_YB(2048)
+#undef PK_YB
+    default: return false;
+  }
+}
+
 hipError_t launch_bin_packed(int dtype, int nmesh, const void* cmesh, const void* cmesh2,
-                             const BinSpec& b, double* partials, hipStream_t s) {
+                             const BinSpec& b, double* partials, hipStream_t s, int ylayout) {
   const size_t total = (size_t)nmesh * nmesh * (nmesh / 2);
   size_t g = (total + 255) / 256;
   if (g > 1024) g = 1024;
+  int lw = -1, lbx = 0;
+  if (ylayout) {
+    const bool ok = dtype == PK_F32 ? ylayout_bits<float>(nmesh, &lw, &lbx)
+                                    : ylayout_bits<double>(nmesh, &lw, &lbx);
+    if (!ok) return hipErrorInvalidValue;
+  }
   if (dtype == PK_F32)
     hipLaunchKernelGGL(k_bin_packed<float>, dim3((unsigned)g), dim3(256), bin_lds_bytes(b), s,
                        nmesh, static_cast<const cpx<float>*>(cmesh),
-                       static_cast<const cpx<float>*>(cmesh2), b, partials);
+                       static_cast<const cpx<float>*>(cmesh2), b, partials, lw, lbx);
   else
     hipLaunchKernelGGL(k_bin_packed<double>, dim3((unsigned)g), dim3(256), bin_lds_bytes(b), s,
                        nmesh, static_cast<const cpx<double>*>(cmesh),
-                       static_cast<const cpx<double>*>(cmesh2), b, partials);
+                       static_cast<const cpx<double>*>(cmesh2), b, partials, lw, lbx);
   return hipGetLastError();
 }
 

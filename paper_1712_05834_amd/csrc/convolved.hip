@@ -15,11 +15,12 @@
 // associated Legendre recurrence in z and the powers of (x + i y), so the
 // same routine serves the positions (r^) and the wave vectors (k^).  The
 // catalog (data and randoms in one) is bucketed by column once, with the
-// amounts w s; every harmonic then rescales the sorted amounts by Y_lm(r^)
-// of the record's position, paints (with the z-pass), runs the y-pass and
-// an x-pass that adds its lines into F_ell.  This file holds the weight sums,
-// the amounts and the fused x-pass + accumulation; bucketing, painting, the
-// y-pass and the binning are the kernels of the FFTPower path.
+// amounts w s; one pass over the sorted records then writes the amounts
+// times Y_lm(r^) of the record's position for every harmonic, and each
+// harmonic paints (with the z-pass), runs the y-pass into the x-pass layout
+// and an x-pass that adds its lines into F_ell.  This file holds the weight
+// sums, the amounts and the fused x-pass + accumulation; bucketing, painting,
+// the y-pass and the binning are the kernels of the FFTPower path.
 #include "fft_config.h"
 #include "internal.h"
 
@@ -148,14 +149,60 @@ __global__ void __launch_bounds__(256)
 __device__ __forceinline__ unsigned record_cell_bits(float w) { return __float_as_uint(w); }
 __device__ __forceinline__ unsigned record_cell_bits(double w) { return (unsigned)w; }
 
-// amount_j = base_j Y_lm(r^_j) for the records of one column per wavefront:
-// base holds w s of every record, r^ points from the observer to the
-// record's position (ix + t_x, iy + t_y, iz + t_z) h in the periodic box.
+// Every real harmonic Y_lm with ell <= 4 at the unit vector (x, y, z), up to
+// its normalisation, written to y[ell (ell + 1) + m]: Q_ell^|m|(z) times
+// Re (x + i y)^|m| (m >= 0) or Im (x + i y)^|m| (m < 0) -- the terms of
+// real_harmonic, with the powers and the recurrences shared by all 25.
+__device__ __forceinline__ void harmonics_to_4(double x, double y, double z, double* out) {
+  double re[5], im[5];
+  re[0] = 1.0;
+  im[0] = 0.0;
+#pragma unroll
+  for (int m = 1; m <= 4; ++m) {
+    re[m] = re[m - 1] * x - im[m - 1] * y;
+    im[m] = re[m - 1] * y + im[m - 1] * x;
+  }
+#pragma unroll
+  for (int m = 0; m <= 4; ++m) {
+    double q0 = 1.0;  // Q_m^m = (2m - 1)!!
+#pragma unroll
+    for (int i = 1; i <= m; ++i) q0 *= (double)(2 * i - 1);
+    double q1 = 0.0;
+#pragma unroll
+    for (int l = m; l <= 4; ++l) {
+      double q;
+      if (l == m) {
+        q = q0;
+      } else if (l == m + 1) {
+        q = (double)(2 * m + 1) * z * q0;
+        q1 = q;
+      } else {
+        q = ((double)(2 * l - 1) * z * q1 - (double)(l + m - 1) * q0) / (double)(l - m);
+        q0 = q1;
+        q1 = q;
+      }
+      out[l * (l + 1) + m] = q * re[m];
+      if (m > 0) out[l * (l + 1) - m] = q * im[m];
+    }
+  }
+}
+
+// amount[k][j] = base_j Y_k(r^_j) for every harmonic k of the set, for the
+// records of one column per wavefront: base holds w s of every record, r^
+// points from the observer to the record's position (ix + t_x, iy + t_y,
+// iz + t_z) h in the periodic box.  One pass writes all harmonics, so the
+// records are read once rather than once per harmonic.  slot[q] (q =
+// ell (ell + 1) + m) is the harmonic's index k in the set, or -1.
+struct YlmSlots {
+  int slot[kMaxHarmonics];
+  double knorm[kMaxHarmonics];
+};
+
 template <typename T, typename R>
 __global__ void __launch_bounds__(256)
     k_ylm_records(const R* __restrict__ rec, const T* __restrict__ base,
                   const int* __restrict__ offsets, int N, double h, double ox, double oy,
-                  double oz, int ell, int am, int sine, double knorm, T* __restrict__ amount) {
+                  double oz, YlmSlots ys, size_t stride, T* __restrict__ amount) {
   const int col = (int)blockIdx.x * 4 + (int)(threadIdx.x >> 6);
   if (col >= N * N) return;
   const int ix = col / N;
@@ -178,7 +225,13 @@ __global__ void __launch_bounds__(256)
       ry = 0.0;
       rz = 1.0;
     }
-    amount[j] = static_cast<T>((double)base[j] * real_harmonic(ell, am, sine, knorm, rx, ry, rz));
+    double y[kMaxHarmonics];
+    harmonics_to_4(rx, ry, rz, y);
+    const double b = (double)base[j];
+#pragma unroll
+    for (int q = 0; q < kMaxHarmonics; ++q)
+      if (ys.slot[q] >= 0)
+        amount[(size_t)ys.slot[q] * stride + j] = static_cast<T>(b * (ys.knorm[q] * y[q]));
   }
 }
 
@@ -206,29 +259,47 @@ __device__ __forceinline__ double mode_factor(int nx, int ny, int nz, int kx, in
 
 // Last FFT pass (along x) of one harmonic's spectrum A_lm, fused with the
 // accumulation F_ell (+)= coef Y_lm(k^) A_lm / W(k): the transformed lines are
-// added into F instead of being written back.  Column kz' >= 1 holds
-// c(kx, ky, kz'); column 0 packs the planes kz = 0 and N/2 and needs the
-// partner mode (-kx, -ky), which another workgroup transforms, so its lines
-// go to `side` ([kx][ky]) for k_plane_accumulate.
+// added into F instead of being written back.  A arrives from the y-pass in
+// its output layout (YLayout: the kx lines of a tile lie in a few pages
+// rather than one page per kx) and F is kept in the same layout, so the
+// read-modify-write of F has the locality of the loads.  Column kz' >= 1
+// holds c(kx, ky, kz'); column 0 packs the planes kz = 0 and N/2 and needs
+// the partner mode (-kx, -ky), which another workgroup transforms, so its
+// lines go to `side` ([kx][ky]) for k_plane_accumulate.
 template <typename T, int N>
-__global__ void __launch_bounds__((ColCfg<T, N>::THREADS))
+__global__ void __launch_bounds__((XCfg<T, N>::THREADS))
     k_fft_x_accumulate(const cpx<T>* __restrict__ mesh, cpx<T>* __restrict__ f,
                        cpx<T>* __restrict__ side, const cpx<T>* __restrict__ tw, int ell, int am,
                        int sine, double knorm, double coef, const T* __restrict__ sinv,
                        int first) {
-  using Cf = ColCfg<T, N>;
-  constexpr int E = Cf::E, TPL = Cf::TPL, C = Cf::C, NC = Cf::NC;
+  using Cf = XCfg<T, N>;
+  using YL = YLayout<T, N>;
+  using Ix = typename YL::Ix;
+  static_assert(YL::CX == Cf::C, "y-pass layout built for this tile width");
+  constexpr int E = Cf::E, TPL = Cf::TPL, C = Cf::C;
   __shared__ cpx<T> lds[Cf::LDS_ELEMS];
   __shared__ cpx<T> tws[stage_table_size<N, E>() + 1];
   build_stage_table<T, N, E>(tws, TwGlobal<T>{tw, 1});
   const TwStage<T, N, E> tw1{tws};
   const int c = threadIdx.x % C, t = threadIdx.x / C;
-  const int tile = xcd_pair_tile(blockIdx.x, N * Cf::CHUNKS);
+  const int tile = xcd_group_tile<YL::G>(blockIdx.x, N * Cf::CHUNKS);
   const int ky = tile / Cf::CHUNKS, col = (tile % Cf::CHUNKS) * C + c;
-  const size_t base = (size_t)ky * NC + col, step = (size_t)N * NC;
-  cpx<T> v[E];
+  // kx = t + TPL e: with TPL a multiple of BX the offsets of a thread's
+  // points differ by a constant
+  constexpr bool REG = TPL % YL::BX == 0;
+  constexpr Ix kstep = REG ? (Ix)(TPL / YL::BX) * ((Ix)N * YL::BX * YL::W) : 0;
+  auto at = [&](int e) -> Ix {
+    if constexpr (REG) return YL::at(t, ky, col) + (Ix)e * kstep;
+    return YL::at(t + TPL * e, ky, col);
+  };
+  // the running F is loaded with the lines, so its latency overlaps the FFT
+  cpx<T> v[E], old[E];
 #pragma unroll
-  for (int e = 0; e < E; ++e) v[e] = mesh[base + (size_t)(t + TPL * e) * step];
+  for (int e = 0; e < E; ++e) v[e] = mesh[at(e)];
+  if (!first && col != 0) {
+#pragma unroll
+    for (int e = 0; e < E; ++e) old[e] = f[at(e)];
+  }
   LdsCols<T, C> lc{lds, c};
   stockham<T, N, E, 1>(v, t, tw1, lc);
   const int ny = signed_wave(ky, N);
@@ -241,29 +312,27 @@ __global__ void __launch_bounds__((ColCfg<T, N>::THREADS))
     }
     const T g = static_cast<T>(
         mode_factor<T>(signed_wave(kx, N), ny, col, kx, ky, ell, am, sine, knorm, coef, sinv));
-    const size_t idx = base + (size_t)kx * step;
     cpx<T> o = {g * v[e].x, g * v[e].y};
     if (!first) {
-      const cpx<T> old = f[idx];
-      o.x += old.x;
-      o.y += old.y;
+      o.x += old[e].x;
+      o.y += old[e].y;
     }
-    f[idx] = o;
+    f[at(e)] = o;
   }
 }
 
 // The packed column of the harmonic (`side`, after the x-pass): its kz = 0
-// value (Z + conj Z(-k)) / 2 is accumulated into column 0 of F.  F stores the
-// kz = 0 value alone there: F_ell is Hermitian on that plane (A_lm is the
-// transform of a real field and Y_lm(-k^) = Y_lm(k^) for even ell), so this
-// is the packed form of a spectrum whose kz = N/2 plane is zero -- those
-// modes have |n| >= N/2 and are never binned.
+// value (Z + conj Z(-k)) / 2 is accumulated into the plane buffer of F
+// ([kx][ky]).  F is Hermitian on that plane (A_lm is the transform of a real
+// field and Y_lm(-k^) = Y_lm(k^) for even ell), so the plane read as a
+// packed column is the packed form of a spectrum whose kz = N/2 plane is
+// zero -- those modes have |n| >= N/2 and are never binned.
 template <typename T>
 __global__ void __launch_bounds__(256)
-    k_plane_accumulate(int N, const cpx<T>* __restrict__ side, cpx<T>* __restrict__ f, int ell,
-                       int am, int sine, double knorm, double coef, const T* __restrict__ sinv,
-                       int first) {
-  const int NC = N / 2, mask = N - 1;
+    k_plane_accumulate(int N, const cpx<T>* __restrict__ side, cpx<T>* __restrict__ plane,
+                       int ell, int am, int sine, double knorm, double coef,
+                       const T* __restrict__ sinv, int first) {
+  const int mask = N - 1;
   for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < N * N;
        idx += gridDim.x * blockDim.x) {
     const int kx = idx / N, ky = idx % N;
@@ -271,14 +340,13 @@ __global__ void __launch_bounds__(256)
     const cpx<T> v = {T(0.5) * (z.x + zp.x), T(0.5) * (z.y - zp.y)};
     const T g = static_cast<T>(mode_factor<T>(signed_wave(kx, N), signed_wave(ky, N), 0, kx, ky,
                                               ell, am, sine, knorm, coef, sinv));
-    const size_t at = (size_t)idx * NC;
     cpx<T> o = {g * v.x, g * v.y};
     if (!first) {
-      const cpx<T> old = f[at];
+      const cpx<T> old = plane[idx];
       o.x += old.x;
       o.y += old.y;
     }
-    f[at] = o;
+    plane[idx] = o;
   }
 }
 
@@ -327,7 +395,21 @@ hipError_t launch_ylm_value(int dtype, const void* pos, const void* wd, int64_t 
 
 hipError_t launch_ylm_records(int dtype, int nmesh, double boxsize, const void* rec,
                               const void* base, const void* bucket_ws, const double* observer,
-                              const Harmonic& hm, void* amount, hipStream_t s) {
+                              const HarmonicSet& hs, size_t stride, void* amount,
+                              hipStream_t s) {
+  if (hs.n < 1 || hs.n > kMaxHarmonics) return hipErrorInvalidValue;
+  YlmSlots ys;
+  for (int q = 0; q < kMaxHarmonics; ++q) {
+    ys.slot[q] = -1;
+    ys.knorm[q] = 0.0;
+  }
+  for (int k = 0; k < hs.n; ++k) {
+    const Harmonic& hm = hs.h[k];
+    if (hm.ell > 4 || hm.am > hm.ell) return hipErrorInvalidValue;
+    const int q = hm.ell * (hm.ell + 1) + (hm.sine ? -hm.am : hm.am);
+    ys.slot[q] = k;
+    ys.knorm[q] = hm.knorm;
+  }
   // the column offsets follow the N^2 column counts at the start of the
   // bucketing workspace
   const int* offsets = static_cast<const int*>(bucket_ws) + (size_t)nmesh * nmesh;
@@ -336,39 +418,39 @@ hipError_t launch_ylm_records(int dtype, int nmesh, double boxsize, const void* 
   if (dtype == PK_F32)
     hipLaunchKernelGGL((k_ylm_records<float, float4>), dim3(g), dim3(256), 0, s,
                        static_cast<const float4*>(rec), static_cast<const float*>(base), offsets,
-                       nmesh, h, observer[0], observer[1], observer[2], hm.ell, hm.am, hm.sine,
-                       hm.knorm, static_cast<float*>(amount));
+                       nmesh, h, observer[0], observer[1], observer[2], ys, stride,
+                       static_cast<float*>(amount));
   else
     hipLaunchKernelGGL((k_ylm_records<double, double4>), dim3(g), dim3(256), 0, s,
                        static_cast<const double4*>(rec), static_cast<const double*>(base), offsets,
-                       nmesh, h, observer[0], observer[1], observer[2], hm.ell, hm.am, hm.sine,
-                       hm.knorm, static_cast<double*>(amount));
+                       nmesh, h, observer[0], observer[1], observer[2], ys, stride,
+                       static_cast<double*>(amount));
   return hipGetLastError();
 }
 
 template <typename T, int N>
-static hipError_t x_accumulate_t(const void* cmesh, void* field, void* side, const void* tw,
-                                 const Harmonic& h, double coef, const T* sinv, int first,
-                                 hipStream_t s) {
-  using Cf = ColCfg<T, N>;
+static hipError_t x_accumulate_t(const void* ymesh, void* field, void* plane, void* side,
+                                 const void* tw, const Harmonic& h, double coef, const T* sinv,
+                                 int first, hipStream_t s) {
+  using Cf = XCfg<T, N>;
   hipLaunchKernelGGL((k_fft_x_accumulate<T, N>), dim3((unsigned)(N * Cf::CHUNKS)),
-                     dim3(Cf::THREADS), 0, s, static_cast<const cpx<T>*>(cmesh),
+                     dim3(Cf::THREADS), 0, s, static_cast<const cpx<T>*>(ymesh),
                      static_cast<cpx<T>*>(field), static_cast<cpx<T>*>(side),
                      static_cast<const cpx<T>*>(tw), h.ell, h.am, h.sine, h.knorm, coef, sinv,
                      first);
   hipLaunchKernelGGL(k_plane_accumulate<T>, dim3(grid_for((size_t)N * N, 4096)), dim3(256), 0,
-                     s, N, static_cast<const cpx<T>*>(side), static_cast<cpx<T>*>(field), h.ell,
+                     s, N, static_cast<const cpx<T>*>(side), static_cast<cpx<T>*>(plane), h.ell,
                      h.am, h.sine, h.knorm, coef, sinv, first);
   return hipGetLastError();
 }
 
 template <typename T>
-static hipError_t x_accumulate_n(int nmesh, const void* cmesh, void* field, void* side,
-                                 const void* tw, const Harmonic& h, double coef, const T* sinv,
-                                 int first, hipStream_t s) {
+static hipError_t x_accumulate_n(int nmesh, const void* ymesh, void* field, void* plane,
+                                 void* side, const void* tw, const Harmonic& h, double coef,
+                                 const T* sinv, int first, hipStream_t s) {
   switch (nmesh) {
 #define PK_XA(NN) \
-  case NN: return x_accumulate_t<T, NN>(cmesh, field, side, tw, h, coef, sinv, first, s);
+  case NN: return x_accumulate_t<T, NN>(ymesh, field, plane, side, tw, h, coef, sinv, first, s);
     PK_XA(8) PK_XA(16) PK_XA(32) PK_XA(64) PK_XA(128) PK_XA(256) PK_XA(512) PK_XA(1024)
     PK_XA(2048)
 #undef PK_XA
@@ -376,17 +458,17 @@ static hipError_t x_accumulate_n(int nmesh, const void* cmesh, void* field, void
   }
 }
 
-hipError_t launch_x_accumulate(int dtype, int nmesh, const void* cmesh, void* field, void* side,
-                               const Harmonic& h, double coef, const MeshTables& t, int order,
-                               int compensated, int first, hipStream_t s) {
+hipError_t launch_x_accumulate(int dtype, int nmesh, const void* ymesh, void* field, void* plane,
+                               void* side, const Harmonic& h, double coef, const MeshTables& t,
+                               int order, int compensated, int first, hipStream_t s) {
   if (dtype == PK_F32) {
     const float* sinv =
         compensated ? static_cast<const float*>(t.sinc_inv) + (size_t)(order - 2) * nmesh : nullptr;
-    return x_accumulate_n<float>(nmesh, cmesh, field, side, t.tw, h, coef, sinv, first, s);
+    return x_accumulate_n<float>(nmesh, ymesh, field, plane, side, t.tw, h, coef, sinv, first, s);
   }
   const double* sinv =
       compensated ? static_cast<const double*>(t.sinc_inv) + (size_t)(order - 2) * nmesh : nullptr;
-  return x_accumulate_n<double>(nmesh, cmesh, field, side, t.tw, h, coef, sinv, first, s);
+  return x_accumulate_n<double>(nmesh, ymesh, field, plane, side, t.tw, h, coef, sinv, first, s);
 }
 
 }  // namespace pk

@@ -108,9 +108,10 @@ size_t xpass_static_lds(int dtype, int nmesh);
 hipError_t launch_xpass_bin(int dtype, int nmesh, const void* mesh_a, const void* mesh_b,
                             const MeshTables& t, int order, int compensated, const BinSpec& b,
                             double* partials, void* side_a, void* side_b, hipStream_t s);
-// cmesh2 != NULL: cross power Re(c conj(c2)) instead of |c|^2.
+// cmesh2 != NULL: cross power Re(c conj(c2)) instead of |c|^2.  ylayout = 1:
+// both spectra are in the y-pass output layout instead of the packed one.
 hipError_t launch_bin_packed(int dtype, int nmesh, const void* cmesh, const void* cmesh2,
-                             const BinSpec& b, double* partials, hipStream_t s);
+                             const BinSpec& b, double* partials, hipStream_t s, int ylayout = 0);
 // cross = 0: za (and the interlaced zb) combined; cross = 1: Re(a conj(b)).
 hipError_t launch_plane_bin(int dtype, int nmesh, const void* za, const void* zb, size_t zstride,
                             const MeshTables& t, int order, int compensated, const BinSpec& b,
@@ -149,15 +150,25 @@ hipError_t launch_survey_sums(int dtype, const void* wd, int64_t nd, const void*
 hipError_t launch_ylm_value(int dtype, const void* pos, const void* wd, int64_t nd, const void* wr,
                             int64_t nr, const double* observer, const Harmonic& h,
                             const double* sums, void* value, hipStream_t s);
-// amount[j] = base[j] Y_lm(r^_j) over the sorted records of launch_bucket.
+// The harmonics of one set of survey multipoles (at most 1 + 3 + 5 + 7 + 9).
+constexpr int kMaxHarmonics = 25;
+struct HarmonicSet {
+  int n = 0;
+  Harmonic h[kMaxHarmonics];
+};
+// amount[k stride + j] = base[j] Y_k(r^_j), for every harmonic k of the set,
+// over the sorted records of launch_bucket (one pass over the records).
 hipError_t launch_ylm_records(int dtype, int nmesh, double boxsize, const void* rec,
                               const void* base, const void* bucket_ws, const double* observer,
-                              const Harmonic& hm, void* amount, hipStream_t s);
-// x-pass of a y-transformed packed spectrum fused with field (+)= coef
-// Y_lm(k^) A / W(k); side: N^2 complex scratch for the packed column.
-hipError_t launch_x_accumulate(int dtype, int nmesh, const void* cmesh, void* field, void* side,
-                               const Harmonic& h, double coef, const MeshTables& t, int order,
-                               int compensated, int first, hipStream_t s);
+                              const HarmonicSet& hs, size_t stride, void* amount,
+                              hipStream_t s);
+// x-pass of a y-transformed spectrum in the y-pass output layout (ymesh,
+// from launch_fft_y_relayout) fused with field (+)= coef Y_lm(k^) A / W(k);
+// field is in the same layout, its kz = 0 plane goes to plane ([kx][ky],
+// N^2 complex) instead; side: N^2 complex scratch for the packed column.
+hipError_t launch_x_accumulate(int dtype, int nmesh, const void* ymesh, void* field, void* plane,
+                               void* side, const Harmonic& h, double coef, const MeshTables& t,
+                               int order, int compensated, int first, hipStream_t s);
 
 }  // namespace pk
 
