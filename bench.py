@@ -177,6 +177,9 @@ def main():
     ap.add_argument("--lanes", type=int, default=BATCH["lanes"],
                     help="concurrent lanes of the batch-mocks workload")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--shuffle", action="store_true",
+                    help="permute the catalog (seeded) before timing: a catalog in no "
+                         "particular order instead of the generator's cell order")
     ap.add_argument("--cpu-sample", type=float, default=0.5,
                     help="fraction of the catalog the oracle paints for cpu_baseline")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -219,8 +222,10 @@ def main():
     t0 = time.perf_counter()
     pos_host = make_catalog(w)
     npart = len(pos_host)
+    if args.shuffle:
+        pos_host = pos_host[np.random.default_rng(12345).permutation(npart)]
     log(f"workload {args.workload}: {npart} particles generated in "
-        f"{time.perf_counter() - t0:.1f} s")
+        f"{time.perf_counter() - t0:.1f} s" + (" (shuffled)" if args.shuffle else ""))
 
     dev = torch.device("cuda:0")
     pos = torch.from_numpy(pos_host).to(dev)
@@ -280,6 +285,7 @@ def main():
             "nmesh": w["n"], "boxsize": w["box"], "window": w["window"],
             "interlaced": w["interlaced"], "npart": npart, "nmu": w["nmu"],
             "poles": list(w["poles"]), "los": "z",
+            "order": "shuffled" if args.shuffle else "as generated",
         },
         "mparticles_per_s_painted": npart / (paint_ms * 1e-3) / 1e6 if paint_ms > 0 else None,
         "stage_ms": mean_ms,
@@ -291,7 +297,7 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": measured_traffic(args.workload, dominant),
+            "traffic": None if args.shuffle else measured_traffic(args.workload, dominant),
         },
         "cpu_baseline": None,
     }

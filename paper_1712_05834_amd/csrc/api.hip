@@ -715,8 +715,10 @@ hipError_t enqueue_fftpower(pk_ctx* ctx, hipStream_t s, const pk_mesh_desc* m,
   void* rec = ws + l.rec;
   void* wrec = (weight || value) ? ws + l.wrec : nullptr;
   stage(kBucket);
+  // the meshes are free until the painting: scratch of the bucketing
   hipError_t e = launch_bucket(m->dtype, m->nmesh, m->boxsize, pos, weight, value, n,
-                               ws + l.bucket, rec, wrec, wsums, s);
+                               ws + l.bucket, rec, wrec, wsums, s, ws + l.mesh_a,
+                               l.side_a - l.mesh_a);
   stage(kPaintZ);
   if (e == hipSuccess)
     e = launch_paint_z(m->dtype, m->nmesh, m->window, m->interlaced != 0, rec, wrec,
@@ -1171,7 +1173,7 @@ pk_status pk_convolved_power(pk_ctx* ctx, const pk_mesh_desc* m, const pk_bin_de
                          sums, value, s);
   if (e == hipSuccess)
     e = launch_bucket(m->dtype, m->nmesh, m->boxsize, pos, nullptr, value, n, ws + l.bucket,
-                      ws + l.rec, ws + l.wbase, bsums, s);
+                      ws + l.rec, ws + l.wbase, bsums, s, ws + l.mesh, l.bpart - l.mesh);
   void* rec = ws + l.rec;
   void* base = ws + l.wbase;
   void* ymesh = ws + l.ymesh;

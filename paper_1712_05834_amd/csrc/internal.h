@@ -78,10 +78,14 @@ hipError_t launch_paint_atomic(int dtype, int order, int nmesh, double boxsize, 
 // Sorted painting fused with the z-pass (paint_sorted.hip).
 size_t bucket_bytes(int nmesh);
 // value: per-particle field values V or NULL; records carry w V, the sums
-// are {sum w, sum (w V)^2}.
+// are {sum w, sum (w V)^2}.  scratch: device memory free during the
+// bucketing (n 4-vector records and n amounts, each rounded up to 256 bytes);
+// without it, or for catalogs under 2^14 particles, only the route for
+// catalogs in column order is taken.
 hipError_t launch_bucket(int dtype, int nmesh, double boxsize, const void* pos, const void* weight,
                          const void* value, int64_t n, void* bucket_ws, void* rec, void* wrec,
-                         double* wsums, hipStream_t s);
+                         double* wsums, hipStream_t s, void* scratch = nullptr,
+                         size_t scratch_bytes = 0);
 hipError_t launch_paint_z(int dtype, int nmesh, int order, bool inter, const void* rec,
                           const void* wrec, const void* bucket_ws, const double* wsums,
                           const void* tw, void* mesh_a, void* mesh_b, hipStream_t s);

@@ -11,6 +11,19 @@
 //                     written to its column's segment; the slots of a step are
 //                     reserved with one atomic per column through the same kind
 //                     of LDS table.
+// Catalogs that are not in column order (random order: no runs) take a
+// second route instead, chosen on the device by k_order_probe from sampled
+// neighbouring particles, without a round trip to the host (the workgroups
+// of k_bucket_count and k_bucket_scatter run the route chosen):
+// 1'. counting        per block of the catalog, LDS counts of the x-slabs
+//                     ix, stored as [slab][block]; their prefix sums (the
+//                     same scan kernels) give every block its own range in
+//                     each slab.
+// 3'. scattering      the records (and amounts) written slab by slab into
+//                     scratch memory, places ranked by LDS atomics.
+// 3''. k_slab_columns one workgroup per slab: LDS counts of its columns,
+//                     their offsets, then the records scattered into column
+//                     order.  No global atomics at all.
 // 4. k_paint_z        one workgroup owns a TX x TY block of full z-columns of
 //                     both meshes: it reads the records of the columns whose
 //                     windows reach the block, adds the window weights into
@@ -73,6 +86,24 @@ __device__ __forceinline__ WaveRun wave_run(int key) {
   return r;
 }
 
+// Route of a bucketing launch, chosen on the device by k_order_probe: mode
+// holds kProbeGroups counts of sampled neighbouring pairs that share a
+// column, out of kProbeSamples; with at least a quarter the catalog is taken
+// to be in column order (run route), else the slab route runs.  The kernels
+// of the other route return at once.  mode NULL: the run route alone.
+constexpr int kRouteRuns = 0, kRouteSlabs = 1;
+constexpr int kProbeGroups = 16, kProbeSamples = kProbeGroups * 256;
+__device__ __forceinline__ int route_of(const int* mode) {
+  if (mode == nullptr) return kRouteRuns;
+  int same = 0;
+#pragma unroll
+  for (int g = 0; g < kProbeGroups; ++g) same += mode[g];
+  return 4 * same >= kProbeSamples ? kRouteRuns : kRouteSlabs;
+}
+__device__ __forceinline__ bool off_route(const int* mode, int route) {
+  return route_of(mode) != route;
+}
+
 // Block-local table of column counts in LDS: runs of the same column from
 // the block's particles are added here and reach the global counters with one
 // atomic per column and block.  Global atomics (performed beyond the XCD's L2)
@@ -113,12 +144,166 @@ __device__ __forceinline__ void hash_clear(int* keys, int* cnts) {
 constexpr int kBucketUnroll = 4;
 constexpr int kBucketStep = 256 * kBucketUnroll;
 
+constexpr int kSlabBlocks = 1024;      // catalog blocks of the slab route (at most; <= N)
+constexpr int kMaxSlabs = 2048;        // x-slabs = N, N <= 2048
+constexpr int64_t kSlabMinParticles = 1 << 14;  // smaller catalogs: run route
+
+template <typename T>
+__device__ __forceinline__ int column_key(const T* __restrict__ pos, int64_t i, int nmesh,
+                                          double boxsize, double inv_box, double cpl) {
+  const int mask = nmesh - 1;
+  const double ux = cell_coordinate_rcp((double)pos[3 * i], boxsize, inv_box, cpl);
+  const double uy = cell_coordinate_rcp((double)pos[3 * i + 1], boxsize, inv_box, cpl);
+  return (((int)floor(ux)) & mask) * nmesh + (((int)floor(uy)) & mask);
+}
+
+// Arguments of the slab route's parts of k_bucket_count and
+// k_bucket_scatter: catalog blocks of chunk particles (nblocks of them), the
+// [slab][block] counts and their prefix sums, the scratch records and
+// amounts (amounts NULL without weights or values).
+struct SlabArgs {
+  int64_t chunk;
+  int nblocks;
+  int* hist;
+  const int* hoff;
+  void* trec;
+  void* twrec;
+};
+
+// Slab route, counting (run by the workgroups of k_bucket_count): block
+// blk of the catalog (particles blk chunk .. blk chunk + chunk - 1, nblocks
+// blocks): counts of its particles per x-slab in LDS, stored to
+// hist[slab][blk]; weight sums of the block to wpart as in the run route.
+template <typename T>
+__device__ void slab_count_block(const T* __restrict__ pos, const T* __restrict__ weight,
+                                 const T* __restrict__ value, int64_t n, int nmesh,
+                                 double boxsize, double inv_box, double cells_per_len,
+                                 const SlabArgs& sa, int blk, double* __restrict__ wpart) {
+  __shared__ int lh[kMaxSlabs];
+  __shared__ double part[2][4];
+  const int mask = nmesh - 1;
+  constexpr int U = kBucketUnroll;
+  const int64_t chunk = sa.chunk;
+  const int nblocks = sa.nblocks;
+  int* __restrict__ hist = sa.hist;
+  {
+    for (int b = threadIdx.x; b < nmesh; b += blockDim.x) lh[b] = 0;
+    __syncthreads();
+    double ws = 0.0, ws2 = 0.0;
+    const int64_t begin = (int64_t)blk * chunk;
+    const int64_t end = begin + chunk < n ? begin + chunk : n;
+    for (int64_t i0 = begin + threadIdx.x; i0 < end; i0 += kBucketStep) {
+      int slab[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int64_t i = i0 + u * 256;
+        slab[u] = -1;
+        if (i < end) {
+          const double ux =
+              cell_coordinate_rcp((double)pos[3 * i], boxsize, inv_box, cells_per_len);
+          slab[u] = ((int)floor(ux)) & mask;
+          const double wp = weight ? (double)weight[i] : 1.0;
+          const double wv = value ? wp * (double)value[i] : wp;
+          ws += wp;
+          ws2 += wv * wv;
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+        if (slab[u] >= 0) atomicAdd(&lh[slab[u]], 1);
+    }
+    ws = wave_sum_d(ws);
+    ws2 = wave_sum_d(ws2);
+    if ((threadIdx.x & 63) == 0) {
+      part[0][threadIdx.x >> 6] = ws;
+      part[1][threadIdx.x >> 6] = ws2;
+    }
+    __syncthreads();
+    for (int b = threadIdx.x; b < nmesh; b += blockDim.x) hist[(size_t)b * nblocks + blk] = lh[b];
+    if (threadIdx.x == 0) {
+      wpart[2 * blk] = ((part[0][0] + part[0][1]) + part[0][2]) + part[0][3];
+      wpart[2 * blk + 1] = ((part[1][0] + part[1][1]) + part[1][2]) + part[1][3];
+    }
+  }
+}
+
+// Slab route, scattering (run by the workgroups of k_bucket_scatter): the
+// records of block blk (same blocks as the counting) written into the slabs
+// of the scratch arrays: the block's range of slab x starts at hoff[x][blk]
+// (exclusive prefix sums of hist); places within it are taken in LDS.
+// Record and amount as in the run route.
+template <typename T>
+__device__ void slab_scatter_block(const T* __restrict__ pos, const T* __restrict__ weight,
+                                   const T* __restrict__ value, int64_t n, int nmesh,
+                                   double boxsize, double inv_box, double cells_per_len,
+                                   const SlabArgs& sa, int blk) {
+  using RecT = typename Rec<T>::type;
+  __shared__ int cur[kMaxSlabs];
+  const int mask = nmesh - 1;
+  constexpr int U = kBucketUnroll;
+  const int64_t chunk = sa.chunk;
+  const int nblocks = sa.nblocks;
+  const int* __restrict__ hoff = sa.hoff;
+  RecT* __restrict__ trec = static_cast<RecT*>(sa.trec);
+  T* __restrict__ twrec = static_cast<T*>(sa.twrec);
+  {
+  for (int b = threadIdx.x; b < nmesh; b += blockDim.x) cur[b] = hoff[(size_t)b * nblocks + blk];
+  __syncthreads();
+  const int64_t begin = (int64_t)blk * chunk;
+  const int64_t end = begin + chunk < n ? begin + chunk : n;
+  for (int64_t i0 = begin + threadIdx.x; i0 < end; i0 += kBucketStep) {
+    RecT r[U];
+    int slab[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t i = i0 + u * 256;
+      slab[u] = -1;
+      r[u] = RecT{};
+      if (i < end) {
+        double uu[3], f[3];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+          uu[d] = cell_coordinate_rcp((double)pos[3 * i + d], boxsize, inv_box, cells_per_len);
+          f[d] = floor(uu[d]);
+        }
+        slab[u] = ((int)f[0]) & mask;
+        const unsigned iy = ((unsigned)(int)f[1]) & mask, iz = ((unsigned)(int)f[2]) & mask;
+        r[u].x = static_cast<T>(uu[0] - f[0]);
+        r[u].y = static_cast<T>(uu[1] - f[1]);
+        r[u].z = static_cast<T>(uu[2] - f[2]);
+        if constexpr (sizeof(T) == 4) {
+          r[u].w = __uint_as_float((iy << 16) | iz);
+        } else {
+          r[u].w = (double)((iy << 16) | iz);
+        }
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t i = i0 + u * 256;
+      if (slab[u] >= 0) {
+        const int slot = atomicAdd(&cur[slab[u]], 1);
+        trec[slot] = r[u];
+        if (twrec) twrec[slot] = weight ? (value ? weight[i] * value[i] : weight[i]) : value[i];
+      }
+    }
+  }
+  }
+}
+
 template <typename T>
 __global__ void __launch_bounds__(256)
     k_bucket_count(const T* __restrict__ pos, const T* __restrict__ weight,
                    const T* __restrict__ value, int64_t n, int64_t chunk, int nmesh,
                    double boxsize, double inv_box, double cells_per_len,
-                   int* __restrict__ count, double* __restrict__ wpart) {
+                   int* __restrict__ count, double* __restrict__ wpart,
+                   const int* __restrict__ mode, SlabArgs sa) {
+  if (route_of(mode) == kRouteSlabs) {
+    if ((int)blockIdx.x < sa.nblocks)
+      slab_count_block<T>(pos, weight, value, n, nmesh, boxsize, inv_box, cells_per_len, sa,
+                          blockIdx.x, wpart);
+    return;
+  }
   __shared__ int hkeys[kHashSize], hcnts[kHashSize];
   hash_clear(hkeys, hcnts);
   __syncthreads();
@@ -173,7 +358,9 @@ __global__ void __launch_bounds__(256)
 
 // sum w and sum w^2 from the per-block partials, in block order.
 __global__ void __launch_bounds__(1024)
-    k_weight_sums(const double* __restrict__ wpart, int nblocks, double* __restrict__ wsums) {
+    k_weight_sums(const double* __restrict__ wpart, int nblocks_runs, int nblocks_slabs,
+                  double* __restrict__ wsums, const int* __restrict__ mode) {
+  const int nblocks = route_of(mode) == kRouteSlabs ? nblocks_slabs : nblocks_runs;
   __shared__ double sh[2][1024];
   double a = 0.0, b = 0.0;
   for (int i = threadIdx.x; i < nblocks; i += 1024) {
@@ -202,7 +389,14 @@ __global__ void __launch_bounds__(256)
                      const T* __restrict__ value, int64_t n, int64_t chunk, int nmesh,
                      double boxsize, double inv_box, double cells_per_len,
                      int* __restrict__ cursor,
-                     typename Rec<T>::type* __restrict__ rec, T* __restrict__ wrec) {
+                     typename Rec<T>::type* __restrict__ rec, T* __restrict__ wrec,
+                     const int* __restrict__ mode, SlabArgs sa) {
+  if (route_of(mode) == kRouteSlabs) {
+    if ((int)blockIdx.x < sa.nblocks)
+      slab_scatter_block<T>(pos, weight, value, n, nmesh, boxsize, inv_box, cells_per_len, sa,
+                            blockIdx.x);
+    return;
+  }
   // per step: the runs of each column in the step are ranked in the LDS
   // table, one global atomic per column reserves the step's slots, then every
   // particle writes its record at base + rank
@@ -295,54 +489,156 @@ __device__ __forceinline__ int block_scan_excl(int v, int* sh, int& total) {
   return r;
 }
 
+// An exclusive scan: counts in, offsets (n + 1 entries) and an optional copy
+// (cursor) out; the scan kernels run the job of the route taken (the column
+// counts of the run route or the [slab][block] counts of the slab route).
+struct ScanJob {
+  const int* count;
+  int n;
+  int* block_sums;
+  int* offsets;
+  int* cursor;
+};
+__device__ __forceinline__ ScanJob job_of(const ScanJob& runs, const ScanJob& slabs,
+                                          const int* mode) {
+  const bool sl = route_of(mode) == kRouteSlabs;
+  ScanJob j;
+  j.count = sl ? slabs.count : runs.count;
+  j.n = sl ? slabs.n : runs.n;
+  j.block_sums = sl ? slabs.block_sums : runs.block_sums;
+  j.offsets = sl ? slabs.offsets : runs.offsets;
+  j.cursor = sl ? slabs.cursor : runs.cursor;
+  return j;
+}
+
 __global__ void __launch_bounds__(1024)
-    k_scan_blocks(const int* __restrict__ count, int n, int* __restrict__ block_sums) {
+    k_scan_blocks(ScanJob runs, ScanJob slabs, const int* __restrict__ mode) {
+  const ScanJob j = job_of(runs, slabs, mode);
+  if ((int)blockIdx.x * 4096 >= j.n) return;
   __shared__ int sh[17];
   const int base = blockIdx.x * 4096 + threadIdx.x * 4;
   int s = 0;
 #pragma unroll
-  for (int j = 0; j < 4; ++j) s += (base + j < n) ? count[base + j] : 0;
+  for (int k = 0; k < 4; ++k) s += (base + k < j.n) ? j.count[base + k] : 0;
   int total;
   (void)block_scan_excl(s, sh, total);
-  if (threadIdx.x == 0) block_sums[blockIdx.x] = total;
+  if (threadIdx.x == 0) j.block_sums[blockIdx.x] = total;
 }
 
-__global__ void __launch_bounds__(1024) k_scan_sums(int* __restrict__ block_sums, int nb) {
+__global__ void __launch_bounds__(1024)
+    k_scan_sums(ScanJob runs, ScanJob slabs, const int* __restrict__ mode) {
+  const ScanJob j = job_of(runs, slabs, mode);
+  const int nb = (j.n + 4095) / 4096;
   __shared__ int sh[17];
   int carry = 0;
   for (int start = 0; start < nb; start += 1024) {
     const int i = start + threadIdx.x;
-    const int v = i < nb ? block_sums[i] : 0;
+    const int v = i < nb ? j.block_sums[i] : 0;
     int total;
     const int ex = block_scan_excl(v, sh, total);
-    if (i < nb) block_sums[i] = carry + ex;
+    if (i < nb) j.block_sums[i] = carry + ex;
     carry += total;
   }
 }
 
 __global__ void __launch_bounds__(1024)
-    k_scan_final(const int* __restrict__ count, int n, const int* __restrict__ block_sums,
-                 int* __restrict__ offsets, int* __restrict__ cursor) {
+    k_scan_final(ScanJob runs, ScanJob slabs, const int* __restrict__ mode) {
+  const ScanJob j = job_of(runs, slabs, mode);
+  const int nb = (j.n + 4095) / 4096;
+  if ((int)blockIdx.x >= nb) return;
   __shared__ int sh[17];
   const int base = blockIdx.x * 4096 + threadIdx.x * 4;
   int v[4];
   int s = 0;
 #pragma unroll
-  for (int j = 0; j < 4; ++j) {
-    v[j] = (base + j < n) ? count[base + j] : 0;
-    s += v[j];
+  for (int k = 0; k < 4; ++k) {
+    v[k] = (base + k < j.n) ? j.count[base + k] : 0;
+    s += v[k];
   }
   int total;
-  int ex = block_scan_excl(s, sh, total) + block_sums[blockIdx.x];
+  int ex = block_scan_excl(s, sh, total) + j.block_sums[blockIdx.x];
 #pragma unroll
-  for (int j = 0; j < 4; ++j) {
-    if (base + j < n) {
-      offsets[base + j] = ex;
-      cursor[base + j] = ex;
+  for (int k = 0; k < 4; ++k) {
+    if (base + k < j.n) {
+      j.offsets[base + k] = ex;
+      if (j.cursor) j.cursor[base + k] = ex;
     }
-    ex += v[j];
+    ex += v[k];
   }
-  if (blockIdx.x == gridDim.x - 1 && threadIdx.x == blockDim.x - 1) offsets[n] = ex;
+  if ((int)blockIdx.x == nb - 1 && threadIdx.x == blockDim.x - 1) j.offsets[j.n] = ex;
+}
+
+// ---- the slab route (catalogs not in column order)
+
+// The route's sample: kProbeSamples pairs (i, i + 1) spread over the catalog
+// (n >= 2), one per thread of kProbeGroups workgroups; each workgroup stores
+// how many of its pairs share a column.
+template <typename T>
+__global__ void __launch_bounds__(256)
+    k_order_probe(const T* __restrict__ pos, int64_t n, int nmesh, double boxsize,
+                  double inv_box, double cpl, int* __restrict__ mode) {
+  const int j = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+  // i <= n - 2, so i + 1 is a particle
+  const int64_t i = (int64_t)((double)j * (double)(n - 2) / (double)(kProbeSamples - 1));
+  int same = column_key(pos, i, nmesh, boxsize, inv_box, cpl) ==
+                     column_key(pos, i + 1, nmesh, boxsize, inv_box, cpl)
+                 ? 1
+                 : 0;
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) same += __shfl_xor(same, off, 64);
+  __shared__ int sh[4];
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = same;
+  __syncthreads();
+  if (threadIdx.x == 0) mode[blockIdx.x] = sh[0] + sh[1] + sh[2] + sh[3];
+}
+
+__device__ __forceinline__ int record_iy(float4 r) { return (int)(__float_as_uint(r.w) >> 16); }
+__device__ __forceinline__ int record_iy(double4 r) { return (int)((unsigned)r.w >> 16); }
+
+// One workgroup (1024 threads) per x-slab (slabs taken in turn): LDS counts of the slab's columns
+// iy, their exclusive prefix sums from the slab start give the column offsets
+// (offsets[ix N + iy]; the last slab also writes offsets[N^2] = n), then
+// every record of the slab goes to its column at a place taken in LDS.
+template <typename T>
+__global__ void __launch_bounds__(1024)
+    k_slab_columns(int nmesh, const int* __restrict__ mode, const int* __restrict__ hoff,
+                   int nblocks, const typename Rec<T>::type* __restrict__ trec,
+                   const T* __restrict__ twrec, int* __restrict__ offsets,
+                   typename Rec<T>::type* __restrict__ rec, T* __restrict__ wrec) {
+  if (off_route(mode, kRouteSlabs)) return;
+  using RecT = typename Rec<T>::type;
+  __shared__ int cnt[kMaxSlabs];
+  __shared__ int sh[17];
+  for (int ix = blockIdx.x; ix < nmesh; ix += gridDim.x) {
+  const int s0 = hoff[(size_t)ix * nblocks], s1 = hoff[(size_t)(ix + 1) * nblocks];
+  for (int b = threadIdx.x; b < nmesh; b += blockDim.x) cnt[b] = 0;
+  __syncthreads();
+  for (int64_t j = s0 + (int64_t)threadIdx.x; j < s1; j += blockDim.x)
+    atomicAdd(&cnt[record_iy(trec[j])], 1);
+  __syncthreads();
+  // two columns per thread (N <= 2048)
+  const int b0 = 2 * threadIdx.x, b1 = b0 + 1;
+  const int c0 = b0 < nmesh ? cnt[b0] : 0, c1 = b1 < nmesh ? cnt[b1] : 0;
+  int total;
+  const int ex = s0 + block_scan_excl(c0 + c1, sh, total);  // barriers: counts read first
+  if (b0 < nmesh) {
+    cnt[b0] = ex;
+    offsets[(size_t)ix * nmesh + b0] = ex;
+  }
+  if (b1 < nmesh) {
+    cnt[b1] = ex + c0;
+    offsets[(size_t)ix * nmesh + b1] = ex + c0;
+  }
+  if (ix == nmesh - 1 && threadIdx.x == 0) offsets[(size_t)nmesh * nmesh] = s1;
+  __syncthreads();
+  for (int64_t j = s0 + (int64_t)threadIdx.x; j < s1; j += blockDim.x) {
+    const RecT r = trec[j];
+    const int slot = atomicAdd(&cnt[record_iy(r)], 1);
+    rec[slot] = r;
+    if (wrec) wrec[slot] = twrec[j];
+  }
+  __syncthreads();  // the cursors are done with before the next slab clears them
+  }
 }
 
 // ---- fused paint + r2c z-pass
@@ -685,61 +981,128 @@ __global__ void __launch_bounds__((PaintCfg<T, N, P, MODE>::THREADS))
 
 constexpr int kCountBlocks = 8192;
 
-size_t bucket_bytes(int nmesh) {
-  const size_t n2 = (size_t)nmesh * nmesh;
-  const size_t nb = (n2 + 4095) / 4096;
-  // count, offsets (+1), cursor, scan block sums; then float64 weight partials
-  const size_t ints = (3 * n2 + 1 + nb + 1) & ~(size_t)1;
-  return ints * sizeof(int) + 2 * kCountBlocks * sizeof(double);
-}
+static size_t round256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// Bucketing workspace: count, offsets (+1), cursor, scan block sums (ints);
+// float64 weight partials; then the route flag and, for the slab route, the
+// [slab][block] counts, their prefix sums (+1) and scan block sums.
+struct BucketWs {
+  size_t count, offsets, cursor, bsums, wpart, mode, hist, hoff, hbsums, total;
+  int nb, nbh;
+  explicit BucketWs(int nmesh) {
+    const size_t n2 = (size_t)nmesh * nmesh;
+    nb = (int)((n2 + 4095) / 4096);
+    count = 0;
+    offsets = count + n2 * sizeof(int);
+    cursor = offsets + (n2 + 1) * sizeof(int);
+    bsums = cursor + n2 * sizeof(int);
+    wpart = round256(bsums + (size_t)(nb + 1) * sizeof(int));
+    mode = round256(wpart + 2 * kCountBlocks * sizeof(double));
+    const size_t nh = (size_t)nmesh * kSlabBlocks;
+    nbh = (int)((nh + 4095) / 4096);
+    hist = mode + 256;
+    hoff = round256(hist + nh * sizeof(int));
+    hbsums = round256(hoff + (nh + 1) * sizeof(int));
+    total = round256(hbsums + (size_t)(nbh + 1) * sizeof(int));
+  }
+};
+
+size_t bucket_bytes(int nmesh) { return BucketWs(nmesh).total; }
 
 hipError_t launch_bucket(int dtype, int nmesh, double boxsize, const void* pos, const void* weight,
                          const void* value, int64_t n, void* bucket_ws, void* rec, void* wrec,
-                         double* wsums, hipStream_t s) {
+                         double* wsums, hipStream_t s, void* scratch, size_t scratch_bytes) {
   const int n2 = nmesh * nmesh;
   const double inv_box = 1.0 / boxsize, cpl = nmesh / boxsize;
-  int* count = static_cast<int*>(bucket_ws);
-  int* offsets = count + n2;
-  int* cursor = offsets + n2 + 1;
-  int* bsums = cursor + n2;
-  const int nb = (n2 + 4095) / 4096;
-  const size_t ints = (3 * (size_t)n2 + 1 + nb + 1) & ~(size_t)1;
-  double* wpart = reinterpret_cast<double*>(static_cast<int*>(bucket_ws) + ints);
+  const BucketWs L(nmesh);
+  char* bw = static_cast<char*>(bucket_ws);
+  int* count = reinterpret_cast<int*>(bw + L.count);
+  int* offsets = reinterpret_cast<int*>(bw + L.offsets);
+  int* cursor = reinterpret_cast<int*>(bw + L.cursor);
+  int* bsums = reinterpret_cast<int*>(bw + L.bsums);
+  double* wpart = reinterpret_cast<double*>(bw + L.wpart);
+  const int nb = L.nb;
+  const bool amounts = weight || value;
+  // the slab route needs scratch for the records (and amounts) in slab order
+  const size_t es = dtype == PK_F32 ? 4 : 8;
+  const size_t trec_bytes = round256((size_t)(n > 0 ? n : 0) * 4 * es);
+  const size_t twrec_bytes = amounts ? round256((size_t)(n > 0 ? n : 0) * es) : 0;
+  const bool slabs = scratch != nullptr && n >= kSlabMinParticles && nmesh <= kMaxSlabs &&
+                     scratch_bytes >= trec_bytes + twrec_bytes;
+  int* mode = slabs ? reinterpret_cast<int*>(bw + L.mode) : nullptr;
   hipError_t e = launch_fill_zero(count, (size_t)n2 * sizeof(int), s);
   if (e != hipSuccess) return e;
-  // contiguous chunks of whole steps, at most kCountBlocks blocks
+  if (slabs) {
+    if (dtype == PK_F32)
+      hipLaunchKernelGGL(k_order_probe<float>, dim3(kProbeGroups), dim3(256), 0, s,
+                         static_cast<const float*>(pos), n, nmesh, boxsize, inv_box, cpl, mode);
+    else
+      hipLaunchKernelGGL(k_order_probe<double>, dim3(kProbeGroups), dim3(256), 0, s,
+                         static_cast<const double*>(pos), n, nmesh, boxsize, inv_box, cpl, mode);
+  }
+  // run route: contiguous chunks of whole steps, at most kCountBlocks blocks
   int64_t steps = (n + kBucketStep - 1) / kBucketStep;
   if (steps < 1) steps = 1;
   int64_t blocks = steps < kCountBlocks ? steps : kCountBlocks;
   const int64_t chunk = (steps + blocks - 1) / blocks * kBucketStep;
   blocks = (n + chunk - 1) / chunk;
   if (blocks < 1) blocks = 1;
+  // slab route: at most min(kSlabBlocks, N) contiguous blocks of whole steps
+  // (so that its [slab][block] counts are no more than the N^2 column counts)
+  const int64_t scap = kSlabBlocks < nmesh ? kSlabBlocks : nmesh;
+  int64_t sblocks = steps < scap ? steps : scap;
+  const int64_t schunk = (steps + sblocks - 1) / sblocks * kBucketStep;
+  sblocks = (n + schunk - 1) / schunk;
+  if (sblocks < 1) sblocks = 1;
+  const int nh = nmesh * (int)sblocks;
+  char* sc = static_cast<char*>(scratch);
+  SlabArgs sa{schunk, slabs ? (int)sblocks : 0, reinterpret_cast<int*>(bw + L.hist),
+              reinterpret_cast<const int*>(bw + L.hoff), sc,
+              slabs && amounts ? sc + trec_bytes : nullptr};
+  // counts (the workgroups run the route the probe chose)
   if (dtype == PK_F32)
     hipLaunchKernelGGL(k_bucket_count<float>, dim3((unsigned)blocks), dim3(256), 0, s,
                        static_cast<const float*>(pos), static_cast<const float*>(weight),
                        static_cast<const float*>(value), n, chunk, nmesh, boxsize, inv_box, cpl, count,
-                       wpart);
+                       wpart, mode, sa);
   else
     hipLaunchKernelGGL(k_bucket_count<double>, dim3((unsigned)blocks), dim3(256), 0, s,
                        static_cast<const double*>(pos), static_cast<const double*>(weight),
                        static_cast<const double*>(value), n, chunk, nmesh, boxsize, inv_box, cpl, count,
-                       wpart);
-  hipLaunchKernelGGL(k_weight_sums, dim3(1), dim3(1024), 0, s, wpart, (int)blocks, wsums);
-  hipLaunchKernelGGL(k_scan_blocks, dim3(nb), dim3(1024), 0, s, count, n2, bsums);
-  hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(1024), 0, s, bsums, nb);
-  hipLaunchKernelGGL(k_scan_final, dim3(nb), dim3(1024), 0, s, count, n2, bsums, offsets, cursor);
+                       wpart, mode, sa);
+  hipLaunchKernelGGL(k_weight_sums, dim3(1), dim3(1024), 0, s, wpart, (int)blocks, (int)sblocks,
+                     wsums, mode);
+  // one scan, of the route's counts
+  const ScanJob runs_job{count, n2, bsums, offsets, cursor};
+  const ScanJob slabs_job{sa.hist, nh, reinterpret_cast<int*>(bw + L.hbsums),
+                          reinterpret_cast<int*>(bw + L.hoff), nullptr};
+  hipLaunchKernelGGL(k_scan_blocks, dim3(nb), dim3(1024), 0, s, runs_job, slabs_job, mode);
+  hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(1024), 0, s, runs_job, slabs_job, mode);
+  hipLaunchKernelGGL(k_scan_final, dim3(nb), dim3(1024), 0, s, runs_job, slabs_job, mode);
   if (dtype == PK_F32)
     hipLaunchKernelGGL(k_bucket_scatter<float>, dim3((unsigned)blocks), dim3(256), 0, s,
                        static_cast<const float*>(pos), static_cast<const float*>(weight),
                        static_cast<const float*>(value), n, chunk, nmesh, boxsize, inv_box, cpl, cursor,
-                       static_cast<float4*>(rec),
-                       (weight || value) ? static_cast<float*>(wrec) : nullptr);
+                       static_cast<float4*>(rec), amounts ? static_cast<float*>(wrec) : nullptr,
+                       mode, sa);
   else
     hipLaunchKernelGGL(k_bucket_scatter<double>, dim3((unsigned)blocks), dim3(256), 0, s,
                        static_cast<const double*>(pos), static_cast<const double*>(weight),
                        static_cast<const double*>(value), n, chunk, nmesh, boxsize, inv_box, cpl, cursor,
-                       static_cast<double4*>(rec),
-                       (weight || value) ? static_cast<double*>(wrec) : nullptr);
+                       static_cast<double4*>(rec), amounts ? static_cast<double*>(wrec) : nullptr,
+                       mode, sa);
+  if (!slabs) return hipGetLastError();
+  // slab route: the slabs into column order
+  if (dtype == PK_F32)
+    hipLaunchKernelGGL(k_slab_columns<float>, dim3((unsigned)nmesh), dim3(1024), 0, s, nmesh,
+                       mode, sa.hoff, (int)sblocks, static_cast<const float4*>(sa.trec),
+                       static_cast<const float*>(sa.twrec), offsets, static_cast<float4*>(rec),
+                       amounts ? static_cast<float*>(wrec) : nullptr);
+  else
+    hipLaunchKernelGGL(k_slab_columns<double>, dim3((unsigned)nmesh), dim3(1024), 0, s, nmesh,
+                       mode, sa.hoff, (int)sblocks, static_cast<const double4*>(sa.trec),
+                       static_cast<const double*>(sa.twrec), offsets, static_cast<double4*>(rec),
+                       amounts ? static_cast<double*>(wrec) : nullptr);
   return hipGetLastError();
 }
 

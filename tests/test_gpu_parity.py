@@ -269,3 +269,33 @@ def test_api_front_end(ctx):
     painted, wsums = mesh.paint()
     np.testing.assert_allclose(painted.cpu().numpy(), oracle.paint_mesh(pos, n, box, 3),
                                atol=1e-12)
+
+
+@pytest.mark.parametrize("dtype", ["f8", "f4"])
+@pytest.mark.parametrize("window,inter", [("cic", True), ("tsc", False)])
+def test_fftpower_catalog_order_routes_agree(ctx, dtype, window, inter):
+    # The bucketing takes one of two routes, chosen on the device from the
+    # order of the catalog: in column order (runs of equal columns) or not
+    # (slab partition).  The same weighted catalog, sorted by column and
+    # shuffled, must give the same spectra, both matching the oracle.
+    n, box, npart = 64, 500.0, 120_000
+    rng = np.random.default_rng(2024)
+    pos = rng.uniform(0.0, box, (npart, 3)).astype(NDT[dtype]).astype(np.float64)
+    w = rng.uniform(0.5, 1.5, npart).astype(NDT[dtype]).astype(np.float64)
+    cell = np.floor(pos / (box / n)).astype(np.int64) % n
+    by_column = np.lexsort((cell[:, 2], cell[:, 1], cell[:, 0]))
+    shuffled = rng.permutation(npart)
+    b = _lib.bin_desc(n // 2, 0.0, 1.0, 3, (0, 2), 2)
+    res = {}
+    for name, idx in (("column order", by_column), ("shuffled", shuffled)):
+        res[name] = _run_fftpower(ctx, pos[idx].astype(NDT[dtype]), w[idx].astype(NDT[dtype]),
+                                  n, box, window, inter, True, dtype, b)
+    want = oracle.fftpower(pos, n, box, window, inter, True, w, nmu=3, poles=(0, 2))
+    for name, got in res.items():
+        check_power(got, want, TOL[dtype], f"{dtype} {window} {name}")
+    a, s = res["column order"], res["shuffled"]
+    np.testing.assert_array_equal(a["modes"], s["modes"])
+    ok = a["modes"] > 0
+    rtol = 1e-13 if dtype == "f8" else 1e-6
+    np.testing.assert_allclose(s["power"][ok], a["power"][ok], rtol=rtol)
+    assert s["shotnoise"] == pytest.approx(a["shotnoise"], rel=1e-12)
