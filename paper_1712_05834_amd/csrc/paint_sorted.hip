@@ -595,10 +595,19 @@ __global__ void __launch_bounds__(256)
 __device__ __forceinline__ int record_iy(float4 r) { return (int)(__float_as_uint(r.w) >> 16); }
 __device__ __forceinline__ int record_iy(double4 r) { return (int)((unsigned)r.w >> 16); }
 
-// One workgroup (1024 threads) per x-slab (slabs taken in turn): LDS counts of the slab's columns
-// iy, their exclusive prefix sums from the slab start give the column offsets
-// (offsets[ix N + iy]; the last slab also writes offsets[N^2] = n), then
-// every record of the slab goes to its column at a place taken in LDS.
+// One workgroup (1024 threads) per x-slab (slabs taken in turn): LDS counts
+// of the slab's columns iy, their exclusive prefix sums from the slab start
+// give the column offsets (offsets[ix N + iy]; the last slab also writes
+// offsets[N^2] = n).  The records then go to their columns in steps of S:
+// each step is sorted by column in LDS (counting sort) and written out in
+// that order, so that the records of one column leave as one contiguous run
+// rather than as single 16-byte stores scattered over all N columns.
+template <typename T>
+struct ColStage {
+  static constexpr int S = sizeof(T) == 4 ? 4096 : 2048;  // records per step
+  static constexpr int U = S / 1024;                        // per thread
+};
+
 template <typename T>
 __global__ void __launch_bounds__(1024)
     k_slab_columns(int nmesh, const int* __restrict__ mode, const int* __restrict__ hoff,
@@ -607,37 +616,84 @@ __global__ void __launch_bounds__(1024)
                    typename Rec<T>::type* __restrict__ rec, T* __restrict__ wrec) {
   if (off_route(mode, kRouteSlabs)) return;
   using RecT = typename Rec<T>::type;
-  __shared__ int cnt[kMaxSlabs];
+  constexpr int S = ColStage<T>::S, U = ColStage<T>::U;
+  __shared__ int cnt[kMaxSlabs];     // running place of each column
+  __shared__ int lb[kMaxSlabs + 1];  // step counts, then their prefix sums
+  __shared__ RecT srec[S];
+  __shared__ T samt[S];
+  __shared__ unsigned short scol[S];
   __shared__ int sh[17];
+  const int b0 = 2 * threadIdx.x, b1 = b0 + 1;  // two columns per thread (N <= 2048)
   for (int ix = blockIdx.x; ix < nmesh; ix += gridDim.x) {
-  const int s0 = hoff[(size_t)ix * nblocks], s1 = hoff[(size_t)(ix + 1) * nblocks];
-  for (int b = threadIdx.x; b < nmesh; b += blockDim.x) cnt[b] = 0;
-  __syncthreads();
-  for (int64_t j = s0 + (int64_t)threadIdx.x; j < s1; j += blockDim.x)
-    atomicAdd(&cnt[record_iy(trec[j])], 1);
-  __syncthreads();
-  // two columns per thread (N <= 2048)
-  const int b0 = 2 * threadIdx.x, b1 = b0 + 1;
-  const int c0 = b0 < nmesh ? cnt[b0] : 0, c1 = b1 < nmesh ? cnt[b1] : 0;
-  int total;
-  const int ex = s0 + block_scan_excl(c0 + c1, sh, total);  // barriers: counts read first
-  if (b0 < nmesh) {
-    cnt[b0] = ex;
-    offsets[(size_t)ix * nmesh + b0] = ex;
-  }
-  if (b1 < nmesh) {
-    cnt[b1] = ex + c0;
-    offsets[(size_t)ix * nmesh + b1] = ex + c0;
-  }
-  if (ix == nmesh - 1 && threadIdx.x == 0) offsets[(size_t)nmesh * nmesh] = s1;
-  __syncthreads();
-  for (int64_t j = s0 + (int64_t)threadIdx.x; j < s1; j += blockDim.x) {
-    const RecT r = trec[j];
-    const int slot = atomicAdd(&cnt[record_iy(r)], 1);
-    rec[slot] = r;
-    if (wrec) wrec[slot] = twrec[j];
-  }
-  __syncthreads();  // the cursors are done with before the next slab clears them
+    const int s0 = hoff[(size_t)ix * nblocks], s1 = hoff[(size_t)(ix + 1) * nblocks];
+    for (int b = threadIdx.x; b < nmesh; b += blockDim.x) cnt[b] = 0;
+    __syncthreads();
+    for (int64_t j = s0 + (int64_t)threadIdx.x; j < s1; j += blockDim.x)
+      atomicAdd(&cnt[record_iy(trec[j])], 1);
+    __syncthreads();
+    {
+      const int c0 = b0 < nmesh ? cnt[b0] : 0, c1 = b1 < nmesh ? cnt[b1] : 0;
+      int total;
+      const int ex = s0 + block_scan_excl(c0 + c1, sh, total);  // barriers: counts read first
+      if (b0 < nmesh) {
+        cnt[b0] = ex;
+        offsets[(size_t)ix * nmesh + b0] = ex;
+      }
+      if (b1 < nmesh) {
+        cnt[b1] = ex + c0;
+        offsets[(size_t)ix * nmesh + b1] = ex + c0;
+      }
+      if (ix == nmesh - 1 && threadIdx.x == 0) offsets[(size_t)nmesh * nmesh] = s1;
+    }
+    for (int64_t base = s0; base < s1; base += S) {
+      for (int b = threadIdx.x; b < nmesh; b += blockDim.x) lb[b] = 0;
+      __syncthreads();  // also orders the cursors written above before their use
+      RecT r[U];
+      T am[U];
+      int col[U], rk[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int64_t j = base + threadIdx.x + u * 1024;
+        col[u] = -1;
+        rk[u] = 0;
+        if (j < s1) {
+          r[u] = trec[j];
+          am[u] = wrec ? twrec[j] : T(0);
+          col[u] = record_iy(r[u]);
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+        if (col[u] >= 0) rk[u] = atomicAdd(&lb[col[u]], 1);
+      __syncthreads();
+      const int c0 = b0 < nmesh ? lb[b0] : 0, c1 = b1 < nmesh ? lb[b1] : 0;
+      int m;
+      const int ex = block_scan_excl(c0 + c1, sh, m);  // barriers: counts read first
+      if (b0 < nmesh) lb[b0] = ex;
+      if (b1 < nmesh) lb[b1] = ex + c0;
+      if (threadIdx.x == 0) lb[nmesh] = m;
+      __syncthreads();
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        if (col[u] >= 0) {
+          const int p = lb[col[u]] + rk[u];
+          srec[p] = r[u];
+          samt[p] = am[u];
+          scol[p] = (unsigned short)col[u];
+        }
+      }
+      __syncthreads();
+      for (int e = threadIdx.x; e < m; e += blockDim.x) {
+        const int c = scol[e];
+        const int g = cnt[c] + (e - lb[c]);
+        rec[g] = srec[e];
+        if (wrec) wrec[g] = samt[e];
+      }
+      __syncthreads();
+      for (int c = threadIdx.x; c < nmesh; c += blockDim.x) cnt[c] += lb[c + 1] - lb[c];
+      __syncthreads();  // lb is read before the next step clears it
+    }
+    __syncthreads();  // the cursors are done with before the next slab clears them
   }
 }
 
