@@ -299,3 +299,23 @@ def test_fftpower_catalog_order_routes_agree(ctx, dtype, window, inter):
     rtol = 1e-13 if dtype == "f8" else 1e-6
     np.testing.assert_allclose(s["power"][ok], a["power"][ok], rtol=rtol)
     assert s["shotnoise"] == pytest.approx(a["shotnoise"], rel=1e-12)
+
+
+@pytest.mark.parametrize("dtype", ["f8", "f4"])
+def test_fftpower_shuffled_catalog_in_one_slab(ctx, dtype):
+    # A catalog in random order whose particles all lie in one x-slab (and
+    # a few in a second one): the bucketing's slab route then has one slab
+    # holding nearly everything and N - 2 empty slabs.
+    n, box, npart = 32, 320.0, 60_000
+    h = box / n
+    rng = np.random.default_rng(77)
+    pos = rng.uniform(0.0, box, (npart, 3))
+    pos[:, 0] = rng.uniform(5 * h, 6 * h, npart)
+    pos[:100, 0] = rng.uniform(20 * h, 21 * h, 100)
+    pos = pos[rng.permutation(npart)].astype(NDT[dtype])
+    w = rng.uniform(0.5, 1.5, npart).astype(NDT[dtype])
+    b = _lib.bin_desc(n // 2, 0.0, 1.0, 2, (0, 2), 2)
+    got = _run_fftpower(ctx, pos, w, n, box, "tsc", True, True, dtype, b)
+    want = oracle.fftpower(pos.astype(np.float64), n, box, "tsc", True, True,
+                           w.astype(np.float64), nmu=2, poles=(0, 2))
+    check_power(got, want, TOL[dtype], f"{dtype} one slab")
