@@ -1,0 +1,45 @@
+"""bench.py's contract pieces that need no GPU: the one-GPU refusal, the
+algorithmic bytes of each stage, and that measured traffic is reported only
+for the kernel sources it was measured on."""
+
+import json
+import os
+import subprocess
+import sys
+
+import bench
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=300)
+    assert r.returncode != 0
+    assert "one GPU" in r.stderr
+    assert r.stdout.strip() == ""
+
+
+def test_algorithmic_bytes_per_stage():
+    w = dict(bench.WORKLOADS["lognormal-512"])
+    npart, n3 = 9_997_050, 512 ** 3
+    # float32, interlaced: two meshes of 4-byte reals
+    assert bench.algorithmic_bytes("paint_z", w, npart) == 3 * 4 * npart + 2 * 4 * n3
+    assert bench.algorithmic_bytes("fft_y", w, npart) == 2 * 2 * 4 * n3
+    assert bench.algorithmic_bytes("xpass_bin", w, npart) == 2 * 4 * n3
+    assert bench.algorithmic_bytes("bucket", w, npart) == 0
+    w.update(dtype="f8", interlaced=False)
+    assert bench.algorithmic_bytes("paint_z", w, npart) == 3 * 8 * npart + 8 * n3
+
+
+def test_traffic_only_for_the_measured_sources(tmp_path, monkeypatch):
+    for wl in ("lognormal-512", "zeldovich-1024"):
+        path = os.path.join(ROOT, "profiles", f"traffic_{wl}.json")
+        rec = json.load(open(path))
+        assert set(rec["kernels"]) >= {"paint_z", "fft_y", "xpass_bin"}
+        monkeypatch.setattr(bench, "source_hash", lambda: rec["source_hash"])
+        got = bench.measured_traffic(wl, "paint_z")
+        assert got == rec["kernels"]["paint_z"]["bytes_per_launch"] and got > 0
+        monkeypatch.setattr(bench, "source_hash", lambda: "0" * 16)
+        assert bench.measured_traffic(wl, "paint_z") is None
+    assert bench.measured_traffic("no-such-workload", "paint_z") is None
