@@ -126,6 +126,63 @@ def measured_traffic(workload, kernel):
     return None if k is None else k.get("bytes_per_launch")
 
 
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def run_fft_reference(args):
+    """The stand-alone hand-written r2c (pk_fft_r2c: z, y and x passes in
+    place on the packed layout) timed beside rocFFT's r2c (torch.fft.rfftn,
+    out of place) on the same float32 meshes: a reference point only, the
+    power-spectrum path does not use it."""
+    import numpy as np
+    import torch
+
+    from paper_1712_05834_amd import _lib
+
+    dev = torch.device("cuda:0")
+    ctx = _lib.Context(0)
+    out = {"metric": "r2c 3-D FFT time, hand-written vs rocFFT (torch.fft.rfftn)",
+           "unit": "ms", "dtype": "f32", "data": "synthetic (standard normal mesh)", "sizes": []}
+    for n in (256, 512, 1024):
+        src = torch.randn((n, n, n), dtype=torch.float32, device=dev,
+                          generator=torch.Generator(device=dev).manual_seed(n))
+        work = torch.empty_like(src)
+        m = _lib.mesh_desc(n, 1000.0, "cic", False, True, "f4")
+        ours, roc = [], []
+        for rep in range(args.warmup + args.steps):
+            work.copy_(src)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            ctx.pk_fft_r2c(m, work)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            spec = torch.fft.rfftn(src)
+            torch.cuda.synchronize()
+            t2 = time.perf_counter()
+            del spec
+            if rep >= args.warmup:
+                ours.append(t1 - t0)
+                roc.append(t2 - t1)
+        row = {"n": n, "hand_written_ms": 1e3 * float(np.median(ours)),
+               "rocfft_ms": 1e3 * float(np.median(roc))}
+        row["rocfft_over_hand_written"] = row["rocfft_ms"] / row["hand_written_ms"]
+        log(f"r2c {n}^3: hand-written {row['hand_written_ms']:.3f} ms, "
+            f"rocFFT {row['rocfft_ms']:.3f} ms (median of {args.steps})")
+        out["sizes"].append(row)
+        del src, work
+        torch.cuda.empty_cache()
+    ctx.close()
+    print(json.dumps(out))
+
+
 def cpu_baseline(w, pos, frac):
     """Oracle (float64, CPU) on a bounded sample: painting of a fraction of the
     catalog onto both meshes (scaled by 1 / frac), the full r2c of each mesh
@@ -156,6 +213,7 @@ def cpu_baseline(w, pos, frac):
         "value": 1.0 / per_mesh,
         "unit": "meshes/s",
         "cores": os.cpu_count(),
+        "cpu": cpu_model(),
         "kind": "oracle",
         "sample": (f"float64 oracle on this host: painting of {len(sub)} of {len(pos)} "
                    f"particles onto {'both meshes' if w['interlaced'] else 'the mesh'} "
@@ -171,7 +229,8 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="lognormal-512",
-                    choices=sorted(WORKLOADS) + ["batch-mocks", "serve", "survey-512"])
+                    choices=sorted(WORKLOADS) + ["batch-mocks", "serve", "survey-512",
+                                                 "fft-reference"])
     ap.add_argument("--mocks", type=int, default=BATCH["count"],
                     help="number of mocks of the batch-mocks workload")
     ap.add_argument("--lanes", type=int, default=BATCH["lanes"],
@@ -217,6 +276,9 @@ def main():
         return
     if args.workload == "survey-512":
         run_survey(args)
+        return
+    if args.workload == "fft-reference":
+        run_fft_reference(args)
         return
     w = WORKLOADS[args.workload]
     t0 = time.perf_counter()
