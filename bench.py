@@ -576,6 +576,22 @@ def run_serve(args):
         log(f"qps {qps:g}: p50 {st['p50_ms']:.1f} ms, p99 {st['p99_ms']:.1f} ms, "
             f"{st['throughput_rps']:.1f} req/s")
     top = levels[-1]
+    # float32 against the float64 path, per request of the last level (untimed)
+    errs = []
+    for r in served:
+        m8 = _lib.mesh_desc(r.mesh.nmesh, r.mesh.boxsize, r.mesh.window, r.mesh.interlaced,
+                            r.mesh.compensated, "f8")
+        p8 = r.pos.double()
+        ws8 = torch.empty(_lib.workspace_bytes(m8, r.bins, r.npart), dtype=torch.uint8,
+                          device=dev)
+        r8 = torch.empty(_lib.result_doubles(r.bins), dtype=torch.float64, device=dev)
+        ctx.pk_fftpower(m8, r.bins, p8, None, r.npart, ws8, r8)
+        want = ctx.pk_result_to_host(m8, r.bins, r8)
+        ok = want["modes"] > 0
+        errs.append(float(np.max(np.abs(r.result["power"][ok] / want["power"][ok] - 1))))
+        del ws8, p8, r8
+    log(f"float32 against float64 over {len(errs)} requests: max rel err {max(errs):.2e}, "
+        f"median {np.median(errs):.2e}")
     line = {
         "metric": "p50/p99 request latency and sustained requests/s (FFTPower serving)",
         "value": top["throughput_rps"],
@@ -593,6 +609,7 @@ def run_serve(args):
                    "lanes": SERVE["lanes"], "meshes": list(SERVE["meshes"]),
                    "np_range": list(SERVE["np_range"]), "qps": list(SERVE["qps"])},
         "latency": levels,
+        "fp32_vs_fp64_max_rel_err": {"max": max(errs), "median": float(np.median(errs))},
         "roofline": None,
         "cpu_baseline": None,
     }
