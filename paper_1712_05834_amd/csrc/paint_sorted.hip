@@ -16,11 +16,14 @@
 // neighbouring particles, without a round trip to the host (the workgroups
 // of k_bucket_count and k_bucket_scatter run the route chosen):
 // 1'. counting        per block of the catalog, LDS counts of the x-slabs
-//                     ix, stored as [slab][block]; their prefix sums (the
-//                     same scan kernels) give every block its own range in
-//                     each slab.
-// 3'. scattering      the records (and amounts) written slab by slab into
-//                     scratch memory, places ranked by LDS atomics.
+//                     ix, stored as [block][slab] and added into per-slab
+//                     totals (one atomic per slab and block).
+// 3'. scattering      each block scans the slab totals in LDS (slab starts),
+//                     reserves its range in every slab (one atomic per slab
+//                     and block) and writes its records (and amounts) slab
+//                     by slab into scratch memory, places ranked by LDS
+//                     atomics.  (The scan kernels of the run route then scan
+//                     zero counts; k_slab_columns writes the offsets.)
 // 3''. k_slab_columns one workgroup per slab: LDS counts of its columns,
 //                     their offsets, then the records scattered into column
 //                     order.  No global atomics at all.
@@ -159,13 +162,14 @@ __device__ __forceinline__ int column_key(const T* __restrict__ pos, int64_t i, 
 
 // Arguments of the slab route's parts of k_bucket_count and
 // k_bucket_scatter: catalog blocks of chunk particles (nblocks of them), the
-// [slab][block] counts and their prefix sums, the scratch records and
+// [block][slab] counts, the slab totals and cursors, the scratch records and
 // amounts (amounts NULL without weights or values).
 struct SlabArgs {
   int64_t chunk;
   int nblocks;
-  int* hist;
-  const int* hoff;
+  int* hist;    // [block][slab] counts
+  int* total;   // per-slab totals (zeroed by k_order_probe)
+  int* cursor;  // per-slab ranges reserved so far (zeroed by k_order_probe)
   void* trec;
   void* twrec;
 };
@@ -173,7 +177,8 @@ struct SlabArgs {
 // Slab route, counting (run by the workgroups of k_bucket_count): block
 // blk of the catalog (particles blk chunk .. blk chunk + chunk - 1, nblocks
 // blocks): counts of its particles per x-slab in LDS, stored to
-// hist[slab][blk]; weight sums of the block to wpart as in the run route.
+// hist[blk][slab] and added into the slab totals; weight sums of the block
+// to wpart as in the run route.
 template <typename T>
 __device__ void slab_count_block(const T* __restrict__ pos, const T* __restrict__ weight,
                                  const T* __restrict__ value, int64_t n, int nmesh,
@@ -184,7 +189,6 @@ __device__ void slab_count_block(const T* __restrict__ pos, const T* __restrict_
   const int mask = nmesh - 1;
   constexpr int U = kBucketUnroll;
   const int64_t chunk = sa.chunk;
-  const int nblocks = sa.nblocks;
   int* __restrict__ hist = sa.hist;
   {
     for (int b = threadIdx.x; b < nmesh; b += blockDim.x) lh[b] = 0;
@@ -219,7 +223,11 @@ __device__ void slab_count_block(const T* __restrict__ pos, const T* __restrict_
       part[1][threadIdx.x >> 6] = ws2;
     }
     __syncthreads();
-    for (int b = threadIdx.x; b < nmesh; b += blockDim.x) hist[(size_t)b * nblocks + blk] = lh[b];
+    for (int b = threadIdx.x; b < nmesh; b += blockDim.x) {
+      const int c = lh[b];
+      hist[(size_t)blk * nmesh + b] = c;
+      if (c) atomicAdd(&sa.total[b], c);
+    }
     if (threadIdx.x == 0) {
       wpart[2 * blk] = ((part[0][0] + part[0][1]) + part[0][2]) + part[0][3];
       wpart[2 * blk + 1] = ((part[1][0] + part[1][1]) + part[1][2]) + part[1][3];
@@ -227,11 +235,44 @@ __device__ void slab_count_block(const T* __restrict__ pos, const T* __restrict_
   }
 }
 
+// Exclusive prefix sums of the slab totals (nmesh <= 2048 of them) into
+// start[] by a 256-thread workgroup: eight per thread, then a scan of the
+// thread sums over the four waves.
+__device__ __forceinline__ void slab_starts_256(const int* __restrict__ total, int nmesh,
+                                                int* start, int* sh) {
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  int v[8], s = 0;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    const int b = t * 8 + k;
+    v[k] = b < nmesh ? total[b] : 0;
+    s += v[k];
+  }
+  int x = s;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const int y = __shfl_up(x, off, 64);
+    if (lane >= off) x += y;
+  }
+  if (lane == 63) sh[wave] = x;
+  __syncthreads();
+  int ex = x - s;
+  for (int w = 0; w < wave; ++w) ex += sh[w];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    const int b = t * 8 + k;
+    if (b < nmesh) start[b] = ex;
+    ex += v[k];
+  }
+  __syncthreads();
+}
+
 // Slab route, scattering (run by the workgroups of k_bucket_scatter): the
 // records of block blk (same blocks as the counting) written into the slabs
-// of the scratch arrays: the block's range of slab x starts at hoff[x][blk]
-// (exclusive prefix sums of hist); places within it are taken in LDS.
-// Record and amount as in the run route.
+// of the scratch arrays: the block reserves its range in every slab it has
+// particles in (slab start from the totals + one atomic on the slab's
+// cursor); places within it are taken in LDS.  Record and amount as in the
+// run route.
 template <typename T>
 __device__ void slab_scatter_block(const T* __restrict__ pos, const T* __restrict__ weight,
                                    const T* __restrict__ value, int64_t n, int nmesh,
@@ -241,13 +282,16 @@ __device__ void slab_scatter_block(const T* __restrict__ pos, const T* __restric
   __shared__ int cur[kMaxSlabs];
   const int mask = nmesh - 1;
   constexpr int U = kBucketUnroll;
+  __shared__ int sh[4];
   const int64_t chunk = sa.chunk;
-  const int nblocks = sa.nblocks;
-  const int* __restrict__ hoff = sa.hoff;
   RecT* __restrict__ trec = static_cast<RecT*>(sa.trec);
   T* __restrict__ twrec = static_cast<T*>(sa.twrec);
   {
-  for (int b = threadIdx.x; b < nmesh; b += blockDim.x) cur[b] = hoff[(size_t)b * nblocks + blk];
+  slab_starts_256(sa.total, nmesh, cur, sh);  // ends with a barrier
+  for (int b = threadIdx.x; b < nmesh; b += blockDim.x) {
+    const int c = sa.hist[(size_t)blk * nmesh + b];
+    if (c) cur[b] += atomicAdd(&sa.cursor[b], c);
+  }
   __syncthreads();
   const int64_t begin = (int64_t)blk * chunk;
   const int64_t end = begin + chunk < n ? begin + chunk : n;
@@ -489,95 +533,74 @@ __device__ __forceinline__ int block_scan_excl(int v, int* sh, int& total) {
   return r;
 }
 
-// An exclusive scan: counts in, offsets (n + 1 entries) and an optional copy
-// (cursor) out; the scan kernels run the job of the route taken (the column
-// counts of the run route or the [slab][block] counts of the slab route).
-struct ScanJob {
-  const int* count;
-  int n;
-  int* block_sums;
-  int* offsets;
-  int* cursor;
-};
-__device__ __forceinline__ ScanJob job_of(const ScanJob& runs, const ScanJob& slabs,
-                                          const int* mode) {
-  const bool sl = route_of(mode) == kRouteSlabs;
-  ScanJob j;
-  j.count = sl ? slabs.count : runs.count;
-  j.n = sl ? slabs.n : runs.n;
-  j.block_sums = sl ? slabs.block_sums : runs.block_sums;
-  j.offsets = sl ? slabs.offsets : runs.offsets;
-  j.cursor = sl ? slabs.cursor : runs.cursor;
-  return j;
-}
-
+// Exclusive scan of the run route's column counts into offsets (n + 1
+// entries) and cursor.  On the slab route the counts are all zero (the run
+// route's counting returned at once) and k_slab_columns writes the offsets
+// afterwards, so these kernels need not know the route.
 __global__ void __launch_bounds__(1024)
-    k_scan_blocks(ScanJob runs, ScanJob slabs, const int* __restrict__ mode) {
-  const ScanJob j = job_of(runs, slabs, mode);
-  if ((int)blockIdx.x * 4096 >= j.n) return;
+    k_scan_blocks(const int* __restrict__ count, int n, int* __restrict__ block_sums) {
   __shared__ int sh[17];
   const int base = blockIdx.x * 4096 + threadIdx.x * 4;
   int s = 0;
 #pragma unroll
-  for (int k = 0; k < 4; ++k) s += (base + k < j.n) ? j.count[base + k] : 0;
+  for (int j = 0; j < 4; ++j) s += (base + j < n) ? count[base + j] : 0;
   int total;
   (void)block_scan_excl(s, sh, total);
-  if (threadIdx.x == 0) j.block_sums[blockIdx.x] = total;
+  if (threadIdx.x == 0) block_sums[blockIdx.x] = total;
 }
 
-__global__ void __launch_bounds__(1024)
-    k_scan_sums(ScanJob runs, ScanJob slabs, const int* __restrict__ mode) {
-  const ScanJob j = job_of(runs, slabs, mode);
-  const int nb = (j.n + 4095) / 4096;
+__global__ void __launch_bounds__(1024) k_scan_sums(int* __restrict__ block_sums, int nb) {
   __shared__ int sh[17];
   int carry = 0;
   for (int start = 0; start < nb; start += 1024) {
     const int i = start + threadIdx.x;
-    const int v = i < nb ? j.block_sums[i] : 0;
+    const int v = i < nb ? block_sums[i] : 0;
     int total;
     const int ex = block_scan_excl(v, sh, total);
-    if (i < nb) j.block_sums[i] = carry + ex;
+    if (i < nb) block_sums[i] = carry + ex;
     carry += total;
   }
 }
 
 __global__ void __launch_bounds__(1024)
-    k_scan_final(ScanJob runs, ScanJob slabs, const int* __restrict__ mode) {
-  const ScanJob j = job_of(runs, slabs, mode);
-  const int nb = (j.n + 4095) / 4096;
-  if ((int)blockIdx.x >= nb) return;
+    k_scan_final(const int* __restrict__ count, int n, const int* __restrict__ block_sums,
+                 int* __restrict__ offsets, int* __restrict__ cursor) {
   __shared__ int sh[17];
   const int base = blockIdx.x * 4096 + threadIdx.x * 4;
   int v[4];
   int s = 0;
 #pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    v[k] = (base + k < j.n) ? j.count[base + k] : 0;
-    s += v[k];
+  for (int j = 0; j < 4; ++j) {
+    v[j] = (base + j < n) ? count[base + j] : 0;
+    s += v[j];
   }
   int total;
-  int ex = block_scan_excl(s, sh, total) + j.block_sums[blockIdx.x];
+  int ex = block_scan_excl(s, sh, total) + block_sums[blockIdx.x];
 #pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    if (base + k < j.n) {
-      j.offsets[base + k] = ex;
-      if (j.cursor) j.cursor[base + k] = ex;
+  for (int j = 0; j < 4; ++j) {
+    if (base + j < n) {
+      offsets[base + j] = ex;
+      cursor[base + j] = ex;
     }
-    ex += v[k];
+    ex += v[j];
   }
-  if ((int)blockIdx.x == nb - 1 && threadIdx.x == blockDim.x - 1) j.offsets[j.n] = ex;
+  if (blockIdx.x == gridDim.x - 1 && threadIdx.x == blockDim.x - 1) offsets[n] = ex;
 }
 
 // ---- the slab route (catalogs not in column order)
 
 // The route's sample: kProbeSamples pairs (i, i + 1) spread over the catalog
 // (n >= 2), one per thread of kProbeGroups workgroups; each workgroup stores
-// how many of its pairs share a column.
+// how many of its pairs share a column.  It also clears the slab route's
+// counters.
 template <typename T>
 __global__ void __launch_bounds__(256)
     k_order_probe(const T* __restrict__ pos, int64_t n, int nmesh, double boxsize,
-                  double inv_box, double cpl, int* __restrict__ mode) {
+                  double inv_box, double cpl, int* __restrict__ mode,
+                  int* __restrict__ slab_counters) {
   const int j = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+  // the slab totals and cursors (2 nmesh <= kProbeSamples ints) start at zero
+  if (j < 2 * nmesh) slab_counters[j] = 0;
   // i <= n - 2, so i + 1 is a particle
   const int64_t i = (int64_t)((double)j * (double)(n - 2) / (double)(kProbeSamples - 1));
   int same = column_key(pos, i, nmesh, boxsize, inv_box, cpl) ==
@@ -610,8 +633,8 @@ struct ColStage {
 
 template <typename T>
 __global__ void __launch_bounds__(1024)
-    k_slab_columns(int nmesh, const int* __restrict__ mode, const int* __restrict__ hoff,
-                   int nblocks, const typename Rec<T>::type* __restrict__ trec,
+    k_slab_columns(int nmesh, const int* __restrict__ mode, const int* __restrict__ total,
+                   const typename Rec<T>::type* __restrict__ trec,
                    const T* __restrict__ twrec, int* __restrict__ offsets,
                    typename Rec<T>::type* __restrict__ rec, T* __restrict__ wrec) {
   if (off_route(mode, kRouteSlabs)) return;
@@ -625,7 +648,13 @@ __global__ void __launch_bounds__(1024)
   __shared__ int sh[17];
   const int b0 = 2 * threadIdx.x, b1 = b0 + 1;  // two columns per thread (N <= 2048)
   for (int ix = blockIdx.x; ix < nmesh; ix += gridDim.x) {
-    const int s0 = hoff[(size_t)ix * nblocks], s1 = hoff[(size_t)(ix + 1) * nblocks];
+    // the slab's start: the totals of the slabs before it
+    int s0;
+    {
+      const int v = (b0 < ix ? total[b0] : 0) + (b1 < ix ? total[b1] : 0);
+      (void)block_scan_excl(v, sh, s0);
+    }
+    const int s1 = s0 + total[ix];
     for (int b = threadIdx.x; b < nmesh; b += blockDim.x) cnt[b] = 0;
     __syncthreads();
     for (int64_t j = s0 + (int64_t)threadIdx.x; j < s1; j += blockDim.x)
@@ -1041,10 +1070,10 @@ static size_t round256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 // Bucketing workspace: count, offsets (+1), cursor, scan block sums (ints);
 // float64 weight partials; then the route flag and, for the slab route, the
-// [slab][block] counts, their prefix sums (+1) and scan block sums.
+// [block][slab] counts and the slab totals and cursors.
 struct BucketWs {
-  size_t count, offsets, cursor, bsums, wpart, mode, hist, hoff, hbsums, total;
-  int nb, nbh;
+  size_t count, offsets, cursor, bsums, wpart, mode, hist, slabc, total;
+  int nb;
   explicit BucketWs(int nmesh) {
     const size_t n2 = (size_t)nmesh * nmesh;
     nb = (int)((n2 + 4095) / 4096);
@@ -1055,11 +1084,9 @@ struct BucketWs {
     wpart = round256(bsums + (size_t)(nb + 1) * sizeof(int));
     mode = round256(wpart + 2 * kCountBlocks * sizeof(double));
     const size_t nh = (size_t)nmesh * kSlabBlocks;
-    nbh = (int)((nh + 4095) / 4096);
     hist = mode + 256;
-    hoff = round256(hist + nh * sizeof(int));
-    hbsums = round256(hoff + (nh + 1) * sizeof(int));
-    total = round256(hbsums + (size_t)(nbh + 1) * sizeof(int));
+    slabc = round256(hist + nh * sizeof(int));
+    total = round256(slabc + 2 * (size_t)nmesh * sizeof(int));
   }
 };
 
@@ -1086,15 +1113,18 @@ hipError_t launch_bucket(int dtype, int nmesh, double boxsize, const void* pos, 
   const bool slabs = scratch != nullptr && n >= kSlabMinParticles && nmesh <= kMaxSlabs &&
                      scratch_bytes >= trec_bytes + twrec_bytes;
   int* mode = slabs ? reinterpret_cast<int*>(bw + L.mode) : nullptr;
+  int* slabc = reinterpret_cast<int*>(bw + L.slabc);  // totals [N], then cursors [N]
   hipError_t e = launch_fill_zero(count, (size_t)n2 * sizeof(int), s);
   if (e != hipSuccess) return e;
   if (slabs) {
     if (dtype == PK_F32)
       hipLaunchKernelGGL(k_order_probe<float>, dim3(kProbeGroups), dim3(256), 0, s,
-                         static_cast<const float*>(pos), n, nmesh, boxsize, inv_box, cpl, mode);
+                         static_cast<const float*>(pos), n, nmesh, boxsize, inv_box, cpl, mode,
+                         slabc);
     else
       hipLaunchKernelGGL(k_order_probe<double>, dim3(kProbeGroups), dim3(256), 0, s,
-                         static_cast<const double*>(pos), n, nmesh, boxsize, inv_box, cpl, mode);
+                         static_cast<const double*>(pos), n, nmesh, boxsize, inv_box, cpl, mode,
+                         slabc);
   }
   // run route: contiguous chunks of whole steps, at most kCountBlocks blocks
   int64_t steps = (n + kBucketStep - 1) / kBucketStep;
@@ -1104,17 +1134,14 @@ hipError_t launch_bucket(int dtype, int nmesh, double boxsize, const void* pos, 
   blocks = (n + chunk - 1) / chunk;
   if (blocks < 1) blocks = 1;
   // slab route: at most min(kSlabBlocks, N) contiguous blocks of whole steps
-  // (so that its [slab][block] counts are no more than the N^2 column counts)
   const int64_t scap = kSlabBlocks < nmesh ? kSlabBlocks : nmesh;
   int64_t sblocks = steps < scap ? steps : scap;
   const int64_t schunk = (steps + sblocks - 1) / sblocks * kBucketStep;
   sblocks = (n + schunk - 1) / schunk;
   if (sblocks < 1) sblocks = 1;
-  const int nh = nmesh * (int)sblocks;
   char* sc = static_cast<char*>(scratch);
-  SlabArgs sa{schunk, slabs ? (int)sblocks : 0, reinterpret_cast<int*>(bw + L.hist),
-              reinterpret_cast<const int*>(bw + L.hoff), sc,
-              slabs && amounts ? sc + trec_bytes : nullptr};
+  SlabArgs sa{schunk, slabs ? (int)sblocks : 0, reinterpret_cast<int*>(bw + L.hist), slabc,
+              slabc + nmesh, sc, slabs && amounts ? sc + trec_bytes : nullptr};
   // counts (the workgroups run the route the probe chose)
   if (dtype == PK_F32)
     hipLaunchKernelGGL(k_bucket_count<float>, dim3((unsigned)blocks), dim3(256), 0, s,
@@ -1128,13 +1155,10 @@ hipError_t launch_bucket(int dtype, int nmesh, double boxsize, const void* pos, 
                        wpart, mode, sa);
   hipLaunchKernelGGL(k_weight_sums, dim3(1), dim3(1024), 0, s, wpart, (int)blocks, (int)sblocks,
                      wsums, mode);
-  // one scan, of the route's counts
-  const ScanJob runs_job{count, n2, bsums, offsets, cursor};
-  const ScanJob slabs_job{sa.hist, nh, reinterpret_cast<int*>(bw + L.hbsums),
-                          reinterpret_cast<int*>(bw + L.hoff), nullptr};
-  hipLaunchKernelGGL(k_scan_blocks, dim3(nb), dim3(1024), 0, s, runs_job, slabs_job, mode);
-  hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(1024), 0, s, runs_job, slabs_job, mode);
-  hipLaunchKernelGGL(k_scan_final, dim3(nb), dim3(1024), 0, s, runs_job, slabs_job, mode);
+  // the run route's scan (zero counts on the slab route)
+  hipLaunchKernelGGL(k_scan_blocks, dim3(nb), dim3(1024), 0, s, count, n2, bsums);
+  hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(1024), 0, s, bsums, nb);
+  hipLaunchKernelGGL(k_scan_final, dim3(nb), dim3(1024), 0, s, count, n2, bsums, offsets, cursor);
   if (dtype == PK_F32)
     hipLaunchKernelGGL(k_bucket_scatter<float>, dim3((unsigned)blocks), dim3(256), 0, s,
                        static_cast<const float*>(pos), static_cast<const float*>(weight),
@@ -1151,12 +1175,12 @@ hipError_t launch_bucket(int dtype, int nmesh, double boxsize, const void* pos, 
   // slab route: the slabs into column order
   if (dtype == PK_F32)
     hipLaunchKernelGGL(k_slab_columns<float>, dim3((unsigned)nmesh), dim3(1024), 0, s, nmesh,
-                       mode, sa.hoff, (int)sblocks, static_cast<const float4*>(sa.trec),
+                       mode, sa.total, static_cast<const float4*>(sa.trec),
                        static_cast<const float*>(sa.twrec), offsets, static_cast<float4*>(rec),
                        amounts ? static_cast<float*>(wrec) : nullptr);
   else
     hipLaunchKernelGGL(k_slab_columns<double>, dim3((unsigned)nmesh), dim3(1024), 0, s, nmesh,
-                       mode, sa.hoff, (int)sblocks, static_cast<const double4*>(sa.trec),
+                       mode, sa.total, static_cast<const double4*>(sa.trec),
                        static_cast<const double*>(sa.twrec), offsets, static_cast<double4*>(rec),
                        amounts ? static_cast<double*>(wrec) : nullptr);
   return hipGetLastError();
