@@ -147,7 +147,7 @@ __device__ __forceinline__ void hash_clear(int* keys, int* cnts) {
 constexpr int kBucketUnroll = 4;
 constexpr int kBucketStep = 256 * kBucketUnroll;
 
-constexpr int kSlabBlocks = 1024;      // catalog blocks of the slab route (at most; <= N)
+constexpr int kSlabBlocks = 1024;      // catalog blocks of the slab route (at most)
 constexpr int kMaxSlabs = 2048;        // x-slabs = N, N <= 2048
 constexpr int64_t kSlabMinParticles = 1 << 14;  // smaller catalogs: run route
 
@@ -1133,8 +1133,10 @@ hipError_t launch_bucket(int dtype, int nmesh, double boxsize, const void* pos, 
   const int64_t chunk = (steps + blocks - 1) / blocks * kBucketStep;
   blocks = (n + chunk - 1) / chunk;
   if (blocks < 1) blocks = 1;
-  // slab route: at most min(kSlabBlocks, N) contiguous blocks of whole steps
-  const int64_t scap = kSlabBlocks < nmesh ? kSlabBlocks : nmesh;
+  // slab route: at most min(kSlabBlocks, max(256, N)) contiguous blocks of
+  // whole steps (each block costs one atomic per slab twice; 256 keep the
+  // CUs busy at small N)
+  const int64_t scap = nmesh > 256 ? (nmesh < kSlabBlocks ? nmesh : kSlabBlocks) : 256;
   int64_t sblocks = steps < scap ? steps : scap;
   const int64_t schunk = (steps + sblocks - 1) / sblocks * kBucketStep;
   sblocks = (n + schunk - 1) / schunk;
