@@ -1,7 +1,9 @@
 """GPU parity at the benchmark workloads' full sizes.
 
 * Log-normal mock, 512^3, TSC interlaced, float32, P(k, mu) with 5 mu bins
-  and ell = 0, 2, 4: the whole FFTPower result against the float64 oracle.
+  and ell = 0, 2, 4: the whole FFTPower result against the float64 oracle,
+  for the catalog in generator (cell) order and shuffled (the two routes of
+  the bucketing).
 * Zel'dovich lattice of 512^3 particles on a 1024^3 CIC interlaced float32
   mesh: too large for the oracle's full run inside a test, so it is checked
   on samples the oracle computes one by one (painted cells of both meshes,
@@ -61,6 +63,15 @@ def test_lognormal_512_tsc_interlaced_full(ctx):
     rel = np.abs(got["power"][ok] / want["power"][ok] - 1)
     print(f"max |dP/P| = {rel.max():.2e}", flush=True)
     check_power(got, want, 1e-5, "lognormal-512")
+    # the same catalog in random order takes the other bucketing route
+    # (slab partition instead of column runs) and must give the same result
+    shuffled = pos[np.random.default_rng(12345).permutation(len(pos))]
+    got_s = _fftpower(ctx, m, b, dev(shuffled))
+    check_power(got_s, want, 1e-5, "lognormal-512 shuffled")
+    np.testing.assert_allclose(got_s["power"][ok], got["power"][ok], rtol=1e-6)
+    for ell in (0, 2, 4):
+        np.testing.assert_allclose(got_s["poles"][ell][ok], got["poles"][ell][ok],
+                                   rtol=0, atol=1e-6 * np.abs(got["power"][ok]).max())
 
 
 def _plane_cells(rng, n, x0, count):
