@@ -383,7 +383,19 @@ __global__ void __launch_bounds__(1024)
       const int pi = s / b.nk - 1;
       if ((b.zero_mask >> pi) & 1) src = s % b.nk;
     }
-    for (int g = lane; g < ngroups; g += 16) acc += partials[(size_t)g * b.nsum + src];
+    // eight rows' loads in flight, then added in the same order (g = lane,
+    // lane + 16, ...); a row past the end adds an exact zero
+    constexpr int AHEAD = 8;
+    for (int g0 = lane; g0 < ngroups; g0 += 16 * AHEAD) {
+      double v[AHEAD];
+#pragma unroll
+      for (int k = 0; k < AHEAD; ++k) {
+        const int g = g0 + 16 * k;
+        v[k] = g < ngroups ? partials[(size_t)g * b.nsum + src] : 0.0;
+      }
+#pragma unroll
+      for (int k = 0; k < AHEAD; ++k) acc += v[k];
+    }
   }
   part[lane][slot_in] = acc;
   __syncthreads();
