@@ -239,21 +239,42 @@ __device__ __forceinline__ int signed_wave(int i, int n) { return i < n / 2 ? i 
 
 // Mode factor of the accumulation: coef Y_lm(k^) / W(k) (W the window's
 // sinc^p, or 1 without compensation) at the signed mode (nx, ny, nz); at the
-// DC mode k^ is taken as z^ (the DC mode is never binned).
+// DC mode k^ is taken as z^ (the DC mode is never binned).  Evaluated in the
+// field's precision T (the factor multiplies a T value): the same recurrence
+// as real_harmonic.
 template <typename T>
-__device__ __forceinline__ double mode_factor(int nx, int ny, int nz, int kx, int ky, int ell,
-                                              int am, int sine, double knorm, double coef,
-                                              const T* __restrict__ sinv) {
-  const double n2 = (double)nx * nx + (double)ny * ny + (double)nz * nz;
-  double ux = 0.0, uy = 0.0, uz = 1.0;
-  if (n2 > 0.0) {
-    const double inv = 1.0 / sqrt(n2);
-    ux = nx * inv;
-    uy = ny * inv;
-    uz = nz * inv;
+__device__ __forceinline__ T mode_factor(int nx, int ny, int nz, int kx, int ky, int ell, int am,
+                                         int sine, double knorm, double coef,
+                                         const T* __restrict__ sinv) {
+  const int n2 = nx * nx + ny * ny + nz * nz;
+  T ux = T(0), uy = T(0), uz = T(1);
+  if (n2 > 0) {
+    const T inv = T(1) / sqrt(static_cast<T>(n2));
+    ux = static_cast<T>(nx) * inv;
+    uy = static_cast<T>(ny) * inv;
+    uz = static_cast<T>(nz) * inv;
   }
-  double g = coef * real_harmonic(ell, am, sine, knorm, ux, uy, uz);
-  if (sinv) g *= (double)sinv[kx] * (double)sinv[ky] * (double)sinv[nz];
+  T re = T(1), im = T(0);
+  for (int i = 0; i < am; ++i) {
+    const T r2 = re * ux - im * uy;
+    im = re * uy + im * ux;
+    re = r2;
+  }
+  T q0 = T(1);
+  for (int i = 1; i <= am; ++i) q0 *= static_cast<T>(2 * i - 1);
+  T q = q0;
+  if (ell > am) {
+    T q1 = static_cast<T>(2 * am + 1) * uz * q0;
+    for (int l = am + 2; l <= ell; ++l) {
+      const T q2 = (static_cast<T>(2 * l - 1) * uz * q1 - static_cast<T>(l + am - 1) * q0) /
+                   static_cast<T>(l - am);
+      q0 = q1;
+      q1 = q2;
+    }
+    q = q1;
+  }
+  T g = static_cast<T>(coef * knorm) * q * (sine ? im : re);
+  if (sinv) g *= sinv[kx] * sinv[ky] * sinv[nz];
   return g;
 }
 
@@ -310,8 +331,8 @@ __global__ void __launch_bounds__((XCfg<T, N>::THREADS))
       side[(size_t)kx * N + ky] = v[e];
       continue;
     }
-    const T g = static_cast<T>(
-        mode_factor<T>(signed_wave(kx, N), ny, col, kx, ky, ell, am, sine, knorm, coef, sinv));
+    const T g =
+        mode_factor<T>(signed_wave(kx, N), ny, col, kx, ky, ell, am, sine, knorm, coef, sinv);
     cpx<T> o = {g * v[e].x, g * v[e].y};
     if (!first) {
       o.x += old[e].x;
@@ -338,8 +359,8 @@ __global__ void __launch_bounds__(256)
     const int kx = idx / N, ky = idx % N;
     const cpx<T> z = side[idx], zp = side[((N - kx) & mask) * N + ((N - ky) & mask)];
     const cpx<T> v = {T(0.5) * (z.x + zp.x), T(0.5) * (z.y - zp.y)};
-    const T g = static_cast<T>(mode_factor<T>(signed_wave(kx, N), signed_wave(ky, N), 0, kx, ky,
-                                              ell, am, sine, knorm, coef, sinv));
+    const T g = mode_factor<T>(signed_wave(kx, N), signed_wave(ky, N), 0, kx, ky, ell, am, sine,
+                               knorm, coef, sinv);
     cpx<T> o = {g * v.x, g * v.y};
     if (!first) {
       const cpx<T> old = plane[idx];
