@@ -1083,7 +1083,7 @@ SurveyLayout survey_layout(const pk_mesh_desc* m, const pk_bin_desc* b, int64_t 
   l.side = take(n * n * 2 * es);
   l.fields = take((size_t)nf * l.field_bytes);
   l.planes = take((size_t)nf * l.plane_bytes);
-  l.bpart = take((size_t)(l.gb + l.gp) * b->nk * sizeof(double));
+  l.bpart = take((size_t)b->npoles * (l.gb + l.gp) * b->nk * sizeof(double));
   l.total = off;
   return l;
 }
@@ -1205,19 +1205,27 @@ pk_status pk_convolved_power(pk_ctx* ctx, const pk_mesh_desc* m, const pk_bin_de
                               4.0 * pi / (2 * ells[f] + 1), *t, m->window, m->compensated,
                               first_of[k], s);
   }
-  // sums of Re F_0 conj F_ell per k bin (the fields in the y-pass output
-  // layout, their kz = 0 planes apart), then the weight sums
+  // sums of Re F_0 conj F_ell per k bin: one pass over the fields (in the
+  // y-pass output layout) for every pole, then each pole's kz = 0 plane and
+  // its reduction; then the weight sums
   double* part = reinterpret_cast<double*>(ws + l.bpart);
+  const size_t pstride = (size_t)(l.gb + l.gp) * spec.nsum;
+  const void* others[4] = {nullptr, nullptr, nullptr, nullptr};
+  int fof[4] = {0, 0, 0, 0};
+  for (int i = 0; i < b->npoles; ++i) {
+    while (ells[fof[i]] != b->poles[i]) ++fof[i];
+    others[i] = fof[i] == 0 ? nullptr : field(fof[i]);
+  }
+  if (e == hipSuccess)
+    e = launch_bin_fields(m->dtype, m->nmesh, field(0), others, b->npoles, spec, part, pstride, s,
+                          1);
   for (int i = 0; i < b->npoles && e == hipSuccess; ++i) {
-    int f = 0;
-    while (ells[f] != b->poles[i]) ++f;
-    const void* c2 = f == 0 ? nullptr : field(f);
-    e = launch_bin_packed(m->dtype, m->nmesh, field(0), c2, spec, part, s, 1);
+    const int f = fof[i];
+    double* pi = part + (size_t)i * pstride;
+    e = launch_plane_bin(m->dtype, m->nmesh, plane(0), f == 0 ? nullptr : plane(f), 1, *t,
+                         m->window, 0, spec, pi + (size_t)l.gb * spec.nsum, s, f == 0 ? 0 : 1);
     if (e == hipSuccess)
-      e = launch_plane_bin(m->dtype, m->nmesh, plane(0), f == 0 ? nullptr : plane(f), 1, *t,
-                           m->window, 0, spec, part + (size_t)l.gb * spec.nsum, s, c2 ? 1 : 0);
-    if (e == hipSuccess)
-      e = launch_reduce(part, l.gb + l.gp, spec, result_dev + (size_t)i * b->nk, s);
+      e = launch_reduce(pi, l.gb + l.gp, spec, result_dev + (size_t)i * b->nk, s);
   }
   if (e == hipSuccess)
     e = hipMemcpyAsync(result_dev + (size_t)b->npoles * b->nk, sums, 4 * sizeof(double),

@@ -365,6 +365,60 @@ __global__ void __launch_bounds__(256)
   flush_bins(sb, b.nsum, partials + (size_t)blockIdx.x * b.nsum);
 }
 
+// Cross sums of one field with up to four others in one pass: for each
+// mode of the (packed or y-layout, as k_bin_packed) spectra, column kz' >= 1,
+// h = 2, the k-bin sums of Re(c conj(d_i)), d_i = others.p[i] or c itself
+// when NULL.  Field i's block sums go to partials + i * pstride.  The binning
+// is plain k bins (no mu bins, no poles).
+struct OtherFields {
+  const void* p[4];
+};
+
+template <typename T>
+__global__ void __launch_bounds__(256)
+    k_bin_fields(int N, const cpx<T>* __restrict__ cm, OtherFields others, int nf, BinSpec b,
+                 double* __restrict__ partials, size_t pstride, int lw, int lbx) {
+  extern __shared__ double sb[];
+  zero_bins(sb, nf * b.nsum);
+  __syncthreads();
+  const int NC = N / 2;
+  const size_t total = (size_t)N * N * NC;
+  const int ln = __ffs(N) - 1;
+  const cpx<T>* __restrict__ d[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) d[i] = static_cast<const cpx<T>*>(others.p[i]);
+  for (size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+       idx += (size_t)gridDim.x * blockDim.x) {
+    int col, kx, ky;
+    if (lw < 0) {
+      col = (int)(idx % NC);
+      const size_t rest = idx / NC;
+      ky = (int)(rest % N);
+      kx = (int)(rest / N);
+    } else {
+      col = (int)(((idx >> (lw + 2 * ln)) << lw) | (idx & ((1u << lw) - 1)));
+      ky = (int)((idx >> (lw + lbx)) & (size_t)(N - 1));
+      kx = (int)((((idx >> (lw + lbx + ln)) & (size_t)((N >> lbx) - 1)) << lbx) |
+                 ((idx >> lw) & ((1u << lbx) - 1)));
+    }
+    if (col == 0) continue;
+    const int nx = signed_index(kx, N), ny = signed_index(ky, N);
+    const int k = kbin_of(nx * nx + ny * ny + col * col, b);
+    if (k < 0) continue;
+    const cpx<T> c = cm[idx];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      if (i < nf) {
+        const cpx<T> e = d[i] ? d[i][idx] : c;
+        atomicAdd(&sb[i * b.nsum + k], (double)(T(2) * (c.x * e.x + c.y * e.y)));
+      }
+    }
+  }
+  __syncthreads();
+  for (int i = 0; i < nf; ++i)
+    flush_bins(sb + i * b.nsum, b.nsum, partials + i * pstride + (size_t)blockIdx.x * b.nsum);
+}
+
 // result[s] = sum_g partials[g][src(s)]; the slots of an ell = 0 pole take
 // the sum of the plain power slots.  64 slots per workgroup, 16 lanes per
 // slot: lane l sums the rows g = l, l + 16, ... in increasing g, then the 16
@@ -724,6 +778,34 @@ hipError_t launch_bin_packed(int dtype, int nmesh, const void* cmesh, const void
     hipLaunchKernelGGL(k_bin_packed<double>, dim3((unsigned)g), dim3(256), bin_lds_bytes(b), s,
                        nmesh, static_cast<const cpx<double>*>(cmesh),
                        static_cast<const cpx<double>*>(cmesh2), b, partials, lw, lbx);
+  return hipGetLastError();
+}
+
+hipError_t launch_bin_fields(int dtype, int nmesh, const void* cmesh, const void* const* others,
+                             int nf, const BinSpec& b, double* partials, size_t pstride,
+                             hipStream_t s, int ylayout) {
+  if (nf < 1 || nf > 4) return hipErrorInvalidValue;
+  const size_t total = (size_t)nmesh * nmesh * (nmesh / 2);
+  size_t g = (total + 255) / 256;
+  if (g > 1024) g = 1024;
+  int lw = -1, lbx = 0;
+  if (ylayout) {
+    const bool ok = dtype == PK_F32 ? ylayout_bits<float>(nmesh, &lw, &lbx)
+                                    : ylayout_bits<double>(nmesh, &lw, &lbx);
+    if (!ok) return hipErrorInvalidValue;
+  }
+  OtherFields of{};
+  for (int i = 0; i < nf; ++i) of.p[i] = others[i];
+  const size_t lds = (size_t)nf * b.nsum * sizeof(double);
+  if (lds > kLdsBytesPerGroup) return hipErrorInvalidValue;
+  if (dtype == PK_F32)
+    hipLaunchKernelGGL(k_bin_fields<float>, dim3((unsigned)g), dim3(256), lds, s, nmesh,
+                       static_cast<const cpx<float>*>(cmesh), of, nf, b, partials, pstride, lw,
+                       lbx);
+  else
+    hipLaunchKernelGGL(k_bin_fields<double>, dim3((unsigned)g), dim3(256), lds, s, nmesh,
+                       static_cast<const cpx<double>*>(cmesh), of, nf, b, partials, pstride, lw,
+                       lbx);
   return hipGetLastError();
 }
 

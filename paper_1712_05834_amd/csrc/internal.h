@@ -116,6 +116,12 @@ hipError_t launch_xpass_bin(int dtype, int nmesh, const void* mesh_a, const void
 // both spectra are in the y-pass output layout instead of the packed one.
 hipError_t launch_bin_packed(int dtype, int nmesh, const void* cmesh, const void* cmesh2,
                              const BinSpec& b, double* partials, hipStream_t s, int ylayout = 0);
+// Plain k-bin sums of Re(c conj(d_i)) for nf <= 4 other spectra d_i (NULL:
+// c itself) in one pass; field i's workgroup sums go to partials + i pstride
+// (launch_bin_packed's grid and row layout).  ylayout as launch_bin_packed.
+hipError_t launch_bin_fields(int dtype, int nmesh, const void* cmesh, const void* const* others,
+                             int nf, const BinSpec& b, double* partials, size_t pstride,
+                             hipStream_t s, int ylayout);
 // cross = 0: za (and the interlaced zb) combined; cross = 1: Re(a conj(b)).
 hipError_t launch_plane_bin(int dtype, int nmesh, const void* za, const void* zb, size_t zstride,
                             const MeshTables& t, int order, int compensated, const BinSpec& b,
