@@ -126,6 +126,10 @@ __global__ void __launch_bounds__(256)
     } else {
       w = (wr ? (double)wr[i - nd] : 1.0) * neg_alpha;
     }
+    if (ell == 0) {  // Y_00 is the constant knorm: the position is not read
+      value[i] = static_cast<T>(w * knorm);
+      continue;
+    }
     double rx = (double)pos[3 * i] - ox, ry = (double)pos[3 * i + 1] - oy,
            rz = (double)pos[3 * i + 2] - oz;
     const double rn = sqrt(rx * rx + ry * ry + rz * rz);
