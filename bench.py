@@ -21,6 +21,7 @@ import hashlib
 import json
 import math
 import os
+import re
 import sys
 import time
 
@@ -103,12 +104,22 @@ def algorithmic_bytes(stage, w, npart):
     }.get(stage, 0)
 
 
+def _code_only(text):
+    """The source with // and /* */ comments and blank lines removed (the
+    kernels' sources contain no string literals with comment markers)."""
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    lines = (re.sub(r"//.*", "", line).rstrip() for line in text.splitlines())
+    return "\n".join(line for line in lines if line)
+
+
 def source_hash():
+    """Hash of the kernel sources' code (comments and blank lines ignored), so
+    that measured traffic stays attached to the code it was measured on."""
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_1712_05834_amd", "csrc")
     for f in sorted(os.listdir(csrc)):
-        with open(os.path.join(csrc, f), "rb") as fh:
-            h.update(f.encode() + fh.read())
+        with open(os.path.join(csrc, f), encoding="utf-8") as fh:
+            h.update(f.encode() + _code_only(fh.read()).encode())
     return h.hexdigest()[:16]
 
 

@@ -25,8 +25,8 @@
 //                     atomics.  (The scan kernels of the run route then scan
 //                     zero counts; k_slab_columns writes the offsets.)
 // 3''. k_slab_columns one workgroup per slab: LDS counts of its columns,
-//                     their offsets, then the records scattered into column
-//                     order.  No global atomics at all.
+//                     their offsets, then the records moved into column order
+//                     (LDS atomics only).
 // 4. k_paint_z        one workgroup owns a TX x TY block of full z-columns of
 //                     both meshes: it reads the records of the columns whose
 //                     windows reach the block, adds the window weights into
@@ -400,7 +400,8 @@ __global__ void __launch_bounds__(256)
   }
 }
 
-// sum w and sum w^2 from the per-block partials, in block order.
+// sum w and sum w^2 from the per-block partials of the route taken, in block
+// order.
 __global__ void __launch_bounds__(1024)
     k_weight_sums(const double* __restrict__ wpart, int nblocks_runs, int nblocks_slabs,
                   double* __restrict__ wsums, const int* __restrict__ mode) {

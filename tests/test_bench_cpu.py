@@ -43,3 +43,9 @@ def test_traffic_only_for_the_measured_sources(tmp_path, monkeypatch):
         monkeypatch.setattr(bench, "source_hash", lambda: "0" * 16)
         assert bench.measured_traffic(wl, "paint_z") is None
     assert bench.measured_traffic("no-such-workload", "paint_z") is None
+
+
+def test_source_hash_ignores_comments():
+    code = "int f(int x) {  // the answer\n  /* more\n  words */ return x;\n}\n\n"
+    assert bench._code_only(code) == "int f(int x) {\n   return x;\n}"
+    assert bench._code_only(code) == bench._code_only(code.replace("the answer", "another"))
