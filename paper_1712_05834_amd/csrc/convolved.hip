@@ -157,10 +157,11 @@ __device__ __forceinline__ unsigned record_cell_bits(double w) { return (unsigne
 // its normalisation, written to y[ell (ell + 1) + m]: Q_ell^|m|(z) times
 // Re (x + i y)^|m| (m >= 0) or Im (x + i y)^|m| (m < 0) -- the terms of
 // real_harmonic, with the powers and the recurrences shared by all 25.
-__device__ __forceinline__ void harmonics_to_4(double x, double y, double z, double* out) {
-  double re[5], im[5];
-  re[0] = 1.0;
-  im[0] = 0.0;
+template <typename U>
+__device__ __forceinline__ void harmonics_to_4(U x, U y, U z, U* out) {
+  U re[5], im[5];
+  re[0] = U(1);
+  im[0] = U(0);
 #pragma unroll
   for (int m = 1; m <= 4; ++m) {
     re[m] = re[m - 1] * x - im[m - 1] * y;
@@ -168,20 +169,21 @@ __device__ __forceinline__ void harmonics_to_4(double x, double y, double z, dou
   }
 #pragma unroll
   for (int m = 0; m <= 4; ++m) {
-    double q0 = 1.0;  // Q_m^m = (2m - 1)!!
+    U q0 = U(1);  // Q_m^m = (2m - 1)!!
 #pragma unroll
-    for (int i = 1; i <= m; ++i) q0 *= (double)(2 * i - 1);
-    double q1 = 0.0;
+    for (int i = 1; i <= m; ++i) q0 *= static_cast<U>(2 * i - 1);
+    U q1 = U(0);
 #pragma unroll
     for (int l = m; l <= 4; ++l) {
-      double q;
+      U q;
       if (l == m) {
         q = q0;
       } else if (l == m + 1) {
-        q = (double)(2 * m + 1) * z * q0;
+        q = static_cast<U>(2 * m + 1) * z * q0;
         q1 = q;
       } else {
-        q = ((double)(2 * l - 1) * z * q1 - (double)(l + m - 1) * q0) / (double)(l - m);
+        q = (static_cast<U>(2 * l - 1) * z * q1 - static_cast<U>(l + m - 1) * q0) /
+            static_cast<U>(l - m);
         q0 = q1;
         q1 = q;
       }
@@ -202,6 +204,31 @@ struct YlmSlots {
   double knorm[kMaxHarmonics];
 };
 
+// Unit vector from the observer to a record's position (float64), rounded
+// to the field precision U; z^ at the observer itself.
+template <typename U, typename R>
+__device__ __forceinline__ void record_direction(const R& r, int ix, double h, double ox,
+                                                 double oy, double oz, U* u) {
+  const unsigned bits = record_cell_bits(r.w);
+  const int iy = (int)(bits >> 16), iz = (int)(bits & 0xffffu);
+  double rx = ((double)ix + (double)r.x) * h - ox, ry = ((double)iy + (double)r.y) * h - oy,
+         rz = ((double)iz + (double)r.z) * h - oz;
+  const double rn = sqrt(rx * rx + ry * ry + rz * rz);
+  if (rn > 0.0) {
+    const double inv = 1.0 / rn;
+    u[0] = static_cast<U>(rx * inv);
+    u[1] = static_cast<U>(ry * inv);
+    u[2] = static_cast<U>(rz * inv);
+  } else {
+    u[0] = U(0);
+    u[1] = U(0);
+    u[2] = U(1);
+  }
+}
+
+// The harmonics are evaluated in the field precision T (the amounts are T
+// values); each lane takes two records per step, so that two chains of
+// load, evaluation and stores are in flight.
 template <typename T, typename R>
 __global__ void __launch_bounds__(256)
     k_ylm_records(const R* __restrict__ rec, const T* __restrict__ base,
@@ -212,30 +239,27 @@ __global__ void __launch_bounds__(256)
   const int ix = col / N;
   const int lane = threadIdx.x & 63;
   const int end = offsets[col + 1];
-  for (int j = offsets[col] + lane; j < end; j += 64) {
-    const R r = rec[j];
-    const unsigned bits = record_cell_bits(r.w);
-    const int iy = (int)(bits >> 16), iz = (int)(bits & 0xffffu);
-    double rx = ((double)ix + (double)r.x) * h - ox, ry = ((double)iy + (double)r.y) * h - oy,
-           rz = ((double)iz + (double)r.z) * h - oz;
-    const double rn = sqrt(rx * rx + ry * ry + rz * rz);
-    if (rn > 0.0) {
-      const double inv = 1.0 / rn;
-      rx *= inv;
-      ry *= inv;
-      rz *= inv;
-    } else {
-      rx = 0.0;
-      ry = 0.0;
-      rz = 1.0;
-    }
-    double y[kMaxHarmonics];
-    harmonics_to_4(rx, ry, rz, y);
-    const double b = (double)base[j];
+  for (int j = offsets[col] + lane; j < end; j += 128) {
+    const int j2 = j + 64;
+    const bool two = j2 < end;
+    const R r1 = rec[j];
+    const R r2 = two ? rec[j2] : r1;
+    const T b1 = base[j];
+    const T b2 = two ? base[j2] : b1;
+    T u1[3], u2[3], y1[kMaxHarmonics], y2[kMaxHarmonics];
+    record_direction<T>(r1, ix, h, ox, oy, oz, u1);
+    record_direction<T>(r2, ix, h, ox, oy, oz, u2);
+    harmonics_to_4<T>(u1[0], u1[1], u1[2], y1);
+    harmonics_to_4<T>(u2[0], u2[1], u2[2], y2);
 #pragma unroll
-    for (int q = 0; q < kMaxHarmonics; ++q)
-      if (ys.slot[q] >= 0)
-        amount[(size_t)ys.slot[q] * stride + j] = static_cast<T>(b * (ys.knorm[q] * y[q]));
+    for (int q = 0; q < kMaxHarmonics; ++q) {
+      if (ys.slot[q] >= 0) {
+        const T kn = static_cast<T>(ys.knorm[q]);
+        T* __restrict__ out = amount + (size_t)ys.slot[q] * stride;
+        out[j] = b1 * (kn * y1[q]);
+        if (two) out[j2] = b2 * (kn * y2[q]);
+      }
+    }
   }
 }
 
