@@ -1040,7 +1040,8 @@ int survey_fields(const pk_bin_desc* b, int* ells) {
 
 struct SurveyLayout {
   size_t pos = 0, value = 0, sums = 0, zero = 0, bsums = 0, sumpart = 0, bucket = 0, rec = 0,
-         wbase = 0, amounts = 0, mesh = 0, ymesh = 0, side = 0, fields = 0, planes = 0,
+         wbase = 0, amounts = 0, mesh = 0, ymesh = 0, ymesh2 = 0, side = 0, side2 = 0,
+         fields = 0, planes = 0,
          bpart = 0, total = 0;
   size_t field_bytes = 0, plane_bytes = 0, amount_bytes = 0;
   int gb = 0, gp = 0, nh = 0;
@@ -1080,7 +1081,9 @@ SurveyLayout survey_layout(const pk_mesh_desc* m, const pk_bin_desc* b, int64_t 
   l.amounts = take((size_t)l.nh * l.amount_bytes);
   l.mesh = take(l.field_bytes);
   l.ymesh = take(l.field_bytes);
+  l.ymesh2 = take(l.field_bytes);
   l.side = take(n * n * 2 * es);
+  l.side2 = take(n * n * 2 * es);
   l.fields = take((size_t)nf * l.field_bytes);
   l.planes = take((size_t)nf * l.plane_bytes);
   l.bpart = take((size_t)b->npoles * (l.gb + l.gp) * b->nk * sizeof(double));
@@ -1191,19 +1194,27 @@ pk_status pk_convolved_power(pk_ctx* ctx, const pk_mesh_desc* m, const pk_bin_de
   if (e == hipSuccess)
     e = launch_ylm_records(m->dtype, m->nmesh, m->boxsize, rec, base, ws + l.bucket, observer, hs,
                            l.amount_bytes / es, ws + l.amounts, s);
-  // each harmonic: paint with the z-pass, the y-pass into the x-pass layout,
-  // the x-pass accumulating into F_ell.  The painted field has mean ~0:
-  // nothing is subtracted before the z-FFT.
+  // the harmonics of each ell two at a time: each painted with the z-pass and
+  // taken through the y-pass into the x-pass layout (ymesh, ymesh2), then one
+  // x-pass adds both into F_ell.  The painted field has mean ~0: nothing is
+  // subtracted before the z-FFT.
   const double pi = 3.14159265358979323846;
-  for (int k = 0; k < hs.n && e == hipSuccess; ++k) {
+  void* ymeshes[2] = {ymesh, ws + l.ymesh2};
+  for (int k = 0; k < hs.n && e == hipSuccess;) {
     const int f = field_of[k];
-    e = launch_paint_z(m->dtype, m->nmesh, m->window, false, rec, amount(k), ws + l.bucket, zero,
-                       t->tw, mesh, nullptr, s);
-    if (e == hipSuccess) e = launch_fft_y_relayout(m->dtype, m->nmesh, mesh, ymesh, t->tw, s);
+    const int np2 = (k + 1 < hs.n && field_of[k + 1] == f) ? 2 : 1;
+    for (int j = 0; j < np2 && e == hipSuccess; ++j) {
+      e = launch_paint_z(m->dtype, m->nmesh, m->window, false, rec, amount(k + j), ws + l.bucket,
+                         zero, t->tw, mesh, nullptr, s);
+      if (e == hipSuccess)
+        e = launch_fft_y_relayout(m->dtype, m->nmesh, mesh, ymeshes[j], t->tw, s);
+    }
     if (e == hipSuccess)
-      e = launch_x_accumulate(m->dtype, m->nmesh, ymesh, field(f), plane(f), ws + l.side, hs.h[k],
-                              4.0 * pi / (2 * ells[f] + 1), *t, m->window, m->compensated,
-                              first_of[k], s);
+      e = launch_x_accumulate(m->dtype, m->nmesh, ymeshes[0], np2 == 2 ? ymeshes[1] : nullptr,
+                              field(f), plane(f), ws + l.side, np2 == 2 ? ws + l.side2 : nullptr,
+                              hs.h[k], hs.h[k + np2 - 1], 4.0 * pi / (2 * ells[f] + 1), *t,
+                              m->window, m->compensated, first_of[k], s);
+    k += np2;
   }
   // sums of Re F_0 conj F_ell per k bin: one pass over the fields (in the
   // y-pass output layout) for every pole, then each pole's kz = 0 plane and

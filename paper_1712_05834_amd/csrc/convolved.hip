@@ -314,13 +314,16 @@ __device__ __forceinline__ T mode_factor(int nx, int ny, int nz, int kx, int ky,
 // read-modify-write of F has the locality of the loads.  Column kz' >= 1
 // holds c(kx, ky, kz'); column 0 packs the planes kz = 0 and N/2 and needs
 // the partner mode (-kx, -ky), which another workgroup transforms, so its
-// lines go to `side` ([kx][ky]) for k_plane_accumulate.
+// lines go to `side` ([kx][ky]) for k_plane_accumulate.  With mesh2, a
+// second harmonic h2 of the same ell is transformed in the same workgroup
+// and added too, so that F is read and written once for both (its packed
+// column goes to side2).
 template <typename T, int N>
 __global__ void __launch_bounds__((XCfg<T, N>::THREADS))
-    k_fft_x_accumulate(const cpx<T>* __restrict__ mesh, cpx<T>* __restrict__ f,
-                       cpx<T>* __restrict__ side, const cpx<T>* __restrict__ tw, int ell, int am,
-                       int sine, double knorm, double coef, const T* __restrict__ sinv,
-                       int first) {
+    k_fft_x_accumulate(const cpx<T>* __restrict__ mesh, const cpx<T>* __restrict__ mesh2,
+                       cpx<T>* __restrict__ f, cpx<T>* __restrict__ side,
+                       cpx<T>* __restrict__ side2, const cpx<T>* __restrict__ tw, Harmonic h1,
+                       Harmonic h2, double coef, const T* __restrict__ sinv, int first) {
   using Cf = XCfg<T, N>;
   using YL = YLayout<T, N>;
   using Ix = typename YL::Ix;
@@ -342,26 +345,40 @@ __global__ void __launch_bounds__((XCfg<T, N>::THREADS))
     return YL::at(t + TPL * e, ky, col);
   };
   // the running F is loaded with the lines, so its latency overlaps the FFT
-  cpx<T> v[E], old[E];
+  const bool two = mesh2 != nullptr;
+  cpx<T> v[E], v2[E], old[E];
 #pragma unroll
   for (int e = 0; e < E; ++e) v[e] = mesh[at(e)];
+  if (two) {
+#pragma unroll
+    for (int e = 0; e < E; ++e) v2[e] = mesh2[at(e)];
+  }
   if (!first && col != 0) {
 #pragma unroll
     for (int e = 0; e < E; ++e) old[e] = f[at(e)];
   }
   LdsCols<T, C> lc{lds, c};
   stockham<T, N, E, 1>(v, t, tw1, lc);
+  if (two) stockham<T, N, E, 1>(v2, t, tw1, lc);
   const int ny = signed_wave(ky, N);
 #pragma unroll
   for (int e = 0; e < E; ++e) {
     const int kx = t + TPL * e;
     if (col == 0) {
       side[(size_t)kx * N + ky] = v[e];
+      if (two) side2[(size_t)kx * N + ky] = v2[e];
       continue;
     }
+    const int nx = signed_wave(kx, N);
     const T g =
-        mode_factor<T>(signed_wave(kx, N), ny, col, kx, ky, ell, am, sine, knorm, coef, sinv);
+        mode_factor<T>(nx, ny, col, kx, ky, h1.ell, h1.am, h1.sine, h1.knorm, coef, sinv);
     cpx<T> o = {g * v[e].x, g * v[e].y};
+    if (two) {
+      const T g2 =
+          mode_factor<T>(nx, ny, col, kx, ky, h2.ell, h2.am, h2.sine, h2.knorm, coef, sinv);
+      o.x += g2 * v2[e].x;
+      o.y += g2 * v2[e].y;
+    }
     if (!first) {
       o.x += old[e].x;
       o.y += old[e].y;
@@ -478,28 +495,36 @@ hipError_t launch_ylm_records(int dtype, int nmesh, double boxsize, const void* 
 }
 
 template <typename T, int N>
-static hipError_t x_accumulate_t(const void* ymesh, void* field, void* plane, void* side,
-                                 const void* tw, const Harmonic& h, double coef, const T* sinv,
-                                 int first, hipStream_t s) {
+static hipError_t x_accumulate_t(const void* ymesh, const void* ymesh2, void* field, void* plane,
+                                 void* side, void* side2, const void* tw, const Harmonic& h,
+                                 const Harmonic& h2, double coef, const T* sinv, int first,
+                                 hipStream_t s) {
   using Cf = XCfg<T, N>;
   hipLaunchKernelGGL((k_fft_x_accumulate<T, N>), dim3((unsigned)(N * Cf::CHUNKS)),
                      dim3(Cf::THREADS), 0, s, static_cast<const cpx<T>*>(ymesh),
-                     static_cast<cpx<T>*>(field), static_cast<cpx<T>*>(side),
-                     static_cast<const cpx<T>*>(tw), h.ell, h.am, h.sine, h.knorm, coef, sinv,
-                     first);
+                     static_cast<const cpx<T>*>(ymesh2), static_cast<cpx<T>*>(field),
+                     static_cast<cpx<T>*>(side), static_cast<cpx<T>*>(side2),
+                     static_cast<const cpx<T>*>(tw), h, h2, coef, sinv, first);
   hipLaunchKernelGGL(k_plane_accumulate<T>, dim3(grid_for((size_t)N * N, 4096)), dim3(256), 0,
                      s, N, static_cast<const cpx<T>*>(side), static_cast<cpx<T>*>(plane), h.ell,
                      h.am, h.sine, h.knorm, coef, sinv, first);
+  if (ymesh2)
+    hipLaunchKernelGGL(k_plane_accumulate<T>, dim3(grid_for((size_t)N * N, 4096)), dim3(256), 0,
+                       s, N, static_cast<const cpx<T>*>(side2), static_cast<cpx<T>*>(plane),
+                       h2.ell, h2.am, h2.sine, h2.knorm, coef, sinv, 0);
   return hipGetLastError();
 }
 
 template <typename T>
-static hipError_t x_accumulate_n(int nmesh, const void* ymesh, void* field, void* plane,
-                                 void* side, const void* tw, const Harmonic& h, double coef,
+static hipError_t x_accumulate_n(int nmesh, const void* ymesh, const void* ymesh2, void* field,
+                                 void* plane, void* side, void* side2, const void* tw,
+                                 const Harmonic& h, const Harmonic& h2, double coef,
                                  const T* sinv, int first, hipStream_t s) {
   switch (nmesh) {
-#define PK_XA(NN) \
-  case NN: return x_accumulate_t<T, NN>(ymesh, field, plane, side, tw, h, coef, sinv, first, s);
+#define PK_XA(NN)                                                                          \
+  case NN:                                                                                 \
+    return x_accumulate_t<T, NN>(ymesh, ymesh2, field, plane, side, side2, tw, h, h2, coef, \
+                                 sinv, first, s);
     PK_XA(8) PK_XA(16) PK_XA(32) PK_XA(64) PK_XA(128) PK_XA(256) PK_XA(512) PK_XA(1024)
     PK_XA(2048)
 #undef PK_XA
@@ -507,17 +532,22 @@ static hipError_t x_accumulate_n(int nmesh, const void* ymesh, void* field, void
   }
 }
 
-hipError_t launch_x_accumulate(int dtype, int nmesh, const void* ymesh, void* field, void* plane,
-                               void* side, const Harmonic& h, double coef, const MeshTables& t,
-                               int order, int compensated, int first, hipStream_t s) {
+hipError_t launch_x_accumulate(int dtype, int nmesh, const void* ymesh, const void* ymesh2,
+                               void* field, void* plane, void* side, void* side2,
+                               const Harmonic& h, const Harmonic& h2, double coef,
+                               const MeshTables& t, int order, int compensated, int first,
+                               hipStream_t s) {
+  if (ymesh2 && (!side2 || h2.ell != h.ell)) return hipErrorInvalidValue;
   if (dtype == PK_F32) {
     const float* sinv =
         compensated ? static_cast<const float*>(t.sinc_inv) + (size_t)(order - 2) * nmesh : nullptr;
-    return x_accumulate_n<float>(nmesh, ymesh, field, plane, side, t.tw, h, coef, sinv, first, s);
+    return x_accumulate_n<float>(nmesh, ymesh, ymesh2, field, plane, side, side2, t.tw, h, h2,
+                                 coef, sinv, first, s);
   }
   const double* sinv =
       compensated ? static_cast<const double*>(t.sinc_inv) + (size_t)(order - 2) * nmesh : nullptr;
-  return x_accumulate_n<double>(nmesh, ymesh, field, plane, side, t.tw, h, coef, sinv, first, s);
+  return x_accumulate_n<double>(nmesh, ymesh, ymesh2, field, plane, side, side2, t.tw, h, h2,
+                                coef, sinv, first, s);
 }
 
 }  // namespace pk

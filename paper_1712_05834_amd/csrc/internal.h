@@ -176,9 +176,13 @@ hipError_t launch_ylm_records(int dtype, int nmesh, double boxsize, const void* 
 // from launch_fft_y_relayout) fused with field (+)= coef Y_lm(k^) A / W(k);
 // field is in the same layout, its kz = 0 plane goes to plane ([kx][ky],
 // N^2 complex) instead; side: N^2 complex scratch for the packed column.
-hipError_t launch_x_accumulate(int dtype, int nmesh, const void* ymesh, void* field, void* plane,
-                               void* side, const Harmonic& h, double coef, const MeshTables& t,
-                               int order, int compensated, int first, hipStream_t s);
+// With ymesh2 (and side2), a second harmonic h2 of the same ell is added in
+// the same pass.
+hipError_t launch_x_accumulate(int dtype, int nmesh, const void* ymesh, const void* ymesh2,
+                               void* field, void* plane, void* side, void* side2,
+                               const Harmonic& h, const Harmonic& h2, double coef,
+                               const MeshTables& t, int order, int compensated, int first,
+                               hipStream_t s);
 
 }  // namespace pk
 
