@@ -256,7 +256,11 @@ pk_status pk_projected_to_host(pk_ctx *ctx, const pk_mesh_desc *m, const pk_bin_
  * >= pk_workspace_bytes(m, b, n) bytes, caller-owned scratch (content on
  * entry ignored).  result_dev as in pk_bin_power, all slots overwritten
  * including sum w and sum w^2.  Nothing is allocated when the context
- * already holds the tables for this mesh size and binning.
+ * already holds the tables for this mesh size and binning.  The particles
+ * are grouped by mesh column on the device, by one of two routes chosen there
+ * from the catalog's order (no host round trip); the order of the float64
+ * sums within a column is not fixed, so results are reproducible to rounding
+ * only.
  * Errors: PK_EINVAL (also a too small workspace), PK_EUNSUPPORTED,
  * PK_EDEVICE. */
 pk_status pk_fftpower(pk_ctx *ctx, const pk_mesh_desc *m, const pk_bin_desc *b,

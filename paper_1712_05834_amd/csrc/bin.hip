@@ -124,7 +124,7 @@ __global__ void __launch_bounds__((XCfg<T, N>::THREADS)) __attribute__((amdgpu_w
                 const T* __restrict__ sinv, BinSpec b, double* __restrict__ partials,
                 cpx<T>* __restrict__ side_a, cpx<T>* __restrict__ side_b) {
   using Cf = XCfg<T, N>;
-  constexpr int E = Cf::E, TPL = Cf::TPL, C = Cf::C, NC = Cf::NC, CHUNKS = Cf::CHUNKS;
+  constexpr int E = Cf::E, TPL = Cf::TPL, C = Cf::C, CHUNKS = Cf::CHUNKS;
   __shared__ cpx<T> lds[Cf::LDS_ELEMS];
   __shared__ cpx<T> tws[stage_table_size<N, E>() + 1];
   // per-index factors, read for every mode: the interlacing phase
