@@ -351,7 +351,7 @@ pk_status pk_fftpower_v(pk_ctx *ctx, const pk_mesh_desc *m, const pk_bin_desc *b
 size_t pk_convolved_doubles(const pk_bin_desc *b);
 /* Device workspace of pk_convolved_power (bytes), 0 for invalid arguments:
  * the concatenated catalog, its records, the painted amounts of every
- * harmonic Y_lm (sum over the fields of 2 ell + 1 values per particle), three
+ * harmonic Y_lm (sum over the fields of 2 ell + 1 values per particle), five
  * meshes and one spectrum per field F_ell kept. */
 size_t pk_convolved_workspace_bytes(const pk_mesh_desc *m, const pk_bin_desc *b, int64_t n_data,
                                     int64_t n_rand);

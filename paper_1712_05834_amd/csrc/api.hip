@@ -467,6 +467,12 @@ void pk_ctx_destroy(pk_ctx* ctx) {
     (void)hipStreamDestroy(ln.stream);
   }
   if (ctx->tables_ready) (void)hipEventDestroy(ctx->tables_ready);
+  if (ctx->aux) {
+    (void)hipStreamSynchronize(ctx->aux);
+    (void)hipStreamDestroy(ctx->aux);
+  }
+  for (auto& ev : ctx->aux_ev)
+    if (ev) (void)hipEventDestroy(ev);
   if (ctx->host_stage) (void)hipHostFree(ctx->host_stage);
   delete ctx;
 }
@@ -1040,7 +1046,8 @@ int survey_fields(const pk_bin_desc* b, int* ells) {
 
 struct SurveyLayout {
   size_t pos = 0, value = 0, sums = 0, zero = 0, bsums = 0, sumpart = 0, bucket = 0, rec = 0,
-         wbase = 0, amounts = 0, mesh = 0, ymesh = 0, ymesh2 = 0, side = 0, side2 = 0,
+         wbase = 0, amounts = 0, mesh = 0, ymesh = 0, ymesh2 = 0, ymesh3 = 0, ymesh4 = 0,
+         side = 0, side2 = 0,
          fields = 0, planes = 0,
          bpart = 0, total = 0;
   size_t field_bytes = 0, plane_bytes = 0, amount_bytes = 0;
@@ -1082,6 +1089,8 @@ SurveyLayout survey_layout(const pk_mesh_desc* m, const pk_bin_desc* b, int64_t 
   l.mesh = take(l.field_bytes);
   l.ymesh = take(l.field_bytes);
   l.ymesh2 = take(l.field_bytes);
+  l.ymesh3 = take(l.field_bytes);
+  l.ymesh4 = take(l.field_bytes);
   l.side = take(n * n * 2 * es);
   l.side2 = take(n * n * 2 * es);
   l.fields = take((size_t)nf * l.field_bytes);
@@ -1195,27 +1204,48 @@ pk_status pk_convolved_power(pk_ctx* ctx, const pk_mesh_desc* m, const pk_bin_de
     e = launch_ylm_records(m->dtype, m->nmesh, m->boxsize, rec, base, ws + l.bucket, observer, hs,
                            l.amount_bytes / es, ws + l.amounts, s);
   // the harmonics of each ell two at a time: each painted with the z-pass and
-  // taken through the y-pass into the x-pass layout (ymesh, ymesh2), then one
-  // x-pass adds both into F_ell.  The painted field has mean ~0: nothing is
-  // subtracted before the z-FFT.
+  // taken through the y-pass into the x-pass layout (a set of two buffers),
+  // then one x-pass adds both into F_ell.  The x-passes run on a second
+  // stream, beside the painting of the next harmonics (the painting is bound
+  // by LDS atomics, the x-pass by memory and FFT work); the buffer sets
+  // alternate, and events order each set's y-passes before its x-pass and
+  // that x-pass before the set is written again.  The painted field has mean
+  // ~0: nothing is subtracted before the z-FFT.
+  if (!ctx->aux) {
+    e = hipStreamCreateWithFlags(&ctx->aux, hipStreamNonBlocking);
+    for (int i = 0; i < 5 && e == hipSuccess; ++i)
+      e = hipEventCreateWithFlags(&ctx->aux_ev[i], hipEventDisableTiming);
+    if (e != hipSuccess) return dev_fail(ctx, e, "survey stream");
+  }
+  hipStream_t sx = ctx->aux;
+  hipEvent_t* ydone = ctx->aux_ev;      // [2]
+  hipEvent_t* xdone = ctx->aux_ev + 2;  // [2]
   const double pi = 3.14159265358979323846;
-  void* ymeshes[2] = {ymesh, ws + l.ymesh2};
-  for (int k = 0; k < hs.n && e == hipSuccess;) {
-    const int f = field_of[k];
+  void* ysets[2][2] = {{ymesh, ws + l.ymesh2}, {ws + l.ymesh3, ws + l.ymesh4}};
+  for (int k = 0, pass = 0; k < hs.n && e == hipSuccess; ++pass) {
+    const int f = field_of[k], set = pass & 1;
     const int np2 = (k + 1 < hs.n && field_of[k + 1] == f) ? 2 : 1;
+    if (pass >= 2) e = hipStreamWaitEvent(s, xdone[set], 0);  // x-pass pass - 2 is done with it
     for (int j = 0; j < np2 && e == hipSuccess; ++j) {
       e = launch_paint_z(m->dtype, m->nmesh, m->window, false, rec, amount(k + j), ws + l.bucket,
                          zero, t->tw, mesh, nullptr, s);
       if (e == hipSuccess)
-        e = launch_fft_y_relayout(m->dtype, m->nmesh, mesh, ymeshes[j], t->tw, s);
+        e = launch_fft_y_relayout(m->dtype, m->nmesh, mesh, ysets[set][j], t->tw, s);
     }
+    if (e == hipSuccess) e = hipEventRecord(ydone[set], s);
+    if (e == hipSuccess) e = hipStreamWaitEvent(sx, ydone[set], 0);
     if (e == hipSuccess)
-      e = launch_x_accumulate(m->dtype, m->nmesh, ymeshes[0], np2 == 2 ? ymeshes[1] : nullptr,
-                              field(f), plane(f), ws + l.side, np2 == 2 ? ws + l.side2 : nullptr,
-                              hs.h[k], hs.h[k + np2 - 1], 4.0 * pi / (2 * ells[f] + 1), *t,
-                              m->window, m->compensated, first_of[k], s);
+      e = launch_x_accumulate(m->dtype, m->nmesh, ysets[set][0],
+                              np2 == 2 ? ysets[set][1] : nullptr, field(f), plane(f),
+                              ws + l.side, np2 == 2 ? ws + l.side2 : nullptr, hs.h[k],
+                              hs.h[k + np2 - 1], 4.0 * pi / (2 * ells[f] + 1), *t, m->window,
+                              m->compensated, first_of[k], sx);
+    if (e == hipSuccess) e = hipEventRecord(xdone[set], sx);
     k += np2;
   }
+  // the binning (on the context stream) after the last x-pass
+  if (e == hipSuccess) e = hipEventRecord(ctx->aux_ev[4], sx);
+  if (e == hipSuccess) e = hipStreamWaitEvent(s, ctx->aux_ev[4], 0);
   // sums of Re F_0 conj F_ell per k bin: one pass over the fields (in the
   // y-pass output layout) for every pole, then each pole's kz = 0 plane and
   // its reduction; then the weight sums

@@ -212,6 +212,11 @@ struct pk_ctx {
   };
   std::vector<Lane> lanes;
   hipEvent_t tables_ready = nullptr;  // recorded on the context stream before lane work
+  // second stream of the survey multipoles (x-passes beside the painting)
+  // and its events: y-pass output ready [2], x-pass done with it [2], all
+  // x-passes done
+  hipStream_t aux = nullptr;
+  hipEvent_t aux_ev[5] = {};
   // pinned host staging of the result sums read back by the *_to_host calls
   // (a copy into pageable memory goes through a bounce buffer); grown on
   // demand, the pageable vector only if pinned memory is refused
