@@ -363,7 +363,10 @@ size_t pk_convolved_workspace_bytes(const pk_mesh_desc *m, const pk_bin_desc *b,
  *   rand_weight device, n_rand weights, or NULL
  *   workspace   device, >= pk_convolved_workspace_bytes, caller-owned
  *   result_dev  device, pk_convolved_doubles(b) float64, overwritten
- * Enqueued on the context stream.  A zero sum of random weights gives NaN
+ * Enqueued on the context stream: part of the work runs on a second stream
+ * that the context owns (created on first use), joined back to the context
+ * stream before the result is written, so the call is ordered on the
+ * context stream like the others.  A zero sum of random weights gives NaN
  * results.  Errors: PK_EINVAL, PK_EUNSUPPORTED, PK_EDEVICE. */
 pk_status pk_convolved_power(pk_ctx *ctx, const pk_mesh_desc *m, const pk_bin_desc *b,
                              const double *observer, const void *data_pos,
