@@ -1211,12 +1211,23 @@ pk_status pk_convolved_power(pk_ctx* ctx, const pk_mesh_desc* m, const pk_bin_de
   // alternate, and events order each set's y-passes before its x-pass and
   // that x-pass before the set is written again.  The painted field has mean
   // ~0: nothing is subtracted before the z-FFT.
-  if (!ctx->aux) {
-    e = hipStreamCreateWithFlags(&ctx->aux, hipStreamNonBlocking);
+  if (e == hipSuccess && !ctx->aux) {
+    // created together; kept only if all of them could be
+    hipStream_t st = nullptr;
+    hipEvent_t ev[5] = {};
+    e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
     for (int i = 0; i < 5 && e == hipSuccess; ++i)
-      e = hipEventCreateWithFlags(&ctx->aux_ev[i], hipEventDisableTiming);
-    if (e != hipSuccess) return dev_fail(ctx, e, "survey stream");
+      e = hipEventCreateWithFlags(&ev[i], hipEventDisableTiming);
+    if (e != hipSuccess) {
+      for (hipEvent_t x : ev)
+        if (x) (void)hipEventDestroy(x);
+      if (st) (void)hipStreamDestroy(st);
+      return dev_fail(ctx, e, "survey stream");
+    }
+    ctx->aux = st;
+    for (int i = 0; i < 5; ++i) ctx->aux_ev[i] = ev[i];
   }
+  if (e != hipSuccess) return dev_fail(ctx, e, "pk_convolved_power");
   hipStream_t sx = ctx->aux;
   hipEvent_t* ydone = ctx->aux_ev;      // [2]
   hipEvent_t* xdone = ctx->aux_ev + 2;  // [2]
@@ -1262,11 +1273,12 @@ pk_status pk_convolved_power(pk_ctx* ctx, const pk_mesh_desc* m, const pk_bin_de
                           1);
   for (int i = 0; i < b->npoles && e == hipSuccess; ++i) {
     const int f = fof[i];
-    double* pi = part + (size_t)i * pstride;
+    double* pole_part = part + (size_t)i * pstride;
     e = launch_plane_bin(m->dtype, m->nmesh, plane(0), f == 0 ? nullptr : plane(f), 1, *t,
-                         m->window, 0, spec, pi + (size_t)l.gb * spec.nsum, s, f == 0 ? 0 : 1);
+                         m->window, 0, spec, pole_part + (size_t)l.gb * spec.nsum, s,
+                         f == 0 ? 0 : 1);
     if (e == hipSuccess)
-      e = launch_reduce(pi, l.gb + l.gp, spec, result_dev + (size_t)i * b->nk, s);
+      e = launch_reduce(pole_part, l.gb + l.gp, spec, result_dev + (size_t)i * b->nk, s);
   }
   if (e == hipSuccess)
     e = hipMemcpyAsync(result_dev + (size_t)b->npoles * b->nk, sums, 4 * sizeof(double),
