@@ -159,8 +159,9 @@ __global__ void __launch_bounds__((ColCfg<T, N>::THREADS))
 // y-pass of the power-spectrum path: the same transform as k_fft_cols along
 // y, read from the plain packed layout of one mesh and written out of place
 // in the layout the fused x-pass reads (YLayout).  Each row of C columns that
-// a workgroup writes is contiguous; the sibling tile (next chunk, same
-// x-plane, same XCD) writes the other half of its 128-byte lines.
+// a workgroup writes is contiguous: a whole 128-byte line when C is 16
+// complex floats; with 8 the sibling tile (next chunk, same x-plane, same
+// XCD) writes the other half of its lines.
 template <typename T, int N>
 __global__ void __launch_bounds__((YCfg<T, N>::THREADS))
     k_fft_y_relayout(const T* __restrict__ src0, cpx<T>* __restrict__ dst,

@@ -28,7 +28,7 @@ struct ZCfg {
 // LDS footprint capped at 80 KB so two workgroups fit on a CU.  EM caps the
 // points per thread (the fused x-pass + binning keeps two meshes' lines in
 // registers and uses fewer points per thread).
-template <typename T, int N, int EM = e_max<T>(), int LDS_KB = 80>
+template <typename T, int N, int EM = e_max<T>(), int LDS_KB = 80, int CMIN = 8>
 struct ColCfg {
   static constexpr int L = N;
   static constexpr int E = L < EM ? L : EM;
@@ -36,7 +36,7 @@ struct ColCfg {
   static constexpr int NC = N / 2;
   static constexpr int pick() {
     int c = 256 / TPL;
-    if (c < 8) c = 8;
+    if (c < CMIN) c = CMIN;
     while (c > 1 && c * TPL > 1024) c /= 2;
     while (c > 1 && (long)c * lds_pad_len<L>() * (long)sizeof(cpx<T>) > LDS_KB * 1024) c /= 2;
     if (c > NC) c = NC;
@@ -72,9 +72,11 @@ __device__ __forceinline__ int xcd_group_tile(int g, int ntiles) {
 // Launch shape of the y-pass of the power-spectrum path (k_fft_y_relayout):
 // 8 points per thread, 1024 threads for N = 1024 (16 points: 512 threads)
 // -- more waves in flight for this HBM-bound pass (1-2% faster; 4 points per
-// thread was 60% slower at 1024^3).
+// thread was 60% slower at 1024^3).  Up to 16 columns per workgroup where
+// they fit (N <= 512 in float32): each row read and written is then a whole
+// 128-byte line.
 template <typename T, int N>
-using YCfg = ColCfg<T, N, 8>;
+using YCfg = ColCfg<T, N, 8, 80, 16>;
 
 // Launch shape of the fused x-pass + binning kernel.
 // (Line buffers capped at 40 KB -- 4 columns per tile at N = 1024, two
