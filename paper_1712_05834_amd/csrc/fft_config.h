@@ -73,10 +73,12 @@ __device__ __forceinline__ int xcd_group_tile(int g, int ntiles) {
 // 8 points per thread, 1024 threads for N = 1024 (16 points: 512 threads)
 // -- more waves in flight for this HBM-bound pass (1-2% faster; 4 points per
 // thread was 60% slower at 1024^3).  Up to 16 columns per workgroup where
-// they fit (N <= 512 in float32): each row read and written is then a whole
+// they fit (N <= 512; at 1024 in float32 with 16 points per thread and one
+// 144 KB workgroup per CU): each row read and written is then a whole
 // 128-byte line.
 template <typename T, int N>
-using YCfg = ColCfg<T, N, 8, 80, 16>;
+using YCfg = typename std::conditional<(sizeof(T) == 4 && N == 1024), ColCfg<T, N, 16, 160, 16>,
+                                       ColCfg<T, N, 8, 80, 16>>::type;
 
 // Launch shape of the fused x-pass + binning kernel.
 // (Line buffers capped at 40 KB -- 4 columns per tile at N = 1024, two
