@@ -7,10 +7,11 @@ arithmetic), and from fields whose power is known exactly:
   P_b = mean of P(|k|) over the modes of bin b exactly;
 * for any isotropic fixed-amplitude field P_2 = 0, since every exact-n^2
   shell is invariant under axis permutations and sum_shell L_2(mu) = 0;
-* P_4 and P(k, mu) equal brute-force mode averages of P L_4 and P.
-The mode counts of the 64^3 mesh are also stored in tests/golden (written by
-tests/golden/make_golden.py from the oracle) and cross-checked against the
-brute-force enumeration here.
+* P_4, P_6 and P(k, mu) equal brute-force mode averages of P L_4, P L_6 and P,
+  with L_ell taken from Bonnet's recurrence (not from the oracle's closed forms).
+The mode counts of the 64^3 mesh (1-D, and 2-D with 5 |mu| bins) are also
+stored in tests/golden (written by tests/golden/make_golden.py from the oracle)
+and cross-checked against the brute-force enumeration here.
 """
 
 import math
@@ -86,6 +87,35 @@ def test_mu_bin_counts_match_exact_fraction_rule():
     assert any(m == 1 for m in mu2)
 
 
+def test_mode_counts_2d_64_match_fraction_rule_and_golden():
+    # (k, mu) mode counts of the 64^3 mesh with 5 |mu| bins along z: the
+    # stored golden file (written from the oracle) against an exact-Fraction
+    # enumeration of the full grid
+    n, nk, nmu = 64, 32, 5
+    gx, gy, gz = _full_grid(n)
+    n2 = gx * gx + gy * gy + gz * gz
+    b = _brute_kbin(n2, nk)
+    sel = b >= 0
+    # |mu| bin by exact rationals, once per distinct (n_z^2, n^2) pair
+    pairs = np.unique(np.stack([gz[sel] ** 2, n2[sel]]), axis=1)
+    jtab = {}
+    for a2, c in pairs.T:
+        mu2 = Fraction(int(a2), int(c))
+        j = 0
+        while j + 1 <= nmu and Fraction((j + 1) ** 2, nmu * nmu) <= mu2:
+            j += 1
+        jtab[(int(a2), int(c))] = min(j, nmu - 1)
+    j = np.array([jtab[(int(a2), int(c))] for a2, c in zip(gz[sel] ** 2, n2[sel])])
+    brute = np.bincount(b[sel] * nmu + j, minlength=nk * nmu).reshape(nk, nmu)
+    golden = np.loadtxt(os.path.join(GOLDEN, "modecounts2d_n64_dk1_nmu5.txt"), dtype=np.int64)
+    np.testing.assert_array_equal(golden, brute)
+    np.testing.assert_array_equal(brute.sum(axis=1),
+                                  np.loadtxt(os.path.join(GOLDEN, "modecounts_n64_dk1.txt"),
+                                             dtype=np.int64))
+    # bin 1 split over the 5 |mu| bins
+    assert list(brute[1]) == [8, 0, 8, 8, 2]
+
+
 def test_mu_bin_rule_on_hand_picked_ties():
     # (n_los, n^2, Nmu) -> bin: mu = 0.8 and 0.6 sit exactly on edges of 5 bins
     cases = [(4, 25, 5, 4), (3, 25, 5, 3), (5, 25, 5, 4), (0, 25, 5, 0), (1, 2, 2, 1),
@@ -119,6 +149,33 @@ def test_general_edges_and_los_match_brute_force(los):
     np.testing.assert_array_equal(tab["modes2d"], brute2)
 
 
+def _legendre_bonnet(ell, mu):
+    """L_ell(mu) from Bonnet's recurrence (k + 1) L_{k+1} = (2k + 1) mu L_k - k L_{k-1}."""
+    lm, lc = np.ones_like(mu), mu
+    if ell == 0:
+        return lm
+    for k in range(1, ell):
+        lm, lc = lc, ((2 * k + 1) * mu * lc - k * lm) / (k + 1)
+    return lc
+
+
+@pytest.mark.parametrize("ell", [0, 2, 4, 6])
+def test_oracle_legendre_matches_recurrence_and_orthogonality(ell):
+    # Legendre multipoles of Sec. 3.4.1: the oracle's L_ell(mu^2) against
+    # Bonnet's recurrence, and the orthogonality integrals
+    # int_-1^1 L_ell L_ell' dmu = 2 / (2 ell + 1) delta by Gauss-Legendre
+    # quadrature (exact for these degrees)
+    mu = np.linspace(-1.0, 1.0, 201)
+    np.testing.assert_allclose(oracle.legendre(ell, mu * mu), _legendre_bonnet(ell, mu),
+                               rtol=0, atol=1e-14)
+    x, wq = np.polynomial.legendre.leggauss(8)
+    for other in (0, 2, 4, 6):
+        integral = np.sum(wq * oracle.legendre(ell, x * x) * oracle.legendre(other, x * x))
+        want = 2.0 / (2 * ell + 1) if other == ell else 0.0
+        assert abs(integral - want) < 1e-14, (ell, other, integral)
+    assert oracle.legendre(ell, np.array([1.0]))[0] == pytest.approx(1.0, abs=1e-15)
+
+
 def _brute_expected(n, box, pk, nk, nmu, los=2):
     gx, gy, gz = _full_grid(n)
     n2 = gx * gx + gy * gy + gz * gz
@@ -127,15 +184,12 @@ def _brute_expected(n, box, pk, nk, nmu, los=2):
     kf = 2 * np.pi / box
     p = pk(kf * np.sqrt(n2[sel]))
     nl = (gx, gy, gz)[los][sel]
-    mu2 = nl * nl / n2[sel]
-    l2 = (3 * mu2 - 1) / 2
-    l4 = (35 * mu2 ** 2 - 30 * mu2 + 3) / 8
+    mu = nl / np.sqrt(n2[sel])
     cnt = np.bincount(b[sel], minlength=nk)
-    out = {
-        "p0": np.bincount(b[sel], weights=p, minlength=nk) / cnt,
-        "p2": 5 * np.bincount(b[sel], weights=p * l2, minlength=nk) / cnt,
-        "p4": 9 * np.bincount(b[sel], weights=p * l4, minlength=nk) / cnt,
-    }
+    out = {"p0": np.bincount(b[sel], weights=p, minlength=nk) / cnt}
+    for ell in (2, 4, 6):
+        out[f"p{ell}"] = (2 * ell + 1) * np.bincount(
+            b[sel], weights=p * _legendre_bonnet(ell, mu), minlength=nk) / cnt
     j = _brute_mubin(nl, n2[sel], nmu)
     f = b[sel] * nmu + j
     c2 = np.bincount(f, minlength=nk * nmu)
@@ -152,7 +206,7 @@ def test_fixed_amplitude_field_power_is_exact(los):
     assert abs(f.sum() - n ** 3) < 1e-8 * n ** 3
     c = oracle.r2c(f)
     res = oracle.fftpower_from_spectra(c, None, n, box, 2, False, wsum=float(n ** 3),
-                                       w2sum=1.0, npart=1, nmu=nmu, poles=(0, 2, 4),
+                                       w2sum=1.0, npart=1, nmu=nmu, poles=(0, 2, 4, 6),
                                        los=los)
     want = _brute_expected(n, box, pk, nk, nmu, los)
     ok = res["modes"] > 0
@@ -162,6 +216,10 @@ def test_fixed_amplitude_field_power_is_exact(los):
     assert np.all(np.abs(res["poles"][2][ok]) <= 1e-12 * want["p0"][ok])
     np.testing.assert_allclose(res["poles"][4][ok], want["p4"][ok], rtol=0,
                                atol=1e-12 * want["p0"][ok].max())
+    np.testing.assert_allclose(res["poles"][6][ok], want["p6"][ok], rtol=0,
+                               atol=1e-12 * want["p0"][ok].max())
+    # P_6 is not identically zero on the lattice, so the comparison has teeth
+    assert np.max(np.abs(want["p6"][ok])) > 1e-6 * want["p0"][ok].max()
     np.testing.assert_allclose(res["power2d"], want["pkmu"], rtol=1e-12, equal_nan=True)
 
 
