@@ -147,6 +147,18 @@ size_t pk_mesh_bytes(const pk_mesh_desc *m);
  * pk_result_to_host applies V / (sum w)^2.  0 for an invalid descriptor. */
 size_t pk_result_doubles(const pk_bin_desc *b);
 
+/* Sizing query for FFTPower k-bins (Sec. 3.4.1: bins of width dk from kmin
+ * up to kmax, wave numbers in units of k_f = 2 pi / L): the number of whole
+ * bins [kmin_f + b dk_f, kmin_f + (b + 1) dk_f) whose top edge does not
+ * exceed kmax_f, i.e. the largest nk with kmin_f + nk dk_f <= kmax_f (an
+ * edge within 1e-9 dk_f of kmax_f counts as equal, so exact multiples are
+ * kept).  kmax_f = N/2 gives the bins up to the Nyquist index, the largest
+ * binning allowed for interlaced meshes.  Pure host arithmetic, no context.
+ * Returns PK_EINVAL (negative) for non-finite arguments, kmin_f < 0,
+ * dk_f <= 0 or kmax_f <= kmin_f; 0 when no whole bin fits; at most 4096 (the
+ * largest nk a pk_bin_desc accepts), else PK_EUNSUPPORTED. */
+int32_t pk_num_kbins(double kmin_f, double dk_f, double kmax_f);
+
 /* Device workspace that pk_fftpower needs for this request (bytes). */
 size_t pk_workspace_bytes(const pk_mesh_desc *m, const pk_bin_desc *b, int64_t npart);
 
@@ -213,6 +225,10 @@ pk_status pk_compensate(pk_ctx *ctx, const pk_mesh_desc *m, void *cmesh_inout,
 
 /* Binning of a packed spectrum as it is (no interlacing or compensation is
  * applied here) into the sums described at pk_result_doubles (Sec. 3.4.1).
+ * The sums are unnormalised: the factor V / (sum w)^2 of P = V |delta(k)|^2
+ * is applied by pk_result_to_host, which reads sum w from the same result
+ * buffer, so that no call needs a host round trip between painting and
+ * binning.
  * result_dev: device, pk_result_doubles(b) float64; every sum slot is
  * overwritten, the two weight slots are left unchanged.
  * Errors: PK_EINVAL (also for an interlaced m with a top edge above N/2),
@@ -249,7 +265,9 @@ pk_status pk_bin_projected(pk_ctx *ctx, const pk_mesh_desc *m, const pk_bin_desc
 pk_status pk_projected_to_host(pk_ctx *ctx, const pk_mesh_desc *m, const pk_bin_desc *b,
                                int keep, const double *result_dev, pk_result *out);
 
-/* The whole FFTPower hot path for one catalog: paint (both meshes if
+/* The whole FFTPower hot path for one catalog (Sec. 3.3.1 painting, Eq. 1;
+ * Sec. 3.3.2 windows, interlacing and compensation, Eq. 2; Sec. 3.4.1
+ * binning into P(k), P(k, mu) and P_ell): paint (both meshes if
  * interlaced), r2c, interlace, compensate, bin.  n <= 2^31 - 1 (the sorted
  * records are indexed with 32-bit offsets; PK_EUNSUPPORTED beyond; pk_paint
  * has no such limit).  workspace: device,
@@ -380,9 +398,14 @@ pk_status pk_convolved_power(pk_ctx *ctx, const pk_mesh_desc *m, const pk_bin_de
 pk_status pk_convolved_to_host(pk_ctx *ctx, const pk_mesh_desc *m, const pk_bin_desc *b,
                                double norm, const double *result_dev, pk_result *out);
 
-/* Synchronises the context stream, copies the sums back and finalises them
- * with the mode tables (counts, mean |k|, mean |mu|):
- *   P = V sum(h P) / (sum w)^2 / N_b,  P_ell = (2 ell + 1) ... likewise.
+/* FFTPower finalisation (Sec. 3.4.1: P(k) and P(k, mu) as mode averages of
+ * V |delta(k)|^2 with delta = DFT(F) / sum w, the painted field being 1 + delta
+ * of Sec. 3.3.1; P_ell the Legendre moments; shot noise reported, not
+ * subtracted).  Synchronises the context stream, copies the sums back and
+ * finalises them with the mode tables (counts, mean |k|, mean |mu|):
+ *   P = V sum(h P) / (sum w)^2 / N_b,
+ *   P_ell = (2 ell + 1) V sum(h P L_ell) / (sum w)^2 / N_b,
+ *   P(k, mu) likewise per (k, mu)-bin; empty bins give NaN and count 0.
  * out: host struct with caller-allocated arrays (see pk_result).
  * Errors: PK_EINVAL, PK_EDEVICE. */
 pk_status pk_result_to_host(pk_ctx *ctx, const pk_mesh_desc *m, const pk_bin_desc *b,

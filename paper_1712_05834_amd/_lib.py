@@ -28,9 +28,10 @@ EXPORTS = (
     "pk_fftpower_batch", "pk_bin_cross", "pk_fftpower_v", "pk_projected_doubles",
     "pk_bin_projected", "pk_projected_to_host", "pk_convolved_doubles",
     "pk_convolved_workspace_bytes", "pk_convolved_power", "pk_convolved_to_host", "pk_fft_c2r",
-    "pk_shape_table_len", "pk_shape_spectrum",
+    "pk_shape_table_len", "pk_shape_spectrum", "pk_num_kbins",
 )
 PK_MAX_LANES = 64
+PK_DEVICE_NONE = -1
 
 
 class PkError(RuntimeError):
@@ -106,6 +107,7 @@ def load(path=None):
             "pk_last_error": (ctypes.c_char_p, [vp]),
             "pk_mesh_bytes": (sz, [md]),
             "pk_result_doubles": (sz, [bd]),
+            "pk_num_kbins": (i32, [dbl, dbl, dbl]),
             "pk_workspace_bytes": (sz, [md, bd, i64]),
             "pk_ctx_table_bytes": (sz, [vp]),
             "pk_paint": (i32, [vp, md, vp, vp, i64, dbl, vp, vp]),
@@ -162,6 +164,16 @@ def bin_desc(nk, kmin_f=0.0, dk_f=1.0, nmu=0, poles=(), los=2):
     return BinDesc(float(kmin_f), float(dk_f), int(nk), int(nmu), len(poles), arr, int(los))
 
 
+def num_kbins(kmin_f, dk_f, kmax_f):
+    """pk_num_kbins: whole k-bins of width dk_f from kmin_f whose top edge is
+    at most kmax_f (units of k_f).  Raises ValueError for invalid edges."""
+    nk = int(load().pk_num_kbins(float(kmin_f), float(dk_f), float(kmax_f)))
+    if nk < 0:
+        raise ValueError(f"invalid k-bin edges kmin={kmin_f}, dk={dk_f}, kmax={kmax_f} "
+                         f"(status {nk})")
+    return nk
+
+
 def mesh_bytes(m):
     return int(load().pk_mesh_bytes(ctypes.byref(m)))
 
@@ -195,19 +207,66 @@ def _ptr(t):
     return None if t is None else ctypes.c_void_p(t.data_ptr())
 
 
+def mesh_torch_dtype(m):
+    """torch dtype of positions, weights and meshes of a mesh description."""
+    import torch
+
+    return torch.float32 if m.dtype == PK_F32 else torch.float64
+
+
+def device_arg(t, name, device, dtype=None, numel=0, nbytes=0, optional=False):
+    """Checks a tensor before its address crosses the C ABI, and returns that
+    address: a contiguous tensor on GPU ``device`` (any GPU for a
+    validation-only context, device < 0), of ``dtype`` when given, with at
+    least ``numel`` elements and ``nbytes`` bytes.  The library reads raw
+    addresses, so a host tensor or a short buffer would be a device memory
+    fault; here it is a ValueError before any launch."""
+    import torch
+
+    if t is None:
+        if optional:
+            return None
+        raise ValueError(f"{name} is required")
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor, not {type(t).__name__}")
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be on the GPU (got a tensor on {t.device})")
+    if device is not None and device >= 0 and t.device.index != device:
+        raise ValueError(f"{name} is on cuda:{t.device.index}, the context on cuda:{device}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if dtype is not None and t.dtype != dtype:
+        raise ValueError(f"{name} must be {dtype} (got {t.dtype})")
+    if t.numel() < numel:
+        raise ValueError(f"{name} holds {t.numel()} elements, {numel} are needed")
+    if t.numel() * t.element_size() < nbytes:
+        raise ValueError(f"{name} holds {t.numel() * t.element_size()} bytes, {nbytes} are "
+                         "needed")
+    return ctypes.c_void_p(t.data_ptr())
+
+
 class Context:
-    """One pk_ctx bound to a device and a HIP stream."""
+    """One pk_ctx bound to a device and a HIP stream.
+
+    ``device=PK_DEVICE_NONE`` (-1) gives a validation-only context: every
+    argument is checked as on a device, and calls that would reach a device
+    fail with PK_EDEVICE (no GPU needed).  Every tensor argument is checked by
+    ``device_arg`` before its address is passed to the library."""
 
     def __init__(self, device=0, stream=None):
-        import torch
-
         self.lib = load()
-        if stream is None:
-            stream = torch.cuda.current_stream(device)
-        self.stream = stream
         handle = ctypes.c_void_p()
-        st = self.lib.pk_ctx_create(ctypes.byref(handle), int(device),
-                                    ctypes.c_void_p(stream.cuda_stream))
+        if device == PK_DEVICE_NONE:
+            self.stream = None
+            st = self.lib.pk_ctx_create(ctypes.byref(handle), PK_DEVICE_NONE, None)
+        else:
+            import torch
+
+            if stream is None:
+                stream = torch.cuda.current_stream(device)
+            self.stream = stream
+            st = self.lib.pk_ctx_create(ctypes.byref(handle), int(device),
+                                        ctypes.c_void_p(stream.cuda_stream))
         if st != PK_OK:
             raise PkError(st, self.lib.pk_last_error(None).decode())
         self.handle = handle
@@ -228,6 +287,36 @@ class Context:
         if st != PK_OK:
             raise PkError(st, self.lib.pk_last_error(self.handle).decode())
 
+    # ---- argument checks (shapes from the descriptors; nothing is launched)
+
+    def _arg(self, t, name, **kw):
+        return device_arg(t, name, self.device, **kw)
+
+    def _mesh_arg(self, m, t, name, optional=False):
+        """A real mesh or packed spectrum of m: the mesh dtype, pk_mesh_bytes."""
+        return self._arg(t, name, dtype=mesh_torch_dtype(m), nbytes=mesh_bytes(m),
+                         optional=optional)
+
+    def _catalog_args(self, m, pos, weight, n, names=("pos", "weight")):
+        n = int(n)
+        dt = mesh_torch_dtype(m)
+        return (self._arg(pos, names[0], dtype=dt, numel=3 * n, optional=n == 0),
+                self._arg(weight, names[1], dtype=dt, numel=n, optional=True))
+
+    def _f64_arg(self, t, name, count, optional=False):
+        import torch
+
+        return self._arg(t, name, dtype=torch.float64, numel=count, optional=optional)
+
+    def _result_arg(self, b, t):
+        return self._f64_arg(t, "result", result_doubles(b))
+
+    @staticmethod
+    def _nbytes(t):
+        return 0 if t is None else t.numel() * t.element_size()
+
+    # ---- diagnostics
+
     def pk_ctx_set_timing(self, enable):
         self._check(self.lib.pk_ctx_set_timing(self.handle, int(bool(enable))))
 
@@ -243,39 +332,56 @@ class Context:
     def table_bytes(self):
         return int(self.lib.pk_ctx_table_bytes(self.handle))
 
+    # ---- stages
+
     def pk_paint(self, m, pos, weight, n, shift_cells, mesh, wsums=None):
-        self._check(self.lib.pk_paint(self.handle, ctypes.byref(m), _ptr(pos), _ptr(weight),
-                                      int(n), float(shift_cells), _ptr(mesh), _ptr(wsums)))
+        p, w = self._catalog_args(m, pos, weight, n)
+        mp = self._mesh_arg(m, mesh, "mesh")
+        ws = self._f64_arg(wsums, "wsums", 2, optional=True)
+        self._check(self.lib.pk_paint(self.handle, ctypes.byref(m), p, w, int(n),
+                                      float(shift_cells), mp, ws))
 
     def pk_fft_r2c(self, m, mesh):
-        self._check(self.lib.pk_fft_r2c(self.handle, ctypes.byref(m), _ptr(mesh)))
+        self._check(self.lib.pk_fft_r2c(self.handle, ctypes.byref(m),
+                                        self._mesh_arg(m, mesh, "mesh")))
 
     def pk_fft_c2r(self, m, mesh):
-        self._check(self.lib.pk_fft_c2r(self.handle, ctypes.byref(m), _ptr(mesh)))
+        self._check(self.lib.pk_fft_c2r(self.handle, ctypes.byref(m),
+                                        self._mesh_arg(m, mesh, "mesh")))
 
     def pk_shape_spectrum(self, m, cmesh, table):
-        self._check(self.lib.pk_shape_spectrum(self.handle, ctypes.byref(m), _ptr(cmesh),
-                                               _ptr(table), int(table.numel())))
+        c = self._mesh_arg(m, cmesh, "cmesh")
+        tb = self._f64_arg(table, "table", shape_table_len(m))
+        self._check(self.lib.pk_shape_spectrum(self.handle, ctypes.byref(m), c, tb,
+                                               int(table.numel())))
 
     def pk_compensate(self, m, cmesh, cmesh_b=None):
-        self._check(self.lib.pk_compensate(self.handle, ctypes.byref(m), _ptr(cmesh),
-                                           _ptr(cmesh_b)))
+        c = self._mesh_arg(m, cmesh, "cmesh")
+        cb = self._mesh_arg(m, cmesh_b, "cmesh_b", optional=True)
+        self._check(self.lib.pk_compensate(self.handle, ctypes.byref(m), c, cb))
 
     def pk_bin_power(self, m, b, cmesh, result):
-        self._check(self.lib.pk_bin_power(self.handle, ctypes.byref(m), ctypes.byref(b),
-                                          _ptr(cmesh), _ptr(result)))
+        c = self._mesh_arg(m, cmesh, "cmesh")
+        r = self._result_arg(b, result)
+        self._check(self.lib.pk_bin_power(self.handle, ctypes.byref(m), ctypes.byref(b), c, r))
 
     def pk_bin_cross(self, m, b, cmesh1, cmesh2, result):
+        c1 = self._mesh_arg(m, cmesh1, "cmesh1")
+        c2 = self._mesh_arg(m, cmesh2, "cmesh2")
+        r = self._result_arg(b, result)
         self._check(self.lib.pk_bin_cross(self.handle, ctypes.byref(m), ctypes.byref(b),
-                                          _ptr(cmesh1), _ptr(cmesh2), _ptr(result)))
+                                          c1, c2, r))
 
     def pk_bin_projected(self, m, b, keep, cmesh, result):
+        c = self._mesh_arg(m, cmesh, "cmesh")
+        r = self._f64_arg(result, "result", projected_doubles(b))
         self._check(self.lib.pk_bin_projected(self.handle, ctypes.byref(m), ctypes.byref(b),
-                                              int(keep), _ptr(cmesh), _ptr(result)))
+                                              int(keep), c, r))
 
     def pk_projected_to_host(self, m, b, keep, result):
         import numpy as np
 
+        rp = self._f64_arg(result, "result", projected_doubles(b))
         nk = b.nk
         out = {"k": np.empty(nk), "power": np.empty(nk), "modes": np.empty(nk, dtype=np.int64)}
         dbl, i64 = ctypes.c_double, ctypes.c_int64
@@ -284,25 +390,30 @@ class Context:
                    out["modes"].ctypes.data_as(ctypes.POINTER(i64)),
                    None, None, None, None, None, 0.0, 0.0, 0.0)
         self._check(self.lib.pk_projected_to_host(self.handle, ctypes.byref(m), ctypes.byref(b),
-                                                  int(keep), _ptr(result), ctypes.byref(r)))
+                                                  int(keep), rp, ctypes.byref(r)))
         out["poles"] = {}
         out["shotnoise"], out["wsum"], out["w2sum"] = r.shotnoise, r.wsum, r.w2sum
         return out
 
     def pk_convolved_power(self, m, b, observer, data_pos, data_weight, n_data, rand_pos,
                            rand_weight, n_rand, workspace, result):
-        nbytes = workspace.numel() * workspace.element_size()
+        dp, dw = self._catalog_args(m, data_pos, data_weight, n_data,
+                                    ("data_pos", "data_weight"))
+        rp, rw = self._catalog_args(m, rand_pos, rand_weight, n_rand,
+                                    ("rand_pos", "rand_weight"))
+        ws = self._arg(workspace, "workspace")
+        res = self._f64_arg(result, "result", convolved_doubles(b))
         obs = (ctypes.c_double * 3)(*[float(v) for v in observer])
         self._check(self.lib.pk_convolved_power(
-            self.handle, ctypes.byref(m), ctypes.byref(b), obs, _ptr(data_pos),
-            _ptr(data_weight), int(n_data), _ptr(rand_pos), _ptr(rand_weight), int(n_rand),
-            _ptr(workspace), nbytes, _ptr(result)))
+            self.handle, ctypes.byref(m), ctypes.byref(b), obs, dp, dw, int(n_data), rp, rw,
+            int(n_rand), ws, self._nbytes(workspace), res))
 
     def pk_convolved_to_host(self, m, b, norm, result):
         """Host dict: k, modes, poles {ell: P_ell}, shotnoise, wsum / w2sum of
         the data, and alpha read from the weight sums of the result."""
         import numpy as np
 
+        rp = self._f64_arg(result, "result", convolved_doubles(b))
         nk = b.nk
         out = {"k": np.empty(nk), "modes": np.empty(nk, dtype=np.int64)}
         poles = np.empty((b.npoles, nk))
@@ -312,7 +423,7 @@ class Context:
                    poles.ctypes.data_as(ctypes.POINTER(dbl)), None, None, None, None,
                    0.0, 0.0, 0.0)
         self._check(self.lib.pk_convolved_to_host(self.handle, ctypes.byref(m), ctypes.byref(b),
-                                                  float(norm), _ptr(result), ctypes.byref(r)))
+                                                  float(norm), rp, ctypes.byref(r)))
         out["poles"] = {int(b.poles[i]): poles[i] for i in range(b.npoles)}
         out["shotnoise"], out["wsum"], out["w2sum"] = r.shotnoise, r.wsum, r.w2sum
         sums = result[b.npoles * nk:b.npoles * nk + 4].double().cpu().numpy()
@@ -320,16 +431,21 @@ class Context:
         return out
 
     def pk_fftpower(self, m, b, pos, weight, n, workspace, result):
-        nbytes = workspace.numel() * workspace.element_size()
-        self._check(self.lib.pk_fftpower(self.handle, ctypes.byref(m), ctypes.byref(b), _ptr(pos),
-                                         _ptr(weight), int(n), _ptr(workspace), nbytes,
-                                         _ptr(result)))
+        p, w = self._catalog_args(m, pos, weight, n)
+        ws = self._arg(workspace, "workspace")
+        r = self._result_arg(b, result)
+        self._check(self.lib.pk_fftpower(self.handle, ctypes.byref(m), ctypes.byref(b), p, w,
+                                         int(n), ws, self._nbytes(workspace), r))
 
     def pk_fftpower_v(self, m, b, pos, weight, value, n, workspace, result):
-        nbytes = workspace.numel() * workspace.element_size()
-        self._check(self.lib.pk_fftpower_v(self.handle, ctypes.byref(m), ctypes.byref(b),
-                                           _ptr(pos), _ptr(weight), _ptr(value), int(n),
-                                           _ptr(workspace), nbytes, _ptr(result)))
+        p, w = self._catalog_args(m, pos, weight, n)
+        v = self._arg(value, "value", dtype=mesh_torch_dtype(m), numel=int(n), optional=True)
+        ws = self._arg(workspace, "workspace")
+        r = self._result_arg(b, result)
+        self._check(self.lib.pk_fftpower_v(self.handle, ctypes.byref(m), ctypes.byref(b), p, w,
+                                           v, int(n), ws, self._nbytes(workspace), r))
+
+    # ---- lanes
 
     def pk_ctx_set_lanes(self, nlanes):
         self._check(self.lib.pk_ctx_set_lanes(self.handle, int(nlanes)))
@@ -338,10 +454,12 @@ class Context:
         return int(self.lib.pk_ctx_lanes(self.handle))
 
     def pk_fftpower_async(self, lane, m, b, pos, weight, n, workspace, result):
-        nbytes = workspace.numel() * workspace.element_size()
+        p, w = self._catalog_args(m, pos, weight, n)
+        ws = self._arg(workspace, "workspace")
+        r = self._result_arg(b, result)
         self._check(self.lib.pk_fftpower_async(self.handle, int(lane), ctypes.byref(m),
-                                               ctypes.byref(b), _ptr(pos), _ptr(weight), int(n),
-                                               _ptr(workspace), nbytes, _ptr(result)))
+                                               ctypes.byref(b), p, w, int(n), ws,
+                                               self._nbytes(workspace), r))
 
     def pk_lane_query(self, lane):
         st = int(self.lib.pk_lane_query(self.handle, int(lane)))
@@ -357,23 +475,39 @@ class Context:
         allowed), results: sequences of device tensors; lane_workspaces: one
         device tensor per lane, all of the same size."""
         count = len(ms)
+        if not (len(bs) == len(pos) == len(weights) == len(ns) == len(results) == count):
+            raise ValueError("batch arguments must all have one entry per request")
+        vp = ctypes.c_void_p
+        pp, wp, rp = [], [], []
+        for i in range(count):
+            p, w = self._catalog_args(ms[i], pos[i], weights[i], ns[i],
+                                      (f"pos[{i}]", f"weight[{i}]"))
+            pp.append(p)
+            wp.append(w)
+            rp.append(self._f64_arg(results[i], f"result[{i}]", result_doubles(bs[i])))
+        if not lane_workspaces:
+            raise ValueError("one workspace per lane is needed")
+        nbytes = self._nbytes(lane_workspaces[0])
+        lw = [self._arg(t, f"lane_workspace[{j}]", nbytes=nbytes)
+              for j, t in enumerate(lane_workspaces)]
+        if any(self._nbytes(t) != nbytes for t in lane_workspaces):
+            raise ValueError("every lane workspace must have the same size")
         marr = (MeshDesc * max(count, 1))(*ms)
         barr = (BinDesc * max(count, 1))(*bs)
-        vp = ctypes.c_void_p
 
-        def ptrs(ts):
-            return (vp * max(len(ts), 1))(*[None if t is None else t.data_ptr() for t in ts])
+        def arr(ptrs):
+            return (vp * max(len(ptrs), 1))(*[None if q is None else q.value for q in ptrs])
 
-        nbytes = lane_workspaces[0].numel() * lane_workspaces[0].element_size()
-        assert all(w.numel() * w.element_size() == nbytes for w in lane_workspaces)
         narr = (ctypes.c_int64 * max(count, 1))(*[int(n) for n in ns])
         self._check(self.lib.pk_fftpower_batch(
-            self.handle, count, marr, barr, ptrs(pos), ptrs(weights), narr,
-            ptrs(lane_workspaces), nbytes, ptrs(results)))
+            self.handle, count, marr, barr, arr(pp), arr(wp), narr, arr(lw), nbytes, arr(rp)))
+
+    # ---- finalisation
 
     def pk_result_to_host(self, m, b, result):
         import numpy as np
 
+        rp = self._result_arg(b, result)
         nk, nmu, npoles = b.nk, b.nmu, b.npoles
         out = {
             "k": np.empty(nk), "power": np.empty(nk), "modes": np.empty(nk, dtype=np.int64),
@@ -393,7 +527,7 @@ class Context:
                    p(out["poles"], dbl), p(out.get("k2d"), dbl), p(out.get("mu2d"), dbl),
                    p(out.get("power2d"), dbl), p(out.get("modes2d"), i64), 0.0, 0.0, 0.0)
         self._check(self.lib.pk_result_to_host(self.handle, ctypes.byref(m), ctypes.byref(b),
-                                               _ptr(result), ctypes.byref(r)))
+                                               rp, ctypes.byref(r)))
         res = {k: v for k, v in out.items() if k != "poles"}
         res["poles"] = {int(b.poles[i]): out["poles"][i].copy() for i in range(npoles)}
         res["shotnoise"], res["wsum"], res["w2sum"] = r.shotnoise, r.wsum, r.w2sum

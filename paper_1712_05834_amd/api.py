@@ -44,8 +44,9 @@ class CatalogMesh:
         want = torch.float32 if dtype in ("f4", "float32") else torch.float64
         if pos.dtype != want or pos.dim() != 2 or pos.shape[1] != 3 or not pos.is_cuda:
             raise ValueError(f"pos must be a CUDA (N, 3) tensor of {want}")
-        if weight is not None and (weight.dtype != want or weight.shape != (pos.shape[0],)):
-            raise ValueError(f"weight must be a CUDA (N,) tensor of {want}")
+        if weight is not None and (weight.dtype != want or weight.shape != (pos.shape[0],)
+                                   or not weight.is_cuda or weight.device != pos.device):
+            raise ValueError(f"weight must be an (N,) tensor of {want} on {pos.device}")
         self.pos = pos.contiguous()
         self.weight = None if weight is None else weight.contiguous()
         self.Nmesh = int(Nmesh)
@@ -82,14 +83,17 @@ def to_mesh(pos, Nmesh, BoxSize, resampler="cic", interlaced=False, compensated=
 
 
 def bins_for(mesh, mode="1d", dk=None, kmin=0.0, kmax=None, Nmu=5, poles=(), los=(0, 0, 1)):
-    """C bin descriptor from FFTPower keywords (k in units of h/Mpc, like L)."""
+    """C bin descriptor from FFTPower keywords (k in units of h/Mpc, like L):
+    bins of width dk (default k_f) from kmin, as many whole bins as fit below
+    kmax (default the Nyquist wave number k_N = pi N / L)."""
     kf = 2.0 * math.pi / mesh.BoxSize
     dk_f = 1.0 if dk is None else float(dk) / kf
     kmin_f = float(kmin) / kf
-    if kmax is None:
-        nk = int(math.floor((mesh.Nmesh // 2 - kmin_f) / dk_f + 1e-9))
-    else:
-        nk = int(math.ceil((float(kmax) / kf - kmin_f) / dk_f - 1e-9))
+    # whole bins whose top edge is at most kmax (default: the Nyquist index)
+    kmax_f = mesh.Nmesh // 2 if kmax is None else float(kmax) / kf
+    nk = _lib.num_kbins(kmin_f, dk_f, kmax_f)
+    if nk == 0:
+        raise ValueError("no whole k-bin of width dk fits between kmin and kmax")
     axis = [i for i, v in enumerate(los) if v][0]
     if sum(1 for v in los if v) != 1:
         raise ValueError("los must be a unit vector along one axis")
@@ -143,9 +147,13 @@ def ConvolvedFFTPower(mesh, randoms, poles=(0, 2, 4), observer=(0.0, 0.0, 0.0), 
     if (randoms.dtype != want or randoms.dim() != 2 or randoms.shape[1] != 3
             or not randoms.is_cuda):
         raise ValueError(f"randoms must be a CUDA (N, 3) tensor of {want}")
+    if randoms.device != mesh.pos.device:
+        raise ValueError(f"randoms must be on {mesh.pos.device}")
     if randoms_weight is not None and (randoms_weight.dtype != want
-                                       or randoms_weight.shape != (randoms.shape[0],)):
-        raise ValueError(f"randoms_weight must be a CUDA (N,) tensor of {want}")
+                                       or randoms_weight.shape != (randoms.shape[0],)
+                                       or not randoms_weight.is_cuda
+                                       or randoms_weight.device != randoms.device):
+        raise ValueError(f"randoms_weight must be an (N,) tensor of {want} on {randoms.device}")
     b = bins_for(mesh, "1d", dk, kmin, kmax, 0, tuple(poles), (0, 0, 1))
     randoms = randoms.contiguous()
     nd, nr = mesh.pos.shape[0], randoms.shape[0]

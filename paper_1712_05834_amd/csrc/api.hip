@@ -492,6 +492,14 @@ size_t pk_result_doubles(const pk_bin_desc* b) {
   return (size_t)nsum_of(b) + 2;
 }
 
+int32_t pk_num_kbins(double kmin_f, double dk_f, double kmax_f) {
+  if (!std::isfinite(kmin_f) || !std::isfinite(dk_f) || !std::isfinite(kmax_f)) return PK_EINVAL;
+  if (kmin_f < 0 || !(dk_f > 0) || !(kmax_f > kmin_f)) return PK_EINVAL;
+  const double nk = std::floor((kmax_f - kmin_f) / dk_f + 1e-9);
+  if (nk > 4096.0) return PK_EUNSUPPORTED;
+  return (int32_t)nk;
+}
+
 size_t pk_workspace_bytes(const pk_mesh_desc* m, const pk_bin_desc* b, int64_t npart) {
   (void)npart;
   if (check_mesh(m) || check_bins(b, m)) return 0;
