@@ -83,7 +83,15 @@ def test_cross_power_matches_oracle(ctx, dtype, window, inter):
     assert np.max(np.abs(got["poles"][2][ok] - want["poles"][2][ok]) / scale) <= TOL[dtype]
     ok2 = want["modes2d"] > 0
     np.testing.assert_array_equal(got["modes2d"], want["modes2d"])
-    assert np.all(np.isfinite(got["power2d"][ok2]))
+    # P(k, mu) of the cross power per (k, mu)-bin against the oracle, on the
+    # scale of the geometric mean of the two auto powers of that bin
+    a1 = oracle.cross_from_spectra(o1, o1, n, box, w1s, w1s, nmu=4, interlaced=inter)
+    a2 = oracle.cross_from_spectra(o2, o2, n, box, w2s, w2s, nmu=4, interlaced=inter)
+    scale2 = np.sqrt(np.abs(a1["power2d"][ok2]) * np.abs(a2["power2d"][ok2]))
+    err2 = np.abs(got["power2d"][ok2] - want["power2d"][ok2]) / scale2
+    print(f"cross {window} {dtype}: max P(k,mu) err {err2.max():.2e}")
+    assert err2.max() <= TOL[dtype]
+    np.testing.assert_allclose(got["mu2d"][ok2], want["mu2d"][ok2], rtol=1e-12)
     assert got["shotnoise"] == 0.0
 
 
