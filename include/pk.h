@@ -236,6 +236,25 @@ pk_status pk_compensate(pk_ctx *ctx, const pk_mesh_desc *m, void *cmesh_inout,
 pk_status pk_bin_power(pk_ctx *ctx, const pk_mesh_desc *m, const pk_bin_desc *b,
                        const void *cmesh, double *result_dev);
 
+/* pk_bin_power for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same binning and the same result slots, but the squared bin edges and
+ * the per-workgroup partial sums are kept in a fixed 8 MiB array of device
+ * memory that the library holds on each GPU from its load until the process
+ * ends (its address is looked up by pk_ctx_create).  The call allocates
+ * nothing: no hipMalloc, no hipFree, no table of the context (the counts and
+ * mean |k| that pk_result_to_host adds are built there, on first use of a
+ * binning).  Its grids shrink to the partial rows that fit the array, so
+ * every binning pk_bin_power accepts fits; larger ones are refused with
+ * PK_EUNSUPPORTED and a message.  All calls on one GPU share the array:
+ * calls that overlap on one GPU (other streams, other contexts, other host
+ * threads) race and must not be issued.  The sums equal pk_bin_power's up to
+ * the order of float64 additions.
+ * Errors: as pk_bin_power; PK_EDEVICE if the array's address could not be
+ * obtained on this device. */
+pk_status pk_bin_power_noalloc(pk_ctx *ctx, const pk_mesh_desc *m, const pk_bin_desc *b,
+                               const void *cmesh, double *result_dev);
+
 /* Cross power of two fields on the same mesh (the two-field form of the
  * FFTPower estimator, Sec. 3.4.1): as pk_bin_power with |c|^2 replaced by
  * Re(c1 conj(c2)) mode by mode, for packed spectra prepared the same way

@@ -28,7 +28,7 @@ EXPORTS = (
     "pk_fftpower_batch", "pk_bin_cross", "pk_fftpower_v", "pk_projected_doubles",
     "pk_bin_projected", "pk_projected_to_host", "pk_convolved_doubles",
     "pk_convolved_workspace_bytes", "pk_convolved_power", "pk_convolved_to_host", "pk_fft_c2r",
-    "pk_shape_table_len", "pk_shape_spectrum", "pk_num_kbins",
+    "pk_shape_table_len", "pk_shape_spectrum", "pk_num_kbins", "pk_bin_power_noalloc",
 )
 PK_MAX_LANES = 64
 PK_DEVICE_NONE = -1
@@ -117,6 +117,7 @@ def load(path=None):
             "pk_shape_spectrum": (i32, [vp, md, vp, vp, i64]),
             "pk_compensate": (i32, [vp, md, vp, vp]),
             "pk_bin_power": (i32, [vp, md, bd, vp, vp]),
+            "pk_bin_power_noalloc": (i32, [vp, md, bd, vp, vp]),
             "pk_bin_cross": (i32, [vp, md, bd, vp, vp, vp]),
             "pk_projected_doubles": (sz, [bd]),
             "pk_bin_projected": (i32, [vp, md, bd, ctypes.c_int, vp, vp]),
@@ -364,6 +365,12 @@ class Context:
         c = self._mesh_arg(m, cmesh, "cmesh")
         r = self._result_arg(b, result)
         self._check(self.lib.pk_bin_power(self.handle, ctypes.byref(m), ctypes.byref(b), c, r))
+
+    def pk_bin_power_noalloc(self, m, b, cmesh, result):
+        c = self._mesh_arg(m, cmesh, "cmesh")
+        r = self._result_arg(b, result)
+        self._check(self.lib.pk_bin_power_noalloc(self.handle, ctypes.byref(m), ctypes.byref(b),
+                                                  c, r))
 
     def pk_bin_cross(self, m, b, cmesh1, cmesh2, result):
         c1 = self._mesh_arg(m, cmesh1, "cmesh1")

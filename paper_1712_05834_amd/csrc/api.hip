@@ -4,6 +4,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 
@@ -11,9 +12,50 @@
 
 using namespace pk;
 
+// Device memory of pk_bin_power_noalloc: the squared bin edges and the
+// per-workgroup partial sums live in this fixed array instead of memory the
+// library allocates.  Each GPU holds its own copy (at its own address) from
+// the load of the library until the process ends; every call on a GPU shares
+// it, so calls that overlap on one GPU race.
+constexpr size_t kNoAllocScratchBytes = 8u << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
 namespace {
 
 thread_local std::string g_create_error;
+
+// Device address of `scratch` per device, looked up once per device with that
+// device current (pk_ctx_create).  In host code the array's name is only a
+// host-side stand-in; kernels and copies take these addresses.
+constexpr int kMaxScratchDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxScratchDevices] = {};
+hipError_t g_scratch_err[kMaxScratchDevices] = {};
+
+void bind_scratch(int device) {
+  if (device < 0 || device >= kMaxScratchDevices) return;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_ptr[device]) return;
+  void* p = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (e == hipSuccess && p) {
+    g_scratch_ptr[device] = p;
+    g_scratch_err[device] = hipSuccess;
+  } else {
+    g_scratch_err[device] = e == hipSuccess ? hipErrorInvalidSymbol : e;
+    (void)hipGetLastError();
+  }
+}
+
+void* scratch_of(int device, hipError_t* err) {
+  if (device < 0 || device >= kMaxScratchDevices) {
+    *err = hipErrorInvalidDevice;
+    return nullptr;
+  }
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  *err = g_scratch_err[device];
+  return g_scratch_ptr[device];
+}
 
 struct DeviceGuard {
   int prev = -1;
@@ -444,6 +486,10 @@ pk_status pk_ctx_create(pk_ctx** ctx, int device, void* hip_stream) {
   }
   c->device = device;
   c->stream = static_cast<hipStream_t>(hip_stream);
+  if (device != PK_DEVICE_NONE) {
+    DeviceGuard g(device);
+    bind_scratch(device);  // a failure is reported by pk_bin_power_noalloc
+  }
   *ctx = c;
   return PK_OK;
 }
@@ -600,6 +646,45 @@ pk_status pk_compensate(pk_ctx* ctx, const pk_mesh_desc* m, void* cmesh_inout,
 pk_status pk_bin_power(pk_ctx* ctx, const pk_mesh_desc* m, const pk_bin_desc* b,
                        const void* cmesh, double* result_dev) {
   return bin_packed(ctx, m, b, cmesh, nullptr, result_dev, "pk_bin_power");
+}
+
+pk_status pk_bin_power_noalloc(pk_ctx* ctx, const pk_mesh_desc* m, const pk_bin_desc* b,
+                               const void* cmesh, double* result_dev) {
+  if (!ctx) return PK_EINVAL;
+  if (const char* why = check_mesh(m)) return fail(ctx, PK_EINVAL, why);
+  if (const char* why = check_bins(b, m)) return fail(ctx, PK_EINVAL, why);
+  if (!cmesh || !result_dev) return fail(ctx, PK_EINVAL, "cmesh or result is NULL");
+  if (const char* why = check_lds(b, m)) return fail(ctx, PK_EUNSUPPORTED, why);
+  // scratch: the nk + 1 squared edges, then one row of nsum partial sums per
+  // workgroup of the two binning kernels; the grids shrink to the rows that fit
+  const size_t edges = align256(((size_t)b->nk + 1) * sizeof(double));
+  const size_t row = (size_t)nsum_of(b) * sizeof(double);
+  const size_t rows = edges < kNoAllocScratchBytes ? (kNoAllocScratchBytes - edges) / row : 0;
+  if (rows < 2)
+    return fail(ctx, PK_EUNSUPPORTED,
+                "pk_bin_power_noalloc: the bin sums need more than its " +
+                    std::to_string(kNoAllocScratchBytes >> 20) + " MiB of fixed device memory");
+  if (ctx->device == PK_DEVICE_NONE) return fail(ctx, PK_EDEVICE, "validation-only context");
+  hipError_t e = hipSuccess;
+  unsigned char* base = static_cast<unsigned char*>(scratch_of(ctx->device, &e));
+  if (!base)
+    return fail(ctx, PK_EDEVICE, std::string("pk_bin_power_noalloc: no address of the fixed "
+                                             "scratch on this device: ") + hipGetErrorString(e));
+  DeviceGuard g(ctx->device);
+  const int gp = (int)std::min<size_t>(std::min(plane_bin_groups(m->nmesh), 64), rows / 2);
+  const int gb = (int)std::min<size_t>(bin_packed_groups(m->nmesh), rows - gp);
+  double* e2 = reinterpret_cast<double*>(base);
+  double* partials = reinterpret_cast<double*>(base + edges);
+  const BinSpec spec = make_spec(m, b, e2);
+  e = launch_edges_squared(b->kmin_f, b->dk_f, b->nk, e2, ctx->stream);
+  if (e == hipSuccess)
+    e = launch_bin_packed(m->dtype, m->nmesh, cmesh, nullptr, spec, partials, ctx->stream, 0, gb);
+  if (e == hipSuccess)
+    e = launch_plane_bin(m->dtype, m->nmesh, cmesh, nullptr, m->nmesh / 2, MeshTables{}, m->window,
+                         0, spec, partials + (size_t)gb * spec.nsum, ctx->stream, 0, gp);
+  if (e == hipSuccess) e = launch_reduce(partials, gb + gp, spec, result_dev, ctx->stream);
+  if (e != hipSuccess) return dev_fail(ctx, e, "pk_bin_power_noalloc");
+  return PK_OK;
 }
 
 size_t pk_projected_doubles(const pk_bin_desc* b) {

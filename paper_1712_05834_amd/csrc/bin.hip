@@ -759,11 +759,17 @@ static bool ylayout_bits(int nmesh, int* lw, int* lbx) {
   }
 }
 
-hipError_t launch_bin_packed(int dtype, int nmesh, const void* cmesh, const void* cmesh2,
-                             const BinSpec& b, double* partials, hipStream_t s, int ylayout) {
+int bin_packed_groups(int nmesh) {
   const size_t total = (size_t)nmesh * nmesh * (nmesh / 2);
-  size_t g = (total + 255) / 256;
-  if (g > 1024) g = 1024;
+  const size_t g = (total + 255) / 256;
+  return (int)(g > 1024 ? 1024 : g);
+}
+
+hipError_t launch_bin_packed(int dtype, int nmesh, const void* cmesh, const void* cmesh2,
+                             const BinSpec& b, double* partials, hipStream_t s, int ylayout,
+                             int max_groups) {
+  size_t g = (size_t)bin_packed_groups(nmesh);
+  if (max_groups > 0 && g > (size_t)max_groups) g = (size_t)max_groups;
   int lw = -1, lbx = 0;
   if (ylayout) {
     const bool ok = dtype == PK_F32 ? ylayout_bits<float>(nmesh, &lw, &lbx)
@@ -811,8 +817,8 @@ hipError_t launch_bin_fields(int dtype, int nmesh, const void* cmesh, const void
 
 hipError_t launch_plane_bin(int dtype, int nmesh, const void* za, const void* zb, size_t zstride,
                             const MeshTables& t, int order, int compensated, const BinSpec& b,
-                            double* partials, hipStream_t s, int cross) {
-  const int g = plane_bin_groups(nmesh);
+                            double* partials, hipStream_t s, int cross, int groups) {
+  const int g = groups > 0 ? groups : plane_bin_groups(nmesh);
   if (dtype == PK_F32) {
     const float* sinv = compensated ? static_cast<const float*>(t.sinc_inv) + (size_t)(order - 2) * nmesh : nullptr;
     hipLaunchKernelGGL(k_plane_bin<float>, dim3(g), dim3(256), bin_lds_bytes(b), s, nmesh,
@@ -843,6 +849,23 @@ hipError_t launch_bin_projected(int dtype, int nmesh, const void* cmesh, int kee
   else
     hipLaunchKernelGGL(k_bin_projected<double>, dim3(g), dim3(256), lds, s, nmesh,
                        static_cast<const cpx<double>*>(cmesh), keep, b, partials);
+  return hipGetLastError();
+}
+
+// Squared bin edges on the device, with contraction off so that the product
+// and the sum are rounded separately, as in the host table.
+__global__ void __launch_bounds__(256)
+    k_edges_squared(double kmin, double dk, int nk, double* __restrict__ e2) {
+#pragma clang fp contract(off)
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i <= nk; i += gridDim.x * blockDim.x) {
+    const double e = kmin + (double)i * dk;
+    e2[i] = e * e;
+  }
+}
+
+hipError_t launch_edges_squared(double kmin, double dk, int nk, double* e2, hipStream_t s) {
+  const int blocks = (nk + 1 + 255) / 256;
+  hipLaunchKernelGGL(k_edges_squared, dim3(blocks), dim3(256), 0, s, kmin, dk, nk, e2);
   return hipGetLastError();
 }
 

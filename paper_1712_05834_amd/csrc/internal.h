@@ -114,8 +114,12 @@ hipError_t launch_xpass_bin(int dtype, int nmesh, const void* mesh_a, const void
                             double* partials, void* side_a, void* side_b, hipStream_t s);
 // cmesh2 != NULL: cross power Re(c conj(c2)) instead of |c|^2.  ylayout = 1:
 // both spectra are in the y-pass output layout instead of the packed one.
+// max_groups > 0 caps the grid (and so the partial rows written); the
+// default grid is bin_packed_groups(nmesh).
+int bin_packed_groups(int nmesh);
 hipError_t launch_bin_packed(int dtype, int nmesh, const void* cmesh, const void* cmesh2,
-                             const BinSpec& b, double* partials, hipStream_t s, int ylayout = 0);
+                             const BinSpec& b, double* partials, hipStream_t s, int ylayout = 0,
+                             int max_groups = 0);
 // Plain k-bin sums of Re(c conj(d_i)) for nf <= 4 other spectra d_i (NULL:
 // c itself) in one pass; field i's workgroup sums go to partials + i pstride
 // (launch_bin_packed's grid and row layout).  ylayout as launch_bin_packed.
@@ -123,9 +127,14 @@ hipError_t launch_bin_fields(int dtype, int nmesh, const void* cmesh, const void
                              int nf, const BinSpec& b, double* partials, size_t pstride,
                              hipStream_t s, int ylayout);
 // cross = 0: za (and the interlaced zb) combined; cross = 1: Re(a conj(b)).
+// groups > 0 sets the grid (else plane_bin_groups(nmesh)); t is read only
+// for interlacing (zb, cross = 0) and compensation.
 hipError_t launch_plane_bin(int dtype, int nmesh, const void* za, const void* zb, size_t zstride,
                             const MeshTables& t, int order, int compensated, const BinSpec& b,
-                            double* partials, hipStream_t s, int cross = 0);
+                            double* partials, hipStream_t s, int cross = 0, int groups = 0);
+// e2[i] = (kmin + i dk)^2 for i = 0 .. nk, each product and sum rounded on
+// its own: the same values as the host-built edge table.
+hipError_t launch_edges_squared(double kmin, double dk, int nk, double* e2, hipStream_t s);
 hipError_t launch_reduce(const double* partials, int ngroups, const BinSpec& b, double* result,
                          hipStream_t s);
 // Projected power: sums [|c|^2, counts, |n|] x nk over the kept axes' grid.
