@@ -194,20 +194,43 @@ def run_fft_reference(args):
     print(json.dumps(out))
 
 
+def oracle_errors(got, want):
+    """Largest per-bin error of a GPU FFTPower result against the float64
+    oracle's, on the definitions of the float32 bar: |dP| / |P| for P(k) and
+    P(k, mu), |dP_ell| / |P_0| for ell > 0 (P_ell crosses zero); counts must
+    agree exactly."""
+    import numpy as np
+
+    ok = want["modes"] > 0
+    out = {"counts_equal": bool(np.array_equal(got["modes"], want["modes"])),
+           "P": float(np.max(np.abs(got["power"][ok] / want["power"][ok] - 1)))}
+    for ell, p in want["poles"].items():
+        if ell:
+            out[f"P_{ell}"] = float(np.max(np.abs(got["poles"][ell][ok] - p[ok])
+                                           / np.abs(want["power"][ok])))
+    if "power2d" in want:
+        ok2 = want["modes2d"] > 0
+        out["P_kmu"] = float(np.max(np.abs(got["power2d"][ok2] / want["power2d"][ok2] - 1)))
+    return out
+
+
 def cpu_baseline(w, pos, frac):
-    """Oracle (float64, CPU) on a bounded sample: painting of a fraction of the
-    catalog onto both meshes (scaled by 1 / frac), the full r2c of each mesh
-    and the full binning."""
+    """The CPU float64 oracle on a bounded sample of the catalog: painting of
+    both meshes, the full r2c of each mesh and the full binning, each stage
+    timed; the painting is scaled by 1 / frac to the whole catalog.  Returns
+    the baseline entry, the oracle's result for the sample and the sample
+    itself (to run the GPU path on the same particles)."""
     import numpy as np
 
     import oracle
     from oracle.paint import WINDOW_ORDER
 
     n, box, order = w["n"], w["box"], WINDOW_ORDER[w["window"]]
-    sub = pos[: max(1, int(len(pos) * frac))].astype(np.float64)
+    sub = pos[: max(1, int(len(pos) * frac))]
+    sub64 = sub.astype(np.float64)
     t0 = time.perf_counter()
-    ma = oracle.paint_mesh(sub, n, box, order)
-    mb = oracle.paint_mesh(sub, n, box, order, shift_cells=0.5) if w["interlaced"] else None
+    ma = oracle.paint_mesh(sub64, n, box, order)
+    mb = oracle.paint_mesh(sub64, n, box, order, shift_cells=0.5) if w["interlaced"] else None
     t_paint = time.perf_counter() - t0
     t0 = time.perf_counter()
     ca = oracle.r2c(ma)
@@ -216,11 +239,14 @@ def cpu_baseline(w, pos, frac):
     del mb
     t_fft = time.perf_counter() - t0
     t0 = time.perf_counter()
-    oracle.fftpower_from_spectra(ca, cb, n, box, order, True, float(len(sub)), float(len(sub)),
-                                 len(sub), nmu=w["nmu"], poles=w["poles"])
+    want = oracle.fftpower_from_spectra(ca, cb, n, box, order, True, float(len(sub)),
+                                        float(len(sub)), len(sub), nmu=w["nmu"],
+                                        poles=w["poles"])
     t_bin = time.perf_counter() - t0
+    del ca, cb
     per_mesh = t_paint / frac + t_fft + t_bin
-    return {
+    scaled = "" if frac >= 1 else f", scaled x{1 / frac:g}"
+    entry = {
         "value": 1.0 / per_mesh,
         "unit": "meshes/s",
         "cores": os.cpu_count(),
@@ -228,10 +254,40 @@ def cpu_baseline(w, pos, frac):
         "kind": "oracle",
         "sample": (f"float64 oracle on this host: painting of {len(sub)} of {len(pos)} "
                    f"particles onto {'both meshes' if w['interlaced'] else 'the mesh'} "
-                   f"({t_paint:.1f} s, single thread, scaled x{1 / frac:g}), full r2c "
+                   f"({t_paint:.1f} s, single thread{scaled}), full r2c "
                    f"({t_fft:.1f} s, scipy workers={os.cpu_count()}) and full binning "
                    f"({t_bin:.1f} s, single thread) of one {n}^3 mesh"),
     }
+    return entry, want, sub
+
+
+def oracle_on_items(items, unit):
+    """cpu_baseline of the batch and serving workloads: the float64 oracle on
+    a few of the catalogs, timed, and the GPU results of those catalogs
+    against it.  items: (label, positions on the host, nmesh, boxsize,
+    window, interlaced, poles, GPU result)."""
+    import numpy as np
+
+    import oracle
+
+    t_total, errs = 0.0, []
+    for label, pos, n, box, window, inter, poles, got in items:
+        t0 = time.perf_counter()
+        want = oracle.fftpower(pos.astype(np.float64), n, box, window, inter, True, nmu=0,
+                               poles=poles)
+        t_total += time.perf_counter() - t0
+        e = oracle_errors(got, want)
+        e["catalog"] = label
+        errs.append(e)
+    worst = {"P": max(e["P"] for e in errs), "counts_equal": all(e["counts_equal"] for e in errs)}
+    for key in {k for e in errs for k in e if k.startswith("P_")}:
+        worst[key] = max(e.get(key, 0.0) for e in errs)
+    entry = {"value": len(items) / t_total, "unit": unit, "cores": os.cpu_count(),
+             "cpu": cpu_model(), "kind": "oracle",
+             "sample": (f"float64 oracle on this host ({os.cpu_count()} cores for the r2c, "
+                        f"one for painting and binning) on {len(items)} of the catalogs: "
+                        + "; ".join(e["catalog"] for e in errs) + f" ({t_total:.1f} s)")}
+    return entry, {"worst": worst, "per_catalog": errs}
 
 
 def main():
@@ -250,8 +306,9 @@ def main():
     ap.add_argument("--shuffle", action="store_true",
                     help="permute the catalog (seeded) before timing: a catalog in no "
                          "particular order instead of the generator's cell order")
-    ap.add_argument("--cpu-sample", type=float, default=0.5,
-                    help="fraction of the catalog the oracle paints for cpu_baseline")
+    ap.add_argument("--cpu-sample", type=float, default=None,
+                    help="fraction of the catalog the oracle paints for cpu_baseline "
+                         "(default: the whole catalog at 512^3 and below, 3%% at 1024^3)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (3 times) and exit: the "
                          "reference for scaling rocprofv3 FETCH_SIZE / WRITE_SIZE counters")
@@ -379,8 +436,24 @@ def main():
         "cpu_baseline": None,
     }
     if not args.no_cpu_baseline:
-        log("timing the CPU oracle on a bounded sample")
-        line["cpu_baseline"] = cpu_baseline(w, pos_host, args.cpu_sample)
+        frac = args.cpu_sample if args.cpu_sample else (1.0 if w["n"] <= 512 else 0.03)
+        log(f"timing the CPU oracle on {frac:g} of the catalog")
+        line["cpu_baseline"], want, sub = cpu_baseline(w, pos_host, frac)
+        if len(sub) == npart:
+            got, basis = out, "the timed run's result, whole catalog"
+        else:
+            # the GPU path once more, untimed, on the oracle's sample
+            sub_d = torch.from_numpy(np.ascontiguousarray(sub)).to(dev)
+            ws_s = torch.empty(_lib.workspace_bytes(m, b, len(sub)), dtype=torch.uint8,
+                               device=dev)
+            ctx.pk_fftpower(m, b, sub_d, None, len(sub), ws_s, res)
+            got = ctx.pk_result_to_host(m, b, res)
+            basis = f"the same path on the oracle's sample of {len(sub)} particles"
+        err = oracle_errors(got, want)
+        err["basis"] = basis
+        line["max_rel_err_vs_oracle"] = err
+        log("error against the float64 oracle: " + ", ".join(
+            f"{k} {v:.2e}" for k, v in err.items() if isinstance(v, float)))
     print(json.dumps(line), flush=True)
 
 
@@ -469,6 +542,18 @@ def run_batch(args):
         "fp32_vs_fp64_max_rel_err": {"max": max(errs), "median": float(np.median(errs))},
         "cpu_baseline": None,
     }
+    if not args.no_cpu_baseline:
+        # the smallest catalog of each mesh size, against the float64 oracle
+        items = []
+        for nm in BATCH["meshes"]:
+            idx = [i for i in range(len(pos)) if ms[i].nmesh == nm]
+            if not idx:
+                continue
+            i = min(idx, key=lambda j: npart[j])
+            items.append((f"mock {i}: {npart[i]} particles on {nm}^3", pos[i].cpu().numpy(), nm,
+                          BATCH["box"], BATCH["window"], True, BATCH["poles"], out[i]))
+        log(f"float64 oracle on {len(items)} mocks")
+        line["cpu_baseline"], line["max_rel_err_vs_oracle"] = oracle_on_items(items, "mocks/s")
     print(json.dumps(line), flush=True)
 
 
@@ -624,6 +709,24 @@ def run_serve(args):
         "roofline": None,
         "cpu_baseline": None,
     }
+    if not args.no_cpu_baseline:
+        # the smallest request of each mesh size up to 512^3 (and each kind of
+        # window and interlacing that occurs among them), against the oracle
+        items, seen = [], set()
+        for r in sorted(served, key=lambda q: q.npart):
+            key = (r.mesh.nmesh, r.mesh.window, r.mesh.interlaced)
+            if r.mesh.nmesh > 512 or r.npart > 3_000_000 or key in seen:
+                continue
+            seen.add(key)
+            win = {2: "cic", 3: "tsc", 4: "pcs"}[r.mesh.window]
+            items.append((f"request {r.rid}: {r.npart} particles, {r.mesh.nmesh}^3 {win}"
+                          f"{' interlaced' if r.mesh.interlaced else ''}", r.pos.cpu().numpy(),
+                          r.mesh.nmesh, r.mesh.boxsize, win, bool(r.mesh.interlaced), (0, 2),
+                          r.result))
+            if len(items) == 6:
+                break
+        log(f"float64 oracle on {len(items)} requests")
+        line["cpu_baseline"], line["max_rel_err_vs_oracle"] = oracle_on_items(items, "requests/s")
     print(json.dumps(line), flush=True)
 
 

@@ -49,3 +49,23 @@ def test_source_hash_ignores_comments():
     code = "int f(int x) {  // the answer\n  /* more\n  words */ return x;\n}\n\n"
     assert bench._code_only(code) == "int f(int x) {\n   return x;\n}"
     assert bench._code_only(code) == bench._code_only(code.replace("the answer", "another"))
+
+
+def test_oracle_errors_follow_the_float32_bar_definitions():
+    # |dP|/|P| per bin, |dP_ell| / |P_0| for ell > 0, P(k, mu) relative
+    import numpy as np
+
+    want = {"modes": np.array([0, 4, 6]), "power": np.array([np.nan, 2.0, 4.0]),
+            "poles": {0: np.array([np.nan, 2.0, 4.0]), 2: np.array([np.nan, 0.0, -1.0])},
+            "modes2d": np.array([[0, 0], [2, 2]]), "power2d": np.array([[np.nan, np.nan],
+                                                                       [1.0, 3.0]])}
+    got = {"modes": np.array([0, 4, 6]), "power": np.array([np.nan, 2.0002, 4.0]),
+           "poles": {0: np.array([np.nan, 2.0, 4.0]), 2: np.array([np.nan, 0.001, -1.0])},
+           "power2d": np.array([[np.nan, np.nan], [1.0, 3.003]])}
+    e = bench.oracle_errors(got, want)
+    assert e["counts_equal"]
+    assert abs(e["P"] - 1e-4) < 1e-12
+    assert abs(e["P_2"] - 0.001 / 2.0) < 1e-12
+    assert abs(e["P_kmu"] - 1e-3) < 1e-12
+    got["modes"] = np.array([0, 4, 5])
+    assert not bench.oracle_errors(got, want)["counts_equal"]
