@@ -103,6 +103,26 @@ int nsum_of(const pk_bin_desc* b) {
   return b->nk * (1 + b->npoles) + (b->nmu > 1 ? b->nk * b->nmu : 0);
 }
 
+// Accumulated sums of a binning: the power, the poles with ell > 0 and the
+// (k, mu) bins (ell = 0 poles alias the power).
+int nlds_of(const pk_bin_desc* b) {
+  int npl = 0;
+  for (int i = 0; i < b->npoles; ++i) npl += b->poles[i] != 0 ? 1 : 0;
+  // the power sum is accumulated only without (k, mu) bins
+  return b->nk * (npl + (b->nmu > 1 ? b->nmu : 1));
+}
+
+// LDS bytes of the bin accumulators: two 64-bit words per sum, one flag word.
+size_t bin_acc_bytes(const pk_bin_desc* b) {
+  return ((size_t)nlds_of(b) * 2 + 1) * sizeof(unsigned long long);
+}
+
+// Largest compensation factor of one mode, squared: prod_d sinc^-2p(pi n_d / N)
+// is largest at |n_d| = N/2, where each factor is (pi / 2)^p.
+double comp2_max(const pk_mesh_desc* m) {
+  return m->compensated ? std::pow(3.14159265358979323846 / 2.0, 6.0 * m->window) : 1.0;
+}
+
 const char* check_bins(const pk_bin_desc* b, const pk_mesh_desc* m) {
   if (!b) return "bin descriptor is NULL";
   if (!std::isfinite(b->kmin_f) || b->kmin_f < 0) return "kmin_f must be finite and >= 0";
@@ -132,8 +152,9 @@ constexpr int kMaxLdsSlots = 8192;
 
 const char* check_lds(const pk_bin_desc* b, const pk_mesh_desc* m) {
   if (nsum_of(b) > kMaxLdsSlots) return "too many bin slots for the LDS accumulator";
-  if (m && xpass_static_lds(m->dtype, m->nmesh) +
-                   (size_t)nsum_of(b) * sizeof(double) > kLdsBytesPerGroup)
+  if (bin_acc_bytes(b) > kLdsBytesPerGroup)
+    return "too many bin slots for the LDS accumulator";
+  if (m && xpass_static_lds(m->dtype, m->nmesh) + bin_acc_bytes(b) > kLdsBytesPerGroup)
     return "too many bin slots for the LDS accumulator at this mesh size and precision";
   if (mode_table_slots(b->nk, b->nmu > 1 ? b->nmu : 0) > kMaxLdsSlots)
     return "too many (k, mu) bins for the mode-table accumulator";
@@ -239,6 +260,12 @@ BinSpec make_spec(const pk_mesh_desc* m, const pk_bin_desc* b, const double* e2_
   }
   s.off2d = b->nmu > 1 ? b->nk * (1 + b->npoles) : -1;
   s.nsum = nsum_of(b);
+  s.power_from_2d = b->nmu > 1 ? 1 : 0;
+  const int p0 = s.power_from_2d ? 0 : 1;  // LDS slots of the power sum (k-bins)
+  for (int i = 0; i < s.npl; ++i) s.pole_lds[i] = b->nk * (p0 + i);
+  s.fix_hb = m->dtype == PK_F32 ? 32 : 64;
+  s.off2d_lds = b->nmu > 1 ? b->nk * s.npl : -1;
+  s.nlds = nlds_of(b);
   s.kmin_f = b->kmin_f;
   s.dk_f = b->dk_f;
   s.e2 = e2_dev;
@@ -315,6 +342,13 @@ pk_status get_bin_tables(pk_ctx* ctx, const pk_mesh_desc* m, const pk_bin_desc* 
   *out = bt.get();
   ctx->bin_tables.emplace(key, std::move(bt));
   return PK_OK;
+}
+
+// Largest (Hermitian-weighted) number of modes in one bin of a binning.
+double mode_max(const BinTables* bt) {
+  int64_t mx = 1;
+  for (int64_t c : bt->modes) mx = c > mx ? c : mx;
+  return (double)mx;
 }
 
 // Context-owned scratch for the stand-alone binning (partial sums); grown on
@@ -402,7 +436,7 @@ Layout layout_of(const pk_mesh_desc* m, const pk_bin_desc* b, int64_t npart) {
   const size_t side = align256(n * n * 2 * es);
   const int two = m->interlaced ? 1 : 0;
   const size_t np = npart > 0 ? (size_t)npart : 0;
-  l.gx = xpass_bin_groups(m->dtype, m->nmesh, nsum_of(b));
+  l.gx = xpass_bin_groups(m->dtype, m->nmesh, bin_acc_bytes(b));
   l.gp = plane_bin_groups(m->nmesh);
   size_t off = 0;
   l.mesh_a = off;
@@ -416,7 +450,7 @@ Layout layout_of(const pk_mesh_desc* m, const pk_bin_desc* b, int64_t npart) {
   l.side_b = off;
   off += two * side;
   l.partials = off;
-  off += align256((size_t)(l.gx + l.gp) * nsum_of(b) * sizeof(double));
+  off += align256((size_t)(l.gx + l.gp) * 2 * nsum_of(b) * sizeof(double));
   l.bucket = off;
   off += align256(bucket_bytes(m->nmesh));
   l.rec = off;
@@ -441,17 +475,27 @@ pk_status bin_packed(pk_ctx* ctx, const pk_mesh_desc* m, const pk_bin_desc* b, c
   if (pk_status st = get_bin_tables(ctx, m, b, &bt)) return st;
   const MeshTables* t = nullptr;
   if (pk_status st = get_mesh_tables(ctx, m->nmesh, m->dtype, &t)) return st;
-  const BinSpec spec = make_spec(m, b, bt->e2_dev);
-  const size_t total = (size_t)m->nmesh * m->nmesh * (m->nmesh / 2);
-  size_t gb = (total + 255) / 256;
-  if (gb > 1024) gb = 1024;
+  BinSpec spec = make_spec(m, b, bt->e2_dev);
+  const size_t gb = (size_t)bin_packed_groups(m->nmesh);
   const int gp = plane_bin_groups(m->nmesh);
   double* partials = nullptr;
-  if (pk_status st = get_scratch(ctx, (gb + gp) * spec.nsum * sizeof(double), &partials)) return st;
-  hipError_t e = launch_bin_packed(m->dtype, m->nmesh, c1, c2, spec, partials, ctx->stream);
+  if (pk_status st = get_scratch(ctx, ((gb + gp) * 2 * spec.nsum + 1) * sizeof(double), &partials))
+    return st;
+  // the bound of the exact sums: every term is at most 2 max|component|^2
+  // per mode, and a bin holds at most all N^3 (weighted) modes of the packed
+  // spectrum (a factor 4 to spare); the same scale as pk_bin_power_noalloc,
+  // so that the two give the same sums bit for bit
+  double* amax = partials + (gb + gp) * 2 * spec.nsum;
+  spec.bound_scale = 8.0 * (double)m->nmesh * m->nmesh * m->nmesh;
+  spec.bound_dev = amax;
+  spec.bound_sq = 1;
+  hipError_t e = launch_absmax(m->dtype, c1, c2, (size_t)m->nmesh * m->nmesh * m->nmesh, amax,
+                               ctx->stream);
+  if (e == hipSuccess)
+    e = launch_bin_packed(m->dtype, m->nmesh, c1, c2, spec, partials, ctx->stream);
   if (e == hipSuccess)
     e = launch_plane_bin(m->dtype, m->nmesh, c1, c2, m->nmesh / 2, *t, m->window, 0, spec,
-                         partials + gb * spec.nsum, ctx->stream, c2 ? 1 : 0);
+                         partials + gb * 2 * spec.nsum, ctx->stream, c2 ? 1 : 0);
   if (e == hipSuccess) e = launch_reduce(partials, (int)(gb + gp), spec, result_dev, ctx->stream);
   if (e != hipSuccess) return dev_fail(ctx, e, who);
   return PK_OK;
@@ -657,8 +701,8 @@ pk_status pk_bin_power_noalloc(pk_ctx* ctx, const pk_mesh_desc* m, const pk_bin_
   if (const char* why = check_lds(b, m)) return fail(ctx, PK_EUNSUPPORTED, why);
   // scratch: the nk + 1 squared edges, then one row of nsum partial sums per
   // workgroup of the two binning kernels; the grids shrink to the rows that fit
-  const size_t edges = align256(((size_t)b->nk + 1) * sizeof(double));
-  const size_t row = (size_t)nsum_of(b) * sizeof(double);
+  const size_t edges = align256(((size_t)b->nk + 1) * sizeof(double)) + 256;  // + the max
+  const size_t row = (size_t)nsum_of(b) * 2 * sizeof(double);
   const size_t rows = edges < kNoAllocScratchBytes ? (kNoAllocScratchBytes - edges) / row : 0;
   if (rows < 2)
     return fail(ctx, PK_EUNSUPPORTED,
@@ -674,14 +718,24 @@ pk_status pk_bin_power_noalloc(pk_ctx* ctx, const pk_mesh_desc* m, const pk_bin_
   const int gp = (int)std::min<size_t>(std::min(plane_bin_groups(m->nmesh), 64), rows / 2);
   const int gb = (int)std::min<size_t>(bin_packed_groups(m->nmesh), rows - gp);
   double* e2 = reinterpret_cast<double*>(base);
+  double* amax = reinterpret_cast<double*>(base + edges - 256);
   double* partials = reinterpret_cast<double*>(base + edges);
-  const BinSpec spec = make_spec(m, b, e2);
+  BinSpec spec = make_spec(m, b, e2);
+  // bound of the exact sums as in pk_bin_power, with every mode of the
+  // packed spectrum (N^3 counted with their weights) as the count
+  const double nmodes = (double)m->nmesh * m->nmesh * m->nmesh;
+  spec.bound_scale = 8.0 * nmodes;
+  spec.bound_dev = amax;
+  spec.bound_sq = 1;
   e = launch_edges_squared(b->kmin_f, b->dk_f, b->nk, e2, ctx->stream);
+  if (e == hipSuccess)
+    e = launch_absmax(m->dtype, cmesh, nullptr, (size_t)m->nmesh * m->nmesh * m->nmesh, amax,
+                      ctx->stream);
   if (e == hipSuccess)
     e = launch_bin_packed(m->dtype, m->nmesh, cmesh, nullptr, spec, partials, ctx->stream, 0, gb);
   if (e == hipSuccess)
     e = launch_plane_bin(m->dtype, m->nmesh, cmesh, nullptr, m->nmesh / 2, MeshTables{}, m->window,
-                         0, spec, partials + (size_t)gb * spec.nsum, ctx->stream, 0, gp);
+                         0, spec, partials + (size_t)gb * 2 * spec.nsum, ctx->stream, 0, gp);
   if (e == hipSuccess) e = launch_reduce(partials, gb + gp, spec, result_dev, ctx->stream);
   if (e != hipSuccess) return dev_fail(ctx, e, "pk_bin_power_noalloc");
   return PK_OK;
@@ -718,9 +772,10 @@ pk_status pk_bin_projected(pk_ctx* ctx, const pk_mesh_desc* m, const pk_bin_desc
   spec.npl = 0;
   spec.zero_mask = 0;
   spec.off2d = -1;
+  spec.exact = 0;  // float64 partial rows
   const int gp = projected_groups(m->nmesh, keep);
   double* partials = nullptr;
-  if (pk_status st = get_scratch(ctx, (size_t)gp * spec.nsum * sizeof(double), &partials))
+  if (pk_status st = get_scratch(ctx, (size_t)gp * 2 * spec.nsum * sizeof(double), &partials))
     return st;
   hipError_t e = launch_bin_projected(m->dtype, m->nmesh, cmesh, keep, spec, partials, ctx->stream);
   if (e == hipSuccess) e = launch_reduce(partials, gp, spec, result_dev, ctx->stream);
@@ -809,6 +864,14 @@ hipError_t enqueue_fftpower(pk_ctx* ctx, hipStream_t s, const pk_mesh_desc* m,
   void* side_b = m->interlaced ? ws + l.side_b : nullptr;
   double* partials = reinterpret_cast<double*>(ws + l.partials);
   double* wsums = result_dev + spec.nsum;
+  // bound of the exact bin sums: |c(k)| <= sum |w| <= sqrt(n sum w^2) for a
+  // painted field (window weights are positive and sum to one), times the
+  // compensation and the number of modes per bin (prepare_tables), the
+  // Hermitian weight and the pair of modes binned together (a factor 8)
+  BinSpec bs = spec;
+  bs.bound_scale = spec.bound_scale * (double)(n > 0 ? n : 1);
+  bs.bound_dev = wsums + 1;
+  bs.bound_sq = 0;
   if (timed)
     for (bool& r : ctx->stage_ran) r = false;
   void* rec = ws + l.rec;
@@ -831,14 +894,14 @@ hipError_t enqueue_fftpower(pk_ctx* ctx, hipStream_t s, const pk_mesh_desc* m,
   if (e == hipSuccess && yb) e = launch_fft_y_relayout(m->dtype, m->nmesh, mesh_b, yb, t->tw, s);
   stage(kXpassBin);
   if (e == hipSuccess)
-    e = launch_xpass_bin(m->dtype, m->nmesh, ya, yb, *t, m->window, m->compensated, spec,
+    e = launch_xpass_bin(m->dtype, m->nmesh, ya, yb, *t, m->window, m->compensated, bs,
                          partials, side_a, side_b, s);
   stage(kPlaneBin);
   if (e == hipSuccess)
     e = launch_plane_bin(m->dtype, m->nmesh, side_a, side_b, 1, *t, m->window, m->compensated,
-                         spec, partials + (size_t)l.gx * spec.nsum, s);
+                         bs, partials + (size_t)l.gx * 2 * spec.nsum, s);
   stage(kReduce);
-  if (e == hipSuccess) e = launch_reduce(partials, l.gx + l.gp, spec, result_dev, s);
+  if (e == hipSuccess) e = launch_reduce(partials, l.gx + l.gp, bs, result_dev, s);
   if (timed) mark_end(ctx);
   return e;
 }
@@ -851,6 +914,7 @@ pk_status prepare_tables(pk_ctx* ctx, const pk_mesh_desc* m, const pk_bin_desc* 
   if (pk_status st = get_bin_tables(ctx, m, b, &bt)) return st;
   if (pk_status st = get_mesh_tables(ctx, m->nmesh, m->dtype, t)) return st;
   *spec = make_spec(m, b, bt->e2_dev);
+  spec->bound_scale = 8.0 * comp2_max(m) * mode_max(bt);  // times n sum w^2 at launch
   return PK_OK;
 }
 
@@ -1142,7 +1206,7 @@ struct SurveyLayout {
          wbase = 0, amounts = 0, mesh = 0, ymesh = 0, ymesh2 = 0, ymesh3 = 0, ymesh4 = 0,
          side = 0, side2 = 0,
          fields = 0, planes = 0,
-         bpart = 0, total = 0;
+         bpart = 0, amax = 0, total = 0;
   size_t field_bytes = 0, plane_bytes = 0, amount_bytes = 0;
   int gb = 0, gp = 0, nh = 0;
 };
@@ -1188,7 +1252,8 @@ SurveyLayout survey_layout(const pk_mesh_desc* m, const pk_bin_desc* b, int64_t 
   l.side2 = take(n * n * 2 * es);
   l.fields = take((size_t)nf * l.field_bytes);
   l.planes = take((size_t)nf * l.plane_bytes);
-  l.bpart = take((size_t)b->npoles * (l.gb + l.gp) * b->nk * sizeof(double));
+  l.bpart = take((size_t)b->npoles * (l.gb + l.gp) * 2 * b->nk * sizeof(double));
+  l.amax = take(sizeof(double));
   l.total = off;
   return l;
 }
@@ -1354,7 +1419,8 @@ pk_status pk_convolved_power(pk_ctx* ctx, const pk_mesh_desc* m, const pk_bin_de
   // y-pass output layout) for every pole, then each pole's kz = 0 plane and
   // its reduction; then the weight sums
   double* part = reinterpret_cast<double*>(ws + l.bpart);
-  const size_t pstride = (size_t)(l.gb + l.gp) * spec.nsum;
+  const size_t pstride = (size_t)(l.gb + l.gp) * 2 * spec.nsum;
+  spec.exact = 0;  // the cross sums of the fields are float64 rows
   const void* others[4] = {nullptr, nullptr, nullptr, nullptr};
   int fof[4] = {0, 0, 0, 0};
   for (int i = 0; i < b->npoles; ++i) {
@@ -1367,9 +1433,18 @@ pk_status pk_convolved_power(pk_ctx* ctx, const pk_mesh_desc* m, const pk_bin_de
   for (int i = 0; i < b->npoles && e == hipSuccess; ++i) {
     const int f = fof[i];
     double* pole_part = part + (size_t)i * pstride;
-    e = launch_plane_bin(m->dtype, m->nmesh, plane(0), f == 0 ? nullptr : plane(f), 1, *t,
-                         m->window, 0, spec, pole_part + (size_t)l.gb * spec.nsum, s,
-                         f == 0 ? 0 : 1);
+    // the exact sums' bound from the largest component of the two planes
+    BinSpec ps = spec;
+    double* amax = reinterpret_cast<double*>(ws + l.amax);
+    ps.bound_scale = 8.0 * (double)m->nmesh * m->nmesh;
+    ps.bound_dev = amax;
+    ps.bound_sq = 1;
+    e = launch_absmax(m->dtype, plane(0), f == 0 ? nullptr : plane(f),
+                      (size_t)m->nmesh * m->nmesh * 2, amax, s);
+    if (e == hipSuccess)
+      e = launch_plane_bin(m->dtype, m->nmesh, plane(0), f == 0 ? nullptr : plane(f), 1, *t,
+                           m->window, 0, ps, pole_part + (size_t)l.gb * 2 * spec.nsum, s,
+                           f == 0 ? 0 : 1);
     if (e == hipSuccess)
       e = launch_reduce(pole_part, l.gb + l.gp, spec, result_dev + (size_t)i * b->nk, s);
   }

@@ -84,15 +84,128 @@ __device__ __forceinline__ T ratio(int a, int b) {
   }
 }
 
+// ---- exact bin sums: fixed point
+//
+// Every bin sum is accumulated as an integer in units of 2^-S: each term is
+// rounded to that grid once (towards minus infinity), and integer addition is
+// associative, so the sums do not depend on the order in which lanes, waves
+// or workgroups add their terms -- a result is the same bit for bit on every
+// run, whatever the number of workgroups.  S is chosen from a bound B on
+// every partial sum, so nothing overflows.  A slot is two 64-bit LDS words,
+// in one of two splits (BinSpec::fix_hb):
+//  * 64: a 128-bit two's complement integer (low, high), |sum| < 2^126; the
+//    carry of the low word's addition is read from the returning atomic and
+//    added to the high word with the rest of the term, which keeps
+//    concurrent additions exact.  Float64 spectra: a typical term keeps more
+//    than 53 significant bits.
+//  * 32: the low 32 bits of the term in the first word (an unsigned count
+//    that cannot overflow before 2^32 additions) and the rest, signed, in the
+//    second, |sum| < 2^95; both added without return (no wait on the LDS).
+//    Float32 spectra: a typical term keeps more than 30 significant bits,
+//    far below the float32 path's own rounding.
+
+__device__ __forceinline__ int fix_shift(const BinSpec& b) {
+  double bound = b.bound_scale;
+  if (b.bound_dev) {
+    const double v = *b.bound_dev;
+    bound *= b.bound_sq ? v * v : v;
+  }
+  if (!(bound > 0.0)) return 0;  // every term is zero
+  int e;
+  (void)frexp(bound, &e);  // bound < 2^e
+  return (b.fix_hb == 32 ? 94 : 126) - e;
+}
+
+// trunc(v 2^S) as (lo, hi) words of a 128-bit two's complement integer,
+// from the bits of v: the 53-bit significand shifted into place.
+__host__ __device__ __forceinline__ void fix_split(double v, int S, unsigned long long& lo,
+                                                   unsigned long long& hi) {
+  const unsigned long long bits = __builtin_bit_cast(unsigned long long, v);
+  const int e = (int)((bits >> 52) & 0x7ff);
+  const unsigned long long mant = bits & 0xfffffffffffffull;
+  const unsigned long long m = e ? (mant | (1ull << 52)) : mant;
+  const int sh = (e ? e : 1) - 1075 + S;  // v = m 2^(sh - S)
+  if (sh >= 64) {
+    lo = 0;
+    hi = m << (sh - 64);
+  } else if (sh >= 0) {
+    lo = m << sh;
+    hi = sh > 11 ? m >> (64 - sh) : 0;
+  } else {
+    lo = sh > -64 ? m >> (-sh) : 0;
+    hi = 0;
+  }
+  if (bits >> 63) {  // negate: two's complement of (hi, lo)
+    lo = ~lo + 1ull;
+    hi = ~hi + (lo == 0 ? 1ull : 0ull);
+  }
+}
+
+// floor(v 2^S) = hi 2^32 + lo with 0 <= lo < 2^32 and hi signed, for
+// |v 2^S| < 2^95: doubles split exactly by floors of power-of-two scalings.
+__host__ __device__ __forceinline__ void fix_split32(double v, int S, unsigned long long& lo,
+                                                     unsigned long long& hi) {
+  const double y = ldexp(v, S);
+  const double hd = floor(ldexp(y, -32));
+  const double ld = y - ldexp(hd, 32);  // exact, in [0, 2^32)
+  const double hh = floor(ldexp(hd, -32));
+  const double hl = hd - ldexp(hh, 32);  // exact, in [0, 2^32)
+  lo = (unsigned long long)(unsigned)ld;
+  hi = (unsigned long long)((long long)(int)hh * 4294967296ll + (long long)(unsigned)hl);
+}
+
+// Adds a finite term: the 32-bit split for float32 spectra, the 128-bit one
+// for float64 (fixed by the element type, as BinSpec::fix_hb is).
+template <typename T>
+__device__ __forceinline__ void fix_add(unsigned long long* acc, int nlds, int slot, double v,
+                                        int S) {
+  unsigned long long lo, hi;
+  if constexpr (sizeof(T) == 4) {
+    fix_split32(v, S, lo, hi);
+    atomicAdd(&acc[slot], lo);
+    atomicAdd(&acc[nlds + slot], hi);
+  } else {
+    fix_split(v, S, lo, hi);
+    if ((lo | hi) == 0) return;
+    const unsigned long long old = atomicAdd(&acc[slot], lo);
+    const unsigned long long carry = old + lo < old ? 1ull : 0ull;
+    if (hi + carry) atomicAdd(&acc[nlds + slot], hi + carry);
+  }
+}
+
+// The value of a slot's words, (hi 2^hb + lo) 2^-S, rounded to double the
+// same way every time (hi signed, lo unsigned).
+__host__ __device__ __forceinline__ double fix_words_value(unsigned long long lo,
+                                                           unsigned long long hi, int S,
+                                                           int hb = 64) {
+  if (hb == 32) {
+    // the unique form hi 2^32 + lo with lo < 2^32, so that equal integers
+    // round to the same double whatever their split
+    hi += lo >> 32;
+    lo &= 0xffffffffull;
+  }
+  const double v = ldexp((double)(long long)hi, hb) + (double)lo;
+  return ldexp(v, -S);
+}
+
+__device__ __forceinline__ double fix_value(const unsigned long long* acc, const BinSpec& b,
+                                            int slot, int S) {
+  return fix_words_value(acc[slot], acc[b.nlds + slot], S, b.fix_hb);
+}
+
 // Adds one mode of (Hermitian-weighted) power hp to the LDS bins.  The
 // per-mode products hp L_ell are formed in the path's precision; every sum
-// is float64.
+// is exact (fixed point, see above).
 template <typename T>
-__device__ __forceinline__ void accumulate(double* sb, const BinSpec& b, int n2, int nlos2,
-                                           T hp) {
+__device__ __forceinline__ void accumulate(unsigned long long* sb, const BinSpec& b, int S, int n2,
+                                           int nlos2, T hp) {
   const int k = kbin_of(n2, b);
   if (k < 0) return;
-  atomicAdd(&sb[k], (double)hp);
+  if (!isfinite(hp)) {  // flagged: the workgroup's sums become NaN
+    atomicOr(&sb[2 * b.nlds], 1ull);
+    return;
+  }
+  if (!b.power_from_2d) fix_add<T>(sb, b.nlds, k, (double)hp, S);
   if (b.npl > 0) {
     const T mu2 = ratio<T>(nlos2, n2);
     // at most 4 poles: unrolled, so that the pole tables are read with
@@ -100,19 +213,86 @@ __device__ __forceinline__ void accumulate(double* sb, const BinSpec& b, int n2,
 #pragma unroll
     for (int i = 0; i < 4; ++i)
       if (i < b.npl)
-        atomicAdd(&sb[b.pole_slot[i] + k], (double)(hp * legendre<T>(b.pole_ell[i], mu2)));
+        fix_add<T>(sb, b.nlds, b.pole_lds[i] + k, (double)(hp * legendre<T>(b.pole_ell[i], mu2)),
+                   S);
   }
-  if (b.off2d >= 0) atomicAdd(&sb[b.off2d + k * b.nmu + mubin_of(nlos2, n2, b.nmu)], (double)hp);
+  if (b.off2d_lds >= 0)
+    fix_add<T>(sb, b.nlds, b.off2d_lds + k * b.nmu + mubin_of(nlos2, n2, b.nmu), (double)hp,
+               S);
 }
 
 __device__ __forceinline__ int signed_index(int i, int n) { return i < n / 2 ? i : i - n; }
 
+// float64 accumulators (survey cross sums, projected power, plan-time tables)
 __device__ __forceinline__ void zero_bins(double* sb, int n) {
   for (int i = threadIdx.x; i < n; i += blockDim.x) sb[i] = 0.0;
 }
 
 __device__ __forceinline__ void flush_bins(const double* sb, int n, double* out) {
   for (int i = threadIdx.x; i < n; i += blockDim.x) out[i] = sb[i];
+}
+
+__device__ __forceinline__ void zero_bins(unsigned long long* sb, const BinSpec& b) {
+  for (int i = threadIdx.x; i <= 2 * b.nlds; i += blockDim.x) sb[i] = 0;
+}
+
+// Marker of a sum that met a non-finite term (never a valid sum: those stay
+// below 2^126 in magnitude).
+constexpr unsigned long long kFixNanHi = 0x8000000000000000ull, kFixNanLo = ~0ull;
+
+// One partial row in the result's slot order (the slots of ell = 0 poles are
+// zero: they alias the power sum).  Exact rows hold the 128-bit sums (low
+// words [0, nsum), high words [nsum, 2 nsum)); otherwise float64 values.
+__device__ __forceinline__ void flush_bins(const unsigned long long* sb, const BinSpec& b, int S,
+                                           double* row) {
+  const bool bad = sb[2 * b.nlds] != 0;
+  unsigned long long* words = reinterpret_cast<unsigned long long*>(row);
+  for (int r = threadIdx.x; r < b.nsum; r += blockDim.x) {
+    int slot = -1;
+    if (r < b.nk && b.power_from_2d) {
+      // the exact sum of the k-bin's mu-bin sums (both splits add with carry)
+      unsigned long long lo = 0, hi = 0;
+      for (int j = 0; j < b.nmu; ++j) {
+        const int q = b.off2d_lds + r * b.nmu + j;
+        if (b.fix_hb == 32) {
+          lo += sb[q] & 0xffffffffull;
+          hi += sb[b.nlds + q] + (sb[q] >> 32);
+        } else {
+          const unsigned long long old = lo;
+          lo += sb[q];
+          hi += sb[b.nlds + q] + (lo < old ? 1ull : 0ull);
+        }
+      }
+      if (b.exact) {
+        words[r] = bad ? kFixNanLo : lo;
+        words[b.nsum + r] = bad ? kFixNanHi : hi;
+      } else {
+        row[r] = bad ? __longlong_as_double(0x7ff8000000000000ll)
+                     : fix_words_value(lo, hi, S, b.fix_hb);
+      }
+      continue;
+    }
+    if (r < b.nk) {
+      slot = r;
+    } else if (r < b.nk * (1 + b.npoles)) {
+      const int pi = r / b.nk - 1;
+      if (!((b.zero_mask >> pi) & 1)) {
+        // the accumulated poles keep the order of b.poles
+        int rank = 0;
+        for (int j = 0; j < pi; ++j) rank += ((b.zero_mask >> j) & 1) ? 0 : 1;
+        slot = b.pole_lds[rank] + r % b.nk;
+      }
+    } else {
+      slot = b.off2d_lds + (r - b.off2d);
+    }
+    if (b.exact) {
+      words[r] = bad ? kFixNanLo : (slot >= 0 ? sb[slot] : 0ull);
+      words[b.nsum + r] = bad ? kFixNanHi : (slot >= 0 ? sb[b.nlds + slot] : 0ull);
+    } else {
+      row[r] = bad ? __longlong_as_double(0x7ff8000000000000ll)
+                   : (slot >= 0 ? fix_value(sb, b, slot, S) : 0.0);
+    }
+  }
 }
 
 // At least 4 waves per SIMD (at most 128 VGPRs): two 512-thread workgroups
@@ -131,8 +311,9 @@ __global__ void __launch_bounds__((XCfg<T, N>::THREADS)) __attribute__((amdgpu_w
   // exp(i pi n / N) of the signed index n of i, and the compensation 1 / sinc^p
   __shared__ cpx<T> phx[N];
   __shared__ T sxs[N];
-  extern __shared__ double sb[];
-  zero_bins(sb, b.nsum);
+  extern __shared__ unsigned long long sbx[];
+  zero_bins(sbx, b);
+  const int fs = fix_shift(b);
   const cpx<T>* __restrict__ ph1 = phase + 3 * (N / 2);  // ph1[n] = exp(i pi n / N)
   for (int i = threadIdx.x; i < N; i += blockDim.x) {
     phx[i] = ph1[signed_index(i, N)];
@@ -249,16 +430,17 @@ __global__ void __launch_bounds__((XCfg<T, N>::THREADS)) __attribute__((amdgpu_w
       const int nl2_yz = los == 1 ? ny2 : nz * nz;
       if (j == 0) {
         constexpr int H = N / 2;
-        accumulate<T>(sb, b, nyz2, los == 0 ? 0 : nl2_yz, T(2) * pws[pidx(cc_, 0)]);
-        accumulate<T>(sb, b, H * H + nyz2, los == 0 ? H * H : nl2_yz, T(2) * pws[pidx(cc_, H)]);
+        accumulate<T>(sbx, b, fs, nyz2, los == 0 ? 0 : nl2_yz, T(2) * pws[pidx(cc_, 0)]);
+        accumulate<T>(sbx, b, fs, H * H + nyz2, los == 0 ? H * H : nl2_yz,
+                      T(2) * pws[pidx(cc_, H)]);
       } else {
         const T pw = pws[pidx(cc_, j)] + pws[pidx(cc_, N - j)];
-        accumulate<T>(sb, b, j * j + nyz2, los == 0 ? j * j : nl2_yz, T(2) * pw);
+        accumulate<T>(sbx, b, fs, j * j + nyz2, los == 0 ? j * j : nl2_yz, T(2) * pw);
       }
     }
     __syncthreads();  // the staged power is read before the next tile's FFT reuses the LDS
   }
-  flush_bins(sb, b.nsum, partials + (size_t)blockIdx.x * b.nsum);
+  flush_bins(sbx, b, fs, partials + (size_t)blockIdx.x * 2 * b.nsum);
 }
 
 // One thread per (kx, ky): modes (kx, ky, 0) and (kx, ky, N/2), weight h = 1.
@@ -269,8 +451,9 @@ __global__ void __launch_bounds__(256)
     k_plane_bin(int N, const cpx<T>* __restrict__ za, const cpx<T>* __restrict__ zb, size_t zs,
                 const cpx<T>* __restrict__ phase, const T* __restrict__ sinv, BinSpec b,
                 double* __restrict__ partials, int cross) {
-  extern __shared__ double sb[];
-  zero_bins(sb, b.nsum);
+  extern __shared__ unsigned long long sbx[];
+  zero_bins(sbx, b);
+  const int fs = fix_shift(b);
   __syncthreads();
   const int mask = N - 1;
   const int los = b.los;
@@ -314,11 +497,11 @@ __global__ void __launch_bounds__(256)
       }
       const int n2 = nx * nx + ny * ny + nz * nz;
       const int nl = los == 0 ? nx : (los == 1 ? ny : nz);
-      accumulate<T>(sb, b, n2, nl * nl, pw);
+      accumulate<T>(sbx, b, fs, n2, nl * nl, pw);
     }
   }
   __syncthreads();
-  flush_bins(sb, b.nsum, partials + (size_t)blockIdx.x * b.nsum);
+  flush_bins(sbx, b, fs, partials + (size_t)blockIdx.x * 2 * b.nsum);
 }
 
 // Stand-alone binning of a packed spectrum, columns kz' >= 1 (h = 2): |c|^2,
@@ -331,8 +514,9 @@ template <typename T>
 __global__ void __launch_bounds__(256)
     k_bin_packed(int N, const cpx<T>* __restrict__ cm, const cpx<T>* __restrict__ cm2, BinSpec b,
                  double* __restrict__ partials, int lw, int lbx) {
-  extern __shared__ double sb[];
-  zero_bins(sb, b.nsum);
+  extern __shared__ unsigned long long sbx[];
+  zero_bins(sbx, b);
+  const int fs = fix_shift(b);
   __syncthreads();
   const int NC = N / 2;
   const size_t total = (size_t)N * N * NC;
@@ -359,10 +543,10 @@ __global__ void __launch_bounds__(256)
     const T pw = cc.x * dd.x + cc.y * dd.y;
     const int n2 = nx * nx + ny * ny + nz * nz;
     const int nl = los == 0 ? nx : (los == 1 ? ny : nz);
-    accumulate<T>(sb, b, n2, nl * nl, T(2) * pw);
+    accumulate<T>(sbx, b, fs, n2, nl * nl, T(2) * pw);
   }
   __syncthreads();
-  flush_bins(sb, b.nsum, partials + (size_t)blockIdx.x * b.nsum);
+  flush_bins(sbx, b, fs, partials + (size_t)blockIdx.x * 2 * b.nsum);
 }
 
 // Cross sums of one field with up to four others in one pass: for each
@@ -416,7 +600,8 @@ __global__ void __launch_bounds__(256)
   }
   __syncthreads();
   for (int i = 0; i < nf; ++i)
-    flush_bins(sb + i * b.nsum, b.nsum, partials + i * pstride + (size_t)blockIdx.x * b.nsum);
+    flush_bins(sb + i * b.nsum, b.nsum,
+               partials + i * pstride + (size_t)blockIdx.x * 2 * b.nsum);
 }
 
 // result[s] = sum_g partials[g][src(s)]; the slots of an ell = 0 pole take
@@ -427,36 +612,93 @@ __global__ void __launch_bounds__(256)
 __global__ void __launch_bounds__(1024)
     k_reduce(const double* __restrict__ partials, int ngroups, BinSpec b,
              double* __restrict__ result) {
-  __shared__ double part[16][64];
+  // rows of 2 nsum words; exact rows are 128-bit integers, added exactly (the
+  // order does not matter), float64 rows are added in a fixed order
+  __shared__ unsigned long long part_lo[16][64], part_hi[16][64];
+  __shared__ int part_bad[16][64];
   const int slot_in = threadIdx.x & 63, lane = threadIdx.x >> 6;
   const int s = blockIdx.x * 64 + slot_in;
+  const size_t stride = 2 * (size_t)b.nsum;
+  int src = s;
+  if (s < b.nsum && s >= b.nk && s < b.nk * (1 + b.npoles)) {
+    const int pi = s / b.nk - 1;
+    if ((b.zero_mask >> pi) & 1) src = s % b.nk;
+  }
+  constexpr int AHEAD = 8;
+  if (b.exact) {
+    const unsigned long long* w = reinterpret_cast<const unsigned long long*>(partials);
+    unsigned long long lo = 0, hi = 0;
+    int bad = 0;
+    if (s < b.nsum) {
+      for (int g0 = lane; g0 < ngroups; g0 += 16 * AHEAD) {
+        unsigned long long vl[AHEAD], vh[AHEAD];
+#pragma unroll
+        for (int k = 0; k < AHEAD; ++k) {
+          const int g = g0 + 16 * k;
+          vl[k] = g < ngroups ? w[(size_t)g * stride + src] : 0ull;
+          vh[k] = g < ngroups ? w[(size_t)g * stride + b.nsum + src] : 0ull;
+        }
+#pragma unroll
+        for (int k = 0; k < AHEAD; ++k) {
+          if (vh[k] == kFixNanHi && vl[k] == kFixNanLo) bad = 1;
+          if (b.fix_hb == 32) {
+            // low words count below 2^64; move their upper half to the high word
+            lo += vl[k] & 0xffffffffull;
+            hi += vh[k] + (vl[k] >> 32);
+          } else {
+            const unsigned long long old = lo;
+            lo += vl[k];
+            hi += vh[k] + (lo < old ? 1ull : 0ull);
+          }
+        }
+      }
+    }
+    part_lo[lane][slot_in] = lo;
+    part_hi[lane][slot_in] = hi;
+    part_bad[lane][slot_in] = bad;
+    __syncthreads();
+    if (lane == 0 && s < b.nsum) {
+      unsigned long long tl = 0, th = 0;
+      int tb = 0;
+#pragma unroll
+      for (int l = 0; l < 16; ++l) {
+        if (b.fix_hb == 32) {
+          tl += part_lo[l][slot_in] & 0xffffffffull;
+          th += part_hi[l][slot_in] + (part_lo[l][slot_in] >> 32);
+        } else {
+          const unsigned long long old = tl;
+          tl += part_lo[l][slot_in];
+          th += part_hi[l][slot_in] + (tl < old ? 1ull : 0ull);
+        }
+        tb |= part_bad[l][slot_in];
+      }
+      result[s] = tb ? __longlong_as_double(0x7ff8000000000000ll)
+                     : fix_words_value(tl, th, fix_shift(b), b.fix_hb);
+    }
+    return;
+  }
   double acc = 0.0;
   if (s < b.nsum) {
-    int src = s;
-    if (s >= b.nk && s < b.nk * (1 + b.npoles)) {
-      const int pi = s / b.nk - 1;
-      if ((b.zero_mask >> pi) & 1) src = s % b.nk;
-    }
     // eight rows' loads in flight, then added in the same order (g = lane,
     // lane + 16, ...); a row past the end adds an exact zero
-    constexpr int AHEAD = 8;
     for (int g0 = lane; g0 < ngroups; g0 += 16 * AHEAD) {
       double v[AHEAD];
 #pragma unroll
       for (int k = 0; k < AHEAD; ++k) {
         const int g = g0 + 16 * k;
-        v[k] = g < ngroups ? partials[(size_t)g * b.nsum + src] : 0.0;
+        v[k] = g < ngroups ? partials[(size_t)g * stride + src] : 0.0;
       }
 #pragma unroll
       for (int k = 0; k < AHEAD; ++k) acc += v[k];
     }
   }
-  part[lane][slot_in] = acc;
+  double* part = reinterpret_cast<double*>(&part_lo[0][0]);
+  part[lane * 64 + slot_in] = acc;
   __syncthreads();
   if (lane == 0 && s < b.nsum) {
     double tot = 0.0;
 #pragma unroll
-    for (int l = 0; l < 16; ++l) tot += part[l][slot_in];
+    for (int l = 0; l < 16; ++l) tot += part[l * 64 + slot_in];
     result[s] = tot;
   }
 }
@@ -547,7 +789,7 @@ __global__ void __launch_bounds__(256)
     atomicAdd(&sb[2 * nk + k], sqrt((double)n2));
   }
   __syncthreads();
-  flush_bins(sb, 3 * nk, partials + (size_t)blockIdx.x * 3 * nk);
+  flush_bins(sb, 3 * nk, partials + (size_t)blockIdx.x * 2 * 3 * nk);  // rows of 2 nsum words
 }
 
 // Sums the mode-table partial rows; integer slots are summed as integers.
@@ -650,11 +892,11 @@ __global__ void __launch_bounds__(256)
 // + nsum float64 bins) and from the waves (at most 128 VGPRs: 4 waves per
 // SIMD, 16 per CU).
 template <typename T, int N>
-static int xpass_groups_t(int nsum) {
+static int xpass_groups_t(size_t bin_bytes) {
   using Cf = XCfg<T, N>;
   const long tiles = (long)N * Cf::CHUNKS;
   const size_t lds = ((size_t)Cf::LDS_ELEMS + stage_table_size<N, Cf::E>() + 1 + N) *
-                         sizeof(cpx<T>) + (size_t)N * sizeof(T) + (size_t)nsum * sizeof(double);
+                         sizeof(cpx<T>) + (size_t)N * sizeof(T) + bin_bytes;
   long by_lds = (long)(kLdsBytesPerGroup / (lds > 0 ? lds : 1));
   const long waves = (Cf::THREADS + 63) / 64;
   long by_waves = 16 / (waves > 0 ? waves : 1);
@@ -664,9 +906,9 @@ static int xpass_groups_t(int nsum) {
   return (int)(tiles < groups ? tiles : groups);
 }
 
-int xpass_bin_groups(int dtype, int nmesh, int nsum) {
+int xpass_bin_groups(int dtype, int nmesh, size_t bin_bytes) {
 #define PK_T(NN) \
-  case NN: return dtype == PK_F32 ? xpass_groups_t<float, NN>(nsum) : xpass_groups_t<double, NN>(nsum);
+  case NN: return dtype == PK_F32 ? xpass_groups_t<float, NN>(bin_bytes) : xpass_groups_t<double, NN>(bin_bytes);
   switch (nmesh) {
     PK_T(8) PK_T(16) PK_T(32) PK_T(64) PK_T(128) PK_T(256) PK_T(512) PK_T(1024) PK_T(2048)
     default: return 0;
@@ -702,14 +944,14 @@ int mode_table_groups(int nmesh) {
   return (int)(g < 1024 ? g : 1024);
 }
 
-size_t bin_lds_bytes(const BinSpec& b) { return (size_t)b.nsum * sizeof(double); }
+size_t bin_lds_bytes(const BinSpec& b) { return ((size_t)b.nlds * 2 + 1) * sizeof(unsigned long long); }
 
 template <typename T, int N>
 static hipError_t xpass_bin_t(const void* mesh_a, const void* mesh_b, const MeshTables& t,
                               int order, int compensated, const BinSpec& b, double* partials,
                               void* side_a, void* side_b, hipStream_t s) {
   using Cf = XCfg<T, N>;
-  const int groups = xpass_bin_groups(sizeof(T) == 4 ? PK_F32 : PK_F64, N, b.nsum);
+  const int groups = xpass_bin_groups(sizeof(T) == 4 ? PK_F32 : PK_F64, N, bin_lds_bytes(b));
   const T* sinv = compensated ? static_cast<const T*>(t.sinc_inv) + (size_t)(order - 2) * N
                               : nullptr;
   hipLaunchKernelGGL((k_xpass_bin<T, N>), dim3(groups), dim3(Cf::THREADS), bin_lds_bytes(b), s,
@@ -849,6 +1091,42 @@ hipError_t launch_bin_projected(int dtype, int nmesh, const void* cmesh, int kee
   else
     hipLaunchKernelGGL(k_bin_projected<double>, dim3(g), dim3(256), lds, s, nmesh,
                        static_cast<const cpx<double>*>(cmesh), keep, b, partials);
+  return hipGetLastError();
+}
+
+// The largest |component| of one or two arrays of reals (count each): the
+// bound of the terms that a binning of spectra without weight sums adds
+// (|c|^2 <= 2 max^2).  out: one float64 (as its bits; non-negative doubles
+// order like their bit patterns), zeroed beforehand.  NaN components are
+// skipped here; the binning flags them.
+template <typename T>
+__global__ void __launch_bounds__(256)
+    k_absmax(const T* __restrict__ a, const T* __restrict__ b, size_t count,
+             unsigned long long* __restrict__ out) {
+  double mx = 0.0;
+  for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < count; i += (size_t)gridDim.x * 256) {
+    mx = fmax(mx, fabs((double)a[i]));
+    if (b) mx = fmax(mx, fabs((double)b[i]));
+  }
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off, 64));
+  if ((threadIdx.x & 63) == 0) atomicMax(out, (unsigned long long)__double_as_longlong(mx));
+}
+
+hipError_t launch_absmax(int dtype, const void* a, const void* b, size_t count, double* out,
+                         hipStream_t s) {
+  hipError_t e = launch_fill_zero(out, sizeof(double), s);
+  if (e != hipSuccess) return e;
+  size_t g = (count + 255) / 256;
+  if (g > 1024) g = 1024;
+  if (g < 1) g = 1;
+  auto* o = reinterpret_cast<unsigned long long*>(out);
+  if (dtype == PK_F32)
+    hipLaunchKernelGGL(k_absmax<float>, dim3((unsigned)g), dim3(256), 0, s,
+                       static_cast<const float*>(a), static_cast<const float*>(b), count, o);
+  else
+    hipLaunchKernelGGL(k_absmax<double>, dim3((unsigned)g), dim3(256), 0, s,
+                       static_cast<const double*>(a), static_cast<const double*>(b), count, o);
   return hipGetLastError();
 }
 

@@ -52,6 +52,29 @@ struct BinSpec {
   int pole_slot[4] = {0, 0, 0, 0};
   int off2d = -1;       // first (k, mu) slot, -1 if none
   int nsum = 0;         // number of sum slots (weight slots excluded)
+  // LDS accumulators: the sums that are accumulated (power, poles with
+  // ell > 0, (k, mu) bins) in 128-bit fixed point, two 64-bit words each.
+  int nlds = 0;
+  int pole_lds[4] = {0, 0, 0, 0};  // first LDS slot of accumulated pole i
+  int off2d_lds = -1;
+  // With (k, mu) bins the power sum of a k-bin is the exact sum of its mu-bin
+  // sums: it is formed when the partial row is written, not accumulated.
+  int power_from_2d = 0;
+  // Fixed-point scale: every sum and every term is bounded in magnitude by
+  // B = bound_scale * (bound_dev ? *bound_dev (squared if bound_sq) : 1),
+  // read on the device; units of 2^-S with B 2^S < 2^126.
+  double bound_scale = 0.0;
+  const double* bound_dev = nullptr;
+  int bound_sq = 0;
+  // Word split of the fixed point: 64 = a 128-bit two's complement integer
+  // (low word, high word; the carry of the low word taken from a returning
+  // atomic), 32 = low 32 bits in the first word and the rest (signed) in the
+  // second, both added without return, for sums below 2^95.
+  int fix_hb = 64;
+  // Partial rows (one per workgroup, 2 nsum 64-bit words each) hold the exact
+  // sums as 128-bit integers (low words, then high words) when set, else
+  // float64 values in the first nsum words; k_reduce reads them accordingly.
+  int exact = 1;
   double kmin_f = 0.0;
   double dk_f = 1.0;
   const double* e2 = nullptr;  // device, nk + 1
@@ -104,7 +127,7 @@ hipError_t launch_fft_y_relayout(int dtype, int nmesh, const void* src, void* ds
                                  hipStream_t s);
 
 // Workgroup count of the persistent binning kernels for a mesh size.
-int xpass_bin_groups(int dtype, int nmesh, int nsum);
+int xpass_bin_groups(int dtype, int nmesh, size_t bin_bytes);
 int plane_bin_groups(int nmesh);
 size_t bin_lds_bytes(const BinSpec& b);
 // Static LDS bytes of the fused x-pass + binning kernel (0: unsupported size).
@@ -135,6 +158,10 @@ hipError_t launch_plane_bin(int dtype, int nmesh, const void* za, const void* zb
 // e2[i] = (kmin + i dk)^2 for i = 0 .. nk, each product and sum rounded on
 // its own: the same values as the host-built edge table.
 hipError_t launch_edges_squared(double kmin, double dk, int nk, double* e2, hipStream_t s);
+// *out = max |x| over count reals of a (and of b if not NULL); out is a device
+// float64 that the launch zeroes first (a fill kernel, no memset).
+hipError_t launch_absmax(int dtype, const void* a, const void* b, size_t count, double* out,
+                         hipStream_t s);
 hipError_t launch_reduce(const double* partials, int ngroups, const BinSpec& b, double* result,
                          hipStream_t s);
 // Projected power: sums [|c|^2, counts, |n|] x nk over the kept axes' grid.

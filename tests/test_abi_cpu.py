@@ -125,11 +125,13 @@ def test_null_context_and_create_errors():
 
 
 def test_bin_slots_must_fit_lds_beside_the_fused_xpass(vctx):
-    """About 8192 float64 bin slots fit the workgroup's LDS beside the float32
-    x-pass at N = 1024, but not beside the float64 one (its line buffers and
-    tables are twice as large)."""
+    """The exact bin sums take 16 bytes of LDS each (128-bit fixed point; the
+    ell = 0 pole aliases the power sum and takes none).  Beside the float32
+    x-pass at N = 1024 (90 KB of line buffers and tables) about 4600 sums fit
+    the workgroup's 160 KB, beside the float64 one (108 KB) about 3300: 1000
+    k-bins with ell = 0, 2, 4, 6 (4000 accumulated sums) fit the first only."""
     lib, h = vctx
-    b = _lib.bin_desc(1638, 0.0, 1.0, 0, (0, 2, 4, 6), 2)  # 1638 * (1 + 4) = 8190 slots
+    b = _lib.bin_desc(1000, 0.0, 1.0, 0, (0, 2, 4, 6), 2)
     res = ctypes.c_void_p(1)
     for dtype, want in (("f4", _lib.PK_EDEVICE), ("f8", _lib.PK_EUNSUPPORTED)):
         m = _lib.mesh_desc(1024, 1000.0, "cic", False, True, dtype)
