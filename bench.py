@@ -302,6 +302,12 @@ def main():
                     help="number of mocks of the batch-mocks workload")
     ap.add_argument("--lanes", type=int, default=BATCH["lanes"],
                     help="concurrent lanes of the batch-mocks workload")
+    ap.add_argument("--graph", action="store_true",
+                    help="batch-mocks: capture the whole batch into one HIP graph and time its "
+                         "replays instead of enqueueing it call by call")
+    ap.add_argument("--batch-meshes", default=None,
+                    help="batch-mocks: keep only the mocks on these mesh sizes (comma list), to "
+                         "time parts of the batch")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--shuffle", action="store_true",
                     help="permute the catalog (seeded) before timing: a catalog in no "
@@ -468,9 +474,12 @@ def run_batch(args):
 
     dev = torch.device("cuda:0")
     sizes = synth.mock_batch_sizes(args.mocks, BATCH["seed"], BATCH["meshes"])
+    keep = None if not args.batch_meshes else {int(v) for v in args.batch_meshes.split(",")}
     t0 = time.perf_counter()
     pos, ms, bs, res = [], [], [], []
     for i, (target, n) in enumerate(sizes):
+        if keep is not None and n not in keep:
+            continue
         p = synth.lognormal_catalog_device(n, BATCH["box"], synth.pk_lognormal_c2, target / n ** 3,
                                            seed=BATCH["seed"] + i, device=dev)
         pos.append(p)
@@ -481,15 +490,31 @@ def run_batch(args):
     npart = [int(p.shape[0]) for p in pos]
     log(f"batch-mocks: {len(pos)} mocks, {sum(npart)} particles drawn on the device in "
         f"{time.perf_counter() - t0:.1f} s")
-    ctx = _lib.Context(0)
+    # a stream of our own: graph capture is refused on the legacy default stream
+    stream = torch.cuda.Stream(device=dev)
+    torch.cuda.set_stream(stream)
+    ctx = _lib.Context(0, stream)
     ctx.pk_ctx_set_lanes(args.lanes)
     need = max(_lib.workspace_bytes(m, b, n) for m, b, n in zip(ms, bs, npart))
     lane_ws = [torch.empty(need, dtype=torch.uint8, device=dev) for _ in range(args.lanes)]
     log(f"{args.lanes} lanes, {need / 2**30:.2f} GiB of workspace each")
 
-    def step():
+    def eager_step():
         ctx.pk_fftpower_batch(ms, bs, pos, [None] * len(pos), npart, lane_ws, res)
         return [ctx.pk_result_to_host(m, b, r) for m, b, r in zip(ms, bs, res)]
+
+    step = eager_step
+    graph = None
+    if args.graph:
+        eager_step()  # tables built
+        t_cap = time.perf_counter()
+        graph = ctx.pk_fftpower_batch_graph(ms, bs, pos, [None] * len(pos), npart, lane_ws, res)
+        log(f"batch captured into one HIP graph of {graph.nodes} nodes in "
+            f"{1e3 * (time.perf_counter() - t_cap):.1f} ms")
+
+        def step():
+            graph.launch()
+            return [ctx.pk_result_to_host(m, b, r) for m, b, r in zip(ms, bs, res)]
 
     for _ in range(args.warmup):
         step()
@@ -521,7 +546,7 @@ def run_batch(args):
         del ws8, p8
     line = {
         "metric": "mocks/s (FFTPower of many uneven log-normal mocks)",
-        "value": args.mocks * 1e3 / ms_per_step,
+        "value": len(pos) * 1e3 / ms_per_step,
         "unit": "mocks/s",
         "n_gpus": 1,
         "steps": args.steps,
@@ -532,7 +557,9 @@ def run_batch(args):
         "vs_baseline": None,
         "dtype": "f32 (paint, FFT) + f64 (bin sums)",
         "data": "synthetic (device-drawn log-normal mocks)",
-        "config": {"workload": "batch-mocks", "mocks": args.mocks, "lanes": args.lanes,
+        "config": {"workload": "batch-mocks", "mocks": len(pos), "lanes": args.lanes,
+                   "graph": bool(args.graph),
+                   "batch_meshes": sorted(keep) if keep else list(BATCH["meshes"]),
                    "meshes": list(BATCH["meshes"]), "npart_total": sum(npart),
                    "window": BATCH["window"], "interlaced": True,
                    "poles": list(BATCH["poles"])},

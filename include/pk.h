@@ -350,6 +350,33 @@ pk_status pk_fftpower_batch(pk_ctx *ctx, int count, const pk_mesh_desc *m,
                             void *const *lane_workspace, size_t lane_workspace_bytes,
                             double *const *result_dev);
 
+/* ---- Graph-captured batches (repeated analyses, Sec. 6: the same batch
+ * of mocks run many times).  pk_fftpower_batch_graph records the whole
+ * launch sequence of a batch -- bucketing, fused paint + z-FFT, y-pass,
+ * fused x-pass + binning, reduce for every request, spread over the lanes as
+ * pk_fftpower_batch spreads them (or one after another on the context stream
+ * in lane_workspace[0] when the context has no lanes) -- into one HIP graph,
+ * instantiated once; pk_graph_launch replays it on the context stream with
+ * one host call.  The graph keeps the addresses it was built with: pos,
+ * weight, n, the workspaces and result_dev must stay allocated, and a replay
+ * reads the positions as they are at that time and overwrites the results.
+ * Every table the batch needs is built (and synchronised) before the
+ * capture; nothing is allocated while capturing or replaying.  The context
+ * stream must be a stream created by the caller (not the legacy default
+ * stream) and stage timing must be off.  A replay is ordered on the context
+ * stream like any call; pk_result_to_host reads the results afterwards.
+ * Errors: as pk_fftpower_batch (count >= 1), PK_EINVAL if timing is on,
+ * PK_EDEVICE (capture refused, e.g. on the legacy default stream). */
+typedef struct pk_graph pk_graph;
+pk_status pk_fftpower_batch_graph(pk_ctx *ctx, int count, const pk_mesh_desc *m,
+                                  const pk_bin_desc *b, const void *const *pos,
+                                  const void *const *weight, const int64_t *n,
+                                  void *const *lane_workspace, size_t lane_workspace_bytes,
+                                  double *const *result_dev, pk_graph **graph);
+pk_status pk_graph_launch(pk_ctx *ctx, pk_graph *graph);
+size_t pk_graph_nodes(const pk_graph *graph); /* kernel and dependency nodes; 0 for NULL */
+void pk_graph_destroy(pk_graph *graph);         /* NULL is a no-op */
+
 /* pk_fftpower with per-particle field values (Sec. 3.3.1: the painted field
  * is [1 + delta'] V, delta' the weighted overdensity): each particle paints
  * w V; the normalisation stays sum w, and the second weight slot holds

@@ -29,6 +29,7 @@ EXPORTS = (
     "pk_bin_projected", "pk_projected_to_host", "pk_convolved_doubles",
     "pk_convolved_workspace_bytes", "pk_convolved_power", "pk_convolved_to_host", "pk_fft_c2r",
     "pk_shape_table_len", "pk_shape_spectrum", "pk_num_kbins", "pk_bin_power_noalloc",
+    "pk_fftpower_batch_graph", "pk_graph_launch", "pk_graph_nodes", "pk_graph_destroy",
 )
 PK_MAX_LANES = 64
 PK_DEVICE_NONE = -1
@@ -138,6 +139,13 @@ def load(path=None):
             "pk_fftpower_batch": (i32, [vp, ctypes.c_int, md, bd, ctypes.POINTER(vp),
                                         ctypes.POINTER(vp), ctypes.POINTER(i64),
                                         ctypes.POINTER(vp), sz, ctypes.POINTER(vp)]),
+            "pk_fftpower_batch_graph": (i32, [vp, ctypes.c_int, md, bd, ctypes.POINTER(vp),
+                                              ctypes.POINTER(vp), ctypes.POINTER(i64),
+                                              ctypes.POINTER(vp), sz, ctypes.POINTER(vp),
+                                              ctypes.POINTER(vp)]),
+            "pk_graph_launch": (i32, [vp, vp]),
+            "pk_graph_nodes": (sz, [vp]),
+            "pk_graph_destroy": (None, [vp]),
             "pk_convolved_doubles": (sz, [bd]),
             "pk_convolved_workspace_bytes": (sz, [md, bd, i64, i64]),
             "pk_convolved_power": (i32, [vp, md, bd, ctypes.POINTER(dbl), vp, vp, i64, vp, vp,
@@ -244,6 +252,32 @@ def device_arg(t, name, device, dtype=None, numel=0, nbytes=0, optional=False):
         raise ValueError(f"{name} holds {t.numel() * t.element_size()} bytes, {nbytes} are "
                          "needed")
     return ctypes.c_void_p(t.data_ptr())
+
+
+class Graph:
+    """A captured batch (pk_fftpower_batch_graph): launch() replays it on the
+    context's stream.  It holds references to the arrays it was built with."""
+
+    def __init__(self, ctx, handle, keep):
+        self.ctx, self.handle, self._keep = ctx, handle, keep
+
+    @property
+    def nodes(self):
+        return int(self.ctx.lib.pk_graph_nodes(self.handle))
+
+    def launch(self):
+        self.ctx._check(self.ctx.lib.pk_graph_launch(self.ctx.handle, self.handle))
+
+    def close(self):
+        if getattr(self, "handle", None):
+            self.ctx.lib.pk_graph_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class Context:
@@ -481,6 +515,21 @@ class Context:
         """ms, bs: sequences of MeshDesc / BinDesc; pos, weights (None entries
         allowed), results: sequences of device tensors; lane_workspaces: one
         device tensor per lane, all of the same size."""
+        self._check(self.lib.pk_fftpower_batch(
+            self.handle, *self._batch_args(ms, bs, pos, weights, ns, lane_workspaces, results)))
+
+    def pk_fftpower_batch_graph(self, ms, bs, pos, weights, ns, lane_workspaces, results):
+        """The batch captured into a HIP graph (pk_fftpower_batch_graph); the
+        returned Graph replays it with launch().  Every tensor passed must
+        stay alive while the graph is used."""
+        g = ctypes.c_void_p()
+        args = self._batch_args(ms, bs, pos, weights, ns, lane_workspaces, results,
+                                need_lanes=False)
+        self._check(self.lib.pk_fftpower_batch_graph(self.handle, *args, ctypes.byref(g)))
+        return Graph(self, g, keep=(args, list(pos), list(weights), list(lane_workspaces),
+                                    list(results)))
+
+    def _batch_args(self, ms, bs, pos, weights, ns, lane_workspaces, results, need_lanes=True):
         count = len(ms)
         if not (len(bs) == len(pos) == len(weights) == len(ns) == len(results) == count):
             raise ValueError("batch arguments must all have one entry per request")
@@ -506,8 +555,7 @@ class Context:
             return (vp * max(len(ptrs), 1))(*[None if q is None else q.value for q in ptrs])
 
         narr = (ctypes.c_int64 * max(count, 1))(*[int(n) for n in ns])
-        self._check(self.lib.pk_fftpower_batch(
-            self.handle, count, marr, barr, arr(pp), arr(wp), narr, arr(lw), nbytes, arr(rp)))
+        return (count, marr, barr, arr(pp), arr(wp), narr, arr(lw), nbytes, arr(rp))
 
     # ---- finalisation
 

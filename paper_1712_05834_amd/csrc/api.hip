@@ -1023,33 +1023,55 @@ pk_status pk_lane_wait(pk_ctx* ctx, int lane) {
   return PK_OK;
 }
 
-pk_status pk_fftpower_batch(pk_ctx* ctx, int count, const pk_mesh_desc* m, const pk_bin_desc* b,
-                            const void* const* pos, const void* const* weight, const int64_t* n,
-                            void* const* lane_workspace, size_t lane_workspace_bytes,
-                            double* const* result_dev) {
-  if (!ctx) return PK_EINVAL;
+}  // extern "C"
+
+namespace {
+
+// Validation and plan-time tables of a batch (before any work is enqueued).
+pk_status prepare_batch(pk_ctx* ctx, int count, const pk_mesh_desc* m, const pk_bin_desc* b,
+                        const void* const* pos, const int64_t* n, void* const* lane_workspace,
+                        size_t lane_workspace_bytes, double* const* result_dev, int nworkspaces) {
   if (count < 0) return fail(ctx, PK_EINVAL, "count must be >= 0");
   if (count > 0 && (!m || !b || !pos || !n || !result_dev))
     return fail(ctx, PK_EINVAL, "request arrays are NULL");
-  const int nl = (int)ctx->lanes.size();
-  if (nl < 1) return fail(ctx, PK_EINVAL, "no lanes: call pk_ctx_set_lanes first");
   if (!lane_workspace) return fail(ctx, PK_EINVAL, "lane_workspace is NULL");
-  for (int i = 0; i < nl; ++i)
+  for (int i = 0; i < nworkspaces; ++i)
     if (!lane_workspace[i]) return fail(ctx, PK_EINVAL, "a lane workspace is NULL");
   for (int i = 0; i < count; ++i)
     if (pk_status st = check_fftpower(ctx, &m[i], &b[i], pos[i], n[i], lane_workspace[0],
                                       lane_workspace_bytes, result_dev[i]))
       return st;
-  if (count == 0) return PK_OK;
-  DeviceGuard g(ctx->device);
-  // every table first, so that no lane waits behind a table build later
+  // every table first, so that no lane waits behind a table build later (and
+  // nothing is allocated while a graph is captured)
   for (int i = 0; i < count; ++i) {
     const MeshTables* t = nullptr;
     BinSpec spec;
     if (pk_status st = prepare_tables(ctx, &m[i], &b[i], &t, &spec)) return st;
   }
-  // largest requests first, each to the lane with the least queued work
-  // (estimated as the mesh cells plus the particles it has to process)
+  return PK_OK;
+}
+
+// Enqueues a prepared batch: with lanes, largest requests first, each to the
+// lane with the least queued work (estimated as the mesh cells plus the
+// particles it has to process), and the context stream waits for every lane;
+// without lanes, one after another on the context stream in one workspace.
+pk_status schedule_batch(pk_ctx* ctx, int count, const pk_mesh_desc* m, const pk_bin_desc* b,
+                         const void* const* pos, const void* const* weight, const int64_t* n,
+                         void* const* lane_workspace, double* const* result_dev) {
+  const int nl = (int)ctx->lanes.size();
+  if (nl == 0) {
+    for (int i = 0; i < count; ++i) {
+      const MeshTables* t = nullptr;
+      BinSpec spec;
+      if (pk_status st = prepare_tables(ctx, &m[i], &b[i], &t, &spec)) return st;
+      const hipError_t e =
+          enqueue_fftpower(ctx, ctx->stream, &m[i], spec, t, pos[i], weight ? weight[i] : nullptr,
+                           nullptr, n[i], lane_workspace[0], layout_of(&m[i], &b[i], n[i]),
+                           result_dev[i]);
+      if (e != hipSuccess) return dev_fail(ctx, e, "batch");
+    }
+    return PK_OK;
+  }
   std::vector<int> order(count);
   std::vector<double> cost(count);
   for (int i = 0; i < count; ++i) {
@@ -1069,9 +1091,98 @@ pk_status pk_fftpower_batch(pk_ctx* ctx, int count, const pk_mesh_desc* m, const
   // the context stream continues after every lane
   for (int i = 0; i < nl; ++i) {
     const hipError_t e = hipStreamWaitEvent(ctx->stream, ctx->lanes[i].done, 0);
-    if (e != hipSuccess) return dev_fail(ctx, e, "pk_fftpower_batch");
+    if (e != hipSuccess) return dev_fail(ctx, e, "batch");
   }
   return PK_OK;
+}
+
+}  // namespace
+
+struct pk_graph {
+  int device = 0;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  size_t nodes = 0;
+};
+
+extern "C" {
+
+pk_status pk_fftpower_batch(pk_ctx* ctx, int count, const pk_mesh_desc* m, const pk_bin_desc* b,
+                            const void* const* pos, const void* const* weight, const int64_t* n,
+                            void* const* lane_workspace, size_t lane_workspace_bytes,
+                            double* const* result_dev) {
+  if (!ctx) return PK_EINVAL;
+  const int nl = (int)ctx->lanes.size();
+  if (nl < 1) return fail(ctx, PK_EINVAL, "no lanes: call pk_ctx_set_lanes first");
+  if (pk_status st = prepare_batch(ctx, count, m, b, pos, n, lane_workspace, lane_workspace_bytes,
+                                   result_dev, nl))
+    return st;
+  if (count == 0) return PK_OK;
+  DeviceGuard g(ctx->device);
+  return schedule_batch(ctx, count, m, b, pos, weight, n, lane_workspace, result_dev);
+}
+
+pk_status pk_fftpower_batch_graph(pk_ctx* ctx, int count, const pk_mesh_desc* m,
+                                  const pk_bin_desc* b, const void* const* pos,
+                                  const void* const* weight, const int64_t* n,
+                                  void* const* lane_workspace, size_t lane_workspace_bytes,
+                                  double* const* result_dev, pk_graph** out) {
+  if (!ctx) return PK_EINVAL;
+  if (!out) return fail(ctx, PK_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (count < 1) return fail(ctx, PK_EINVAL, "a graph needs at least one request");
+  if (ctx->timing) return fail(ctx, PK_EINVAL, "stage timing records events: disable it first");
+  const int nl = (int)ctx->lanes.size();
+  if (pk_status st = prepare_batch(ctx, count, m, b, pos, n, lane_workspace, lane_workspace_bytes,
+                                   result_dev, nl > 0 ? nl : 1))
+    return st;
+  DeviceGuard g(ctx->device);
+  // the tables were uploaded on the context stream: done before the capture
+  hipError_t e = hipStreamSynchronize(ctx->stream);
+  if (e != hipSuccess) return dev_fail(ctx, e, "pk_fftpower_batch_graph");
+  std::unique_ptr<pk_graph> gr(new (std::nothrow) pk_graph());
+  if (!gr) return fail(ctx, PK_ENOMEM, "host allocation of the graph");
+  gr->device = ctx->device;
+  e = hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal);
+  if (e != hipSuccess) return dev_fail(ctx, e, "hipStreamBeginCapture");
+  const pk_status st = schedule_batch(ctx, count, m, b, pos, weight, n, lane_workspace, result_dev);
+  hipGraph_t graph = nullptr;
+  e = hipStreamEndCapture(ctx->stream, &graph);
+  if (st != PK_OK) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return st;
+  }
+  if (e != hipSuccess) return dev_fail(ctx, e, "hipStreamEndCapture");
+  gr->graph = graph;
+  e = hipGraphGetNodes(graph, nullptr, &gr->nodes);
+  if (e == hipSuccess) e = hipGraphInstantiate(&gr->exec, graph, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    (void)hipGraphDestroy(graph);
+    return dev_fail(ctx, e, "hipGraphInstantiate");
+  }
+  *out = gr.release();
+  return PK_OK;
+}
+
+pk_status pk_graph_launch(pk_ctx* ctx, pk_graph* graph) {
+  if (!ctx) return PK_EINVAL;
+  if (!graph || !graph->exec) return fail(ctx, PK_EINVAL, "graph is NULL");
+  if (ctx->device == PK_DEVICE_NONE) return fail(ctx, PK_EDEVICE, "validation-only context");
+  if (graph->device != ctx->device) return fail(ctx, PK_EINVAL, "graph of another device");
+  DeviceGuard g(ctx->device);
+  const hipError_t e = hipGraphLaunch(graph->exec, ctx->stream);
+  if (e != hipSuccess) return dev_fail(ctx, e, "hipGraphLaunch");
+  return PK_OK;
+}
+
+size_t pk_graph_nodes(const pk_graph* graph) { return graph ? graph->nodes : 0; }
+
+void pk_graph_destroy(pk_graph* graph) {
+  if (!graph) return;
+  DeviceGuard g(graph->device);
+  if (graph->exec) (void)hipGraphExecDestroy(graph->exec);
+  if (graph->graph) (void)hipGraphDestroy(graph->graph);
+  delete graph;
 }
 
 pk_status pk_result_to_host(pk_ctx* ctx, const pk_mesh_desc* m, const pk_bin_desc* b,
