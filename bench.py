@@ -302,6 +302,9 @@ def main():
                     help="number of mocks of the batch-mocks workload")
     ap.add_argument("--lanes", type=int, default=BATCH["lanes"],
                     help="concurrent lanes of the batch-mocks workload")
+    ap.add_argument("--autotune", action="store_true",
+                    help="tune pk_fftpower's launch choices on the first warm-up call (the "
+                         "line then reports the chosen settings)")
     ap.add_argument("--graph", action="store_true",
                     help="batch-mocks: capture the whole batch into one HIP graph and time its "
                          "replays instead of enqueueing it call by call")
@@ -375,9 +378,13 @@ def main():
         ctx.pk_fftpower(m, b, pos, None, npart, ws, res)
         return ctx.pk_result_to_host(m, b, res)
 
-    for _ in range(args.warmup):
+    if args.autotune:
+        ctx.pk_ctx_set_autotune(1)
+    for _ in range(max(args.warmup, 1 if args.autotune else 0)):
         step()
     torch.cuda.synchronize()
+    if args.autotune:
+        log(f"tuned: {ctx.tune_table()}")
     log(f"warmup done ({args.warmup} steps); timing {args.steps} steps")
 
     ctx.pk_ctx_set_timing(True)
@@ -427,6 +434,7 @@ def main():
             "poles": list(w["poles"]), "los": "z",
             "order": "shuffled" if args.shuffle else "as generated",
         },
+        "tuned": ctx.tune_table() if args.autotune else None,
         "mparticles_per_s_painted": npart / (paint_ms * 1e-3) / 1e6 if paint_ms > 0 else None,
         "stage_ms": mean_ms,
         "end_to_end_hbm_frac": total_bytes / (ms_per_step * 1e-3) / (HBM_PEAK_GBS * 1e9),

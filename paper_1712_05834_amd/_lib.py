@@ -30,6 +30,7 @@ EXPORTS = (
     "pk_convolved_workspace_bytes", "pk_convolved_power", "pk_convolved_to_host", "pk_fft_c2r",
     "pk_shape_table_len", "pk_shape_spectrum", "pk_num_kbins", "pk_bin_power_noalloc",
     "pk_fftpower_batch_graph", "pk_graph_launch", "pk_graph_nodes", "pk_graph_destroy",
+    "pk_ctx_set_autotune", "pk_tune_count", "pk_tune_get", "pk_tune_put",
 )
 PK_MAX_LANES = 64
 PK_DEVICE_NONE = -1
@@ -62,6 +63,14 @@ class BinDesc(ctypes.Structure):
         ("npoles", ctypes.c_int32),
         ("poles", ctypes.c_int32 * 4),
         ("los", ctypes.c_int32),
+    ]
+
+
+class TuneEntry(ctypes.Structure):
+    _fields_ = [
+        ("nmesh", ctypes.c_int32), ("dtype", ctypes.c_int32), ("window", ctypes.c_int32),
+        ("interlaced", ctypes.c_int32), ("density", ctypes.c_int32), ("split", ctypes.c_int32),
+        ("rotate", ctypes.c_int32), ("xpass_per_cu", ctypes.c_int32), ("ms", ctypes.c_double),
     ]
 
 
@@ -144,6 +153,10 @@ def load(path=None):
                                               ctypes.POINTER(vp), sz, ctypes.POINTER(vp),
                                               ctypes.POINTER(vp)]),
             "pk_graph_launch": (i32, [vp, vp]),
+            "pk_ctx_set_autotune": (i32, [vp, ctypes.c_int]),
+            "pk_tune_count": (ctypes.c_int, [vp]),
+            "pk_tune_get": (i32, [vp, ctypes.c_int, ctypes.POINTER(TuneEntry)]),
+            "pk_tune_put": (i32, [vp, ctypes.POINTER(TuneEntry)]),
             "pk_graph_nodes": (sz, [vp]),
             "pk_graph_destroy": (None, [vp]),
             "pk_convolved_doubles": (sz, [bd]),
@@ -349,6 +362,26 @@ class Context:
     @staticmethod
     def _nbytes(t):
         return 0 if t is None else t.numel() * t.element_size()
+
+    # ---- run-time tuning
+
+    def pk_ctx_set_autotune(self, mode):
+        self._check(self.lib.pk_ctx_set_autotune(self.handle, int(mode)))
+
+    def tune_table(self):
+        """The tuned launch choices as a list of dicts (to be stored)."""
+        out = []
+        for i in range(int(self.lib.pk_tune_count(self.handle))):
+            e = TuneEntry()
+            self._check(self.lib.pk_tune_get(self.handle, i, ctypes.byref(e)))
+            out.append({f: getattr(e, f) for f, _ in TuneEntry._fields_})
+        return out
+
+    def tune_load(self, table):
+        """Loads entries of tune_table() (from this or another context)."""
+        for d in table:
+            e = TuneEntry(*[d[f] for f, _ in TuneEntry._fields_])
+            self._check(self.lib.pk_tune_put(self.handle, ctypes.byref(e)))
 
     # ---- diagnostics
 

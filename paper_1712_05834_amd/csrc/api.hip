@@ -546,6 +546,8 @@ void pk_ctx_destroy(pk_ctx* ctx) {
   }
   DeviceGuard g(ctx->device);
   (void)hipStreamSynchronize(ctx->stream);
+  for (hipEvent_t ev : ctx->tune_ev)
+    if (ev) (void)hipEventDestroy(ev);
   for (auto& kv : ctx->mesh_tables) (void)hipFree(kv.second.dev);
   for (auto& kv : ctx->bin_tables) (void)hipFree(kv.second->e2_dev);
   if (ctx->scratch) (void)hipFree(ctx->scratch);
@@ -849,10 +851,33 @@ pk_status check_fftpower(pk_ctx* ctx, const pk_mesh_desc* m, const pk_bin_desc* 
 
 // Enqueues the whole path on stream s (tables must exist); stage events are
 // recorded only for the context stream.
+// Key of the tuning table: mesh size, precision, window, interlacing and
+// the density class round(log2(n / N^3)).
+std::tuple<int, int, int, int, int> tune_key(const pk_mesh_desc* m, int64_t n) {
+  const double cells = (double)m->nmesh * m->nmesh * m->nmesh;
+  const int dens = n > 0 ? (int)std::lround(std::log2((double)n / cells)) : -64;
+  return std::make_tuple(m->nmesh, m->dtype, m->window, m->interlaced, dens);
+}
+
+pk_tune_entry default_choice(const pk_mesh_desc* m, int64_t n) {
+  pk_tune_entry c{};
+  std::tie(c.nmesh, c.dtype, c.window, c.interlaced, c.density) = tune_key(m, n);
+  c.split = -1;  // the window's default
+  c.rotate = 1;
+  c.xpass_per_cu = 0;
+  c.ms = 0.0;
+  return c;
+}
+
+pk_tune_entry choice_for(const pk_ctx* ctx, const pk_mesh_desc* m, int64_t n) {
+  auto it = ctx->tuned.find(tune_key(m, n));
+  return it != ctx->tuned.end() ? it->second : default_choice(m, n);
+}
+
 hipError_t enqueue_fftpower(pk_ctx* ctx, hipStream_t s, const pk_mesh_desc* m,
                             const BinSpec& spec, const MeshTables* t, const void* pos,
                             const void* weight, const void* value, int64_t n, void* workspace,
-                            const Layout& l, double* result_dev) {
+                            const Layout& l, double* result_dev, const pk_tune_entry& ch) {
   const bool timed = s == ctx->stream;
   auto stage = [&](int st) {
     if (timed) mark_stage(ctx, st);
@@ -884,7 +909,7 @@ hipError_t enqueue_fftpower(pk_ctx* ctx, hipStream_t s, const pk_mesh_desc* m,
   stage(kPaintZ);
   if (e == hipSuccess)
     e = launch_paint_z(m->dtype, m->nmesh, m->window, m->interlaced != 0, rec, wrec,
-                       ws + l.bucket, wsums, t->tw, mesh_a, mesh_b, s);
+                       ws + l.bucket, wsums, t->tw, mesh_a, mesh_b, s, ch.split, ch.rotate);
   // y-pass out of place into the x-pass layout: A into the spare buffer,
   // then B into A's buffer, which A no longer needs
   stage(kFftY);
@@ -893,15 +918,18 @@ hipError_t enqueue_fftpower(pk_ctx* ctx, hipStream_t s, const pk_mesh_desc* m,
   if (e == hipSuccess) e = launch_fft_y_relayout(m->dtype, m->nmesh, mesh_a, ya, t->tw, s);
   if (e == hipSuccess && yb) e = launch_fft_y_relayout(m->dtype, m->nmesh, mesh_b, yb, t->tw, s);
   stage(kXpassBin);
+  // x-pass workgroups: as many as fit (l.gx) or the tuned number per CU
+  const int gx = ch.xpass_per_cu > 0
+                     ? std::min(l.gx, (int)kComputeUnits * ch.xpass_per_cu) : l.gx;
   if (e == hipSuccess)
     e = launch_xpass_bin(m->dtype, m->nmesh, ya, yb, *t, m->window, m->compensated, bs,
-                         partials, side_a, side_b, s);
+                         partials, side_a, side_b, s, gx);
   stage(kPlaneBin);
   if (e == hipSuccess)
     e = launch_plane_bin(m->dtype, m->nmesh, side_a, side_b, 1, *t, m->window, m->compensated,
-                         bs, partials + (size_t)l.gx * 2 * spec.nsum, s);
+                         bs, partials + (size_t)gx * 2 * spec.nsum, s);
   stage(kReduce);
-  if (e == hipSuccess) e = launch_reduce(partials, l.gx + l.gp, bs, result_dev, s);
+  if (e == hipSuccess) e = launch_reduce(partials, gx + l.gp, bs, result_dev, s);
   if (timed) mark_end(ctx);
   return e;
 }
@@ -950,15 +978,99 @@ pk_status submit_on_lane(pk_ctx* ctx, int lane, const pk_mesh_desc* m, const pk_
   if (e == hipSuccess) e = hipStreamWaitEvent(ln.stream, ctx->tables_ready, 0);
   if (e == hipSuccess)
     e = enqueue_fftpower(ctx, ln.stream, m, spec, t, pos, weight, nullptr, n, workspace,
-                         layout_of(m, b, n), result_dev);
+                         layout_of(m, b, n), result_dev, choice_for(ctx, m, n));
   if (e == hipSuccess) e = hipEventRecord(ln.done, ln.stream);
   if (e != hipSuccess) return dev_fail(ctx, e, "lane submission");
+  return PK_OK;
+}
+
+// The tuner: every candidate setting runs the whole path twice (warm-up,
+// then timed with events on the context stream); the fastest is kept.
+pk_status tune_fftpower(pk_ctx* ctx, const pk_mesh_desc* m, const BinSpec& spec,
+                        const MeshTables* t, const void* pos, const void* weight,
+                        const void* value, int64_t n, void* workspace, const Layout& l,
+                        double* result_dev) {
+  for (hipEvent_t& ev : ctx->tune_ev) {
+    if (!ev) {
+      const hipError_t e = hipEventCreate(&ev);
+      if (e != hipSuccess) return dev_fail(ctx, e, "tuner events");
+    }
+  }
+  std::vector<pk_tune_entry> cands;
+  const pk_tune_entry base = default_choice(m, n);
+  const int splits[2] = {0, 1};
+  for (int si = 0; si < (m->interlaced ? 2 : 1); ++si)
+    for (int rot = 0; rot < 2; ++rot)
+      for (int xpc = 0; xpc < (l.gx > (int)kComputeUnits ? 2 : 1); ++xpc) {
+        pk_tune_entry c = base;
+        c.split = m->interlaced ? splits[si] : 0;
+        c.rotate = rot;
+        c.xpass_per_cu = xpc;
+        cands.push_back(c);
+      }
+  pk_tune_entry best = base;
+  float best_ms = 1e30f;
+  for (pk_tune_entry& c : cands) {
+    hipError_t e = enqueue_fftpower(ctx, ctx->stream, m, spec, t, pos, weight, value, n,
+                                    workspace, l, result_dev, c);
+    if (e == hipSuccess) e = hipEventRecord(ctx->tune_ev[0], ctx->stream);
+    if (e == hipSuccess)
+      e = enqueue_fftpower(ctx, ctx->stream, m, spec, t, pos, weight, value, n, workspace, l,
+                           result_dev, c);
+    if (e == hipSuccess) e = hipEventRecord(ctx->tune_ev[1], ctx->stream);
+    if (e == hipSuccess) e = hipEventSynchronize(ctx->tune_ev[1]);
+    float ms = 0.0f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, ctx->tune_ev[0], ctx->tune_ev[1]);
+    if (e != hipSuccess) return dev_fail(ctx, e, "tuning");
+    if (ms < best_ms) {
+      best_ms = ms;
+      best = c;
+    }
+  }
+  best.ms = best_ms;
+  ctx->tuned[tune_key(m, n)] = best;
   return PK_OK;
 }
 
 }  // namespace
 
 extern "C" {
+
+pk_status pk_ctx_set_autotune(pk_ctx* ctx, int mode) {
+  if (!ctx) return PK_EINVAL;
+  if (mode != 0 && mode != 1) return fail(ctx, PK_EINVAL, "mode must be 0 or 1");
+  ctx->autotune = mode;
+  return PK_OK;
+}
+
+int pk_tune_count(const pk_ctx* ctx) { return ctx ? (int)ctx->tuned.size() : 0; }
+
+pk_status pk_tune_get(const pk_ctx* ctx, int i, pk_tune_entry* out) {
+  if (!ctx || !out || i < 0 || i >= (int)ctx->tuned.size()) return PK_EINVAL;
+  auto it = ctx->tuned.begin();
+  std::advance(it, i);
+  *out = it->second;
+  return PK_OK;
+}
+
+pk_status pk_tune_put(pk_ctx* ctx, const pk_tune_entry* entry) {
+  if (!ctx) return PK_EINVAL;
+  if (!entry) return fail(ctx, PK_EINVAL, "entry is NULL");
+  pk_mesh_desc m{};
+  m.nmesh = entry->nmesh;
+  m.window = entry->window;
+  m.interlaced = entry->interlaced;
+  m.compensated = 1;
+  m.dtype = entry->dtype;
+  m.boxsize = 1.0;
+  if (const char* why = check_mesh(&m)) return fail(ctx, PK_EINVAL, why);
+  if ((entry->split != 0 && entry->split != 1) || (entry->rotate != 0 && entry->rotate != 1) ||
+      entry->xpass_per_cu < 0 || entry->xpass_per_cu > 2)
+    return fail(ctx, PK_EINVAL, "split, rotate must be 0 or 1, xpass_per_cu 0, 1 or 2");
+  ctx->tuned[std::make_tuple(entry->nmesh, entry->dtype, entry->window, entry->interlaced,
+                             entry->density)] = *entry;
+  return PK_OK;
+}
 
 pk_status pk_fftpower_v(pk_ctx* ctx, const pk_mesh_desc* m, const pk_bin_desc* b,
                         const void* pos, const void* weight, const void* value, int64_t n,
@@ -970,8 +1082,14 @@ pk_status pk_fftpower_v(pk_ctx* ctx, const pk_mesh_desc* m, const pk_bin_desc* b
   const MeshTables* t = nullptr;
   BinSpec spec;
   if (pk_status st = prepare_tables(ctx, m, b, &t, &spec)) return st;
+  const Layout l = layout_of(m, b, n);
+  if (ctx->autotune && !ctx->tuned.count(tune_key(m, n)) && !ctx->timing) {
+    if (pk_status st = tune_fftpower(ctx, m, spec, t, pos, weight, value, n, workspace, l,
+                                     result_dev))
+      return st;
+  }
   hipError_t e = enqueue_fftpower(ctx, ctx->stream, m, spec, t, pos, weight, value, n, workspace,
-                                  layout_of(m, b, n), result_dev);
+                                  l, result_dev, choice_for(ctx, m, n));
   if (e != hipSuccess) return dev_fail(ctx, e, "pk_fftpower");
   return PK_OK;
 }
@@ -1067,7 +1185,7 @@ pk_status schedule_batch(pk_ctx* ctx, int count, const pk_mesh_desc* m, const pk
       const hipError_t e =
           enqueue_fftpower(ctx, ctx->stream, &m[i], spec, t, pos[i], weight ? weight[i] : nullptr,
                            nullptr, n[i], lane_workspace[0], layout_of(&m[i], &b[i], n[i]),
-                           result_dev[i]);
+                           result_dev[i], choice_for(ctx, &m[i], n[i]));
       if (e != hipSuccess) return dev_fail(ctx, e, "batch");
     }
     return PK_OK;

@@ -949,9 +949,10 @@ size_t bin_lds_bytes(const BinSpec& b) { return ((size_t)b.nlds * 2 + 1) * sizeo
 template <typename T, int N>
 static hipError_t xpass_bin_t(const void* mesh_a, const void* mesh_b, const MeshTables& t,
                               int order, int compensated, const BinSpec& b, double* partials,
-                              void* side_a, void* side_b, hipStream_t s) {
+                              void* side_a, void* side_b, hipStream_t s, int want) {
   using Cf = XCfg<T, N>;
-  const int groups = xpass_bin_groups(sizeof(T) == 4 ? PK_F32 : PK_F64, N, bin_lds_bytes(b));
+  int groups = xpass_bin_groups(sizeof(T) == 4 ? PK_F32 : PK_F64, N, bin_lds_bytes(b));
+  if (want > 0 && want < groups) groups = want;
   const T* sinv = compensated ? static_cast<const T*>(t.sinc_inv) + (size_t)(order - 2) * N
                               : nullptr;
   hipLaunchKernelGGL((k_xpass_bin<T, N>), dim3(groups), dim3(Cf::THREADS), bin_lds_bytes(b), s,
@@ -963,18 +964,19 @@ static hipError_t xpass_bin_t(const void* mesh_a, const void* mesh_b, const Mesh
 
 hipError_t launch_xpass_bin(int dtype, int nmesh, const void* mesh_a, const void* mesh_b,
                             const MeshTables& t, int order, int compensated, const BinSpec& b,
-                            double* partials, void* side_a, void* side_b, hipStream_t s) {
+                            double* partials, void* side_a, void* side_b, hipStream_t s,
+                            int groups) {
 #define PK_XB(T)                                                                              \
   switch (nmesh) {                                                                            \
-    case 8: return xpass_bin_t<T, 8>(mesh_a, mesh_b, t, order, compensated, b, partials, side_a, side_b, s); \
-    case 16: return xpass_bin_t<T, 16>(mesh_a, mesh_b, t, order, compensated, b, partials, side_a, side_b, s); \
-    case 32: return xpass_bin_t<T, 32>(mesh_a, mesh_b, t, order, compensated, b, partials, side_a, side_b, s); \
-    case 64: return xpass_bin_t<T, 64>(mesh_a, mesh_b, t, order, compensated, b, partials, side_a, side_b, s); \
-    case 128: return xpass_bin_t<T, 128>(mesh_a, mesh_b, t, order, compensated, b, partials, side_a, side_b, s); \
-    case 256: return xpass_bin_t<T, 256>(mesh_a, mesh_b, t, order, compensated, b, partials, side_a, side_b, s); \
-    case 512: return xpass_bin_t<T, 512>(mesh_a, mesh_b, t, order, compensated, b, partials, side_a, side_b, s); \
-    case 1024: return xpass_bin_t<T, 1024>(mesh_a, mesh_b, t, order, compensated, b, partials, side_a, side_b, s); \
-    case 2048: return xpass_bin_t<T, 2048>(mesh_a, mesh_b, t, order, compensated, b, partials, side_a, side_b, s); \
+    case 8: return xpass_bin_t<T, 8>(mesh_a, mesh_b, t, order, compensated, b, partials, side_a, side_b, s, groups); \
+    case 16: return xpass_bin_t<T, 16>(mesh_a, mesh_b, t, order, compensated, b, partials, side_a, side_b, s, groups); \
+    case 32: return xpass_bin_t<T, 32>(mesh_a, mesh_b, t, order, compensated, b, partials, side_a, side_b, s, groups); \
+    case 64: return xpass_bin_t<T, 64>(mesh_a, mesh_b, t, order, compensated, b, partials, side_a, side_b, s, groups); \
+    case 128: return xpass_bin_t<T, 128>(mesh_a, mesh_b, t, order, compensated, b, partials, side_a, side_b, s, groups); \
+    case 256: return xpass_bin_t<T, 256>(mesh_a, mesh_b, t, order, compensated, b, partials, side_a, side_b, s, groups); \
+    case 512: return xpass_bin_t<T, 512>(mesh_a, mesh_b, t, order, compensated, b, partials, side_a, side_b, s, groups); \
+    case 1024: return xpass_bin_t<T, 1024>(mesh_a, mesh_b, t, order, compensated, b, partials, side_a, side_b, s, groups); \
+    case 2048: return xpass_bin_t<T, 2048>(mesh_a, mesh_b, t, order, compensated, b, partials, side_a, side_b, s, groups); \
     default: return hipErrorInvalidValue;                                                    \
   }
   if (dtype == PK_F32) {

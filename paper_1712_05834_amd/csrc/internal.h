@@ -109,9 +109,13 @@ hipError_t launch_bucket(int dtype, int nmesh, double boxsize, const void* pos, 
                          const void* value, int64_t n, void* bucket_ws, void* rec, void* wrec,
                          double* wsums, hipStream_t s, void* scratch = nullptr,
                          size_t scratch_bytes = 0);
+// split: interlaced meshes painted by two single-mesh launches (1), one
+// two-mesh launch (0), or the default for the window (-1); rot: rotation of
+// the accumulator words within 32-cell blocks (1) or none (0).
 hipError_t launch_paint_z(int dtype, int nmesh, int order, bool inter, const void* rec,
                           const void* wrec, const void* bucket_ws, const double* wsums,
-                          const void* tw, void* mesh_a, void* mesh_b, hipStream_t s);
+                          const void* tw, void* mesh_a, void* mesh_b, hipStream_t s,
+                          int split = -1, int rot = 1);
 
 hipError_t launch_fft_z(int dtype, int nmesh, void* mesh, int nmeshes, size_t mesh_stride_bytes,
                         const void* tw, const double* wsum_for_mean, hipStream_t s);
@@ -132,9 +136,12 @@ int plane_bin_groups(int nmesh);
 size_t bin_lds_bytes(const BinSpec& b);
 // Static LDS bytes of the fused x-pass + binning kernel (0: unsupported size).
 size_t xpass_static_lds(int dtype, int nmesh);
+// groups > 0: that many workgroups (at most xpass_bin_groups) instead of
+// as many as the device holds.
 hipError_t launch_xpass_bin(int dtype, int nmesh, const void* mesh_a, const void* mesh_b,
                             const MeshTables& t, int order, int compensated, const BinSpec& b,
-                            double* partials, void* side_a, void* side_b, hipStream_t s);
+                            double* partials, void* side_a, void* side_b, hipStream_t s,
+                            int groups = 0);
 // cmesh2 != NULL: cross power Re(c conj(c2)) instead of |c|^2.  ylayout = 1:
 // both spectra are in the y-pass output layout instead of the packed one.
 // max_groups > 0 caps the grid (and so the partial rows written); the
@@ -259,4 +266,9 @@ struct pk_ctx {
   double* host_stage = nullptr;
   size_t host_stage_n = 0;
   std::vector<double> host_fallback;
+  // run-time tuning of the launch choices per (mesh size, precision, window,
+  // interlacing, catalog density class); see pk_ctx_set_autotune
+  int autotune = 0;
+  std::map<std::tuple<int, int, int, int, int>, pk_tune_entry> tuned;
+  hipEvent_t tune_ev[2] = {};
 };

@@ -805,8 +805,9 @@ struct PaintCfg {
   static constexpr int HHI = MODE == kPaintA ? HHI_A : (MODE == kPaintB ? HHI_B : (HHI_A > HHI_B ? HHI_A : HHI_B));
 };
 
-// LDS word of cell z within an accumulator row: within each block of 32
-// cells the cells are rotated by an even amount that depends on the block.
+// LDS word of cell z within an accumulator row (rot = 1): within each block
+// of 32 cells the cells are rotated by an even amount that depends on the
+// block; rot = 0 keeps cell z at word z (a run-time choice of the tuner).
 // Lanes of a wave often add to cells a power of two apart (lattice-like
 // catalogs: z spaced 8, 64 or 256 cells), which would put all their float64
 // atomics on one bank pair; the rotation spreads them (the padded row stride
@@ -815,8 +816,9 @@ struct PaintCfg {
 // on the row, so a particle's z words are computed once for all its rows.
 // Rows shorter than 32 cells are left as they are.
 template <int N>
-__device__ __forceinline__ int acc_word(int z) {
+__device__ __forceinline__ int acc_word(int z, int rotate) {
   if constexpr (N < 32) return z;
+  if (!rotate) return z;
   const int b = z >> 5;
   const int rot = ((b + 3 * (b >> 3)) & 15) << 1;
   return (z & ~31) | ((z + rot) & 31);
@@ -827,7 +829,7 @@ __global__ void __launch_bounds__((PaintCfg<T, N, P, MODE>::THREADS))
     k_paint_z(const typename Rec<T>::type* __restrict__ rec, const T* __restrict__ wrec,
               const int* __restrict__ offsets, const double* __restrict__ wsums,
               const cpx<T>* __restrict__ tw,
-              T* __restrict__ mesh_a, T* __restrict__ mesh_b) {
+              T* __restrict__ mesh_a, T* __restrict__ mesh_b, int rot) {
   using Cf = PaintCfg<T, N, P, MODE>;
   using Acc = double;
   constexpr int M = Cf::M, TX = Cf::TX, TY = Cf::TY;
@@ -982,7 +984,7 @@ __global__ void __launch_bounds__((PaintCfg<T, N, P, MODE>::THREADS))
         }
         int zw[P];
 #pragma unroll
-        for (int c = 0; c < P; ++c) zw[c] = acc_word<N>((first[2] + c) & mask);
+        for (int c = 0; c < P; ++c) zw[c] = acc_word<N>((first[2] + c) & mask, rot);
 #pragma unroll
         for (int a = 0; a < P; ++a) {
           const int lx = (first[0] + a - X0) & mask;
@@ -1030,7 +1032,7 @@ __global__ void __launch_bounds__((PaintCfg<T, N, P, MODE>::THREADS))
   if (fa) {
 #pragma unroll
     for (int e = 0; e < FE; ++e) {
-      const int wj = acc_word<N>(2 * (t + FTPL * e));
+      const int wj = acc_word<N>(2 * (t + FTPL * e), rot);
       v[e] = {static_cast<T>(arow[wj] - mean), static_cast<T>(arow[wj + 1] - mean)};
     }
   }
@@ -1192,26 +1194,26 @@ hipError_t launch_bucket(int dtype, int nmesh, double boxsize, const void* pos, 
 template <typename T, int N, int P, int MODE>
 static hipError_t paint_z_t(const void* rec, const void* wrec, const int* offsets,
                             const double* wsums, const void* tw,
-                            void* mesh_a, void* mesh_b, hipStream_t s) {
+                            void* mesh_a, void* mesh_b, int rot, hipStream_t s) {
   using Cf = PaintCfg<T, N, P, MODE>;
   const unsigned blocks = (unsigned)((N / Cf::TX) * (N / Cf::TY));
   hipLaunchKernelGGL((k_paint_z<T, N, P, MODE>), dim3(blocks), dim3(Cf::THREADS), 0, s,
                      static_cast<const typename Rec<T>::type*>(rec),
                      static_cast<const T*>(wrec), offsets, wsums,
                      static_cast<const cpx<T>*>(tw), static_cast<T*>(mesh_a),
-                     static_cast<T*>(mesh_b));
+                     static_cast<T*>(mesh_b), rot);
   return hipGetLastError();
 }
 
 template <typename T, int N>
 static hipError_t paint_z_n(int order, bool inter, const void* rec, const void* wrec,
                             const int* offsets, const double* wsums, const void* tw,
-                            void* mesh_a, void* mesh_b, hipStream_t s) {
-#define PK_PZ(P, MODE, A) paint_z_t<T, N, P, MODE>(rec, wrec, offsets, wsums, tw, A, mesh_b, s)
+                            void* mesh_a, void* mesh_b, int split, int rot, hipStream_t s) {
+#define PK_PZ(P, MODE, A) paint_z_t<T, N, P, MODE>(rec, wrec, offsets, wsums, tw, A, mesh_b, rot, s)
 #define PK_PZ_ORDER(MODE, A)                                            \
   (order == 2 ? PK_PZ(2, MODE, A) : (order == 3 ? PK_PZ(3, MODE, A) : PK_PZ(4, MODE, A)))
   if (!inter) return PK_PZ_ORDER(kPaintA, mesh_a);
-  if (!split_interlaced(order)) return PK_PZ_ORDER(kPaintAB, mesh_a);
+  if (!(split < 0 ? split_interlaced(order) : split != 0)) return PK_PZ_ORDER(kPaintAB, mesh_a);
   hipError_t e = PK_PZ_ORDER(kPaintA, mesh_a);
   if (e != hipSuccess) return e;
   return PK_PZ_ORDER(kPaintB, mesh_b);
@@ -1221,19 +1223,20 @@ static hipError_t paint_z_n(int order, bool inter, const void* rec, const void* 
 
 hipError_t launch_paint_z(int dtype, int nmesh, int order, bool inter, const void* rec,
                           const void* wrec, const void* bucket_ws, const double* wsums,
-                          const void* tw, void* mesh_a, void* mesh_b, hipStream_t s) {
+                          const void* tw, void* mesh_a, void* mesh_b, hipStream_t s, int split,
+                          int rot) {
   const int* offsets = static_cast<const int*>(bucket_ws) + (size_t)nmesh * nmesh;
 #define PK_PN(T)                                                                           \
   switch (nmesh) {                                                                         \
-    case 8: return paint_z_n<T, 8>(order, inter, rec, wrec, offsets, wsums, tw, mesh_a, mesh_b, s); \
-    case 16: return paint_z_n<T, 16>(order, inter, rec, wrec, offsets, wsums, tw, mesh_a, mesh_b, s); \
-    case 32: return paint_z_n<T, 32>(order, inter, rec, wrec, offsets, wsums, tw, mesh_a, mesh_b, s); \
-    case 64: return paint_z_n<T, 64>(order, inter, rec, wrec, offsets, wsums, tw, mesh_a, mesh_b, s); \
-    case 128: return paint_z_n<T, 128>(order, inter, rec, wrec, offsets, wsums, tw, mesh_a, mesh_b, s); \
-    case 256: return paint_z_n<T, 256>(order, inter, rec, wrec, offsets, wsums, tw, mesh_a, mesh_b, s); \
-    case 512: return paint_z_n<T, 512>(order, inter, rec, wrec, offsets, wsums, tw, mesh_a, mesh_b, s); \
-    case 1024: return paint_z_n<T, 1024>(order, inter, rec, wrec, offsets, wsums, tw, mesh_a, mesh_b, s); \
-    case 2048: return paint_z_n<T, 2048>(order, inter, rec, wrec, offsets, wsums, tw, mesh_a, mesh_b, s); \
+    case 8: return paint_z_n<T, 8>(order, inter, rec, wrec, offsets, wsums, tw, mesh_a, mesh_b, split, rot, s); \
+    case 16: return paint_z_n<T, 16>(order, inter, rec, wrec, offsets, wsums, tw, mesh_a, mesh_b, split, rot, s); \
+    case 32: return paint_z_n<T, 32>(order, inter, rec, wrec, offsets, wsums, tw, mesh_a, mesh_b, split, rot, s); \
+    case 64: return paint_z_n<T, 64>(order, inter, rec, wrec, offsets, wsums, tw, mesh_a, mesh_b, split, rot, s); \
+    case 128: return paint_z_n<T, 128>(order, inter, rec, wrec, offsets, wsums, tw, mesh_a, mesh_b, split, rot, s); \
+    case 256: return paint_z_n<T, 256>(order, inter, rec, wrec, offsets, wsums, tw, mesh_a, mesh_b, split, rot, s); \
+    case 512: return paint_z_n<T, 512>(order, inter, rec, wrec, offsets, wsums, tw, mesh_a, mesh_b, split, rot, s); \
+    case 1024: return paint_z_n<T, 1024>(order, inter, rec, wrec, offsets, wsums, tw, mesh_a, mesh_b, split, rot, s); \
+    case 2048: return paint_z_n<T, 2048>(order, inter, rec, wrec, offsets, wsums, tw, mesh_a, mesh_b, split, rot, s); \
     default: return hipErrorInvalidValue;                                                  \
   }
   if (dtype == PK_F32) {

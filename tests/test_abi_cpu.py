@@ -286,3 +286,22 @@ def test_binding_refuses_host_and_mistyped_tensors_before_any_launch():
         api.CatalogMesh(pos, 32, 100.0, weight=torch.ones(10))
     ctx.close()
 
+
+
+def test_tuning_table_entry_points_validate():
+    ctx = _lib.Context(_lib.PK_DEVICE_NONE)
+    with pytest.raises(_lib.PkError):
+        ctx.pk_ctx_set_autotune(2)
+    ctx.pk_ctx_set_autotune(1)
+    good = {"nmesh": 128, "dtype": 0, "window": 3, "interlaced": 1, "density": -3,
+            "split": 1, "rotate": 0, "xpass_per_cu": 1, "ms": 0.5}
+    ctx.tune_load([good])
+    assert ctx.tune_table() == [good]
+    for key, bad in (("split", 2), ("rotate", -1), ("xpass_per_cu", 3), ("nmesh", 100),
+                     ("window", 5)):
+        with pytest.raises(_lib.PkError):
+            ctx.tune_load([{**good, key: bad}])
+    # an entry with the same key replaces the old one
+    ctx.tune_load([{**good, "split": 0}])
+    assert len(ctx.tune_table()) == 1 and ctx.tune_table()[0]["split"] == 0
+    ctx.close()
