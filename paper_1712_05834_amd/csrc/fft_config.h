@@ -69,13 +69,13 @@ __device__ __forceinline__ int xcd_group_tile(int g, int ntiles) {
   return blk * 8 * G + (off % 8) * G + off / 8;
 }
 
-// Launch shape of the y-pass of the power-spectrum path (k_fft_y_relayout):
-// 8 points per thread, 1024 threads for N = 1024 (16 points: 512 threads)
-// -- more waves in flight for this HBM-bound pass (1-2% faster; 4 points per
-// thread was 60% slower at 1024^3).  Up to 16 columns per workgroup where
-// they fit (N <= 512; at 1024 in float32 with 16 points per thread and one
-// 144 KB workgroup per CU): each row read and written is then a whole
-// 128-byte line.
+// Launch shape of the y-pass of the power-spectrum path (k_fft_y_relayout).
+// Float32 at N = 1024: 16 points per thread and 16 columns per workgroup
+// (1024 threads, 144 KB of LDS, one workgroup per CU), so that every row read
+// and written is a whole 128-byte line: 1.80 ms per mesh against 2.04 ms with
+// 8 columns of 8 points.  Elsewhere 8 points per thread (16 were 1-2% slower
+// there, 4 were 60% slower at 1024^3) and up to 16 columns where they fit in
+// 80 KB (N <= 512).
 template <typename T, int N>
 using YCfg = typename std::conditional<(sizeof(T) == 4 && N == 1024), ColCfg<T, N, 16, 160, 16>,
                                        ColCfg<T, N, 8, 80, 16>>::type;
