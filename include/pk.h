@@ -351,13 +351,11 @@ pk_status pk_fftpower_batch(pk_ctx *ctx, int count, const pk_mesh_desc *m,
                             double *const *result_dev);
 
 /* ---- Run-time tuning of the launch choices of pk_fftpower.
- * Three choices have no winner that holds for every input: painting an
+ * Two choices have no winner that holds for every input: painting an
  * interlaced pair of meshes in one two-mesh launch or in two single-mesh
- * launches (the halos of the two meshes differ by window), rotating the
- * float64 accumulator words of each 32-cell block of a column (spreads the
- * LDS banks of lattice-like catalogs, costs VALU work on others), and the
- * number of persistent workgroups per CU of the fused x-pass + binning (one
- * or two where the LDS allows two).  With autotuning on, the first
+ * launches (the halos of the two meshes differ by window), and the number
+ * of persistent workgroups per CU of the fused x-pass + binning (one or two
+ * where the LDS allows two).  With autotuning on, the first
  * synchronous pk_fftpower call for a key (N, dtype, window, interlaced and
  * the density class round(log2(n / N^3))) runs the whole path once per
  * candidate (a warm-up run and a timed run each, with HIP events on the
@@ -365,14 +363,13 @@ pk_status pk_fftpower_batch(pk_ctx *ctx, int count, const pk_mesh_desc *m,
  * that call's result is the last run's, with the chosen settings.  Later
  * calls with the key (pk_fftpower, pk_fftpower_v, lanes, batches, graphs
  * built afterwards) use the choice.  Without a choice the defaults are:
- * two launches for CIC, one for TSC and PCS; rotation on; as many x-pass
+ * two launches for CIC, one for TSC and PCS; as many x-pass
  * workgroups as the device holds.  The table can be read and stored by the
  * caller and loaded into another context, so the tuning runs once per
  * machine. */
 typedef struct {
   int32_t nmesh, dtype, window, interlaced, density;  /* the key            */
   int32_t split;         /* interlaced: 1 two single-mesh launches, 0 one  */
-  int32_t rotate;        /* 1 rotated accumulator words, 0 plain           */
   int32_t xpass_per_cu;  /* x-pass workgroups per CU, 0 = as many as fit   */
   double ms;             /* timed run of the chosen settings (diagnostic)  */
 } pk_tune_entry;
@@ -383,7 +380,7 @@ int pk_tune_count(const pk_ctx *ctx);
 /* Entry i (0 .. pk_tune_count - 1) into *out (host).  Errors: PK_EINVAL. */
 pk_status pk_tune_get(const pk_ctx *ctx, int i, pk_tune_entry *out);
 /* Sets (or replaces) the entry of its key; the choice fields must be valid
- * (split, rotate in {0, 1}, xpass_per_cu in {0, 1, 2}).  Errors: PK_EINVAL. */
+ * (split in {0, 1}, xpass_per_cu in {0, 1, 2}).  Errors: PK_EINVAL. */
 pk_status pk_tune_put(pk_ctx *ctx, const pk_tune_entry *entry);
 
 /* ---- Graph-captured batches (repeated analyses, Sec. 6: the same batch

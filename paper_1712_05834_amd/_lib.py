@@ -70,7 +70,7 @@ class TuneEntry(ctypes.Structure):
     _fields_ = [
         ("nmesh", ctypes.c_int32), ("dtype", ctypes.c_int32), ("window", ctypes.c_int32),
         ("interlaced", ctypes.c_int32), ("density", ctypes.c_int32), ("split", ctypes.c_int32),
-        ("rotate", ctypes.c_int32), ("xpass_per_cu", ctypes.c_int32), ("ms", ctypes.c_double),
+        ("xpass_per_cu", ctypes.c_int32), ("ms", ctypes.c_double),
     ]
 
 

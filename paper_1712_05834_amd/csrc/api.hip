@@ -863,7 +863,6 @@ pk_tune_entry default_choice(const pk_mesh_desc* m, int64_t n) {
   pk_tune_entry c{};
   std::tie(c.nmesh, c.dtype, c.window, c.interlaced, c.density) = tune_key(m, n);
   c.split = -1;  // the window's default
-  c.rotate = 1;
   c.xpass_per_cu = 0;
   c.ms = 0.0;
   return c;
@@ -909,7 +908,7 @@ hipError_t enqueue_fftpower(pk_ctx* ctx, hipStream_t s, const pk_mesh_desc* m,
   stage(kPaintZ);
   if (e == hipSuccess)
     e = launch_paint_z(m->dtype, m->nmesh, m->window, m->interlaced != 0, rec, wrec,
-                       ws + l.bucket, wsums, t->tw, mesh_a, mesh_b, s, ch.split, ch.rotate);
+                       ws + l.bucket, wsums, t->tw, mesh_a, mesh_b, s, ch.split);
   // y-pass out of place into the x-pass layout: A into the spare buffer,
   // then B into A's buffer, which A no longer needs
   stage(kFftY);
@@ -1000,14 +999,12 @@ pk_status tune_fftpower(pk_ctx* ctx, const pk_mesh_desc* m, const BinSpec& spec,
   const pk_tune_entry base = default_choice(m, n);
   const int splits[2] = {0, 1};
   for (int si = 0; si < (m->interlaced ? 2 : 1); ++si)
-    for (int rot = 0; rot < 2; ++rot)
-      for (int xpc = 0; xpc < (l.gx > (int)kComputeUnits ? 2 : 1); ++xpc) {
-        pk_tune_entry c = base;
-        c.split = m->interlaced ? splits[si] : 0;
-        c.rotate = rot;
-        c.xpass_per_cu = xpc;
-        cands.push_back(c);
-      }
+    for (int xpc = 0; xpc < (l.gx > (int)kComputeUnits ? 2 : 1); ++xpc) {
+      pk_tune_entry c = base;
+      c.split = m->interlaced ? splits[si] : 0;
+      c.xpass_per_cu = xpc;
+      cands.push_back(c);
+    }
   pk_tune_entry best = base;
   float best_ms = 1e30f;
   for (pk_tune_entry& c : cands) {
@@ -1064,9 +1061,9 @@ pk_status pk_tune_put(pk_ctx* ctx, const pk_tune_entry* entry) {
   m.dtype = entry->dtype;
   m.boxsize = 1.0;
   if (const char* why = check_mesh(&m)) return fail(ctx, PK_EINVAL, why);
-  if ((entry->split != 0 && entry->split != 1) || (entry->rotate != 0 && entry->rotate != 1) ||
-      entry->xpass_per_cu < 0 || entry->xpass_per_cu > 2)
-    return fail(ctx, PK_EINVAL, "split, rotate must be 0 or 1, xpass_per_cu 0, 1 or 2");
+  if ((entry->split != 0 && entry->split != 1) || entry->xpass_per_cu < 0 ||
+      entry->xpass_per_cu > 2)
+    return fail(ctx, PK_EINVAL, "split must be 0 or 1, xpass_per_cu 0, 1 or 2");
   ctx->tuned[std::make_tuple(entry->nmesh, entry->dtype, entry->window, entry->interlaced,
                              entry->density)] = *entry;
   return PK_OK;

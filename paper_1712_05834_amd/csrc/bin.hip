@@ -328,9 +328,14 @@ __global__ void __launch_bounds__((XCfg<T, N>::THREADS)) __attribute__((amdgpu_w
   // binning pass layout: the power of the tile's C x N modes is staged in
   // LDS as pw[col][kx + kx / S] and re-read so that the 64 lanes of a wave
   // see one column at kx spaced S = N / 64 apart: distinct |n| bins, hence
-  // few same-address collisions of the LDS atomics
+  // few same-address collisions of the LDS atomics.  Rows of the C columns
+  // start 64 / C banks apart (N + N / S is a multiple of 64 words), so that
+  // the staging writes of a wave (C columns x 64 / C consecutive kx) fall in
+  // distinct banks.
   constexpr int S = N >= 64 ? N / 64 : 1;
-  constexpr int PROW = N >= 64 ? N + N / S : N;
+  constexpr int WPE = (int)(sizeof(T) / 4);  // 4-byte words per staged value
+  constexpr int RPAD = 64 / (C * WPE) > 1 ? 64 / (C * WPE) : 1;
+  constexpr int PROW = N >= 64 ? N + N / S + RPAD : N;
   T* pws = reinterpret_cast<T*>(lds);
   static_assert((long)C * PROW * sizeof(T) <= (long)Cf::LDS_ELEMS * sizeof(cpx<T>), "staging");
   auto pidx = [](int cc, int kx) { return cc * PROW + (N >= 64 ? kx + kx / S : kx); };

@@ -110,12 +110,11 @@ hipError_t launch_bucket(int dtype, int nmesh, double boxsize, const void* pos, 
                          double* wsums, hipStream_t s, void* scratch = nullptr,
                          size_t scratch_bytes = 0);
 // split: interlaced meshes painted by two single-mesh launches (1), one
-// two-mesh launch (0), or the default for the window (-1); rot: rotation of
-// the accumulator words within 32-cell blocks (1) or none (0).
+// two-mesh launch (0), or the default for the window (-1).
 hipError_t launch_paint_z(int dtype, int nmesh, int order, bool inter, const void* rec,
                           const void* wrec, const void* bucket_ws, const double* wsums,
                           const void* tw, void* mesh_a, void* mesh_b, hipStream_t s,
-                          int split = -1, int rot = 1);
+                          int split = -1);
 
 hipError_t launch_fft_z(int dtype, int nmesh, void* mesh, int nmeshes, size_t mesh_stride_bytes,
                         const void* tw, const double* wsum_for_mean, hipStream_t s);

@@ -749,13 +749,34 @@ constexpr int kPaintA = 0, kPaintB = 1, kPaintAB = 2;
 // TSC: 0.843 against 0.858 ms).
 constexpr bool split_interlaced(int order) { return order == 2; }
 
+// A store of output that no later kernel reads while it is still cached (the
+// painted meshes, 1-9 GB): nontemporal, so that it does not displace the
+// records the next workgroups gather (Zel'dovich 1024^3 paint: 5.18 ->
+// 5.02 ms).
+template <typename T>
+__device__ __forceinline__ void store_stream(cpx<T>* p, cpx<T> v) {
+  if constexpr (sizeof(T) == 4) {
+    const unsigned long long bits =
+        ((unsigned long long)__float_as_uint(v.y) << 32) | __float_as_uint(v.x);
+    __builtin_nontemporal_store(bits, reinterpret_cast<unsigned long long*>(p));
+  } else {
+    __builtin_nontemporal_store(v.x, &p->x);
+    __builtin_nontemporal_store(v.y, &p->y);
+  }
+}
+
 template <typename T, int N, int P, int MODE>
 struct PaintCfg {
   using Acc = double;
   static constexpr int M = N / 2;
   static constexpr int LP = lds_pad_len<M>();           // complex per FFT line
   static constexpr int NM = MODE == kPaintAB ? 2 : 1;
-  static constexpr long ACC_BYTES = (long)N * sizeof(Acc);
+  // accumulator row: cell z at word z + 1 for z in [-1, N + 2], the cells
+  // one window can reach from a particle of the column without wrapping (the
+  // pad words are folded into their periodic images before the z-FFT), so
+  // that the P cells of a stencil are P consecutive words
+  static constexpr int ZPAD_LO = 1, ZPAD_HI = 3;
+  static constexpr long ACC_BYTES = (long)(N + ZPAD_LO + ZPAD_HI) * sizeof(Acc);
   static constexpr long FFT_BYTES = (long)LP * 2 * sizeof(T);
   // row stride: the row rounded to 16 bytes plus 16 bytes, so that
   // consecutive rows start 4 banks apart
@@ -805,31 +826,12 @@ struct PaintCfg {
   static constexpr int HHI = MODE == kPaintA ? HHI_A : (MODE == kPaintB ? HHI_B : (HHI_A > HHI_B ? HHI_A : HHI_B));
 };
 
-// LDS word of cell z within an accumulator row (rot = 1): within each block
-// of 32 cells the cells are rotated by an even amount that depends on the
-// block; rot = 0 keeps cell z at word z (a run-time choice of the tuner).
-// Lanes of a wave often add to cells a power of two apart (lattice-like
-// catalogs: z spaced 8, 64 or 256 cells), which would put all their float64
-// atomics on one bank pair; the rotation spreads them (the padded row stride
-// does the same across rows).  An even rotation keeps the cells 2j, 2j + 1
-// adjacent, as the read-back into complex pairs needs.  It does not depend
-// on the row, so a particle's z words are computed once for all its rows.
-// Rows shorter than 32 cells are left as they are.
-template <int N>
-__device__ __forceinline__ int acc_word(int z, int rotate) {
-  if constexpr (N < 32) return z;
-  if (!rotate) return z;
-  const int b = z >> 5;
-  const int rot = ((b + 3 * (b >> 3)) & 15) << 1;
-  return (z & ~31) | ((z + rot) & 31);
-}
-
 template <typename T, int N, int P, int MODE>
 __global__ void __launch_bounds__((PaintCfg<T, N, P, MODE>::THREADS))
     k_paint_z(const typename Rec<T>::type* __restrict__ rec, const T* __restrict__ wrec,
               const int* __restrict__ offsets, const double* __restrict__ wsums,
               const cpx<T>* __restrict__ tw,
-              T* __restrict__ mesh_a, T* __restrict__ mesh_b, int rot) {
+              T* __restrict__ mesh_a, T* __restrict__ mesh_b) {
   using Cf = PaintCfg<T, N, P, MODE>;
   using Acc = double;
   constexpr int M = Cf::M, TX = Cf::TX, TY = Cf::TY;
@@ -982,9 +984,13 @@ __global__ void __launch_bounds__((PaintCfg<T, N, P, MODE>::THREADS))
           }
           window_frac<T, P>(tt, base, first[d], w[d]);
         }
-        int zw[P];
+        // the P z cells are P consecutive words from first[2] + ZPAD_LO (the
+        // address is computed once per row, the cells are immediate
+        // offsets); products in float64 from the z weights converted once
+        const int zb = first[2] + Cf::ZPAD_LO;
+        double wz[P];
 #pragma unroll
-        for (int c = 0; c < P; ++c) zw[c] = acc_word<N>((first[2] + c) & mask, rot);
+        for (int c = 0; c < P; ++c) wz[c] = (double)w[2][c];
 #pragma unroll
         for (int a = 0; a < P; ++a) {
           const int lx = (first[0] + a - X0) & mask;
@@ -994,10 +1000,10 @@ __global__ void __launch_bounds__((PaintCfg<T, N, P, MODE>::THREADS))
           for (int b2 = 0; b2 < P; ++b2) {
             const int ly = (first[1] + b2 - Y0) & mask;
             if (ly >= TY) continue;
-            const T wab = wa * w[1][b2];
-            Acc* row = acc + ((mesh * TX + lx) * TY + ly) * ROWA;
+            const double wab = (double)(wa * w[1][b2]);
+            Acc* row = acc + ((mesh * TX + lx) * TY + ly) * ROWA + zb;
 #pragma unroll
-            for (int c = 0; c < P; ++c) atomicAdd(&row[zw[c]], (double)(wab * w[2][c]));
+            for (int c = 0; c < P; ++c) atomicAdd(&row[c], wab * wz[c]);
           }
         }
       }
@@ -1006,6 +1012,21 @@ __global__ void __launch_bounds__((PaintCfg<T, N, P, MODE>::THREADS))
     seg_cur = seg_nxt;
     r_cur = r_nxt;
     w_cur = w_nxt;
+  }
+  __syncthreads();
+
+  // periodic images: the front pad word (cell -1) into cell N - 1, the back
+  // pad words (cells N .. N + 2) into cells 0 .. 2 -- four distinct cells per
+  // row, one thread each
+  static_assert(N >= 4, "the images of the pad cells must be distinct");
+  for (int i = threadIdx.x; i < ROWS * 4; i += blockDim.x) {
+    Acc* row = acc + (i >> 2) * ROWA;
+    const int j = i & 3;
+    if (j == 0) {
+      row[N] += row[0];  // cell -1 (word 0) into cell N - 1 (word N)
+    } else {
+      row[j] += row[N + j];  // cell N + j - 1 into cell j - 1 (word j)
+    }
   }
   __syncthreads();
 
@@ -1032,7 +1053,7 @@ __global__ void __launch_bounds__((PaintCfg<T, N, P, MODE>::THREADS))
   if (fa) {
 #pragma unroll
     for (int e = 0; e < FE; ++e) {
-      const int wj = acc_word<N>(2 * (t + FTPL * e), rot);
+      const int wj = 2 * (t + FTPL * e) + Cf::ZPAD_LO;  // cells 2j, 2j + 1
       v[e] = {static_cast<T>(arow[wj] - mean), static_cast<T>(arow[wj + 1] - mean)};
     }
   }
@@ -1061,7 +1082,7 @@ __global__ void __launch_bounds__((PaintCfg<T, N, P, MODE>::THREADS))
       const cpx<T> w = cmul(twm[k], csub(v[e], zc));
       o = {T(0.5) * (s.x + w.y), T(0.5) * (s.y - w.x)};
     }
-    rowp[k] = o;
+    store_stream(rowp + k, o);
   }
 }
 
@@ -1194,22 +1215,22 @@ hipError_t launch_bucket(int dtype, int nmesh, double boxsize, const void* pos, 
 template <typename T, int N, int P, int MODE>
 static hipError_t paint_z_t(const void* rec, const void* wrec, const int* offsets,
                             const double* wsums, const void* tw,
-                            void* mesh_a, void* mesh_b, int rot, hipStream_t s) {
+                            void* mesh_a, void* mesh_b, hipStream_t s) {
   using Cf = PaintCfg<T, N, P, MODE>;
   const unsigned blocks = (unsigned)((N / Cf::TX) * (N / Cf::TY));
   hipLaunchKernelGGL((k_paint_z<T, N, P, MODE>), dim3(blocks), dim3(Cf::THREADS), 0, s,
                      static_cast<const typename Rec<T>::type*>(rec),
                      static_cast<const T*>(wrec), offsets, wsums,
                      static_cast<const cpx<T>*>(tw), static_cast<T*>(mesh_a),
-                     static_cast<T*>(mesh_b), rot);
+                     static_cast<T*>(mesh_b));
   return hipGetLastError();
 }
 
 template <typename T, int N>
 static hipError_t paint_z_n(int order, bool inter, const void* rec, const void* wrec,
                             const int* offsets, const double* wsums, const void* tw,
-                            void* mesh_a, void* mesh_b, int split, int rot, hipStream_t s) {
-#define PK_PZ(P, MODE, A) paint_z_t<T, N, P, MODE>(rec, wrec, offsets, wsums, tw, A, mesh_b, rot, s)
+                            void* mesh_a, void* mesh_b, int split, hipStream_t s) {
+#define PK_PZ(P, MODE, A) paint_z_t<T, N, P, MODE>(rec, wrec, offsets, wsums, tw, A, mesh_b, s)
 #define PK_PZ_ORDER(MODE, A)                                            \
   (order == 2 ? PK_PZ(2, MODE, A) : (order == 3 ? PK_PZ(3, MODE, A) : PK_PZ(4, MODE, A)))
   if (!inter) return PK_PZ_ORDER(kPaintA, mesh_a);
@@ -1223,20 +1244,19 @@ static hipError_t paint_z_n(int order, bool inter, const void* rec, const void* 
 
 hipError_t launch_paint_z(int dtype, int nmesh, int order, bool inter, const void* rec,
                           const void* wrec, const void* bucket_ws, const double* wsums,
-                          const void* tw, void* mesh_a, void* mesh_b, hipStream_t s, int split,
-                          int rot) {
+                          const void* tw, void* mesh_a, void* mesh_b, hipStream_t s, int split) {
   const int* offsets = static_cast<const int*>(bucket_ws) + (size_t)nmesh * nmesh;
 #define PK_PN(T)                                                                           \
   switch (nmesh) {                                                                         \
-    case 8: return paint_z_n<T, 8>(order, inter, rec, wrec, offsets, wsums, tw, mesh_a, mesh_b, split, rot, s); \
-    case 16: return paint_z_n<T, 16>(order, inter, rec, wrec, offsets, wsums, tw, mesh_a, mesh_b, split, rot, s); \
-    case 32: return paint_z_n<T, 32>(order, inter, rec, wrec, offsets, wsums, tw, mesh_a, mesh_b, split, rot, s); \
-    case 64: return paint_z_n<T, 64>(order, inter, rec, wrec, offsets, wsums, tw, mesh_a, mesh_b, split, rot, s); \
-    case 128: return paint_z_n<T, 128>(order, inter, rec, wrec, offsets, wsums, tw, mesh_a, mesh_b, split, rot, s); \
-    case 256: return paint_z_n<T, 256>(order, inter, rec, wrec, offsets, wsums, tw, mesh_a, mesh_b, split, rot, s); \
-    case 512: return paint_z_n<T, 512>(order, inter, rec, wrec, offsets, wsums, tw, mesh_a, mesh_b, split, rot, s); \
-    case 1024: return paint_z_n<T, 1024>(order, inter, rec, wrec, offsets, wsums, tw, mesh_a, mesh_b, split, rot, s); \
-    case 2048: return paint_z_n<T, 2048>(order, inter, rec, wrec, offsets, wsums, tw, mesh_a, mesh_b, split, rot, s); \
+    case 8: return paint_z_n<T, 8>(order, inter, rec, wrec, offsets, wsums, tw, mesh_a, mesh_b, split, s); \
+    case 16: return paint_z_n<T, 16>(order, inter, rec, wrec, offsets, wsums, tw, mesh_a, mesh_b, split, s); \
+    case 32: return paint_z_n<T, 32>(order, inter, rec, wrec, offsets, wsums, tw, mesh_a, mesh_b, split, s); \
+    case 64: return paint_z_n<T, 64>(order, inter, rec, wrec, offsets, wsums, tw, mesh_a, mesh_b, split, s); \
+    case 128: return paint_z_n<T, 128>(order, inter, rec, wrec, offsets, wsums, tw, mesh_a, mesh_b, split, s); \
+    case 256: return paint_z_n<T, 256>(order, inter, rec, wrec, offsets, wsums, tw, mesh_a, mesh_b, split, s); \
+    case 512: return paint_z_n<T, 512>(order, inter, rec, wrec, offsets, wsums, tw, mesh_a, mesh_b, split, s); \
+    case 1024: return paint_z_n<T, 1024>(order, inter, rec, wrec, offsets, wsums, tw, mesh_a, mesh_b, split, s); \
+    case 2048: return paint_z_n<T, 2048>(order, inter, rec, wrec, offsets, wsums, tw, mesh_a, mesh_b, split, s); \
     default: return hipErrorInvalidValue;                                                  \
   }
   if (dtype == PK_F32) {

@@ -294,10 +294,10 @@ def test_tuning_table_entry_points_validate():
         ctx.pk_ctx_set_autotune(2)
     ctx.pk_ctx_set_autotune(1)
     good = {"nmesh": 128, "dtype": 0, "window": 3, "interlaced": 1, "density": -3,
-            "split": 1, "rotate": 0, "xpass_per_cu": 1, "ms": 0.5}
+            "split": 1, "xpass_per_cu": 1, "ms": 0.5}
     ctx.tune_load([good])
     assert ctx.tune_table() == [good]
-    for key, bad in (("split", 2), ("rotate", -1), ("xpass_per_cu", 3), ("nmesh", 100),
+    for key, bad in (("split", 2), ("split", -1), ("xpass_per_cu", 3), ("nmesh", 100),
                      ("window", 5)):
         with pytest.raises(_lib.PkError):
             ctx.tune_load([{**good, key: bad}])

@@ -1,6 +1,6 @@
 """Run-time tuning of pk_fftpower's launch choices: every choice the tuner
-can make (two-mesh or split painting of interlaced meshes, rotated or plain
-accumulator words, x-pass workgroups per CU) gives the result of the default
+can make (two-mesh or split painting of interlaced meshes, x-pass
+workgroups per CU) gives the result of the default
 settings, for every window; a tuned context and a context loaded with its
 table give that result too.  Bar: |dP| / |P| <= 1e-6 and |dP_ell| <= 1e-6
 |P_0| (the binning is exact; the painting's float64 LDS sums are added in a
@@ -45,11 +45,10 @@ def test_every_tuning_choice_gives_the_default_result(window):
     want = _run(ref_ctx, m, b, pos, ws)
     ctx = _lib.Context(0)
     dens = int(round(np.log2(npart / n ** 3)))
-    for split, rot, xpc in itertools.product((0, 1), (0, 1), (0, 1, 2)):
+    for split, xpc in itertools.product((0, 1), (0, 1, 2)):
         ctx.tune_load([{"nmesh": n, "dtype": 0, "window": m.window, "interlaced": 1,
-                        "density": dens, "split": split, "rotate": rot, "xpass_per_cu": xpc,
-                        "ms": 0.0}])
-        _same(_run(ctx, m, b, pos, ws), want, f"{window} split={split} rot={rot} xpc={xpc}")
+                        "density": dens, "split": split, "xpass_per_cu": xpc, "ms": 0.0}])
+        _same(_run(ctx, m, b, pos, ws), want, f"{window} split={split} xpc={xpc}")
     ctx.close()
     ref_ctx.close()
 
@@ -69,7 +68,7 @@ def test_autotune_picks_and_reuses_a_choice():
     assert len(table) == 1
     e = table[0]
     assert (e["nmesh"], e["window"], e["interlaced"]) == (128, 3, 1)
-    assert e["split"] in (0, 1) and e["rotate"] in (0, 1) and e["xpass_per_cu"] in (0, 1)
+    assert e["split"] in (0, 1) and e["xpass_per_cu"] in (0, 1)
     assert e["ms"] > 0
     print(f"\ntuned 128^3 TSC interlaced, 400k particles: {e}")
     _same(got, want, "tuned call")
