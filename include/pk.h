@@ -363,8 +363,8 @@ pk_status pk_fftpower_batch(pk_ctx *ctx, int count, const pk_mesh_desc *m,
  * that call's result is the last run's, with the chosen settings.  Later
  * calls with the key (pk_fftpower, pk_fftpower_v, lanes, batches, graphs
  * built afterwards) use the choice.  Without a choice the defaults are:
- * two launches for CIC, one for TSC and PCS; as many x-pass
- * workgroups as the device holds.  The table can be read and stored by the
+ * one two-mesh paint launch; as many x-pass workgroups as the device
+ * holds.  The table can be read and stored by the
  * caller and loaded into another context, so the tuning runs once per
  * machine. */
 typedef struct {

@@ -741,13 +741,13 @@ constexpr int kPaintLdsBudgetKB = 76;  // two workgroups per CU
 // Meshes a paint launch produces: kPaintA the plain mesh, kPaintB the mesh
 // shifted by half a cell (interlacing), kPaintAB both in one pass.
 constexpr int kPaintA = 0, kPaintB = 1, kPaintAB = 2;
-// Interlaced CIC meshes are painted by two single-mesh launches: the
-// single-mesh tiles are twice as wide and the plain mesh needs a halo of one
-// column instead of two, so each particle is gathered by fewer workgroups
-// (Zel'dovich 1024^3: 5.19 -> 5.00 ms).  For TSC and PCS the halos of the two
-// meshes differ little and one two-mesh launch is faster (log-normal 512^3
-// TSC: 0.843 against 0.858 ms).
-constexpr bool split_interlaced(int order) { return order == 2; }
+// Interlaced meshes are painted by one two-mesh launch by default: each
+// record is read once for both meshes.  With nontemporal mesh stores this is
+// also the faster choice for every window measured (Zel'dovich 1024^3 CIC:
+// 4.99 against 5.03 ms for two single-mesh launches, whose record reads from
+// L2 misses come to 6.0 GB against 4.4 GB; log-normal 512^3 TSC: 0.83
+// against 0.85 ms).  The tuner can still choose two launches per input.
+constexpr bool split_interlaced(int) { return false; }
 
 // A store of output that no later kernel reads while it is still cached (the
 // painted meshes, 1-9 GB): nontemporal, so that it does not displace the
