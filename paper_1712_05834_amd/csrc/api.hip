@@ -302,14 +302,15 @@ pk_status get_bin_tables(pk_ctx* ctx, const pk_mesh_desc* m, const pk_bin_desc* 
   const int groups = mode_table_groups(m->nmesh);
   const int slots = mode_table_slots(b->nk, nmu);
   double* scratch = nullptr;
-  if (e == hipSuccess) e = hipMalloc(&scratch, ((size_t)groups + 1) * slots * sizeof(double));
+  // partial rows of two words per slot, then the reduced table
+  if (e == hipSuccess) e = hipMalloc(&scratch, ((size_t)2 * groups + 1) * slots * sizeof(double));
+  double* table = scratch + (size_t)2 * groups * slots;
   if (e == hipSuccess)
-    e = launch_mode_tables(m->nmesh, spec, scratch, groups, scratch + (size_t)groups * slots,
-                           ctx->stream);
+    e = launch_mode_tables(m->nmesh, spec, scratch, groups, table, ctx->stream);
   std::vector<double> host(slots);
   if (e == hipSuccess)
-    e = hipMemcpyAsync(host.data(), scratch + (size_t)groups * slots, slots * sizeof(double),
-                       hipMemcpyDeviceToHost, ctx->stream);
+    e = hipMemcpyAsync(host.data(), table, slots * sizeof(double), hipMemcpyDeviceToHost,
+                       ctx->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
   if (scratch) (void)hipFree(scratch);
   if (e != hipSuccess) {
@@ -1623,7 +1624,7 @@ pk_status pk_convolved_power(pk_ctx* ctx, const pk_mesh_desc* m, const pk_bin_de
     if (pass >= 2) e = hipStreamWaitEvent(s, xdone[set], 0);  // x-pass pass - 2 is done with it
     for (int j = 0; j < np2 && e == hipSuccess; ++j) {
       e = launch_paint_z(m->dtype, m->nmesh, m->window, false, rec, amount(k + j), ws + l.bucket,
-                         zero, t->tw, mesh, nullptr, s);
+                         zero, t->tw, mesh, nullptr, s, -1, /*exact=*/false);
       if (e == hipSuccess)
         e = launch_fft_y_relayout(m->dtype, m->nmesh, mesh, ysets[set][j], t->tw, s);
     }

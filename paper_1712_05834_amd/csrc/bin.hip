@@ -711,15 +711,20 @@ __global__ void __launch_bounds__(1024)
 // Plan time: per-bin counts (integers), sum h|n| and, for (k, mu) bins, counts,
 // sum h|n| and sum h|mu|, over the r2c half grid with its Hermitian weights.
 __global__ void __launch_bounds__(256)
-    k_mode_tables(int N, BinSpec b, double* __restrict__ partials) {
-  extern __shared__ double sb[];
+    k_mode_tables(int N, BinSpec b, unsigned long long* __restrict__ partials) {
+  // every slot is a 128-bit integer: low words [0, nslots), high words
+  // [nslots, 2 nslots); counts use the low word only, the sums are fixed
+  // point with kModeSumShift fraction bits (exact: a term h|n| < 2^13 has no
+  // bits below 2^-40), so the tables do not depend on the order of the adds
+  extern __shared__ unsigned long long sbw[];
   const int nslots = mode_table_slots(b.nk, b.nmu);
-  zero_bins(sb, nslots);
+  for (int i = threadIdx.x; i < 2 * nslots; i += blockDim.x) sbw[i] = 0;
   __syncthreads();
   const int NH = N / 2 + 1;
   const size_t total = (size_t)N * N * NH;
   const int nk = b.nk, nmu = b.nmu, los = b.los;
-  unsigned long long* cnt = reinterpret_cast<unsigned long long*>(sb);
+  unsigned long long* cnt = sbw;
+  constexpr int S = kModeSumShift;
   for (size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
        idx += (size_t)gridDim.x * blockDim.x) {
     const int kz = (int)(idx % NH);
@@ -732,18 +737,18 @@ __global__ void __launch_bounds__(256)
     const int h = (kz == 0 || kz == N / 2) ? 1 : 2;
     const double kn = sqrt((double)n2);
     atomicAdd(&cnt[k], (unsigned long long)h);
-    atomicAdd(&sb[nk + k], h * kn);
+    fix_add<double>(sbw, nslots, nk + k, h * kn, S);
     if (nmu > 1) {
       const int nl = los == 0 ? nx : (los == 1 ? ny : nz);
       const int f = k * nmu + mubin_of(nl * nl, n2, nmu);
       atomicAdd(&cnt[2 * nk + f], (unsigned long long)h);
-      atomicAdd(&sb[2 * nk + nk * nmu + f], h * kn);
-      atomicAdd(&sb[2 * nk + 2 * nk * nmu + f], h * (double)abs(nl) / kn);
+      fix_add<double>(sbw, nslots, 2 * nk + nk * nmu + f, h * kn, S);
+      fix_add<double>(sbw, nslots, 2 * nk + 2 * nk * nmu + f, h * (double)abs(nl) / kn, S);
     }
   }
   __syncthreads();
-  for (int i = threadIdx.x; i < nslots; i += blockDim.x)
-    partials[(size_t)blockIdx.x * nslots + i] = sb[i];
+  for (int i = threadIdx.x; i < 2 * nslots; i += blockDim.x)
+    partials[(size_t)blockIdx.x * 2 * nslots + i] = sbw[i];
 }
 
 // Mode (nx, ny, nz) of a packed half spectrum, signed indices in
@@ -798,21 +803,23 @@ __global__ void __launch_bounds__(256)
 }
 
 // Sums the mode-table partial rows; integer slots are summed as integers.
-__global__ void k_reduce_tables(const double* __restrict__ partials, int ngroups, int nk, int nmu,
-                                double* __restrict__ out) {
+__global__ void k_reduce_tables(const unsigned long long* __restrict__ partials, int ngroups,
+                                int nk, int nmu, double* __restrict__ out) {
   const int nslots = mode_table_slots(nk, nmu);
   const int s = blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= nslots) return;
   const bool integer = s < nk || (nmu > 1 && s >= 2 * nk && s < 2 * nk + nk * nmu);
+  unsigned long long lo = 0, hi = 0;
+  for (int g = 0; g < ngroups; ++g) {
+    const unsigned long long* row = partials + (size_t)g * 2 * nslots;
+    const unsigned long long old = lo;
+    lo += row[s];
+    hi += row[nslots + s] + (lo < old ? 1ull : 0ull);
+  }
   if (integer) {
-    const unsigned long long* p = reinterpret_cast<const unsigned long long*>(partials);
-    unsigned long long acc = 0;
-    for (int g = 0; g < ngroups; ++g) acc += p[(size_t)g * nslots + s];
-    reinterpret_cast<unsigned long long*>(out)[s] = acc;
+    reinterpret_cast<unsigned long long*>(out)[s] = lo;
   } else {
-    double acc = 0.0;
-    for (int g = 0; g < ngroups; ++g) acc += partials[(size_t)g * nslots + s];
-    out[s] = acc;
+    out[s] = fix_words_value(lo, hi, kModeSumShift);
   }
 }
 
@@ -1164,9 +1171,10 @@ hipError_t launch_reduce(const double* partials, int ngroups, const BinSpec& b, 
 hipError_t launch_mode_tables(int nmesh, const BinSpec& b, double* partials, int ngroups,
                               double* out, hipStream_t s) {
   const int nslots = mode_table_slots(b.nk, b.nmu);
-  hipLaunchKernelGGL(k_mode_tables, dim3(ngroups), dim3(256), (size_t)nslots * sizeof(double), s,
-                     nmesh, b, partials);
-  hipLaunchKernelGGL(k_reduce_tables, dim3((nslots + 255) / 256), dim3(256), 0, s, partials,
+  unsigned long long* words = reinterpret_cast<unsigned long long*>(partials);
+  hipLaunchKernelGGL(k_mode_tables, dim3(ngroups), dim3(256),
+                     (size_t)2 * nslots * sizeof(unsigned long long), s, nmesh, b, words);
+  hipLaunchKernelGGL(k_reduce_tables, dim3((nslots + 255) / 256), dim3(256), 0, s, words,
                      ngroups, b.nk, b.nmu, out);
   return hipGetLastError();
 }

@@ -87,6 +87,9 @@ struct BinSpec {
 //   [0, nk) counts (as uint64 bits), [nk, 2nk) sum h|n|,
 //   then, if nmu > 1: counts2d, sum h|n| 2d, sum h|mu| 2d (nk * nmu each).
 __host__ __device__ inline int mode_table_slots(int nk, int nmu) { return 2 * nk + (nmu > 1 ? 3 * nk * nmu : 0); }
+// Fraction bits of the fixed-point mode-table sums (sum h|n| < 2 N^4 <= 2^45
+// for N <= 2048, held in 128 bits with room to spare).
+constexpr int kModeSumShift = 80;
 
 // LDS available to one workgroup on gfx950, and its compute units.
 constexpr size_t kLdsBytesPerGroup = 160 * 1024;
@@ -110,11 +113,15 @@ hipError_t launch_bucket(int dtype, int nmesh, double boxsize, const void* pos, 
                          double* wsums, hipStream_t s, void* scratch = nullptr,
                          size_t scratch_bytes = 0);
 // split: interlaced meshes painted by two single-mesh launches (1), one
-// two-mesh launch (0), or the default for the window (-1).
+// two-mesh launch (0), or the default for the window (-1).  exact: float32
+// meshes take cell sums in 64-bit fixed point with a scale from wsums[1]
+// (sum of squared amounts) and the record count, independent of the order
+// of the adds; otherwise (float64 meshes, callers whose wsums do not bound
+// the amounts) float64 sums.
 hipError_t launch_paint_z(int dtype, int nmesh, int order, bool inter, const void* rec,
                           const void* wrec, const void* bucket_ws, const double* wsums,
                           const void* tw, void* mesh_a, void* mesh_b, hipStream_t s,
-                          int split = -1);
+                          int split = -1, bool exact = true);
 
 hipError_t launch_fft_z(int dtype, int nmesh, void* mesh, int nmeshes, size_t mesh_stride_bytes,
                         const void* tw, const double* wsum_for_mean, hipStream_t s);

@@ -30,9 +30,11 @@
 // 4. k_paint_z        one workgroup owns a TX x TY block of full z-columns of
 //                     both meshes: it reads the records of the columns whose
 //                     windows reach the block, adds the window weights into
-//                     float64 LDS rows (ds_add_f64), then runs the r2c FFT of
-//                     every column in LDS and writes the packed rows once.  No
-//                     mesh clear, no atomics to HBM, no separate z-pass.
+//                     64-bit LDS rows (exact fixed point, ds_add_u64, for
+//                     float32 meshes; float64, ds_add_f64, otherwise), then
+//                     runs the r2c FFT of every column in LDS and writes the
+//                     packed rows once.  No mesh clear, no atomics to HBM, no
+//                     separate z-pass.
 #include "fft_config.h"
 #include "internal.h"
 #include "window.h"
@@ -209,7 +211,10 @@ __device__ void slab_count_block(const T* __restrict__ pos, const T* __restrict_
           const double wp = weight ? (double)weight[i] : 1.0;
           const double wv = value ? wp * (double)value[i] : wp;
           ws += wp;
-          ws2 += wv * wv;
+          // a non-finite coordinate makes sum (w V)^2 NaN, and with it the
+          // painted cells and the shot noise
+          const double pc = (double)pos[3 * i] + (double)pos[3 * i + 1] + (double)pos[3 * i + 2];
+          ws2 += isfinite(pc) ? wv * wv : __longlong_as_double(0x7ff8000000000000ll);
         }
       }
 #pragma unroll
@@ -370,7 +375,10 @@ __global__ void __launch_bounds__(256)
         const double wp = weight ? (double)weight[i] : 1.0;
         const double wv = value ? wp * (double)value[i] : wp;
         ws += wp;
-        ws2 += wv * wv;
+        // a non-finite coordinate makes sum (w V)^2 NaN, and with it the
+        // painted cells and the shot noise
+        const double pc = (double)pos[3 * i] + (double)pos[3 * i + 1] + (double)pos[3 * i + 2];
+        ws2 += isfinite(pc) ? wv * wv : __longlong_as_double(0x7ff8000000000000ll);
       }
     }
 #pragma unroll
@@ -749,6 +757,12 @@ constexpr int kPaintA = 0, kPaintB = 1, kPaintAB = 2;
 // against 0.85 ms).  The tuner can still choose two launches per input.
 constexpr bool split_interlaced(int) { return false; }
 
+// 1.5 * 2^52 and its bits: adding it to a double of magnitude below 2^51
+// rounds that double to an integer and leaves it, two's complement, in the
+// low bits.
+constexpr double kFixMagic = 6755399441055744.0;
+constexpr unsigned long long kFixMagicBits = 0x4338000000000000ull;
+
 // A store of output that no later kernel reads while it is still cached (the
 // painted meshes, 1-9 GB): nontemporal, so that it does not displace the
 // records the next workgroups gather (Zel'dovich 1024^3 paint: 5.18 ->
@@ -831,7 +845,7 @@ __global__ void __launch_bounds__((PaintCfg<T, N, P, MODE>::THREADS))
     k_paint_z(const typename Rec<T>::type* __restrict__ rec, const T* __restrict__ wrec,
               const int* __restrict__ offsets, const double* __restrict__ wsums,
               const cpx<T>* __restrict__ tw,
-              T* __restrict__ mesh_a, T* __restrict__ mesh_b) {
+              T* __restrict__ mesh_a, T* __restrict__ mesh_b, int exact_in) {
   using Cf = PaintCfg<T, N, P, MODE>;
   using Acc = double;
   constexpr int M = Cf::M, TX = Cf::TX, TY = Cf::TY;
@@ -874,6 +888,38 @@ __global__ void __launch_bounds__((PaintCfg<T, N, P, MODE>::THREADS))
     }
   }
   const double wsum = wsums[0];  // for the mean subtracted before the z-FFT
+  // Exact painting: each product is rounded once to a multiple of 2^-S and
+  // added as a 64-bit integer, so that a cell's sum is the same whatever the
+  // order of its adds (and whatever the tiling).  S is one scale for the
+  // whole mesh, from bounds that hold a priori: a cell's sum is at most
+  // sum |a| <= sqrt(n sum a^2) (amounts a = w V, n records; the window
+  // weights are at most 1), so 2^S sqrt(n sum a^2) < 2^62 keeps every sum in
+  // range; one term is at most max |a| <= sqrt(sum a^2), and 2^S sqrt(sum a^2)
+  // < 2^50 keeps each term below 2^51, where adding 1.5 * 2^52 rounds it to
+  // an integer held in the low mantissa bits.  With unit weights S = 38 for
+  // 10^7 particles and 35 for 1.3 x 10^8 (2.9e-11 per term, far below the
+  // float32 rounding of a cell; float64 meshes take the float64 sums).  A
+  // non-finite amount or coordinate (the bucketing makes the sum of squares
+  // NaN then) makes every cell NaN, as float64 sums would.
+  // (Amounts so large that 2^-S would leave the float32 range, |a| beyond
+  // ~10^27, take the float64 sums.)
+  double fix_scale = 1.0, fix_inv = 1.0;
+  bool fix_bad = false, exact = exact_in != 0;
+  if (exact) {
+    const double nt = (double)offsets[N * N];
+    const double w2 = wsums[1];
+    if (!isfinite(w2)) {
+      fix_bad = true;
+    } else if (nt > 0.0 && w2 > 0.0) {
+      const int e1 = ilogb(sqrt(nt * w2)) + 1, e2 = ilogb(sqrt(w2)) + 1;
+      int S = 62 - e1 < 50 - e2 ? 62 - e1 : 50 - e2;
+      if (S > 120) S = 120;  // tiny amounts: a coarser grid still holds them
+      if (S < -90) exact = false;
+      fix_scale = ldexp(1.0, S);
+      fix_inv = ldexp(1.0, -S);
+    }
+  }
+
   constexpr int STS = stage_table_size<M, Cf::FE>();
   constexpr bool EARLY_TW = M <= Cf::THREADS && STS <= Cf::THREADS;
   cpx<T> tw_m{}, tw_s{};
@@ -988,9 +1034,9 @@ __global__ void __launch_bounds__((PaintCfg<T, N, P, MODE>::THREADS))
         // address is computed once per row, the cells are immediate
         // offsets); products in float64 from the z weights converted once
         const int zb = first[2] + Cf::ZPAD_LO;
-        double wz[P];
+        double wz[P];  // exact painting: scaled by 2^S (exactly)
 #pragma unroll
-        for (int c = 0; c < P; ++c) wz[c] = (double)w[2][c];
+        for (int c = 0; c < P; ++c) wz[c] = exact ? (double)w[2][c] * fix_scale : (double)w[2][c];
 #pragma unroll
         for (int a = 0; a < P; ++a) {
           const int lx = (first[0] + a - X0) & mask;
@@ -1002,8 +1048,19 @@ __global__ void __launch_bounds__((PaintCfg<T, N, P, MODE>::THREADS))
             if (ly >= TY) continue;
             const double wab = (double)(wa * w[1][b2]);
             Acc* row = acc + ((mesh * TX + lx) * TY + ly) * ROWA + zb;
+            if (exact) {
+              // the bits of 1.5 * 2^52 + v minus those of 1.5 * 2^52: v
+              // rounded to an integer, two's complement (|v| < 2^51)
+              unsigned long long* irow = reinterpret_cast<unsigned long long*>(row);
 #pragma unroll
-            for (int c = 0; c < P; ++c) atomicAdd(&row[c], wab * wz[c]);
+              for (int c = 0; c < P; ++c) {
+                const double y = __builtin_fma(wab, wz[c], kFixMagic);
+                atomicAdd(&irow[c], (unsigned long long)__double_as_longlong(y) - kFixMagicBits);
+              }
+            } else {
+#pragma unroll
+              for (int c = 0; c < P; ++c) atomicAdd(&row[c], wab * wz[c]);
+            }
           }
         }
       }
@@ -1021,11 +1078,15 @@ __global__ void __launch_bounds__((PaintCfg<T, N, P, MODE>::THREADS))
   static_assert(N >= 4, "the images of the pad cells must be distinct");
   for (int i = threadIdx.x; i < ROWS * 4; i += blockDim.x) {
     Acc* row = acc + (i >> 2) * ROWA;
+    unsigned long long* irow = reinterpret_cast<unsigned long long*>(row);
     const int j = i & 3;
-    if (j == 0) {
-      row[N] += row[0];  // cell -1 (word 0) into cell N - 1 (word N)
+    // cell -1 (word 0) into cell N - 1 (word N); cell N + j - 1 into cell
+    // j - 1 (word j)
+    const int dst = j == 0 ? N : j, src = j == 0 ? 0 : N + j;
+    if (exact) {
+      irow[dst] += irow[src];
     } else {
-      row[j] += row[N + j];  // cell N + j - 1 into cell j - 1 (word j)
+      row[dst] += row[src];
     }
   }
   __syncthreads();
@@ -1043,7 +1104,15 @@ __global__ void __launch_bounds__((PaintCfg<T, N, P, MODE>::THREADS))
   // r2c along z of every owned column, mean subtracted in float64 before the
   // rounding to T (only the DC mode changes; it keeps the rounding relative to
   // the fluctuations).  The row becomes the padded complex line.
-  const double mean = wsum / ((double)N * N * N);
+  const bool nan_cells = fix_bad;
+  const double mean = nan_cells ? __longlong_as_double(0x7ff8000000000000ll)
+                                : wsum / ((double)N * N * N);
+  // exact painting: the mean is subtracted on the integer grid (it only
+  // moves the DC mode), and the difference d = hi 2^32 + lo goes to float32
+  // as hi 2^(32-S) + lo 2^-S in float32 arithmetic (no float64 operations
+  // per cell; within 1.5 ulp of the rounded value)
+  const long long mean_q = exact && !nan_cells ? __double2ll_rn(mean * fix_scale) : 0ll;
+  const float f_lo = exact ? (float)fix_inv : 0.f, f_hi = exact ? (float)(fix_inv * 4294967296.0) : 0.f;
   constexpr int FE = Cf::FE, FTPL = Cf::FTPL;
   const bool fa = (int)threadIdx.x < Cf::FTHREADS;
   const int r = fa ? (int)threadIdx.x / FTPL : 0, t = (int)threadIdx.x % FTPL;
@@ -1054,7 +1123,15 @@ __global__ void __launch_bounds__((PaintCfg<T, N, P, MODE>::THREADS))
 #pragma unroll
     for (int e = 0; e < FE; ++e) {
       const int wj = 2 * (t + FTPL * e) + Cf::ZPAD_LO;  // cells 2j, 2j + 1
-      v[e] = {static_cast<T>(arow[wj] - mean), static_cast<T>(arow[wj + 1] - mean)};
+      if (exact) {
+        const long long* irow = reinterpret_cast<const long long*>(arow);
+        const long long d0 = irow[wj] - mean_q, d1 = irow[wj + 1] - mean_q;
+        v[e] = {static_cast<T>(fmaf((float)(int)(d0 >> 32), f_hi, (float)(unsigned)d0 * f_lo)),
+                static_cast<T>(fmaf((float)(int)(d1 >> 32), f_hi, (float)(unsigned)d1 * f_lo))};
+        if (nan_cells) v[e] = {static_cast<T>(mean), static_cast<T>(mean)};
+      } else {
+        v[e] = {static_cast<T>(arow[wj] - mean), static_cast<T>(arow[wj + 1] - mean)};
+      }
     }
   }
   __syncthreads();  // all cells read before the row is reused
@@ -1215,22 +1292,22 @@ hipError_t launch_bucket(int dtype, int nmesh, double boxsize, const void* pos, 
 template <typename T, int N, int P, int MODE>
 static hipError_t paint_z_t(const void* rec, const void* wrec, const int* offsets,
                             const double* wsums, const void* tw,
-                            void* mesh_a, void* mesh_b, hipStream_t s) {
+                            void* mesh_a, void* mesh_b, bool exact, hipStream_t s) {
   using Cf = PaintCfg<T, N, P, MODE>;
   const unsigned blocks = (unsigned)((N / Cf::TX) * (N / Cf::TY));
   hipLaunchKernelGGL((k_paint_z<T, N, P, MODE>), dim3(blocks), dim3(Cf::THREADS), 0, s,
                      static_cast<const typename Rec<T>::type*>(rec),
                      static_cast<const T*>(wrec), offsets, wsums,
                      static_cast<const cpx<T>*>(tw), static_cast<T*>(mesh_a),
-                     static_cast<T*>(mesh_b));
+                     static_cast<T*>(mesh_b), exact ? 1 : 0);
   return hipGetLastError();
 }
 
 template <typename T, int N>
 static hipError_t paint_z_n(int order, bool inter, const void* rec, const void* wrec,
                             const int* offsets, const double* wsums, const void* tw,
-                            void* mesh_a, void* mesh_b, int split, hipStream_t s) {
-#define PK_PZ(P, MODE, A) paint_z_t<T, N, P, MODE>(rec, wrec, offsets, wsums, tw, A, mesh_b, s)
+                            void* mesh_a, void* mesh_b, int split, bool exact, hipStream_t s) {
+#define PK_PZ(P, MODE, A) paint_z_t<T, N, P, MODE>(rec, wrec, offsets, wsums, tw, A, mesh_b, exact, s)
 #define PK_PZ_ORDER(MODE, A)                                            \
   (order == 2 ? PK_PZ(2, MODE, A) : (order == 3 ? PK_PZ(3, MODE, A) : PK_PZ(4, MODE, A)))
   if (!inter) return PK_PZ_ORDER(kPaintA, mesh_a);
@@ -1244,19 +1321,23 @@ static hipError_t paint_z_n(int order, bool inter, const void* rec, const void* 
 
 hipError_t launch_paint_z(int dtype, int nmesh, int order, bool inter, const void* rec,
                           const void* wrec, const void* bucket_ws, const double* wsums,
-                          const void* tw, void* mesh_a, void* mesh_b, hipStream_t s, int split) {
+                          const void* tw, void* mesh_a, void* mesh_b, hipStream_t s, int split,
+                          bool exact) {
   const int* offsets = static_cast<const int*>(bucket_ws) + (size_t)nmesh * nmesh;
+  // float64 meshes keep float64 sums: one 64-bit fixed-point scale cannot
+  // span both the a-priori range of a cell and float64 precision within it
+  if (dtype != PK_F32) exact = false;
 #define PK_PN(T)                                                                           \
   switch (nmesh) {                                                                         \
-    case 8: return paint_z_n<T, 8>(order, inter, rec, wrec, offsets, wsums, tw, mesh_a, mesh_b, split, s); \
-    case 16: return paint_z_n<T, 16>(order, inter, rec, wrec, offsets, wsums, tw, mesh_a, mesh_b, split, s); \
-    case 32: return paint_z_n<T, 32>(order, inter, rec, wrec, offsets, wsums, tw, mesh_a, mesh_b, split, s); \
-    case 64: return paint_z_n<T, 64>(order, inter, rec, wrec, offsets, wsums, tw, mesh_a, mesh_b, split, s); \
-    case 128: return paint_z_n<T, 128>(order, inter, rec, wrec, offsets, wsums, tw, mesh_a, mesh_b, split, s); \
-    case 256: return paint_z_n<T, 256>(order, inter, rec, wrec, offsets, wsums, tw, mesh_a, mesh_b, split, s); \
-    case 512: return paint_z_n<T, 512>(order, inter, rec, wrec, offsets, wsums, tw, mesh_a, mesh_b, split, s); \
-    case 1024: return paint_z_n<T, 1024>(order, inter, rec, wrec, offsets, wsums, tw, mesh_a, mesh_b, split, s); \
-    case 2048: return paint_z_n<T, 2048>(order, inter, rec, wrec, offsets, wsums, tw, mesh_a, mesh_b, split, s); \
+    case 8: return paint_z_n<T, 8>(order, inter, rec, wrec, offsets, wsums, tw, mesh_a, mesh_b, split, exact, s); \
+    case 16: return paint_z_n<T, 16>(order, inter, rec, wrec, offsets, wsums, tw, mesh_a, mesh_b, split, exact, s); \
+    case 32: return paint_z_n<T, 32>(order, inter, rec, wrec, offsets, wsums, tw, mesh_a, mesh_b, split, exact, s); \
+    case 64: return paint_z_n<T, 64>(order, inter, rec, wrec, offsets, wsums, tw, mesh_a, mesh_b, split, exact, s); \
+    case 128: return paint_z_n<T, 128>(order, inter, rec, wrec, offsets, wsums, tw, mesh_a, mesh_b, split, exact, s); \
+    case 256: return paint_z_n<T, 256>(order, inter, rec, wrec, offsets, wsums, tw, mesh_a, mesh_b, split, exact, s); \
+    case 512: return paint_z_n<T, 512>(order, inter, rec, wrec, offsets, wsums, tw, mesh_a, mesh_b, split, exact, s); \
+    case 1024: return paint_z_n<T, 1024>(order, inter, rec, wrec, offsets, wsums, tw, mesh_a, mesh_b, split, exact, s); \
+    case 2048: return paint_z_n<T, 2048>(order, inter, rec, wrec, offsets, wsums, tw, mesh_a, mesh_b, split, exact, s); \
     default: return hipErrorInvalidValue;                                                  \
   }
   if (dtype == PK_F32) {

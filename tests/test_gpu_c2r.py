@@ -53,7 +53,7 @@ def test_round_trip_is_n_cubed_times_the_field(ctx, dtype, n):
 
 
 @pytest.mark.parametrize("dtype", ["f8", "f4"])
-@pytest.mark.parametrize("n", [16, 32, 256])
+@pytest.mark.parametrize("n", [16, 32, 256, 512])
 def test_backward_transform_of_a_shaped_spectrum_matches_oracle(ctx, dtype, n):
     rng = np.random.default_rng(100 + n)
     c = oracle.r2c(rng.standard_normal((n, n, n)))

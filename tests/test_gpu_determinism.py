@@ -1,12 +1,15 @@
-"""Bitwise reproducibility of the bin sums (FFTPower binning, Sec. 3.4.1).
+"""Bitwise reproducibility of the bin sums (FFTPower binning, Sec. 3.4.1)
+and of the fused painting (Sec. 3.3.1, Eq. 1).
 
 Every bin sum is an exact 128-bit fixed-point sum (the per-mode terms are
 truncated once to a grid set by an a-priori bound; integer addition does not
 depend on order), and the per-workgroup partial rows are added exactly too.
 So the binning of a given spectrum gives the same bits on every call,
 whatever the order in which lanes and workgroups add and however many
-workgroups there are.  The painting adds float64 terms in LDS in no fixed
-order and is not covered: pk_fftpower is reproducible to rounding only."""
+workgroups there are.  The fused painting of pk_fftpower adds its terms as
+64-bit fixed-point integers on one scale for the whole mesh, so each cell is
+the same whatever the order of its adds and whatever the tiling; with the
+deterministic FFT passes pk_fftpower gives the same bits on every call."""
 
 import numpy as np
 import pytest
@@ -71,22 +74,44 @@ def test_binning_of_a_non_finite_spectrum_is_nan(ctx):
     assert bool(torch.isnan(r[:-2]).any())
 
 
-def test_fused_path_repeats_to_rounding_of_the_painting(ctx):
-    # pk_fftpower twice on one catalog: the binning is exact, the painting's
-    # float64 LDS sums are not in a fixed order; the results agree to the
-    # float32 bar (they usually agree bit for bit)
-    n, box = 128, 700.0
+@pytest.mark.parametrize("window", ["cic", "tsc", "pcs"])
+@pytest.mark.parametrize("weighted", [False, True])
+def test_fused_path_twice_is_bitwise_equal(ctx, window, weighted):
+    # pk_fftpower twice on one catalog (clustered, so that many adds meet in
+    # one cell): the same bits, the painted mesh included
+    n, box, npart = 128, 700.0, 300_000
     rng = np.random.default_rng(7)
-    pos = torch.from_numpy(rng.uniform(0, box, (200_000, 3)).astype(np.float32)).to("cuda:0")
-    m = _lib.mesh_desc(n, box, "tsc", True, True, "f4")
+    centres = rng.uniform(0, box, (300, 3))
+    pos = (centres[rng.integers(0, 300, npart)] + rng.normal(0, 3.0, (npart, 3))) % box
+    pos = torch.from_numpy(pos.astype(np.float32)).to("cuda:0")
+    w = (torch.from_numpy(rng.uniform(0.1, 3.0, npart).astype(np.float32)).to("cuda:0")
+         if weighted else None)
+    m = _lib.mesh_desc(n, box, window, True, True, "f4")
     b = _lib.bin_desc(n // 2, 0.0, 1.0, 4, (0, 2, 4), 2)
-    ws = torch.empty(_lib.workspace_bytes(m, b, 200_000), dtype=torch.uint8, device="cuda:0")
-    outs = []
+    ws = torch.empty(_lib.workspace_bytes(m, b, npart), dtype=torch.uint8, device="cuda:0")
+    rs, meshes = [], []
     for _ in range(2):
         r = torch.empty(_lib.result_doubles(b), dtype=torch.float64, device="cuda:0")
-        ctx.pk_fftpower(m, b, pos, None, 200_000, ws, r)
-        outs.append(ctx.pk_result_to_host(m, b, r))
-    ok = outs[0]["modes"] > 0
-    np.testing.assert_allclose(outs[0]["power"][ok], outs[1]["power"][ok], rtol=1e-6)
-    same = np.array_equal(outs[0]["power"], outs[1]["power"], equal_nan=True)
-    print(f"\npk_fftpower twice: bitwise equal = {same}")
+        ctx.pk_fftpower(m, b, pos, w, npart, ws, r)
+        torch.cuda.synchronize()
+        rs.append(r.clone())
+        meshes.append(ws.clone())
+    assert torch.equal(rs[0], rs[1])
+    assert bool(torch.isfinite(rs[0][:-2]).all())
+    del meshes
+
+
+def test_fused_path_with_a_non_finite_weight_is_nan(ctx):
+    # the fixed-point painting must not turn a NaN amount into finite cells
+    n, box, npart = 32, 100.0, 5000
+    rng = np.random.default_rng(8)
+    pos = torch.from_numpy(rng.uniform(0, box, (npart, 3)).astype(np.float32)).to("cuda:0")
+    w = torch.ones(npart, dtype=torch.float32, device="cuda:0")
+    w[17] = float("nan")
+    m = _lib.mesh_desc(n, box, "cic", True, True, "f4")
+    b = _lib.bin_desc(n // 2, 0.0, 1.0, 0, (0, 2), 2)
+    ws = torch.empty(_lib.workspace_bytes(m, b, npart), dtype=torch.uint8, device="cuda:0")
+    r = torch.empty(_lib.result_doubles(b), dtype=torch.float64, device="cuda:0")
+    ctx.pk_fftpower(m, b, pos, w, npart, ws, r)
+    torch.cuda.synchronize()
+    assert bool(torch.isnan(r[: b.nk]).all())

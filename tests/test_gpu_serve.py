@@ -1,5 +1,5 @@
 """Serving: every request served in a concurrent mix gives the result it
-gives alone (within the float32 bar), and the oracle's.
+gives alone, bit for bit, and the oracle's (within the float32 bar).
 
 Twelve requests of mixed mesh sizes, windows, interlacing, catalog kinds and
 sizes arrive in a burst, so that four lanes run them concurrently."""
@@ -53,10 +53,52 @@ def test_same_alone_and_in_the_mix():
         ctx.pk_fftpower(r.mesh, r.bins, r.pos, None, r.npart, ws, res)
         alone = ctx.pk_result_to_host(r.mesh, r.bins, res)
         check_power(r.result, alone, 1e-5, f"request {r.rid} mix vs alone")
+        # exact paint and bin sums: the mix changes no bit
+        np.testing.assert_array_equal(r.result["power"], alone["power"])
     for r in served[:3]:
         want = oracle.fftpower(r.pos.cpu().numpy().astype(np.float64), r.mesh.nmesh,
                                r.mesh.boxsize, int(r.mesh.window), bool(r.mesh.interlaced), True,
                                nk=r.bins.nk, nmu=r.bins.nmu, poles=(0, 2))
         check_power(r.result, want, 1e-5, f"request {r.rid} vs oracle")
+    torch.cuda.synchronize()
+    ctx.close()
+
+
+def test_large_meshes_alone_and_in_the_mix():
+    """Requests on 256^3 and 512^3 meshes (the fused kernels of the larger
+    instantiations) served concurrently with small ones: each equals its
+    result alone; a 256^3 and a 512^3 request equal the oracle's."""
+    rng = np.random.default_rng(56)
+    reqs = []
+    for i, n in enumerate([256, 512, 64, 256, 512, 128]):
+        box = float(rng.uniform(500, 1500))
+        window = ["tsc", "cic", "pcs"][i % 3]
+        npart = int(10 ** rng.uniform(5, 6.3))
+        pos = torch.from_numpy(synth.uniform_catalog(npart, box, seed=600 + i,
+                                                     dtype=np.float32)).to("cuda:0")
+        m = _lib.mesh_desc(n, box, window, bool(i % 2 == 0), True, "f4")
+        b = _lib.bin_desc(n // 2, 0.0, 1.0, 0, (0, 2), 2)
+        reqs.append(Request(i, 0.0002 * i, m, b, pos, pos.shape[0]))
+    ctx = _lib.Context(0)
+    backend = LibpkBackend(ctx, lanes=3)
+    print(f"\nserving {len(reqs)} requests (64^3 .. 512^3) on 3 lanes", flush=True)
+    served = Server(backend, budget=32 << 30).run(reqs)
+    for r in served:
+        ws = torch.empty(_lib.workspace_bytes(r.mesh, r.bins, r.npart), dtype=torch.uint8,
+                         device="cuda:0")
+        res = torch.empty(_lib.result_doubles(r.bins), dtype=torch.float64, device="cuda:0")
+        ctx.pk_fftpower(r.mesh, r.bins, r.pos, None, r.npart, ws, res)
+        alone = ctx.pk_result_to_host(r.mesh, r.bins, res)
+        check_power(r.result, alone, 1e-5, f"request {r.rid} (N={r.mesh.nmesh}) mix vs alone")
+        np.testing.assert_array_equal(r.result["power"], alone["power"])
+        del ws
+    for r in served:
+        if r.rid not in (0, 1):
+            continue
+        print(f"oracle for request {r.rid}: N={r.mesh.nmesh}, {r.npart} particles", flush=True)
+        want = oracle.fftpower(r.pos.cpu().numpy().astype(np.float64), r.mesh.nmesh,
+                               r.mesh.boxsize, int(r.mesh.window), bool(r.mesh.interlaced), True,
+                               nk=r.bins.nk, nmu=0, poles=(0, 2))
+        check_power(r.result, want, 1e-5, f"request {r.rid} (N={r.mesh.nmesh}) vs oracle")
     torch.cuda.synchronize()
     ctx.close()
