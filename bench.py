@@ -137,6 +137,90 @@ def measured_traffic(workload, kernel):
     return None if k is None else k.get("bytes_per_launch")
 
 
+# Kernels of each pk_fftpower stage, by name prefix (plan-time tables and
+# copies are not part of a call).
+STAGE_KERNELS = {
+    "bucket": ("k_fill_zero", "k_order_probe", "k_bucket_count", "k_weight_sums", "k_scan_",
+               "k_slab_columns", "k_bucket_scatter"),
+    "paint_z": ("k_paint_z",),
+    "fft_y": ("k_fft_y_relayout",),
+    "xpass_bin": ("k_xpass_bin",),
+    "plane_bin": ("k_plane_bin",),
+    "reduce": ("k_reduce<", "k_reduce("),
+}
+
+
+def _counter_totals(directory, counter):
+    """{kernel name: [per-dispatch sums of counter]} from the rocprofv3 CSVs
+    under directory (rows of one dispatch summed over their dimensions)."""
+    import csv
+    import glob
+
+    per = {}
+    for path in glob.glob(os.path.join(directory, "**", "*counter_collection.csv"), recursive=True):
+        with open(path) as fh:
+            for row in csv.DictReader(fh):
+                if row.get("Counter_Name") != counter:
+                    continue
+                name = re.sub(r"^void ", "", row.get("Kernel_Name", ""))
+                key = (name, row.get("Dispatch_Id"))
+                per[key] = per.get(key, 0.0) + float(row["Counter_Value"])
+    out = {}
+    for (name, _), v in per.items():
+        out.setdefault(name, []).append(v)
+    return out
+
+
+def write_traffic(workload, directory, npart):
+    """profiles/traffic_<workload>.json from four rocprofv3 --pmc runs under
+    directory: pmc_FETCH_SIZE_<workload>, pmc_WRITE_SIZE_<workload> (the bench
+    with --steps 2 --warmup 1) and pmc_FETCH_SIZE_copy, pmc_WRITE_SIZE_copy
+    (--calibrate-copy 1024).  The counters, in KiB per dispatch, are scaled
+    by what they read for a plain copy of known size."""
+    w = WORKLOADS[workload]
+    copy_bytes = 1024 << 20
+    cal = {}
+    for counter in ("FETCH_SIZE", "WRITE_SIZE"):
+        vals = [v for vs in _counter_totals(os.path.join(directory, f"pmc_{counter}_copy"),
+                                            counter).values() for v in vs]
+        kib = max(vals)  # the copy kernel's dispatches (the largest ones)
+        cal[counter] = (kib, copy_bytes / (kib * 1024.0))
+    stages = {}
+    totals = {c: _counter_totals(os.path.join(directory, f"pmc_{c}_{workload}"), c)
+              for c in ("FETCH_SIZE", "WRITE_SIZE")}
+    calls = len(next((v for k, v in totals["FETCH_SIZE"].items() if "k_xpass_bin" in k), []))
+    for stage, prefixes in STAGE_KERNELS.items():
+        names = sorted({k for c in totals for k in totals[c]
+                        if any(k.startswith("pk::" + p) for p in prefixes)})
+        b = {}
+        for c, key in (("FETCH_SIZE", "fetch_bytes"), ("WRITE_SIZE", "write_bytes")):
+            kib = sum(sum(totals[c].get(k, [])) for k in names)
+            b[key] = kib * 1024.0 * cal[c][1] / max(calls, 1)
+        alg = algorithmic_bytes(stage, w, npart)
+        per = b["fetch_bytes"] + b["write_bytes"]
+        stages[stage] = {"kernels": names, **b, "bytes_per_launch": per,
+                         "algorithmic_bytes": alg,
+                         "ratio_to_algorithmic": per / alg if alg else None}
+    base = "python3 bench.py --workload {wl} --steps 2 --warmup 1 --no-cpu-baseline"
+    rec = {
+        "workload": workload, "npart": npart, "source_hash": source_hash(), "calls": calls,
+        "commands": [f"rocprofv3 --pmc {c} -f csv -d gpurun_out/pmc_{c}_{workload} -o run -- "
+                     + base.format(wl=workload) for c in ("FETCH_SIZE", "WRITE_SIZE")] +
+                    [f"rocprofv3 --pmc {c} -f csv -d gpurun_out/pmc_{c}_copy -o run -- "
+                     "python3 bench.py --calibrate-copy 1024" for c in ("FETCH_SIZE", "WRITE_SIZE")],
+        "calibration": {"copy_bytes": copy_bytes,
+                        "fetch_kib_reported": cal["FETCH_SIZE"][0], "fetch_scale": cal["FETCH_SIZE"][1],
+                        "write_kib_reported": cal["WRITE_SIZE"][0], "write_scale": cal["WRITE_SIZE"][1]},
+        "note": "bytes per pk_fftpower call (all launches of the stage), scaled by the copy "
+                "calibration",
+        "kernels": stages,
+    }
+    path = os.path.join(ROOT, "profiles", f"traffic_{workload}.json")
+    with open(path, "w") as fh:
+        json.dump(rec, fh, indent=1)
+    return path
+
+
 def cpu_model():
     try:
         with open("/proc/cpuinfo") as fh:
@@ -318,10 +402,19 @@ def main():
     ap.add_argument("--cpu-sample", type=float, default=None,
                     help="fraction of the catalog the oracle paints for cpu_baseline "
                          "(default: the whole catalog at 512^3 and below, 3%% at 1024^3)")
+    ap.add_argument("--traffic-from", default=None, metavar="DIR",
+                    help="write profiles/traffic_<workload>.json from the rocprofv3 --pmc "
+                         "FETCH_SIZE / WRITE_SIZE runs under DIR (see write_traffic) and exit; "
+                         "needs --npart, no GPU")
+    ap.add_argument("--npart", type=int, default=0,
+                    help="particles of the workload's catalog (for --traffic-from)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (3 times) and exit: the "
                          "reference for scaling rocprofv3 FETCH_SIZE / WRITE_SIZE counters")
     args = ap.parse_args()
+    if args.traffic_from:
+        print(write_traffic(args.workload, args.traffic_from, args.npart))
+        return
     if args.calibrate_copy:
         import torch
 

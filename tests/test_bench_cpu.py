@@ -69,3 +69,48 @@ def test_oracle_errors_follow_the_float32_bar_definitions():
     assert abs(e["P_kmu"] - 1e-3) < 1e-12
     got["modes"] = np.array([0, 4, 5])
     assert not bench.oracle_errors(got, want)["counts_equal"]
+
+
+def _counter_csv(path, rows):
+    os.makedirs(path, exist_ok=True)
+    with open(os.path.join(path, "run_counter_collection.csv"), "w") as fh:
+        fh.write("Dispatch_Id,Kernel_Name,Counter_Name,Counter_Value\n")
+        for d, name, counter, value in rows:
+            fh.write(f'{d},"{name}",{counter},{value}\n')
+
+
+def test_traffic_summary_scales_counters_by_the_copy(tmp_path, monkeypatch):
+    # a copy of 1 GiB whose FETCH_SIZE reads half its bytes (scale 2) and
+    # WRITE_SIZE all of them; three calls of a pipeline whose paint fetches
+    # 100 KiB (two dimension rows of 50) and writes 1000 KiB per call
+    d = str(tmp_path)
+    gib_kib = 1 << 20
+    _counter_csv(os.path.join(d, "pmc_FETCH_SIZE_copy"),
+                 [(1, "void at::fill_kernel", "FETCH_SIZE", 0),
+                  (2, "void at::copy_kernel", "FETCH_SIZE", gib_kib // 2)])
+    _counter_csv(os.path.join(d, "pmc_WRITE_SIZE_copy"),
+                 [(1, "void at::fill_kernel", "WRITE_SIZE", gib_kib),
+                  (2, "void at::copy_kernel", "WRITE_SIZE", gib_kib)])
+    fetch, write = [], []
+    for call in range(3):
+        base = 10 * call
+        fetch += [(base, "pk::k_paint_z<float, 512, 3, 2>(...)", "FETCH_SIZE", 50),
+                  (base, "pk::k_paint_z<float, 512, 3, 2>(...)", "FETCH_SIZE", 50),
+                  (base + 1, "pk::k_xpass_bin<float, 512>(...)", "FETCH_SIZE", 7)]
+        write += [(base, "pk::k_paint_z<float, 512, 3, 2>(...)", "WRITE_SIZE", 1000),
+                  (base + 1, "pk::k_xpass_bin<float, 512>(...)", "WRITE_SIZE", 1)]
+    fetch.append((99, "pk::k_mode_tables(...)", "FETCH_SIZE", 12345))  # plan time: ignored
+    _counter_csv(os.path.join(d, "pmc_FETCH_SIZE_lognormal-512"), fetch)
+    _counter_csv(os.path.join(d, "pmc_WRITE_SIZE_lognormal-512"), write)
+    monkeypatch.setattr(bench, "ROOT", d)
+    os.makedirs(os.path.join(d, "profiles"))
+    monkeypatch.setattr(bench, "source_hash", lambda: "f" * 16)
+    path = bench.write_traffic("lognormal-512", d, 9_997_050)
+    rec = json.load(open(path))
+    assert rec["calls"] == 3 and rec["source_hash"] == "f" * 16
+    assert rec["calibration"]["fetch_scale"] == 2.0 and rec["calibration"]["write_scale"] == 1.0
+    p = rec["kernels"]["paint_z"]
+    assert p["fetch_bytes"] == 100 * 1024 * 2.0 and p["write_bytes"] == 1000 * 1024
+    assert p["bytes_per_launch"] == p["fetch_bytes"] + p["write_bytes"]
+    assert rec["kernels"]["xpass_bin"]["fetch_bytes"] == 7 * 1024 * 2.0
+    assert rec["kernels"]["bucket"]["fetch_bytes"] == 0
