@@ -41,6 +41,14 @@
 
 namespace pk {
 
+// 1.5 * 2^52 and its bits: adding it to a double of magnitude below 2^51
+// rounds that double to an integer and leaves it, two's complement, in the
+// low bits.
+constexpr double kFixMagic = 6755399441055744.0;
+constexpr unsigned long long kFixMagicBits = 0x4338000000000000ull;
+// slots of the exact painting's grid in the bucketing workspace
+constexpr int kFixScale = 0, kFixInv = 1, kFixState = 2;
+
 template <typename T>
 struct Rec;
 template <>
@@ -408,11 +416,15 @@ __global__ void __launch_bounds__(256)
   }
 }
 
-// sum w and sum w^2 from the per-block partials of the route taken, in block
-// order.
+// sum w and sum (w V)^2 from the per-block partials of the route taken, in
+// block order; then the grid 2^-S of the exact painting from n and
+// sum (w V)^2 (see k_paint_z): fix[kFixScale] = 2^S, fix[kFixInv] = 2^-S,
+// fix[kFixState] = 0 (exact), 1 (non-finite amounts or coordinates: NaN
+// cells) or 2 (S out of range: float64 sums).
 __global__ void __launch_bounds__(1024)
     k_weight_sums(const double* __restrict__ wpart, int nblocks_runs, int nblocks_slabs,
-                  double* __restrict__ wsums, const int* __restrict__ mode) {
+                  double* __restrict__ wsums, const int* __restrict__ mode, int64_t n,
+                  double* __restrict__ fix) {
   const int nblocks = route_of(mode) == kRouteSlabs ? nblocks_slabs : nblocks_runs;
   __shared__ double sh[2][1024];
   double a = 0.0, b = 0.0;
@@ -433,6 +445,20 @@ __global__ void __launch_bounds__(1024)
   if (threadIdx.x == 0) {
     wsums[0] = sh[0][0];
     wsums[1] = sh[1][0];
+    const double w2 = sh[1][0], nt = (double)n;
+    double scale = 1.0, state = 0.0;
+    if (!isfinite(w2)) {
+      state = 1.0;
+    } else if (nt > 0.0 && w2 > 0.0) {
+      const int e1 = ilogb(sqrt(nt * w2)) + 1, e2 = ilogb(sqrt(w2)) + 1;
+      int S = 62 - e1 < 50 - e2 ? 62 - e1 : 50 - e2;
+      if (S > 120) S = 120;  // tiny amounts: a coarser grid still holds them
+      if (S < -90) state = 2.0;
+      scale = ldexp(1.0, S);
+    }
+    fix[kFixScale] = scale;
+    fix[kFixInv] = 1.0 / scale;  // exact: a power of two
+    fix[kFixState] = state;
   }
 }
 
@@ -757,11 +783,6 @@ constexpr int kPaintA = 0, kPaintB = 1, kPaintAB = 2;
 // against 0.85 ms).  The tuner can still choose two launches per input.
 constexpr bool split_interlaced(int) { return false; }
 
-// 1.5 * 2^52 and its bits: adding it to a double of magnitude below 2^51
-// rounds that double to an integer and leaves it, two's complement, in the
-// low bits.
-constexpr double kFixMagic = 6755399441055744.0;
-constexpr unsigned long long kFixMagicBits = 0x4338000000000000ull;
 
 // A store of output that no later kernel reads while it is still cached (the
 // painted meshes, 1-9 GB): nontemporal, so that it does not displace the
@@ -844,7 +865,7 @@ template <typename T, int N, int P, int MODE>
 __global__ void __launch_bounds__((PaintCfg<T, N, P, MODE>::THREADS))
     k_paint_z(const typename Rec<T>::type* __restrict__ rec, const T* __restrict__ wrec,
               const int* __restrict__ offsets, const double* __restrict__ wsums,
-              const cpx<T>* __restrict__ tw,
+              const double* __restrict__ fix, const cpx<T>* __restrict__ tw,
               T* __restrict__ mesh_a, T* __restrict__ mesh_b, int exact_in) {
   using Cf = PaintCfg<T, N, P, MODE>;
   using Acc = double;
@@ -902,22 +923,16 @@ __global__ void __launch_bounds__((PaintCfg<T, N, P, MODE>::THREADS))
   // non-finite amount or coordinate (the bucketing makes the sum of squares
   // NaN then) makes every cell NaN, as float64 sums would.
   // (Amounts so large that 2^-S would leave the float32 range, |a| beyond
-  // ~10^27, take the float64 sums.)
+  // ~10^27, take the float64 sums.)  The bucketing's k_weight_sums sets the
+  // scale once.
   double fix_scale = 1.0, fix_inv = 1.0;
   bool fix_bad = false, exact = exact_in != 0;
   if (exact) {
-    const double nt = (double)offsets[N * N];
-    const double w2 = wsums[1];
-    if (!isfinite(w2)) {
-      fix_bad = true;
-    } else if (nt > 0.0 && w2 > 0.0) {
-      const int e1 = ilogb(sqrt(nt * w2)) + 1, e2 = ilogb(sqrt(w2)) + 1;
-      int S = 62 - e1 < 50 - e2 ? 62 - e1 : 50 - e2;
-      if (S > 120) S = 120;  // tiny amounts: a coarser grid still holds them
-      if (S < -90) exact = false;
-      fix_scale = ldexp(1.0, S);
-      fix_inv = ldexp(1.0, -S);
-    }
+    const double state = fix[kFixState];
+    fix_bad = state == 1.0;
+    if (state == 2.0) exact = false;
+    fix_scale = fix[kFixScale];
+    fix_inv = fix[kFixInv];
   }
 
   constexpr int STS = stage_table_size<M, Cf::FE>();
@@ -1173,7 +1188,7 @@ static size_t round256(size_t x) { return (x + 255) & ~(size_t)255; }
 // float64 weight partials; then the route flag and, for the slab route, the
 // [block][slab] counts and the slab totals and cursors.
 struct BucketWs {
-  size_t count, offsets, cursor, bsums, wpart, mode, hist, slabc, total;
+  size_t count, offsets, cursor, bsums, wpart, fix, mode, hist, slabc, total;
   int nb;
   explicit BucketWs(int nmesh) {
     const size_t n2 = (size_t)nmesh * nmesh;
@@ -1183,7 +1198,8 @@ struct BucketWs {
     cursor = offsets + (n2 + 1) * sizeof(int);
     bsums = cursor + n2 * sizeof(int);
     wpart = round256(bsums + (size_t)(nb + 1) * sizeof(int));
-    mode = round256(wpart + 2 * kCountBlocks * sizeof(double));
+    fix = round256(wpart + 2 * kCountBlocks * sizeof(double));  // kFix* slots
+    mode = round256(fix + 4 * sizeof(double));
     const size_t nh = (size_t)nmesh * kSlabBlocks;
     hist = mode + 256;
     slabc = round256(hist + nh * sizeof(int));
@@ -1257,7 +1273,7 @@ hipError_t launch_bucket(int dtype, int nmesh, double boxsize, const void* pos, 
                        static_cast<const double*>(value), n, chunk, nmesh, boxsize, inv_box, cpl, count,
                        wpart, mode, sa);
   hipLaunchKernelGGL(k_weight_sums, dim3(1), dim3(1024), 0, s, wpart, (int)blocks, (int)sblocks,
-                     wsums, mode);
+                     wsums, mode, n, reinterpret_cast<double*>(bw + L.fix));
   // the run route's scan (zero counts on the slab route)
   hipLaunchKernelGGL(k_scan_blocks, dim3(nb), dim3(1024), 0, s, count, n2, bsums);
   hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(1024), 0, s, bsums, nb);
@@ -1291,13 +1307,13 @@ hipError_t launch_bucket(int dtype, int nmesh, double boxsize, const void* pos, 
 
 template <typename T, int N, int P, int MODE>
 static hipError_t paint_z_t(const void* rec, const void* wrec, const int* offsets,
-                            const double* wsums, const void* tw,
+                            const double* wsums, const double* fix, const void* tw,
                             void* mesh_a, void* mesh_b, bool exact, hipStream_t s) {
   using Cf = PaintCfg<T, N, P, MODE>;
   const unsigned blocks = (unsigned)((N / Cf::TX) * (N / Cf::TY));
   hipLaunchKernelGGL((k_paint_z<T, N, P, MODE>), dim3(blocks), dim3(Cf::THREADS), 0, s,
                      static_cast<const typename Rec<T>::type*>(rec),
-                     static_cast<const T*>(wrec), offsets, wsums,
+                     static_cast<const T*>(wrec), offsets, wsums, fix,
                      static_cast<const cpx<T>*>(tw), static_cast<T*>(mesh_a),
                      static_cast<T*>(mesh_b), exact ? 1 : 0);
   return hipGetLastError();
@@ -1305,9 +1321,11 @@ static hipError_t paint_z_t(const void* rec, const void* wrec, const int* offset
 
 template <typename T, int N>
 static hipError_t paint_z_n(int order, bool inter, const void* rec, const void* wrec,
-                            const int* offsets, const double* wsums, const void* tw,
-                            void* mesh_a, void* mesh_b, int split, bool exact, hipStream_t s) {
-#define PK_PZ(P, MODE, A) paint_z_t<T, N, P, MODE>(rec, wrec, offsets, wsums, tw, A, mesh_b, exact, s)
+                            const int* offsets, const double* wsums, const double* fix,
+                            const void* tw, void* mesh_a, void* mesh_b, int split, bool exact,
+                            hipStream_t s) {
+#define PK_PZ(P, MODE, A) \
+  paint_z_t<T, N, P, MODE>(rec, wrec, offsets, wsums, fix, tw, A, mesh_b, exact, s)
 #define PK_PZ_ORDER(MODE, A)                                            \
   (order == 2 ? PK_PZ(2, MODE, A) : (order == 3 ? PK_PZ(3, MODE, A) : PK_PZ(4, MODE, A)))
   if (!inter) return PK_PZ_ORDER(kPaintA, mesh_a);
@@ -1324,20 +1342,22 @@ hipError_t launch_paint_z(int dtype, int nmesh, int order, bool inter, const voi
                           const void* tw, void* mesh_a, void* mesh_b, hipStream_t s, int split,
                           bool exact) {
   const int* offsets = static_cast<const int*>(bucket_ws) + (size_t)nmesh * nmesh;
+  const double* fix = reinterpret_cast<const double*>(static_cast<const char*>(bucket_ws) +
+                                                      BucketWs(nmesh).fix);
   // float64 meshes keep float64 sums: one 64-bit fixed-point scale cannot
   // span both the a-priori range of a cell and float64 precision within it
   if (dtype != PK_F32) exact = false;
 #define PK_PN(T)                                                                           \
   switch (nmesh) {                                                                         \
-    case 8: return paint_z_n<T, 8>(order, inter, rec, wrec, offsets, wsums, tw, mesh_a, mesh_b, split, exact, s); \
-    case 16: return paint_z_n<T, 16>(order, inter, rec, wrec, offsets, wsums, tw, mesh_a, mesh_b, split, exact, s); \
-    case 32: return paint_z_n<T, 32>(order, inter, rec, wrec, offsets, wsums, tw, mesh_a, mesh_b, split, exact, s); \
-    case 64: return paint_z_n<T, 64>(order, inter, rec, wrec, offsets, wsums, tw, mesh_a, mesh_b, split, exact, s); \
-    case 128: return paint_z_n<T, 128>(order, inter, rec, wrec, offsets, wsums, tw, mesh_a, mesh_b, split, exact, s); \
-    case 256: return paint_z_n<T, 256>(order, inter, rec, wrec, offsets, wsums, tw, mesh_a, mesh_b, split, exact, s); \
-    case 512: return paint_z_n<T, 512>(order, inter, rec, wrec, offsets, wsums, tw, mesh_a, mesh_b, split, exact, s); \
-    case 1024: return paint_z_n<T, 1024>(order, inter, rec, wrec, offsets, wsums, tw, mesh_a, mesh_b, split, exact, s); \
-    case 2048: return paint_z_n<T, 2048>(order, inter, rec, wrec, offsets, wsums, tw, mesh_a, mesh_b, split, exact, s); \
+    case 8: return paint_z_n<T, 8>(order, inter, rec, wrec, offsets, wsums, fix, tw, mesh_a, mesh_b, split, exact, s); \
+    case 16: return paint_z_n<T, 16>(order, inter, rec, wrec, offsets, wsums, fix, tw, mesh_a, mesh_b, split, exact, s); \
+    case 32: return paint_z_n<T, 32>(order, inter, rec, wrec, offsets, wsums, fix, tw, mesh_a, mesh_b, split, exact, s); \
+    case 64: return paint_z_n<T, 64>(order, inter, rec, wrec, offsets, wsums, fix, tw, mesh_a, mesh_b, split, exact, s); \
+    case 128: return paint_z_n<T, 128>(order, inter, rec, wrec, offsets, wsums, fix, tw, mesh_a, mesh_b, split, exact, s); \
+    case 256: return paint_z_n<T, 256>(order, inter, rec, wrec, offsets, wsums, fix, tw, mesh_a, mesh_b, split, exact, s); \
+    case 512: return paint_z_n<T, 512>(order, inter, rec, wrec, offsets, wsums, fix, tw, mesh_a, mesh_b, split, exact, s); \
+    case 1024: return paint_z_n<T, 1024>(order, inter, rec, wrec, offsets, wsums, fix, tw, mesh_a, mesh_b, split, exact, s); \
+    case 2048: return paint_z_n<T, 2048>(order, inter, rec, wrec, offsets, wsums, fix, tw, mesh_a, mesh_b, split, exact, s); \
     default: return hipErrorInvalidValue;                                                  \
   }
   if (dtype == PK_F32) {
