@@ -137,16 +137,16 @@ def measured_traffic(workload, kernel):
     return None if k is None else k.get("bytes_per_launch")
 
 
-# Kernels of each pk_fftpower stage, by name prefix (plan-time tables and
-# copies are not part of a call).
+# Kernels of each pk_fftpower stage, by name without template arguments
+# (plan-time tables and copies are not part of a call).
 STAGE_KERNELS = {
-    "bucket": ("k_fill_zero", "k_order_probe", "k_bucket_count", "k_weight_sums", "k_scan_",
-               "k_slab_columns", "k_bucket_scatter"),
+    "bucket": ("k_fill_zero", "k_order_probe", "k_bucket_count", "k_weight_sums", "k_scan_blocks",
+               "k_scan_sums", "k_scan_final", "k_slab_columns", "k_bucket_scatter"),
     "paint_z": ("k_paint_z",),
     "fft_y": ("k_fft_y_relayout",),
     "xpass_bin": ("k_xpass_bin",),
     "plane_bin": ("k_plane_bin",),
-    "reduce": ("k_reduce<", "k_reduce("),
+    "reduce": ("k_reduce",),
 }
 
 
@@ -162,7 +162,7 @@ def _counter_totals(directory, counter):
             for row in csv.DictReader(fh):
                 if row.get("Counter_Name") != counter:
                     continue
-                name = re.sub(r"^void ", "", row.get("Kernel_Name", ""))
+                name = re.sub(r"\(.*\)$", "", re.sub(r"^void ", "", row.get("Kernel_Name", "")))
                 key = (name, row.get("Dispatch_Id"))
                 per[key] = per.get(key, 0.0) + float(row["Counter_Value"])
     out = {}
@@ -191,7 +191,7 @@ def write_traffic(workload, directory, npart):
     calls = len(next((v for k, v in totals["FETCH_SIZE"].items() if "k_xpass_bin" in k), []))
     for stage, prefixes in STAGE_KERNELS.items():
         names = sorted({k for c in totals for k in totals[c]
-                        if any(k.startswith("pk::" + p) for p in prefixes)})
+                        if re.sub(r"<.*", "", k) in {"pk::" + p for p in prefixes}})
         b = {}
         for c, key in (("FETCH_SIZE", "fetch_bytes"), ("WRITE_SIZE", "write_bytes")):
             kib = sum(sum(totals[c].get(k, [])) for k in names)

@@ -872,7 +872,7 @@ __global__ void __launch_bounds__((PaintCfg<T, N, P, MODE>::THREADS))
   constexpr int M = Cf::M, TX = Cf::TX, TY = Cf::TY;
   constexpr int ROWS = Cf::ROWS, ROWA = Cf::ROWA;
   constexpr int mask = N - 1;
-  __shared__ Acc acc[ROWS * ROWA];
+  __shared__ __align__(16) Acc acc[ROWS * ROWA];
   __shared__ cpx<T> twm[M];  // W_N^k, k < M, for the r2c split
   __shared__ cpx<T> tws[stage_table_size<M, Cf::FE>() + 1];
   __shared__ int seg_start[2 * (TX + 4)], seg_cum[2 * (TX + 4) + 1], seg_row[2 * (TX + 4)];
@@ -943,7 +943,10 @@ __global__ void __launch_bounds__((PaintCfg<T, N, P, MODE>::THREADS))
     if ((int)threadIdx.x < STS) tw_s = tw[2 * stage_table_source<M, Cf::FE>(threadIdx.x)];
   }
 
-  for (int i = threadIdx.x; i < ROWS * ROWA; i += blockDim.x) acc[i] = 0;
+  // cleared 16 bytes at a time (half the stores and loop steps of 8)
+  static_assert((ROWS * ROWA) % 2 == 0, "the rows hold whole pairs of words");
+  for (int i = threadIdx.x; i < ROWS * ROWA / 2; i += blockDim.x)
+    reinterpret_cast<double2*>(acc)[i] = double2{0.0, 0.0};
   // prefix sums of the segment lengths: a scan across the first wavefront
   // (the segment threads are its first WX lanes; the other lanes add 0)
   static_assert(WX <= 64, "segment threads within one wavefront");
@@ -1052,17 +1055,28 @@ __global__ void __launch_bounds__((PaintCfg<T, N, P, MODE>::THREADS))
         double wz[P];  // exact painting: scaled by 2^S (exactly)
 #pragma unroll
         for (int c = 0; c < P; ++c) wz[c] = exact ? (double)w[2][c] * fix_scale : (double)w[2][c];
+        // validity and row offsets of the P x and P y cells, once per mesh
+        // (each block then takes only its lane mask and one address add)
+        bool vx[P], vy[P];
+        int rx[P], ry[P];
 #pragma unroll
         for (int a = 0; a < P; ++a) {
           const int lx = (first[0] + a - X0) & mask;
-          if (lx >= TX) continue;
+          vx[a] = lx < TX;
+          rx[a] = (mesh * TX + lx) * TY * ROWA + zb;
+          const int ly = (first[1] + a - Y0) & mask;
+          vy[a] = ly < TY;
+          ry[a] = ly * ROWA;
+        }
+#pragma unroll
+        for (int a = 0; a < P; ++a) {
+          if (!vx[a]) continue;
           const T wa = wp * w[0][a];
 #pragma unroll
           for (int b2 = 0; b2 < P; ++b2) {
-            const int ly = (first[1] + b2 - Y0) & mask;
-            if (ly >= TY) continue;
+            if (!vy[b2]) continue;
             const double wab = (double)(wa * w[1][b2]);
-            Acc* row = acc + ((mesh * TX + lx) * TY + ly) * ROWA + zb;
+            Acc* row = acc + rx[a] + ry[b2];
             if (exact) {
               // the bits of 1.5 * 2^52 + v minus those of 1.5 * 2^52: v
               // rounded to an integer, two's complement (|v| < 2^51)
