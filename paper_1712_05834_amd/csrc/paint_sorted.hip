@@ -776,11 +776,12 @@ constexpr int kPaintLdsBudgetKB = 76;  // two workgroups per CU
 // shifted by half a cell (interlacing), kPaintAB both in one pass.
 constexpr int kPaintA = 0, kPaintB = 1, kPaintAB = 2;
 // Interlaced meshes are painted by one two-mesh launch by default: each
-// record is read once for both meshes.  With nontemporal mesh stores this is
-// also the faster choice for every window measured (Zel'dovich 1024^3 CIC:
-// 4.99 against 5.03 ms for two single-mesh launches, whose record reads from
-// L2 misses come to 6.0 GB against 4.4 GB; log-normal 512^3 TSC: 0.83
-// against 0.85 ms).  The tuner can still choose two launches per input.
+// record is read once for both meshes (Zel'dovich 1024^3 CIC: 4.82 against
+// 4.92 ms for two single-mesh launches, whose record reads from L2 misses
+// come to 6.0 GB against 4.4 GB).  For TSC two launches, with tiles twice
+// as wide, are within the noise of one (log-normal 512^3: 0.664 against
+// 0.674 ms) but fetch 1.36x the algorithmic bytes against 1.15x.  The tuner
+// can choose two launches per input.
 constexpr bool split_interlaced(int) { return false; }
 
 
@@ -1140,8 +1141,11 @@ __global__ void __launch_bounds__((PaintCfg<T, N, P, MODE>::THREADS))
   // moves the DC mode), and the difference d = hi 2^32 + lo goes to float32
   // as hi 2^(32-S) + lo 2^-S in float32 arithmetic (no float64 operations
   // per cell; within 1.5 ulp of the rounded value)
+  // (NaN cells: NaN scales, so that every converted cell is NaN)
   const long long mean_q = exact && !nan_cells ? __double2ll_rn(mean * fix_scale) : 0ll;
-  const float f_lo = exact ? (float)fix_inv : 0.f, f_hi = exact ? (float)(fix_inv * 4294967296.0) : 0.f;
+  const float f_nan = __int_as_float(0x7fc00000);
+  const float f_lo = nan_cells ? f_nan : (float)fix_inv;
+  const float f_hi = nan_cells ? f_nan : (float)(fix_inv * 4294967296.0);
   constexpr int FE = Cf::FE, FTPL = Cf::FTPL;
   const bool fa = (int)threadIdx.x < Cf::FTHREADS;
   const int r = fa ? (int)threadIdx.x / FTPL : 0, t = (int)threadIdx.x % FTPL;
@@ -1157,7 +1161,6 @@ __global__ void __launch_bounds__((PaintCfg<T, N, P, MODE>::THREADS))
         const long long d0 = irow[wj] - mean_q, d1 = irow[wj + 1] - mean_q;
         v[e] = {static_cast<T>(fmaf((float)(int)(d0 >> 32), f_hi, (float)(unsigned)d0 * f_lo)),
                 static_cast<T>(fmaf((float)(int)(d1 >> 32), f_hi, (float)(unsigned)d1 * f_lo))};
-        if (nan_cells) v[e] = {static_cast<T>(mean), static_cast<T>(mean)};
       } else {
         v[e] = {static_cast<T>(arow[wj] - mean), static_cast<T>(arow[wj + 1] - mean)};
       }
