@@ -221,6 +221,29 @@ def write_traffic(workload, directory, npart):
     return path
 
 
+def request_latency(ctx, m, b, pos, npart, step_ms, count=60, lanes=2):
+    """p50 / p99 latency (arrival to result on the host) of `count` requests
+    of the timed workload arriving as a Poisson process at half the rate one
+    GPU sustains (1 / step_ms), served on `lanes` lanes of the context; the
+    catalog stays resident, each request gets its own workspace."""
+    import torch
+
+    from paper_1712_05834_amd import synth
+    from paper_1712_05834_amd.serve import (LibpkBackend, Request, Server, latency_stats,
+                                            poisson_arrivals)
+
+    qps = 0.5 * 1e3 / step_ms
+    backend = LibpkBackend(ctx, lanes)
+    free, _ = torch.cuda.mem_get_info()
+    budget = int(free - 8 * 2 ** 30)
+    Server(backend, budget).run([Request(-1, 0.0, m, b, pos, npart)])  # lanes warmed up
+    arrivals = poisson_arrivals(count, qps, synth.rng_for(77))
+    reqs = [Request(i, a, m, b, pos, npart) for i, a in enumerate(arrivals)]
+    st = latency_stats(Server(backend, budget).run(reqs))
+    st.update(qps=qps, lanes=lanes)
+    return st
+
+
 def cpu_model():
     try:
         with open("/proc/cpuinfo") as fh:
@@ -396,6 +419,9 @@ def main():
                     help="batch-mocks: keep only the mocks on these mesh sizes (comma list), to "
                          "time parts of the batch")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-latency", action="store_true",
+                    help="skip the request-latency leg (p50 / p99 of requests of the workload "
+                         "arriving at half the sustained rate)")
     ap.add_argument("--shuffle", action="store_true",
                     help="permute the catalog (seeded) before timing: a catalog in no "
                          "particular order instead of the generator's cell order")
@@ -541,7 +567,12 @@ def main():
             "traffic": None if args.shuffle else measured_traffic(args.workload, dominant),
         },
         "cpu_baseline": None,
+        "latency": None,
     }
+    if not args.no_latency:
+        line["latency"] = request_latency(ctx, m, b, pos, npart, ms_per_step)
+        log(f"request latency at {line['latency']['qps']:.0f} QPS: p50 "
+            f"{line['latency']['p50_ms']:.2f} ms, p99 {line['latency']['p99_ms']:.2f} ms")
     if not args.no_cpu_baseline:
         frac = args.cpu_sample if args.cpu_sample else (1.0 if w["n"] <= 512 else 0.03)
         log(f"timing the CPU oracle on {frac:g} of the catalog")
