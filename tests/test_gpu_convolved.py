@@ -83,6 +83,26 @@ def test_survey_multipoles_match_oracle(ctx, dtype, window):
     compare(got, want, dtype, (0, 2, 4))
 
 
+def test_survey_multipoles_128_match_oracle(ctx):
+    # 128^3 float32 (tiles of the larger instantiations: 16 columns per
+    # paint workgroup, several x-pass tiles per row), weighted, TSC
+    n, box = 128, 1000.0
+    obs = np.array([0.5 * box, 0.45 * box, -0.5 * box])
+    data, rand = synth.survey_catalog(n, box, synth.pk_lognormal_c2, 0.04, 31, obs, 0.6 * box,
+                                      1.6 * box, rand_factor=2.0, dtype=np.float32)
+    wd = synth.uniform_weights(len(data), seed=32, dtype=np.float32)
+    wr = synth.uniform_weights(len(rand), seed=33, dtype=np.float32)
+    norm = float(np.sum(wd.astype(np.float64))) ** 2 / box ** 3
+    m = _lib.mesh_desc(n, box, "tsc", False, True, "f4")
+    b = _lib.bin_desc(64, 0.0, 1.0, poles=(0, 2, 4))
+    print(f"\nsurvey 128^3: {len(data)} data, {len(rand)} randoms", flush=True)
+    got = run_gpu(ctx, m, b, obs, data, rand, wd, wr, norm)
+    want = oracle.convolved_power(data.astype(np.float64), rand.astype(np.float64),
+                                  wd.astype(np.float64), wr.astype(np.float64), obs, n, box, norm,
+                                  "tsc", (0, 2, 4), True, 0.0, 1.0, 64)
+    compare(got, want, "f4", (0, 2, 4))
+
+
 @pytest.mark.parametrize("dtype", ["f8", "f4"])
 def test_survey_multipoles_ragged_bins_pole_order_unweighted(ctx, dtype):
     # 64^3 (several FFT tiles), fractional edges, poles out of order, unit
@@ -115,15 +135,15 @@ def test_survey_multipoles_single_pole_and_observer_inside(ctx):
     assert np.all(np.isfinite(got["poles"][2][got["modes"] > 0]))
 
 
-@pytest.mark.parametrize("dtype", ["f8", "f4"])
-def test_distant_observer_equals_fftpower_multipoles_256(ctx, dtype):
+@pytest.mark.parametrize("dtype,n", [("f8", 256), ("f4", 256), ("f4", 512)])
+def test_distant_observer_equals_fftpower_multipoles(ctx, dtype, n):
     # a property that holds at any size: with the observer 10^7 box lengths
     # away along -z, every r^ is z^ to 1e-7, F_ell -> L_ell(mu) F_0 mode by
     # mode, and the raw sums of Re F_0 conj F_ell equal the FFTPower sums of
     # |c|^2 L_ell(mu) along z for the same field (data - alpha randoms painted
     # as weights), through independent kernels (fused x-pass against
     # Y_lm paintings and column FFTs)
-    n, box = 256, 1000.0
+    box = 1000.0 * n / 256
     data = synth.lognormal_catalog(n, box, synth.pk_lognormal_c2, 0.05, seed=41,
                                    dtype=NDT[dtype])
     rand = synth.uniform_catalog(2 * len(data), box, seed=42, dtype=NDT[dtype])
