@@ -295,6 +295,76 @@ __device__ __forceinline__ void flush_bins(const unsigned long long* sb, const B
   }
 }
 
+// Binning pass layout of the x-pass: the power of a tile's C x N modes is
+// staged in LDS as pw[col][kx + kx / S] and re-read so that the 64 lanes of a
+// wave see one column at kx spaced S = N / 64 apart: distinct |n| bins, hence
+// few same-address collisions of the LDS atomics.  Rows of the C columns
+// start 64 / C banks apart (N + N / S is a multiple of 64 words), so that the
+// staging writes of a wave (C columns x 64 / C consecutive kx) fall in
+// distinct banks.
+template <typename T, int N, int C>
+struct XStage {
+  static constexpr int S = N >= 64 ? N / 64 : 1;
+  static constexpr int WPE = (int)(sizeof(T) / 4);  // 4-byte words per staged value
+  static constexpr int RPAD = 64 / (C * WPE) > 1 ? 64 / (C * WPE) : 1;
+  static constexpr int PROW = N >= 64 ? N + N / S + RPAD : N;
+  static constexpr long BYTES = (long)C * PROW * sizeof(T);
+  __device__ __forceinline__ static int idx(int cc, int kx) {
+    return cc * PROW + (N >= 64 ? kx + kx / S : kx);
+  }
+  // idx(cc, t + TPL e) - idx(cc, t) for t < TPL, when TPL is a multiple of
+  // S: the points of a thread sit at constant offsets from its first
+  template <int TPL>
+  __host__ __device__ static constexpr int step() {
+    static_assert(N < 64 || TPL % S == 0, "x-pass points per thread a multiple of S apart");
+    return N >= 64 ? TPL + TPL / S : TPL;
+  }
+};
+
+// Bins the staged power of one tile (row ky, packed columns col0 .. col0 +
+// C - 1).  The modes n_x and -n_x of a column share |n|^2 and n_los^2 (for
+// any line of sight), hence every bin, so work item j < N/2 bins the sum of
+// the powers at kx = j and N - j; item 0 bins n_x = 0 and n_x = -N/2
+// separately.  With 64-lane waves, item m = 64 * slot + lane covers column
+// slot / S2 and j = lane * S2 + slot % S2 (distinct |n| bins across a wave:
+// few same-address collisions of the LDS atomics); small workgroups take
+// column m / IC and j = m % IC.
+template <typename T, int N, int C, int THREADS>
+__device__ __forceinline__ void bin_tile(const T* pws, unsigned long long* sbx, const BinSpec& b,
+                                         int fs, int ky, int col0) {
+  using XS = XStage<T, N, C>;
+  constexpr int IC = N / 2;
+  constexpr bool WAVEWISE = IC >= 64 && THREADS % 64 == 0;
+  constexpr int S2 = IC >= 64 ? IC / 64 : 1;
+  const int los = b.los;
+  const int ny = signed_index(ky, N);
+  const int ny2 = ny * ny;
+  for (int m = threadIdx.x; m < C * IC; m += THREADS) {
+    int cc_, j;
+    if constexpr (WAVEWISE) {
+      const int slot = (m >> 6);
+      cc_ = slot / S2;
+      j = (m & 63) * S2 + slot % S2;
+    } else {
+      cc_ = m / IC;
+      j = m % IC;
+    }
+    const int nz = col0 + cc_;
+    if (nz == 0) continue;
+    const int nyz2 = ny2 + nz * nz;
+    const int nl2_yz = los == 1 ? ny2 : nz * nz;
+    if (j == 0) {
+      constexpr int H = N / 2;
+      accumulate<T>(sbx, b, fs, nyz2, los == 0 ? 0 : nl2_yz, T(2) * pws[XS::idx(cc_, 0)]);
+      accumulate<T>(sbx, b, fs, H * H + nyz2, los == 0 ? H * H : nl2_yz,
+                    T(2) * pws[XS::idx(cc_, H)]);
+    } else {
+      const T pw = pws[XS::idx(cc_, j)] + pws[XS::idx(cc_, N - j)];
+      accumulate<T>(sbx, b, fs, j * j + nyz2, los == 0 ? j * j : nl2_yz, T(2) * pw);
+    }
+  }
+}
+
 // At least 4 waves per SIMD (at most 128 VGPRs): two 512-thread workgroups
 // or one 1024-thread workgroup per CU.
 template <typename T, int N>
@@ -322,23 +392,11 @@ __global__ void __launch_bounds__((XCfg<T, N>::THREADS)) __attribute__((amdgpu_w
   build_stage_table<T, N, E>(tws, TwGlobal<T>{tw, 1});  // ends with a barrier
   const TwStage<T, N, E> tw1{tws};
   const int c = threadIdx.x % C, t = threadIdx.x / C;
-  const int los = b.los;
   const bool two = mesh_b != nullptr;
   LdsCols<T, C> lc{lds, c};
-  // binning pass layout: the power of the tile's C x N modes is staged in
-  // LDS as pw[col][kx + kx / S] and re-read so that the 64 lanes of a wave
-  // see one column at kx spaced S = N / 64 apart: distinct |n| bins, hence
-  // few same-address collisions of the LDS atomics.  Rows of the C columns
-  // start 64 / C banks apart (N + N / S is a multiple of 64 words), so that
-  // the staging writes of a wave (C columns x 64 / C consecutive kx) fall in
-  // distinct banks.
-  constexpr int S = N >= 64 ? N / 64 : 1;
-  constexpr int WPE = (int)(sizeof(T) / 4);  // 4-byte words per staged value
-  constexpr int RPAD = 64 / (C * WPE) > 1 ? 64 / (C * WPE) : 1;
-  constexpr int PROW = N >= 64 ? N + N / S + RPAD : N;
+  using XS = XStage<T, N, C>;
   T* pws = reinterpret_cast<T*>(lds);
-  static_assert((long)C * PROW * sizeof(T) <= (long)Cf::LDS_ELEMS * sizeof(cpx<T>), "staging");
-  auto pidx = [](int cc, int kx) { return cc * PROW + (N >= 64 ? kx + kx / S : kx); };
+  static_assert(XS::BYTES <= (long)Cf::LDS_ELEMS * sizeof(cpx<T>), "staging");
   const int ntiles = N * CHUNKS;
   // The meshes arrive in the y-pass output layout (YLayout).  The lines of a
   // tile are loaded into registers one tile ahead: the loads of the next
@@ -378,12 +436,12 @@ __global__ void __launch_bounds__((XCfg<T, N>::THREADS)) __attribute__((amdgpu_w
     const int ky = tile / CHUNKS;
     const int col0 = (tile % CHUNKS) * C;
     const int col = col0 + c;
-    const int ny = signed_index(ky, N);
     const cpx<T> phy = phx[ky], phz = phx[col];
     const T s_yz = sxs[ky] * sxs[col];
     stockham<T, N, E, 1>(va, t, tw1, lc);
     if (two) stockham<T, N, E, 1>(vb, t, tw1, lc);
     const cpx<T> phyz = two ? cmul(phy, phz) : cpx<T>{T(1), T(0)};
+    const int pbase = XS::idx(c, t);
     __syncthreads();  // every wave is done with the FFT exchanges
 #pragma unroll
     for (int e = 0; e < E; ++e) {
@@ -404,45 +462,11 @@ __global__ void __launch_bounds__((XCfg<T, N>::THREADS)) __attribute__((amdgpu_w
         const T s = sxs[kx] * s_yz;
         pw *= s * s;
       }
-      pws[pidx(c, kx)] = pw;
+      pws[pbase + e * XS::template step<TPL>()] = pw;
     }
     __syncthreads();
     if (tile_id + (int)gridDim.x < ntiles) issue_loads(tile_id + (int)gridDim.x);
-    // binning: the modes n_x and -n_x of a column share |n|^2 and n_los^2
-    // (for any line of sight), hence every bin, so work item j < N/2 bins
-    // the sum of the powers at kx = j and N - j; item 0 bins n_x = 0 and
-    // n_x = -N/2 separately.  With 64-lane waves, item m = 64 * slot + lane
-    // covers column slot / S2 and j = lane * S2 + slot % S2 (distinct |n|
-    // bins across a wave: few same-address collisions of the LDS atomics);
-    // small workgroups take column m / IC and j = m % IC.
-    constexpr int IC = N / 2;
-    constexpr bool WAVEWISE = IC >= 64 && Cf::THREADS % 64 == 0;
-    constexpr int S2 = IC >= 64 ? IC / 64 : 1;
-    const int ny2 = ny * ny;
-    for (int m = threadIdx.x; m < C * IC; m += Cf::THREADS) {
-      int cc_, j;
-      if constexpr (WAVEWISE) {
-        const int slot = (m >> 6);
-        cc_ = slot / S2;
-        j = (m & 63) * S2 + slot % S2;
-      } else {
-        cc_ = m / IC;
-        j = m % IC;
-      }
-      const int nz = col0 + cc_;
-      if (nz == 0) continue;
-      const int nyz2 = ny2 + nz * nz;
-      const int nl2_yz = los == 1 ? ny2 : nz * nz;
-      if (j == 0) {
-        constexpr int H = N / 2;
-        accumulate<T>(sbx, b, fs, nyz2, los == 0 ? 0 : nl2_yz, T(2) * pws[pidx(cc_, 0)]);
-        accumulate<T>(sbx, b, fs, H * H + nyz2, los == 0 ? H * H : nl2_yz,
-                      T(2) * pws[pidx(cc_, H)]);
-      } else {
-        const T pw = pws[pidx(cc_, j)] + pws[pidx(cc_, N - j)];
-        accumulate<T>(sbx, b, fs, j * j + nyz2, los == 0 ? j * j : nl2_yz, T(2) * pw);
-      }
-    }
+    bin_tile<T, N, C, Cf::THREADS>(pws, sbx, b, fs, ky, col0);
     __syncthreads();  // the staged power is read before the next tile's FFT reuses the LDS
   }
   flush_bins(sbx, b, fs, partials + (size_t)blockIdx.x * 2 * b.nsum);

@@ -1008,97 +1008,111 @@ __global__ void __launch_bounds__((PaintCfg<T, N, P, MODE>::THREADS))
     r_cur = rec[idx_cur];
     if (wrec) w_cur = wrec[idx_cur];
   }
-  for (int q = threadIdx.x; q < total; q += blockDim.x) {
-    // inside the loop idx_cur is a valid record; past the end the next load
-    // repeats it, so that the load is unconditional and the wait for the
-    // current record does not have to drain it
-    int seg_nxt = seg_cur;
-    const int idx_nxt = locate(q + (int)blockDim.x, seg_nxt);
-    const int idx_ld = idx_nxt >= 0 ? idx_nxt : idx_cur;
-    const RecT r_nxt = rec[idx_ld];
-    T w_nxt = T(1);
-    if (wrec) w_nxt = wrec[idx_ld];
-    {
-      const RecT r = r_cur;
-      const T wp = w_cur;
-      unsigned packed;
-      if constexpr (sizeof(T) == 4) {
-        packed = __float_as_uint(r.w);
-      } else {
-        packed = (unsigned)r.w;
-      }
-      const int ix = seg_row[seg_cur], iy = (int)(packed >> 16), iz = (int)(packed & 0xffff);
-      const T t3[3] = {r.x, r.y, r.z};
-      const int i3[3] = {ix, iy, iz};
-#pragma unroll
-      for (int mesh = 0; mesh < Cf::NM; ++mesh) {
-        int first[3];
-        T w[3][P];
-#pragma unroll
-        for (int d = 0; d < 3; ++d) {
-          // window of u = i + t (+ 1/2 for the interlaced mesh)
-          T tt = t3[d];
-          int base = i3[d];
-          if (MODE == kPaintB || (MODE == kPaintAB && mesh == 1)) {
-            if (tt >= T(0.5)) {
-              tt -= T(0.5);  // exact
-              base += 1;
-            } else {
-              tt += T(0.5);
-            }
-          }
-          window_frac<T, P>(tt, base, first[d], w[d]);
+  // The gather loop is instantiated once per summation mode (EX: exact
+  // fixed-point sums), so that the mode costs no per-cell selects or
+  // branches; the workgroup takes one of them.
+  auto gather = [&](auto ex_tag) {
+    constexpr bool EX = decltype(ex_tag)::value;
+    for (int q = threadIdx.x; q < total; q += blockDim.x) {
+      // inside the loop idx_cur is a valid record; past the end the next load
+      // repeats it, so that the load is unconditional and the wait for the
+      // current record does not have to drain it
+      int seg_nxt = seg_cur;
+      const int idx_nxt = locate(q + (int)blockDim.x, seg_nxt);
+      const int idx_ld = idx_nxt >= 0 ? idx_nxt : idx_cur;
+      const RecT r_nxt = rec[idx_ld];
+      T w_nxt = T(1);
+      if (wrec) w_nxt = wrec[idx_ld];
+      {
+        const RecT r = r_cur;
+        const T wp = w_cur;
+        unsigned packed;
+        if constexpr (sizeof(T) == 4) {
+          packed = __float_as_uint(r.w);
+        } else {
+          packed = (unsigned)r.w;
         }
-        // the P z cells are P consecutive words from first[2] + ZPAD_LO (the
-        // address is computed once per row, the cells are immediate
-        // offsets); products in float64 from the z weights converted once
-        const int zb = first[2] + Cf::ZPAD_LO;
-        double wz[P];  // exact painting: scaled by 2^S (exactly)
+        const int ix = seg_row[seg_cur], iy = (int)(packed >> 16), iz = (int)(packed & 0xffff);
+        const T t3[3] = {r.x, r.y, r.z};
+        const int i3[3] = {ix, iy, iz};
 #pragma unroll
-        for (int c = 0; c < P; ++c) wz[c] = exact ? (double)w[2][c] * fix_scale : (double)w[2][c];
-        // validity and row offsets of the P x and P y cells, once per mesh
-        // (each block then takes only its lane mask and one address add)
-        bool vx[P], vy[P];
-        int rx[P], ry[P];
+        for (int mesh = 0; mesh < Cf::NM; ++mesh) {
+          int first[3];
+          T w[3][P];
 #pragma unroll
-        for (int a = 0; a < P; ++a) {
-          const int lx = (first[0] + a - X0) & mask;
-          vx[a] = lx < TX;
-          rx[a] = (mesh * TX + lx) * TY * ROWA + zb;
-          const int ly = (first[1] + a - Y0) & mask;
-          vy[a] = ly < TY;
-          ry[a] = ly * ROWA;
-        }
-#pragma unroll
-        for (int a = 0; a < P; ++a) {
-          if (!vx[a]) continue;
-          const T wa = wp * w[0][a];
-#pragma unroll
-          for (int b2 = 0; b2 < P; ++b2) {
-            if (!vy[b2]) continue;
-            const double wab = (double)(wa * w[1][b2]);
-            Acc* row = acc + rx[a] + ry[b2];
-            if (exact) {
-              // the bits of 1.5 * 2^52 + v minus those of 1.5 * 2^52: v
-              // rounded to an integer, two's complement (|v| < 2^51)
-              unsigned long long* irow = reinterpret_cast<unsigned long long*>(row);
-#pragma unroll
-              for (int c = 0; c < P; ++c) {
-                const double y = __builtin_fma(wab, wz[c], kFixMagic);
-                atomicAdd(&irow[c], (unsigned long long)__double_as_longlong(y) - kFixMagicBits);
+          for (int d = 0; d < 3; ++d) {
+            // window of u = i + t (+ 1/2 for the interlaced mesh)
+            T tt = t3[d];
+            int base = i3[d];
+            if (MODE == kPaintB || (MODE == kPaintAB && mesh == 1)) {
+              if (tt >= T(0.5)) {
+                tt -= T(0.5);  // exact
+                base += 1;
+              } else {
+                tt += T(0.5);
               }
-            } else {
+            }
+            window_frac<T, P>(tt, base, first[d], w[d]);
+          }
+          // the P z cells are P consecutive words from first[2] + ZPAD_LO (the
+          // address is computed once per row, the cells are immediate
+          // offsets); products in float64 from the z weights converted once
+          const int zb = first[2] + Cf::ZPAD_LO;
+          double wz[P];  // exact painting: scaled by 2^S (exactly)
 #pragma unroll
-              for (int c = 0; c < P; ++c) atomicAdd(&row[c], wab * wz[c]);
+          for (int c = 0; c < P; ++c) wz[c] = EX ? (double)w[2][c] * fix_scale : (double)w[2][c];
+          // validity and row offsets of the P x and P y cells, once per mesh
+          // (each block then takes only its lane mask and one address add)
+          bool vx[P], vy[P];
+          int rx[P], ry[P];
+#pragma unroll
+          for (int a = 0; a < P; ++a) {
+            const int lx = (first[0] + a - X0) & mask;
+            vx[a] = lx < TX;
+            rx[a] = (mesh * TX + lx) * TY * ROWA + zb;
+            const int ly = (first[1] + a - Y0) & mask;
+            vy[a] = ly < TY;
+            ry[a] = ly * ROWA;
+          }
+#pragma unroll
+          for (int a = 0; a < P; ++a) {
+            if (!vx[a]) continue;
+            const T wa = wp * w[0][a];
+#pragma unroll
+            for (int b2 = 0; b2 < P; ++b2) {
+              if (!vy[b2]) continue;
+              const double wab = (double)(wa * w[1][b2]);
+              Acc* row = acc + rx[a] + ry[b2];
+              if constexpr (EX) {
+                // the bits of 1.5 * 2^52 + v minus those of 1.5 * 2^52: v
+                // rounded to an integer, two's complement (|v| < 2^51)
+                unsigned long long* irow = reinterpret_cast<unsigned long long*>(row);
+#pragma unroll
+                for (int c = 0; c < P; ++c) {
+                  const double y = __builtin_fma(wab, wz[c], kFixMagic);
+                  atomicAdd(&irow[c], (unsigned long long)__double_as_longlong(y) - kFixMagicBits);
+                }
+              } else {
+#pragma unroll
+                for (int c = 0; c < P; ++c) atomicAdd(&row[c], wab * wz[c]);
+              }
             }
           }
         }
       }
+      idx_cur = idx_nxt;
+      seg_cur = seg_nxt;
+      r_cur = r_nxt;
+      w_cur = w_nxt;
     }
-    idx_cur = idx_nxt;
-    seg_cur = seg_nxt;
-    r_cur = r_nxt;
-    w_cur = w_nxt;
+  };
+  if constexpr (sizeof(T) == 4) {
+    if (exact)
+      gather(std::true_type{});
+    else
+      gather(std::false_type{});
+  } else {
+    gather(std::false_type{});  // float64 meshes take the float64 sums
   }
   __syncthreads();
 

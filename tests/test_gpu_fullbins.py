@@ -139,3 +139,30 @@ def test_fused_1024_full_catalog_matches_standalone_chain(ctx):
     torch.cuda.empty_cache()
     report(got, chain, "1024^3 fused vs chain")
     check_power(got, chain, 1e-5, "1024^3 fused vs stand-alone chain")
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("compensated", [True, False])
+def test_fused_1024_single_mesh_matches_standalone_chain(ctx, compensated):
+    # one mesh (no interlacing), with and without the window compensation:
+    # the x-pass takes one (tile, mesh) unit per tile
+    n, box = 1024, 2000.0
+    pos = synth.zeldovich_lattice(192, box, synth.pk_zeldovich_c3, seed=4)
+    npart = len(pos)
+    pos_d = dev(pos)
+    m = _lib.mesh_desc(n, box, "cic", False, compensated, "f4")
+    b = _lib.bin_desc(n // 2, 0.0, 1.0, 0, (0, 2), 2)
+    got = fused(ctx, m, b, pos_d, npart)
+    a = torch.empty((n, n, n), dtype=torch.float32, device="cuda:0")
+    wsums = torch.empty(2, dtype=torch.float64, device="cuda:0")
+    ctx.pk_paint(m, pos_d, None, npart, 0.0, a, wsums)
+    ctx.pk_fft_r2c(m, a)
+    ctx.pk_compensate(m, a, None)
+    res = torch.empty(_lib.result_doubles(b), dtype=torch.float64, device="cuda:0")
+    ctx.pk_bin_power(m, b, a, res)
+    res[-2:] = wsums
+    chain = ctx.pk_result_to_host(m, b, res)
+    del a
+    torch.cuda.empty_cache()
+    report(got, chain, f"1024^3 single mesh (compensated {compensated}) fused vs chain")
+    check_power(got, chain, 1e-5, "1024^3 single mesh fused vs stand-alone chain")
