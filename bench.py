@@ -201,7 +201,7 @@ def write_traffic(workload, directory, npart):
         stages[stage] = {"kernels": names, **b, "bytes_per_launch": per,
                          "algorithmic_bytes": alg,
                          "ratio_to_algorithmic": per / alg if alg else None}
-    base = "python3 bench.py --workload {wl} --steps 2 --warmup 1 --no-cpu-baseline"
+    base = "python3 bench.py --workload {wl} --steps 2 --warmup 1 --no-cpu-baseline --no-latency"
     rec = {
         "workload": workload, "npart": npart, "source_hash": source_hash(), "calls": calls,
         "commands": [f"rocprofv3 --pmc {c} -f csv -d gpurun_out/pmc_{c}_{workload} -o run -- "
