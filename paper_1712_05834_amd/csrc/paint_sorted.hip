@@ -977,31 +977,29 @@ __global__ void __launch_bounds__((PaintCfg<T, N, P, MODE>::THREADS))
   // window cells that fall outside the block are outside for the whole wave
   // and their branches are skipped.
   constexpr int nseg = 2 * WX;
-  const int total = seg_cum[nseg];
-  // record index of work item q (-1 past the end); `seg` holds a segment at
-  // or before q's (items only move forward) and returns q's segment.  The
-  // next record is loaded before the current one is processed, so its
-  // latency overlaps the work.
+  static_assert(nseg <= 32, "segment bounds in scalar registers");
+  // the segment bounds are the same for every lane: kept in scalar
+  // registers, so that finding an item's segment takes no LDS reads
+  int scum[nseg + 1];
+#pragma unroll
+  for (int j = 0; j <= nseg; ++j) scum[j] = __builtin_amdgcn_readfirstlane(seg_cum[j]);
+  const int total = scum[nseg];
+  // record index of work item q (-1 past the end), and its segment in `seg`:
+  // the number of segment starts at or below q (independent compares, not a
+  // walk from segment to segment: a step of the loop moves q past several
+  // segments).  The next record is loaded before the current one is
+  // processed, so its latency overlaps the work.
   auto locate = [&](int q, int& seg) -> int {
-    if (q >= total) return -1;
-    int s = seg;
-    while (s + 1 < nseg && seg_cum[s + 1] <= q) ++s;
-    seg = s;
-    return seg_start[s] + (q - seg_cum[s]);
-  };
-  // the first item's segment: the number of segment starts at or below q,
-  // from independent (broadcast) LDS reads instead of a dependent walk
-  auto locate_first = [&](int q, int& seg) -> int {
     if (q >= total) return -1;
     int s = 0;
 #pragma unroll
-    for (int j = 1; j < nseg; ++j) s += seg_cum[j] <= q ? 1 : 0;
+    for (int j = 1; j < nseg; ++j) s += scum[j] <= q ? 1 : 0;
     seg = s;
     return seg_start[s] + (q - seg_cum[s]);
   };
   using RecT = typename Rec<T>::type;
   int seg_cur = 0;
-  int idx_cur = locate_first(threadIdx.x, seg_cur);
+  int idx_cur = locate(threadIdx.x, seg_cur);
   RecT r_cur{};
   T w_cur = T(1);
   if (idx_cur >= 0) {
