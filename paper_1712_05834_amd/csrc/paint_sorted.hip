@@ -944,10 +944,22 @@ __global__ void __launch_bounds__((PaintCfg<T, N, P, MODE>::THREADS))
     if ((int)threadIdx.x < STS) tw_s = tw[2 * stage_table_source<M, Cf::FE>(threadIdx.x)];
   }
 
+  // The mean density, subtracted before the z-FFT.  Exact painting subtracts
+  // it on the integer grid (it only moves the DC mode): every word starts at
+  // -round(mean 2^S) instead of 0, so that the cells need no subtraction when
+  // they are read back (the pad words carry the same start; the fold below
+  // adds one mean back with each of them).
+  const bool nan_cells = fix_bad;
+  const double mean = nan_cells ? __longlong_as_double(0x7ff8000000000000ll)
+                                : wsum / ((double)N * N * N);
+  const long long mean_q = exact && !nan_cells ? __double2ll_rn(mean * fix_scale) : 0ll;
   // cleared 16 bytes at a time (half the stores and loop steps of 8)
   static_assert((ROWS * ROWA) % 2 == 0, "the rows hold whole pairs of words");
-  for (int i = threadIdx.x; i < ROWS * ROWA / 2; i += blockDim.x)
-    reinterpret_cast<double2*>(acc)[i] = double2{0.0, 0.0};
+  {
+    const double f = __longlong_as_double(-mean_q);  // 0.0 unless exact
+    for (int i = threadIdx.x; i < ROWS * ROWA / 2; i += blockDim.x)
+      reinterpret_cast<double2*>(acc)[i] = double2{f, f};
+  }
   // prefix sums of the segment lengths: a scan across the first wavefront
   // (the segment threads are its first WX lanes; the other lanes add 0)
   static_assert(WX <= 64, "segment threads within one wavefront");
@@ -1059,18 +1071,19 @@ __global__ void __launch_bounds__((PaintCfg<T, N, P, MODE>::THREADS))
           double wz[P];  // exact painting: scaled by 2^S (exactly)
 #pragma unroll
           for (int c = 0; c < P; ++c) wz[c] = EX ? (double)w[2][c] * fix_scale : (double)w[2][c];
-          // validity and row offsets of the P x and P y cells, once per mesh
-          // (each block then takes only its lane mask and one address add)
+          // validity and row offsets (in bytes) of the P x and P y cells,
+          // once per mesh (each block then takes only its lane mask and one
+          // address add)
           bool vx[P], vy[P];
           int rx[P], ry[P];
 #pragma unroll
           for (int a = 0; a < P; ++a) {
             const int lx = (first[0] + a - X0) & mask;
             vx[a] = lx < TX;
-            rx[a] = (mesh * TX + lx) * TY * ROWA + zb;
+            rx[a] = ((mesh * TX + lx) * TY * ROWA + zb) * (int)sizeof(Acc);
             const int ly = (first[1] + a - Y0) & mask;
             vy[a] = ly < TY;
-            ry[a] = ly * ROWA;
+            ry[a] = ly * ROWA * (int)sizeof(Acc);
           }
 #pragma unroll
           for (int a = 0; a < P; ++a) {
@@ -1080,7 +1093,7 @@ __global__ void __launch_bounds__((PaintCfg<T, N, P, MODE>::THREADS))
             for (int b2 = 0; b2 < P; ++b2) {
               if (!vy[b2]) continue;
               const double wab = (double)(wa * w[1][b2]);
-              Acc* row = acc + rx[a] + ry[b2];
+              Acc* row = reinterpret_cast<Acc*>(reinterpret_cast<char*>(acc) + rx[a] + ry[b2]);
               if constexpr (EX) {
                 // the bits of 1.5 * 2^52 + v minus those of 1.5 * 2^52: v
                 // rounded to an integer, two's complement (|v| < 2^51)
@@ -1126,7 +1139,7 @@ __global__ void __launch_bounds__((PaintCfg<T, N, P, MODE>::THREADS))
     // j - 1 (word j)
     const int dst = j == 0 ? N : j, src = j == 0 ? 0 : N + j;
     if (exact) {
-      irow[dst] += irow[src];
+      irow[dst] += irow[src] + (unsigned long long)mean_q;
     } else {
       row[dst] += row[src];
     }
@@ -1143,18 +1156,14 @@ __global__ void __launch_bounds__((PaintCfg<T, N, P, MODE>::THREADS))
     build_stage_table<T, M, Cf::FE>(tws, TwGlobal<T>{tw, 2});  // ends with a barrier
   }
 
-  // r2c along z of every owned column, mean subtracted in float64 before the
-  // rounding to T (only the DC mode changes; it keeps the rounding relative to
-  // the fluctuations).  The row becomes the padded complex line.
-  const bool nan_cells = fix_bad;
-  const double mean = nan_cells ? __longlong_as_double(0x7ff8000000000000ll)
-                                : wsum / ((double)N * N * N);
-  // exact painting: the mean is subtracted on the integer grid (it only
-  // moves the DC mode), and the difference d = hi 2^32 + lo goes to float32
-  // as hi 2^(32-S) + lo 2^-S in float32 arithmetic (no float64 operations
-  // per cell; within 1.5 ulp of the rounded value)
+  // r2c along z of every owned column, mean subtracted before the rounding to
+  // T (only the DC mode changes; it keeps the rounding relative to the
+  // fluctuations): in float64 here, or already on the integer grid (exact
+  // painting), where the cell d = hi 2^32 + lo goes to float32 as
+  // hi 2^(32-S) + lo 2^-S in float32 arithmetic (no float64 operations per
+  // cell; within 1.5 ulp of the rounded value).  The row becomes the padded
+  // complex line.
   // (NaN cells: NaN scales, so that every converted cell is NaN)
-  const long long mean_q = exact && !nan_cells ? __double2ll_rn(mean * fix_scale) : 0ll;
   const float f_nan = __int_as_float(0x7fc00000);
   const float f_lo = nan_cells ? f_nan : (float)fix_inv;
   const float f_hi = nan_cells ? f_nan : (float)(fix_inv * 4294967296.0);
@@ -1170,7 +1179,7 @@ __global__ void __launch_bounds__((PaintCfg<T, N, P, MODE>::THREADS))
       const int wj = 2 * (t + FTPL * e) + Cf::ZPAD_LO;  // cells 2j, 2j + 1
       if (exact) {
         const long long* irow = reinterpret_cast<const long long*>(arow);
-        const long long d0 = irow[wj] - mean_q, d1 = irow[wj + 1] - mean_q;
+        const long long d0 = irow[wj], d1 = irow[wj + 1];
         v[e] = {static_cast<T>(fmaf((float)(int)(d0 >> 32), f_hi, (float)(unsigned)d0 * f_lo)),
                 static_cast<T>(fmaf((float)(int)(d1 >> 32), f_hi, (float)(unsigned)d1 * f_lo))};
       } else {
