@@ -48,7 +48,7 @@ __global__ void __launch_bounds__((ZCfg<T, N>::THREADS))
   stockham<T, M, E, 1>(v, t, tw2, line);
   __syncthreads();
 #pragma unroll
-  for (int e = 0; e < E; ++e) line.put(t + TPL * e, v[e]);
+  for (int e = 0; e < E; ++e) line.template put_step<TPL>(t, e, v[e]);
   __syncthreads();
 #pragma unroll
   for (int e = 0; e < E; ++e) {
@@ -57,8 +57,9 @@ __global__ void __launch_bounds__((ZCfg<T, N>::THREADS))
     if (k == 0) {
       out = {v[e].x + v[e].y, v[e].x - v[e].y};  // {X_0, X_{N/2}}, both real
     } else {
-      // X_k = (Z_k + conj Z_{M-k}) / 2 - (i / 2) W_N^k (Z_k - conj Z_{M-k})
-      const cpx<T> zc = cconj(line.get(M - k));
+      // X_k = (Z_k + conj Z_{M-k}) / 2 - (i / 2) W_N^k (Z_k - conj Z_{M-k});
+      // M - k = (TPL - t) + TPL (E - 1 - e)
+      const cpx<T> zc = cconj(line.template get_step<TPL>(TPL - t, E - 1 - e));
       const cpx<T> s = cadd(v[e], zc);
       const cpx<T> w = cmul(tw1(k), csub(v[e], zc));
       out = {T(0.5) * (s.x + w.y), T(0.5) * (s.y - w.x)};
@@ -96,7 +97,7 @@ __global__ void __launch_bounds__((ZCfg<T, N>::THREADS))
 #pragma unroll
   for (int e = 0; e < E; ++e) {
     v[e] = active ? rowp[t + TPL * e] : cpx<T>{T(0), T(0)};
-    line.put(t + TPL * e, v[e]);
+    line.template put_step<TPL>(t, e, v[e]);
   }
   __syncthreads();
 #pragma unroll
@@ -107,7 +108,7 @@ __global__ void __launch_bounds__((ZCfg<T, N>::THREADS))
       // X_0 and X_{N/2} are real: E_0 = X_0 + X_{N/2}, O_0 = X_0 - X_{N/2}
       zk = {v[e].x + v[e].y, v[e].x - v[e].y};
     } else {
-      const cpx<T> xc = cconj(line.get(M - k));
+      const cpx<T> xc = cconj(line.template get_step<TPL>(TPL - t, E - 1 - e));  // X_{M-k}
       const cpx<T> ev = cadd(v[e], xc);
       const cpx<T> od = cmul(cconj(tw1(k)), csub(v[e], xc));
       zk = {ev.x - od.y, ev.y + od.x};

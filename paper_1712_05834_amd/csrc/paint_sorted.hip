@@ -1193,7 +1193,7 @@ __global__ void __launch_bounds__((PaintCfg<T, N, P, MODE>::THREADS))
   __syncthreads();
   if (fa) {
 #pragma unroll
-    for (int e = 0; e < FE; ++e) line.put(t + FTPL * e, v[e]);
+    for (int e = 0; e < FE; ++e) line.template put_step<FTPL>(t, e, v[e]);
   }
   __syncthreads();
   if (!fa) return;
@@ -1207,7 +1207,7 @@ __global__ void __launch_bounds__((PaintCfg<T, N, P, MODE>::THREADS))
     if (k == 0) {
       o = {v[e].x + v[e].y, v[e].x - v[e].y};
     } else {
-      const cpx<T> zc = cconj(line.get(M - k));
+      const cpx<T> zc = cconj(line.template get_step<FTPL>(FTPL - t, FE - 1 - e));  // Z_{M-k}
       const cpx<T> s = cadd(v[e], zc);
       const cpx<T> w = cmul(twm[k], csub(v[e], zc));
       o = {T(0.5) * (s.x + w.y), T(0.5) * (s.y - w.x)};
