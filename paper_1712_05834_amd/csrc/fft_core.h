@@ -247,33 +247,33 @@ struct TwStage {
 
 // Fills a TwStage table (size stage_table_size<L, E>()) from any twiddle
 // source; all threads call it; it ends with a barrier.
-template <typename T, int L, int E, typename Src>
-__device__ __forceinline__ void build_stage_table(cpx<T>* dst, const Src& src) {
-  constexpr int R0 = stage_radix<L, E, 1>();
-  for (int i = threadIdx.x; i < stage_table_size<L, E>(); i += blockDim.x) {
-    int off = 0, p = R0;
-    while (i >= off + p * (E - 1)) {
-      off += p * (E - 1);
-      p *= E;
-    }
-    const int k = (i - off) / (E - 1), m = (i - off) % (E - 1) + 1;
-    dst[i] = src(m * k * (L / (p * E)));
-  }
-  __syncthreads();
-}
-
-// Index j of the source twiddle W_L^j of entry i of the stage table (as
-// build_stage_table fills it), for i < stage_table_size<L, E>().
+// Index j of the source twiddle W_L^j of entry i of the stage table, for
+// i < stage_table_size<L, E>(): entry i lies in the last stage whose offset
+// is at most i (the stages are a compile-time list, so the search is a few
+// compares and selects of constants, not a loop).
 template <int L, int E>
 __host__ __device__ inline int stage_table_source(int i) {
   constexpr int R0 = stage_radix<L, E, 1>();
-  int off = 0, p = R0;
-  while (i >= off + p * (E - 1)) {
+  int base = 0, step = L / (R0 * E);  // the stage's offset and L / (p E)
+  int off = 0;
+#pragma unroll
+  for (int p = R0; p < L; p *= E) {
+    if (i >= off) {
+      base = off;
+      step = L / (p * E);
+    }
     off += p * (E - 1);
-    p *= E;
   }
-  const int k = (i - off) / (E - 1), m = (i - off) % (E - 1) + 1;
-  return m * k * (L / (p * E));
+  const int r = i - base;
+  const int k = r / (E - 1), m = r % (E - 1) + 1;
+  return m * k * step;
+}
+
+template <typename T, int L, int E, typename Src>
+__device__ __forceinline__ void build_stage_table(cpx<T>* dst, const Src& src) {
+  for (int i = threadIdx.x; i < stage_table_size<L, E>(); i += blockDim.x)
+    dst[i] = src(stage_table_source<L, E>(i));
+  __syncthreads();
 }
 
 // Loads the first quarter of the global table W_Nt^j into LDS (all threads

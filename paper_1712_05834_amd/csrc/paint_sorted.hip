@@ -47,7 +47,7 @@ namespace pk {
 constexpr double kFixMagic = 6755399441055744.0;
 constexpr unsigned long long kFixMagicBits = 0x4338000000000000ull;
 // slots of the exact painting's grid in the bucketing workspace
-constexpr int kFixScale = 0, kFixInv = 1, kFixState = 2;
+constexpr int kFixScale = 0, kFixInv = 1, kFixState = 2, kFixMeanQ = 3;
 
 template <typename T>
 struct Rec;
@@ -420,11 +420,13 @@ __global__ void __launch_bounds__(256)
 // block order; then the grid 2^-S of the exact painting from n and
 // sum (w V)^2 (see k_paint_z): fix[kFixScale] = 2^S, fix[kFixInv] = 2^-S,
 // fix[kFixState] = 0 (exact), 1 (non-finite amounts or coordinates: NaN
-// cells) or 2 (S out of range: float64 sums).
+// cells) or 2 (S out of range: float64 sums), and fix[kFixMeanQ] the bits
+// of the int64 round(2^S sum w / N^3), the mean on the integer grid (0
+// unless exact).
 __global__ void __launch_bounds__(1024)
     k_weight_sums(const double* __restrict__ wpart, int nblocks_runs, int nblocks_slabs,
                   double* __restrict__ wsums, const int* __restrict__ mode, int64_t n,
-                  double* __restrict__ fix) {
+                  int nmesh, double* __restrict__ fix) {
   const int nblocks = route_of(mode) == kRouteSlabs ? nblocks_slabs : nblocks_runs;
   __shared__ double sh[2][1024];
   double a = 0.0, b = 0.0;
@@ -456,9 +458,15 @@ __global__ void __launch_bounds__(1024)
       if (S < -90) state = 2.0;
       scale = ldexp(1.0, S);
     }
+    long long mean_q = 0;
+    if (state == 0.0) {
+      const double mean = sh[0][0] / ((double)nmesh * nmesh * nmesh);
+      mean_q = __double2ll_rn(mean * scale);
+    }
     fix[kFixScale] = scale;
     fix[kFixInv] = 1.0 / scale;  // exact: a power of two
     fix[kFixState] = state;
+    fix[kFixMeanQ] = __longlong_as_double(mean_q);
   }
 }
 
@@ -927,6 +935,7 @@ __global__ void __launch_bounds__((PaintCfg<T, N, P, MODE>::THREADS))
   // ~10^27, take the float64 sums.)  The bucketing's k_weight_sums sets the
   // scale once.
   double fix_scale = 1.0, fix_inv = 1.0;
+  long long fix_mean = 0;
   bool fix_bad = false, exact = exact_in != 0;
   if (exact) {
     const double state = fix[kFixState];
@@ -934,6 +943,7 @@ __global__ void __launch_bounds__((PaintCfg<T, N, P, MODE>::THREADS))
     if (state == 2.0) exact = false;
     fix_scale = fix[kFixScale];
     fix_inv = fix[kFixInv];
+    fix_mean = __double_as_longlong(fix[kFixMeanQ]);
   }
 
   constexpr int STS = stage_table_size<M, Cf::FE>();
@@ -949,10 +959,9 @@ __global__ void __launch_bounds__((PaintCfg<T, N, P, MODE>::THREADS))
   // -round(mean 2^S) instead of 0, so that the cells need no subtraction when
   // they are read back (the pad words carry the same start; the fold below
   // adds one mean back with each of them).
+  // (the bucketing computed round(mean 2^S) along with S)
   const bool nan_cells = fix_bad;
-  const double mean = nan_cells ? __longlong_as_double(0x7ff8000000000000ll)
-                                : wsum / ((double)N * N * N);
-  const long long mean_q = exact && !nan_cells ? __double2ll_rn(mean * fix_scale) : 0ll;
+  const long long mean_q = exact && !nan_cells ? fix_mean : 0ll;
   // cleared 16 bytes at a time (half the stores and loop steps of 8)
   static_assert((ROWS * ROWA) % 2 == 0, "the rows hold whole pairs of words");
   {
@@ -1183,6 +1192,8 @@ __global__ void __launch_bounds__((PaintCfg<T, N, P, MODE>::THREADS))
         v[e] = {static_cast<T>(fmaf((float)(int)(d0 >> 32), f_hi, (float)(unsigned)d0 * f_lo)),
                 static_cast<T>(fmaf((float)(int)(d1 >> 32), f_hi, (float)(unsigned)d1 * f_lo))};
       } else {
+        const double mean = nan_cells ? __longlong_as_double(0x7ff8000000000000ll)
+                                      : wsum / ((double)N * N * N);
         v[e] = {static_cast<T>(arow[wj] - mean), static_cast<T>(arow[wj + 1] - mean)};
       }
     }
@@ -1311,7 +1322,7 @@ hipError_t launch_bucket(int dtype, int nmesh, double boxsize, const void* pos, 
                        static_cast<const double*>(value), n, chunk, nmesh, boxsize, inv_box, cpl, count,
                        wpart, mode, sa);
   hipLaunchKernelGGL(k_weight_sums, dim3(1), dim3(1024), 0, s, wpart, (int)blocks, (int)sblocks,
-                     wsums, mode, n, reinterpret_cast<double*>(bw + L.fix));
+                     wsums, mode, n, nmesh, reinterpret_cast<double*>(bw + L.fix));
   // the run route's scan (zero counts on the slab route)
   hipLaunchKernelGGL(k_scan_blocks, dim3(nb), dim3(1024), 0, s, count, n2, bsums);
   hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(1024), 0, s, bsums, nb);
