@@ -1030,6 +1030,8 @@ __global__ void __launch_bounds__((PaintCfg<T, N, P, MODE>::THREADS))
   // The gather loop is instantiated once per summation mode (EX: exact
   // fixed-point sums), so that the mode costs no per-cell selects or
   // branches; the workgroup takes one of them.
+  // 2^S in the mesh precision (exact: -90 <= S <= 120)
+  const T scale_t = static_cast<T>(fix_scale);
   auto gather = [&](auto ex_tag) {
     constexpr bool EX = decltype(ex_tag)::value;
     for (int q = threadIdx.x; q < total; q += blockDim.x) {
@@ -1044,7 +1046,10 @@ __global__ void __launch_bounds__((PaintCfg<T, N, P, MODE>::THREADS))
       if (wrec) w_nxt = wrec[idx_ld];
       {
         const RecT r = r_cur;
-        const T wp = w_cur;
+        // exact painting: the amount carries the grid scale 2^S (a power of
+        // two, within float range, so the float products below are the
+        // unscaled ones times 2^S exactly)
+        const T wp = EX ? w_cur * scale_t : w_cur;
         unsigned packed;
         if constexpr (sizeof(T) == 4) {
           packed = __float_as_uint(r.w);
@@ -1077,9 +1082,9 @@ __global__ void __launch_bounds__((PaintCfg<T, N, P, MODE>::THREADS))
           // address is computed once per row, the cells are immediate
           // offsets); products in float64 from the z weights converted once
           const int zb = first[2] + Cf::ZPAD_LO;
-          double wz[P];  // exact painting: scaled by 2^S (exactly)
+          double wz[P];
 #pragma unroll
-          for (int c = 0; c < P; ++c) wz[c] = EX ? (double)w[2][c] * fix_scale : (double)w[2][c];
+          for (int c = 0; c < P; ++c) wz[c] = (double)w[2][c];
           // validity and row offsets (in bytes) of the P x and P y cells,
           // once per mesh (each block then takes only its lane mask and one
           // address add)
