@@ -1010,11 +1010,20 @@ __global__ void __launch_bounds__((PaintCfg<T, N, P, MODE>::THREADS))
   // walk from segment to segment: a step of the loop moves q past several
   // segments).  The next record is loaded before the current one is
   // processed, so its latency overlaps the work.
+  // Unless the block's y window wraps around the mesh (two of every N / TY
+  // blocks), the second segment of every source row is empty, and only the
+  // first segments' starts need comparing.
+  const bool y_wraps = run1 > 0;
   auto locate = [&](int q, int& seg) -> int {
     if (q >= total) return -1;
     int s = 0;
+    if (y_wraps) {
 #pragma unroll
-    for (int j = 1; j < nseg; ++j) s += scum[j] <= q ? 1 : 0;
+      for (int j = 1; j < nseg; ++j) s += scum[j] <= q ? 1 : 0;
+    } else {
+#pragma unroll
+      for (int j = 2; j < nseg; j += 2) s += scum[j] <= q ? 2 : 0;
+    }
     seg = s;
     return seg_start[s] + (q - seg_cum[s]);
   };
