@@ -115,3 +115,41 @@ def test_fused_path_with_a_non_finite_weight_is_nan(ctx):
     ctx.pk_fftpower(m, b, pos, w, npart, ws, r)
     torch.cuda.synchronize()
     assert bool(torch.isnan(r[: b.nk]).all())
+
+
+@pytest.mark.parametrize("scale", [2.0 ** 45, 2.0 ** -40, 1e12, 1e-12])
+def test_fused_path_does_not_depend_on_the_weight_scale(ctx, scale):
+    # P = |F|^2 / (sum w)^2 and the shot noise are invariant under w -> s w.
+    # The exact painting sets its grid 2^-S from n and sum w^2 (S = 42 at unit
+    # weights here), so these scales take it to S = -3 and S = 82; with s a
+    # power of two the painted integers are the same and so is every bit of
+    # the normalised result.  (The float32 spectrum bounds the range: the
+    # compensated |F|^2 of every mode must stay a normal float32.)
+    n, box, npart = 64, 400.0, 50_000
+    rng = np.random.default_rng(11)
+    pos = torch.from_numpy(rng.uniform(0, box, (npart, 3)).astype(np.float32)).to("cuda:0")
+    w0 = rng.uniform(0.5, 1.5, npart).astype(np.float32)
+    m = _lib.mesh_desc(n, box, "tsc", True, True, "f4")
+    b = _lib.bin_desc(n // 2, 0.0, 1.0, 3, (0, 2), 2)
+    ws = torch.empty(_lib.workspace_bytes(m, b, npart), dtype=torch.uint8, device="cuda:0")
+
+    def run(w):
+        wt = torch.from_numpy(w).to("cuda:0")
+        r = torch.empty(_lib.result_doubles(b), dtype=torch.float64, device="cuda:0")
+        ctx.pk_fftpower(m, b, pos, wt, npart, ws, r)
+        out = ctx.pk_result_to_host(m, b, r)
+        torch.cuda.synchronize()
+        return out
+
+    ref = run(w0)
+    got = run((w0.astype(np.float64) * scale).astype(np.float32))
+    exact = scale in (2.0 ** 45, 2.0 ** -40)
+    rtol = 1e-12 if exact else 1e-5
+    ok, ok2 = ref["modes"] > 0, ref["modes2d"] > 0
+    np.testing.assert_array_equal(got["modes"], ref["modes"])
+    assert np.isfinite(got["power"][ok]).all() and np.isfinite(got["power2d"][ok2]).all()
+    np.testing.assert_allclose(got["power"][ok], ref["power"][ok], rtol=rtol)
+    np.testing.assert_allclose(got["poles"][2][ok], ref["poles"][2][ok],
+                               rtol=0, atol=rtol * np.abs(ref["power"][ok]).max())
+    np.testing.assert_allclose(got["power2d"][ok2], ref["power2d"][ok2], rtol=10 * rtol)
+    np.testing.assert_allclose(got["shotnoise"], ref["shotnoise"], rtol=rtol)
